@@ -1,0 +1,179 @@
+/*
+ * wf.h -- C ABI of the widefield radio-interferometric measurement operator on one
+ * MI355X (gfx950).
+ *
+ * The operator is the hybrid w-stacking / w-projection model of Dabbech & Wiaux,
+ * "A distributed resource-adaptive implementation of the widefield radio-
+ * interferometric measurement model for scalable image formation":
+ *
+ *   y = Phi x + n                        (Sect. 2, eq. 3)
+ *   Phi = [Phi_1 .. Phi_P]^T,  Phi_p = G_p F Z_p              (Sect. 3.2, eq. 6)
+ *   Phi^dag Phi = sum_p Z_p^dag F^dag G_p^dag G_p F Z_p        (Sect. 3.3, eq. 7-8)
+ *
+ * Z_p is the w-layer of bin p times the grid correction, F the 2x-oversampled 2-D DFT,
+ * G_p the sparse de-gridding matrix whose rows are Kaiser-Bessel taps convolved with a
+ * per-visibility residual-w Fourier kernel (Sect. 3.1).  The number of w-bins P and the
+ * strategy are chosen at build time from the memory model (eq. 9) and the cost model
+ * (eq. 10) by the decision tree of Sect. 3.4 / Fig. 2, under one GPU's memory.
+ *
+ * Conventions
+ *  - Every call returns wf_status; 0 (WF_OK) is success.  No C++ exception crosses the
+ *    ABI.  On failure wf_last_error() returns a thread-local message.
+ *  - Image pixel (i, j) of an nx x ny image is at direction cosines
+ *    l = (i - nx/2) cell, m = (j - ny/2) cell; images are row-major [ny][nx] (rows = m).
+ *    nx, ny must be even powers of two in [8, 8192] (the grid is 2nx x 2ny).
+ *  - Visibilities are ordered [chan][row] in the caller's row order; complex values are
+ *    interleaved FP32 (re, im).  Images for several channels are [nchan][ny][nx].
+ *  - Apply calls are asynchronous on the HIP stream passed in (NULL = default stream);
+ *    all their pointer arguments are DEVICE memory owned by the caller.  The operator
+ *    owns its sparse matrices and work grids; a handle belongs to the device that was
+ *    current at build time.  Calls on one handle must not overlap (they share the work
+ *    grids); distinct handles are independent.
+ */
+#ifndef WF_H
+#define WF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wf_op wf_op;
+
+typedef enum {
+  WF_OK = 0,
+  WF_EINVAL = 1,   /* bad argument: shape, non-finite uvw, field too wide (2L^2 >= 1) */
+  WF_ENOMEM = 2,   /* device or host allocation failed                               */
+  WF_EBUDGET = 3,  /* no strategy of the decision tree fits the memory budget        */
+  WF_EHIP = 4,     /* a HIP runtime call failed                                      */
+  WF_ENOTSUP = 5   /* valid request the library does not implement                  */
+} wf_status;
+
+typedef enum { WF_STORE_F32 = 0, WF_STORE_F16 = 1, WF_STORE_BF16 = 2 } wf_store;
+
+/* Strategy of Sect. 3.4 / Fig. 2: (a) precomputed G, (b) precomputed holographic H,
+ * (c) G computed on the fly.  WF_AUTO runs the decision tree. */
+typedef enum { WF_AUTO = 0, WF_PRECOMP_G = 1, WF_PRECOMP_H = 2, WF_ONTHEFLY = 3 } wf_strategy;
+
+typedef struct {
+  int32_t nx, ny;   /* image side in pixels                                    */
+  double cell_rad;  /* pixel size as a direction-cosine step; field L = n cell */
+} wf_image_shape;
+
+typedef struct {
+  int32_t J;               /* Kaiser-Bessel support (odd), default 7                  */
+  double beta;             /* Kaiser-Bessel shape, default 2.34 J                     */
+  int32_t oversample;      /* grid oversampling o (Sect. 3.2), must be 2              */
+  double alpha;            /* w-kernel sampling margin over the chirp band, default 2 */
+  int32_t smax;            /* largest residual-kernel side (odd, <= 15), default 15   */
+  double eps_w;            /* kernel energy dropped by the hard threshold, 1e-6       */
+  int32_t nbins;           /* 0: planner chooses P (eq. 10); > 0 forces P (<= 255)    */
+  wf_strategy strategy;    /* WF_AUTO: decision tree                                  */
+  wf_store store;          /* value precision of the stored G                         */
+  double plan_fraction;    /* planning / clustering subset fraction, default 0.01     */
+  double budget_fraction;  /* share of memory_budget for the sparse matrix, 0.65      */
+  uint64_t seed;           /* SplitMix64 state for the subset draw                    */
+  int32_t tile;            /* grid tile side of the fused G^dag G kernel (0 = auto)   */
+  int32_t max_rows_per_item; /* work-item split for load balance (0 = auto)           */
+} wf_options;
+
+/* Fill *opt with the defaults listed above. */
+void wf_default_options(wf_options* opt);
+
+/* Build the operator (workflow stages 1-3 of Sect. 3.5 / Fig. 3: plan, partition,
+ * precompute).
+ *  uvw_m      host [nrows][3] FP64 baseline coordinates in metres (copied).
+ *  chan_rows  NULL: every channel uses all nrows rows of uvw_m.  Otherwise host
+ *             [nchan] row counts; channel c uses its own consecutive block of
+ *             chan_rows[c] rows of uvw_m (sum must equal nrows).  Each channel is an
+ *             independent operator with its own w-bins (wideband model, Sect. 2).
+ *  freqs_hz   host [nchan] channel frequencies; uvw in wavelengths = uvw_m f / c.
+ *  shape      image geometry, shared by all channels.
+ *  memory_budget_bytes  device memory the planner may assume (e.g. 288e9).
+ *  opt        NULL for defaults.
+ *  hip_stream stream for the build's device work (NULL = default stream); the call
+ *             returns after the build has completed.
+ *  out        receives the handle.
+ * Errors: WF_EINVAL (shapes, non-finite uvw, 2L^2 >= 1), WF_EBUDGET (nothing fits),
+ * WF_ENOTSUP (holographic or on-the-fly strategy requested/required), WF_ENOMEM, WF_EHIP. */
+wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* chan_rows,
+                            const double* freqs_hz, int32_t nchan, wf_image_shape shape,
+                            uint64_t memory_budget_bytes, const wf_options* opt,
+                            void* hip_stream, wf_op** out);
+
+/* y = Phi x (eq. 3, eq. 6).  d_img: real FP32 [nchan][ny][nx];
+ * d_vis: complex FP32 [total rows] in [chan][row] caller order. */
+wf_status wf_forward(wf_op* op, const float* d_img, float* d_vis, void* hip_stream);
+
+/* x = Phi^dag y.  d_vis: complex FP32 [total rows]; d_img: complex FP32 [nchan][ny][nx]. */
+wf_status wf_adjoint(wf_op* op, const float* d_vis, float* d_img, void* hip_stream);
+
+/* Phi^dag Phi x (eq. 7-8): d_img real FP32 [nchan][ny][nx] -> d_out complex FP32
+ * [nchan][ny][nx].  The sum over w-layers is accumulated in place on the device. */
+wf_status wf_psf_apply(wf_op* op, const float* d_img, float* d_out, void* hip_stream);
+
+/* Re{Phi^dag Phi x}, the quantity the forward-backward update uses (Sect. 2, eq. 4):
+ * d_out real FP32 [nchan][ny][nx]. */
+wf_status wf_psf_apply_re(wf_op* op, const float* d_img, float* d_out, void* hip_stream);
+
+typedef struct {
+  int32_t nchan;
+  int32_t nbins;            /* P of this channel                                       */
+  wf_strategy strategy;     /* strategy chosen by the decision tree                    */
+  wf_store store;
+  int32_t Kx, Ky;           /* grid sides (o nx, o ny)                                 */
+  int32_t tile;             /* fused-kernel tile side                                  */
+  int32_t p_wsclean;        /* ceil of eq. 5 over the field (search upper end)         */
+  int32_t p_star;           /* minimiser of eq. 10                                      */
+  int64_t nrows;            /* rows of this channel                                    */
+  int64_t ntaps;            /* stored values of G (K of eq. 9)                          */
+  int64_t nwork;            /* work items of the fused kernel                           */
+  double k_estimate;        /* planner's K(P) estimate at the chosen P                  */
+  double mem_g_bytes;       /* device bytes of G (values + row metadata)                */
+  double mem_model_bytes;   /* eq. 9 (GPU form) at the chosen P                         */
+  double cost_model;        /* eq. 10 at the chosen P                                   */
+  double capped_fraction;   /* rows whose kernel side was capped at smax               */
+  double max_dropped_energy;/* largest per-row dropped kernel energy fraction           */
+  double build_seconds;     /* wall time of the build of this channel                  */
+} wf_plan_info;
+
+/* Plan and matrix statistics of channel chan (Sect. 3.4 quantities). */
+wf_status wf_get_plan(const wf_op* op, int32_t chan, wf_plan_info* out);
+
+/* Ascending w-bin centroids (w_p^stack, wavelengths) of channel chan; cap >= nbins. */
+wf_status wf_get_centroids(const wf_op* op, int32_t chan, double* out, int32_t cap);
+
+/* Per-bin row counts M_p of channel chan; cap >= nbins. */
+wf_status wf_get_bin_rows(const wf_op* op, int32_t chan, int64_t* out, int32_t cap);
+
+/* Diagnostic: one stored row of G for caller-order row `row` of channel chan, converted
+ * to FP32.  Writes the patch side T, the patch origin (q_u0, q_v0) on the periodic grid
+ * (in [0, Kx) x [0, Ky)), the bin, and T*T complex values (row-major [a_v][a_u]) into
+ * host buffer vals (capacity cap complex values).  Synchronous. */
+wf_status wf_get_row(const wf_op* op, int32_t chan, int64_t row, int32_t* T, int32_t* qu0,
+                     int32_t* qv0, int32_t* bin, float* vals, int32_t cap);
+
+/* Diagnostic: X_p = F Z_p x for channel chan and bin p, written as a complex FP32 grid
+ * [Ky][Kx] (row-major, rows = v) into device buffer d_grid.  Asynchronous. */
+wf_status wf_layer_grid(wf_op* op, int32_t chan, int32_t bin, const float* d_img,
+                        float* d_grid, void* hip_stream);
+
+/* Diagnostic timing: when enabled, every launch of kernel `kernel_id` (0 = the fused
+ * G^dag G kernel, 1 = forward row FFT, 2 = forward column FFT, 3 = inverse column FFT,
+ * 4 = inverse row FFT) is bracketed by HIP events on its stream; wf_profile_read
+ * returns the number of launches and their summed duration in ms (synchronising). */
+wf_status wf_profile_enable(wf_op* op, int32_t kernel_id, int32_t enable);
+wf_status wf_profile_read(wf_op* op, int32_t kernel_id, int64_t* launches, double* total_ms);
+
+/* Release all device and host memory of the handle (synchronises its device). */
+wf_status wf_destroy(wf_op* op);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* wf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WF_H */

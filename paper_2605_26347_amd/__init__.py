@@ -1,0 +1,177 @@
+"""MI355X widefield measurement operator: Phi, Phi^dag and Phi^dag Phi under hybrid
+w-stacking / w-projection (Dabbech & Wiaux), behind the C ABI of include/wf.h.
+
+This module only marshals arguments: every step of the operator runs in the HIP
+library libwf.so.  Importing it fails loudly when the library has not been built.
+Device buffers are torch tensors on the current HIP device; calls are asynchronous
+on torch's current stream unless another stream is given.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import WfImageShape, WfOptions, WfPlanInfo, check, STORE, STRATEGY
+
+_lib.load()
+
+__all__ = ["Operator", "default_options"]
+
+
+def default_options(**kw) -> WfOptions:
+    o = WfOptions()
+    _lib.load().wf_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "store":
+            v = STORE[v] if isinstance(v, str) else int(v)
+        elif k == "strategy":
+            v = STRATEGY[v] if isinstance(v, str) else int(v)
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Operator:
+    """Widefield operator for nchan channels sharing one image geometry.
+
+    uvw_m      (nrows, 3) float64 metres (host array).
+    freqs_hz   channel frequencies.
+    chan_rows  optional per-channel row counts (channel c uses its own block of rows).
+    Options: see include/wf.h (J, beta, alpha, smax, eps_w, nbins, strategy, store, ...).
+    """
+
+    def __init__(self, uvw_m, freqs_hz, nx, ny, cell_rad, memory_budget=288e9,
+                 chan_rows=None, stream=None, **opts):
+        self._lib = _lib.load()
+        self._h = ctypes.c_void_p()
+        uvw = np.ascontiguousarray(uvw_m, dtype=np.float64)
+        fr = np.ascontiguousarray(np.atleast_1d(freqs_hz), dtype=np.float64)
+        cr = None
+        if chan_rows is not None:
+            cr = np.ascontiguousarray(chan_rows, dtype=np.int64)
+        self.nchan = int(fr.size)
+        self.nx, self.ny = int(nx), int(ny)
+        self.nrows_total = int(cr.sum()) if cr is not None else int(uvw.shape[0]) * self.nchan
+        self.opts = default_options(**opts)
+        shape = WfImageShape(self.nx, self.ny, float(cell_rad))
+        st = self._lib.wf_build_operator(
+            uvw.ctypes.data_as(ctypes.c_void_p), ctypes.c_int64(uvw.shape[0]),
+            cr.ctypes.data_as(ctypes.c_void_p) if cr is not None else None,
+            fr.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(self.nchan), shape,
+            ctypes.c_uint64(int(memory_budget)), ctypes.byref(self.opts),
+            _stream_handle(stream), ctypes.byref(self._h))
+        check(st, "wf_build_operator")
+
+    # ------------------------------------------------------------------ applies
+    def _call(self, name, a, b, stream):
+        check(getattr(self._lib, name)(self._h, ctypes.c_void_p(a.data_ptr()),
+                                       ctypes.c_void_p(b.data_ptr()), _stream_handle(stream)),
+              name)
+
+    def forward(self, img, out=None, stream=None):
+        """y = Phi x; img float32 [nchan, ny, nx] -> complex64 [total rows]."""
+        import torch
+        if out is None:
+            out = torch.empty(self.nrows_total, dtype=torch.complex64, device=img.device)
+        self._call("wf_forward", img, out, stream)
+        return out
+
+    def adjoint(self, vis, out=None, stream=None):
+        """Phi^dag y; vis complex64 [total rows] -> complex64 [nchan, ny, nx]."""
+        import torch
+        if out is None:
+            out = torch.empty((self.nchan, self.ny, self.nx), dtype=torch.complex64,
+                              device=vis.device)
+        self._call("wf_adjoint", vis, out, stream)
+        return out
+
+    def psf_apply(self, img, out=None, stream=None):
+        """Phi^dag Phi x; img float32 [nchan, ny, nx] -> complex64 [nchan, ny, nx]."""
+        import torch
+        if out is None:
+            out = torch.empty((self.nchan, self.ny, self.nx), dtype=torch.complex64,
+                              device=img.device)
+        self._call("wf_psf_apply", img, out, stream)
+        return out
+
+    def psf_apply_re(self, img, out=None, stream=None):
+        """Re{Phi^dag Phi x}; img float32 -> float32 [nchan, ny, nx]."""
+        import torch
+        if out is None:
+            out = torch.empty((self.nchan, self.ny, self.nx), dtype=torch.float32,
+                              device=img.device)
+        self._call("wf_psf_apply_re", img, out, stream)
+        return out
+
+    # ------------------------------------------------------------------ introspection
+    def plan(self, chan=0) -> dict:
+        info = WfPlanInfo()
+        check(self._lib.wf_get_plan(self._h, chan, ctypes.byref(info)), "wf_get_plan")
+        return {k: getattr(info, k) for k, _ in WfPlanInfo._fields_}
+
+    def centroids(self, chan=0):
+        P = self.plan(chan)["nbins"]
+        out = np.zeros(P, dtype=np.float64)
+        check(self._lib.wf_get_centroids(self._h, chan, out.ctypes.data_as(ctypes.c_void_p), P),
+              "wf_get_centroids")
+        return out
+
+    def bin_rows(self, chan=0):
+        P = self.plan(chan)["nbins"]
+        out = np.zeros(P, dtype=np.int64)
+        check(self._lib.wf_get_bin_rows(self._h, chan, out.ctypes.data_as(ctypes.c_void_p), P),
+              "wf_get_bin_rows")
+        return out
+
+    def get_row(self, row, chan=0):
+        """(T, qu0, qv0, bin, values complex64 [T, T]) of one stored row of G."""
+        T, qu, qv, b = (ctypes.c_int32() for _ in range(4))
+        buf = np.zeros(2 * 32 * 32, dtype=np.float32)
+        check(self._lib.wf_get_row(self._h, chan, ctypes.c_int64(row), ctypes.byref(T),
+                                   ctypes.byref(qu), ctypes.byref(qv), ctypes.byref(b),
+                                   buf.ctypes.data_as(ctypes.c_void_p), 32 * 32), "wf_get_row")
+        t = T.value
+        vals = buf[:2 * t * t].view(np.complex64).reshape(t, t).copy()
+        return t, qu.value, qv.value, b.value, vals
+
+    def layer_grid(self, chan, bin_, img, out=None, stream=None):
+        """X_p = F Z_p x as complex64 [Ky, Kx] (rows = v)."""
+        import torch
+        if out is None:
+            out = torch.empty((2 * self.ny, 2 * self.nx), dtype=torch.complex64,
+                              device=img.device)
+        check(self._lib.wf_layer_grid(self._h, chan, bin_, ctypes.c_void_p(img.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+              "wf_layer_grid")
+        return out
+
+    def profile_enable(self, kernel_id, enable=True):
+        check(self._lib.wf_profile_enable(self._h, kernel_id, int(enable)), "wf_profile_enable")
+
+    def profile_read(self, kernel_id):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        check(self._lib.wf_profile_read(self._h, kernel_id, ctypes.byref(n), ctypes.byref(ms)),
+              "wf_profile_read")
+        return n.value, ms.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.wf_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

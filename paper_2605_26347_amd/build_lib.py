@@ -1,0 +1,73 @@
+"""Compile the HIP/C++ sources of the operator library into libwf.so (gfx950).
+
+Usage: python -m paper_2605_26347_amd.build_lib   (or call build()).
+Each translation unit is compiled by hipcc in parallel, then linked as one shared
+library next to this file.  FP32 packed-math instructions are disabled for all device
+code; the FP64 build kernels are compiled without floating-point contraction so that
+their integer decisions (bins, cells, kernel sides, thresholds) are reproducible.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+OUT = os.path.join(HERE, "libwf.so")
+BUILD = os.path.join(HERE, "_build")
+ARCH = os.environ.get("WF_OFFLOAD_ARCH", "gfx950")
+
+SOURCES = {
+    "k_fft.hip": [],
+    "k_grid.hip": [],
+    "k_build.hip": ["-ffp-contract=off"],
+    "host_plan.cpp": ["-ffp-contract=off"],
+    "wf_abi.cpp": [],
+}
+
+
+def _hipcc():
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def _common():
+    return [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}"]
+
+
+def _compile(src: str, extra: list[str]) -> str:
+    obj = os.path.join(BUILD, src + ".o")
+    cmd = [_hipcc()] + _common() + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build(verbose: bool = True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        futs = {ex.submit(_compile, s, e): s for s, e in SOURCES.items()}
+        objs = [f.result() for f in futs]
+    tmp = OUT + ".tmp"
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, OUT)
+    if verbose:
+        print(f"built {OUT}", file=sys.stderr)
+    return OUT
+
+
+if __name__ == "__main__":
+    build()

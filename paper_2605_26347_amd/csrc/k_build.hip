@@ -1,0 +1,414 @@
+// Build of the de-gridding matrix G (workflow stages 2-3 of Sect. 3.5), FP64.
+//
+// Per visibility row k (one wavefront per row, one row at a time):
+//   * u, v, w in wavelengths = uvw_m * f / c; bin p = nearest w-bin centroid with ties to
+//     the lower bin, i.e. the number of bin midpoints below w (Sect. 3.1 w-stacking);
+//     residual w_proj = w - w_p;
+//   * grid coordinates u_bar = u Kx cell, nearest cell r = floor(u_bar + 1/2);
+//   * residual-w kernel (Sect. 3.1 w-projection, Fig. 1): side n_k from the chirp's
+//     bandwidth over the padded field; the phase-tapered chirp is sampled on n_k x n_k
+//     points over o times the field; a small DFT gives the kernel; the smallest entries
+//     holding at most eps of the energy are dropped (a wave-wide bitonic sort and
+//     prefix sum find the cut; entries within 1e-9 relative of the smallest kept energy
+//     are kept with it) and the kernel is cut to the smallest centred square;
+//   * G row (Sect. 3.2): the kernel convolved with the 7 x 7 Kaiser-Bessel taps at the
+//     row's fractional grid offset, a dense T x T patch, T = n' + J - 1.
+// Decisions that turn floating point into integers (bin, nearest cell, n_k, threshold)
+// use only correctly rounded FP64 operations, without contraction, so that they are
+// reproducible by any IEEE implementation that performs the same operations.
+#include <hip/hip_fp16.h>
+
+#include <float.h>
+
+#include "wf_internal.h"
+
+namespace wf {
+
+constexpr int MAXNK = 15;
+constexpr int MAXT = 21 + 8;  // room for J up to 15 with smax 15
+
+struct KScratch {
+  double2 c[MAXNK * MAXNK];        // samples, then kernel
+  double2 t[MAXNK * MAXNK];        // DFT intermediate
+  double e[256];                   // energies (sorted)
+  double2 roots[MAXNK];            // exp(-2 pi i m / nk)
+  double2 t2[MAXNK * MAXT];        // convolution intermediate
+  double ku[16], kv[16];           // Kaiser-Bessel taps
+};
+
+__device__ __forceinline__ double dev_i0(double x) {
+#pragma clang fp contract(off)
+  const double q = 0.25 * x * x;
+  double term = 1.0, s = 1.0;
+  for (int k = 1; k < 200; ++k) {
+    term = term * q / ((double)k * (double)k);
+    s += term;
+    if (term < 1e-18 * s) break;
+  }
+  return s;
+}
+
+__device__ __forceinline__ double dev_taper(double a_signed, double L) {
+#pragma clang fp contract(off)
+  const double a = fabs(a_signed);
+  const double half = L / 2.0;
+  if (a <= half) return 1.0;
+  return 0.54 + 0.46 * cos(M_PI * (a - half) / half);
+}
+
+__device__ __forceinline__ int dev_nk(double wproj, const KernelParams& kp, bool capped) {
+#pragma clang fp contract(off)
+  if (wproj == 0.0) return 1;
+  const double lp = ((double)kp.o * kp.Lx) / 2.0;
+  const double mp = ((double)kp.o * kp.Ly) / 2.0;
+  const double nn = sqrt(1.0 - lp * lp - mp * mp);
+  const double aw = fabs(wproj);
+  const double bx = 2.0 * ((aw * lp) / nn) * ((double)kp.o * kp.Lx);
+  const double by = 2.0 * ((aw * mp) / nn) * ((double)kp.o * kp.Ly);
+  const double B = bx > by ? bx : by;
+  double nkd = 2.0 * ceil((kp.alpha * B) / 2.0) + 1.0;
+  if (nkd > 1e6) nkd = 1e6;
+  int nk = (int)nkd;
+  if (capped && nk > kp.smax) nk = kp.smax;
+  return nk;
+}
+
+struct RowGeom {
+  double wproj, ub, vb;
+  int p;
+};
+
+__device__ __forceinline__ RowGeom dev_geom(const double* __restrict__ uvw, int64_t k,
+                                            double scale, double gsx, double gsy,
+                                            const double* __restrict__ mids, int P,
+                                            const double* __restrict__ cents) {
+#pragma clang fp contract(off)
+  RowGeom g;
+  const double u = uvw[3 * k] * scale;
+  const double v = uvw[3 * k + 1] * scale;
+  const double w = uvw[3 * k + 2] * scale;
+  int lo = 0, hi = P - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (mids[mid] < w) lo = mid + 1;
+    else hi = mid;
+  }
+  g.p = lo;
+  g.wproj = w - cents[lo];
+  g.ub = u * gsx;
+  g.vb = v * gsy;
+  return g;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// Exact residual kernel of side nk with threshold; workgroup = one wavefront.
+// Leaves the masked kernel in S.c (nk x nk, [s_v][s_u]); returns h' (kept half-side).
+__device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratch& S,
+                           double* dropped) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x;
+  const int nn2 = nk * nk;
+  if (nk == 1) {
+    if (lane == 0) S.c[0] = make_double2(1.0, 0.0);
+    __syncthreads();
+    *dropped = 0.0;
+    return 0;
+  }
+  const int h = (nk - 1) / 2;
+  for (int m = lane; m < nk; m += 64) {
+    double s, c;
+    sincospi((double)(-2 * m) / (double)nk, &s, &c);
+    S.roots[m] = make_double2(c, s);
+  }
+  for (int idx = lane; idx < nn2; idx += 64) {
+    const int b = idx / nk, a = idx - b * nk;
+    const double lpa = ((double)(a - h) * kp.oLx) / (double)nk;
+    const double mpb = ((double)(b - h) * kp.oLy) / (double)nk;
+    const double L2 = lpa * lpa + mpb * mpb;
+    const double n = sqrt(1.0 - L2);
+    const double d = -L2 / (1.0 + n);
+    const double tap = dev_taper(mpb, kp.Ly) * dev_taper(lpa, kp.Lx);
+    const double ph = wproj * (d * tap);
+    double s, c;
+    sincospi(2.0 * ph, &s, &c);
+    S.c[idx] = make_double2(c, -s);   // exp(-2 pi i ph)
+  }
+  __syncthreads();
+  // t[b][su] = sum_a c[b][a] exp(-2 pi i (su-h)(a-h)/nk)
+  for (int idx = lane; idx < nn2; idx += 64) {
+    const int b = idx / nk, su = idx - b * nk;
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < nk; ++a) {
+      int m = ((su - h) * (a - h)) % nk;
+      if (m < 0) m += nk;
+      const double2 r = S.roots[m], x = S.c[b * nk + a];
+      re += x.x * r.x - x.y * r.y;
+      im += x.x * r.y + x.y * r.x;
+    }
+    S.t[idx] = make_double2(re, im);
+  }
+  __syncthreads();
+  const double inv = 1.0 / ((double)nk * (double)nk);
+  for (int idx = lane; idx < nn2; idx += 64) {
+    const int sv = idx / nk, su = idx - sv * nk;
+    double re = 0.0, im = 0.0;
+    for (int b = 0; b < nk; ++b) {
+      int m = ((sv - h) * (b - h)) % nk;
+      if (m < 0) m += nk;
+      const double2 r = S.roots[m], x = S.t[b * nk + su];
+      re += r.x * x.x - r.y * x.y;
+      im += r.x * x.y + r.y * x.x;
+    }
+    S.c[idx] = make_double2(re * inv, im * inv);
+  }
+  __syncthreads();
+  // energies, ascending bitonic sort over 256 slots (+inf padding)
+  for (int i = lane; i < 256; i += 64) {
+    if (i < nn2) {
+      const double2 v = S.c[i];
+      S.e[i] = v.x * v.x + v.y * v.y;
+    } else {
+      S.e[i] = DBL_MAX;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= 256; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < 256; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const bool up = (i & k) == 0;
+          const double a = S.e[i], b = S.e[ixj];
+          if ((a > b) == up) {
+            S.e[i] = b;
+            S.e[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // inclusive prefix sums: lane holds slots 4 lane .. 4 lane + 3
+  double loc[4];
+  double run = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const int i = 4 * lane + q;
+    const double v = (i < nn2) ? S.e[i] : 0.0;
+    run += v;
+    loc[q] = run;
+  }
+  double scan = run;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(scan, o, 64);
+    if (lane >= o) scan += y;
+  }
+  const double offs = scan - run;
+  const double tot = __shfl(scan, 63, 64);
+  const double thr = kp.eps * tot;
+  int cnt = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int i = 4 * lane + q;
+    if (i < nn2 && offs + loc[q] <= thr) ++cnt;
+  }
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  int jdrop = cnt < nn2 - 1 ? cnt : nn2 - 1;
+  const double tau = S.e[jdrop];
+  const double cut = tau * (1.0 - 1e-9);
+  int hp = 0;
+  double dsum = 0.0;
+  for (int idx = lane; idx < nn2; idx += 64) {
+    const double2 v = S.c[idx];
+    const double E = v.x * v.x + v.y * v.y;
+    if (E >= cut) {
+      const int sv = idx / nk, su = idx - sv * nk;
+      const int rv = sv > h ? sv - h : h - sv;
+      const int ru = su > h ? su - h : h - su;
+      const int r = rv > ru ? rv : ru;
+      hp = r > hp ? r : hp;
+    } else {
+      dsum += E;
+      S.c[idx] = make_double2(0.0, 0.0);
+    }
+  }
+  hp = wave_max_i(hp);
+  dsum = wave_sum_d(dsum);
+  *dropped = tot > 0.0 ? dsum / tot : 0.0;
+  __syncthreads();
+  return hp;
+}
+
+__global__ __launch_bounds__(64) void k_rowsym(const double* __restrict__ uvw, int64_t n,
+                                               double scale, double gsx, double gsy,
+                                               const double* __restrict__ mids, int P,
+                                               const double* __restrict__ cents, int Kx,
+                                               int Ky, int tile, KernelParams kp,
+                                               uint64_t* __restrict__ keys,
+                                               float* __restrict__ dropped_out) {
+#pragma clang fp contract(off)
+  __shared__ KScratch S;
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
+    const int nk_full = dev_nk(g.wproj, kp, false);
+    const int nk = nk_full > kp.smax ? kp.smax : nk_full;
+    double dropped;
+    const int hp = wkernel_row(g.wproj, nk, kp, S, &dropped);
+    if (threadIdx.x == 0) {
+      const int T = 2 * hp + 1 + kp.J - 1;
+      const int64_t ru = (int64_t)floor(g.ub + 0.5);
+      const int64_t rv = (int64_t)floor(g.vb + 0.5);
+      const int64_t rum = ((ru % Kx) + Kx) % Kx;
+      const int64_t rvm = ((rv % Ky) + Ky) % Ky;
+      const uint64_t tu = (uint64_t)(rum / tile), lu = (uint64_t)(rum % tile);
+      const uint64_t tv = (uint64_t)(rvm / tile), lv = (uint64_t)(rvm % tile);
+      keys[k] = ((uint64_t)g.p << 56) | (tv << 46) | (tu << 36) | ((uint64_t)T << 31) |
+                (lv << 24) | (lu << 17);
+      const float df = (float)dropped;
+      dropped_out[k] = (nk_full > kp.smax) ? -df - 1e-30f : df;
+    }
+    __syncthreads();
+  }
+}
+
+template <int STORE>
+__device__ __forceinline__ void store_val(void* vals, int64_t i, double re, double im) {
+  if constexpr (STORE == WF_STORE_F32) {
+    reinterpret_cast<float2*>(vals)[i] = make_float2((float)re, (float)im);
+  } else if constexpr (STORE == WF_STORE_F16) {
+    reinterpret_cast<__half2*>(vals)[i] = __floats2half2_rn((float)re, (float)im);
+  } else {
+    // round-to-nearest-even FP32 -> BF16 (finite inputs)
+    auto bf = [](float f) -> uint32_t {
+      const uint32_t b = __float_as_uint(f);
+      return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+    };
+    reinterpret_cast<uint32_t*>(vals)[i] = bf((float)re) | (bf((float)im) << 16);
+  }
+}
+
+template <int STORE>
+__global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, int64_t nsorted,
+                                               const int32_t* __restrict__ perm,
+                                               const uint32_t* __restrict__ meta,
+                                               const uint32_t* __restrict__ voff,
+                                               const int32_t* __restrict__ row_wi,
+                                               const WorkItem* __restrict__ wis, double scale,
+                                               double gsx, double gsy,
+                                               const double* __restrict__ mids, int P,
+                                               const double* __restrict__ cents,
+                                               KernelParams kp, void* __restrict__ vals) {
+#pragma clang fp contract(off)
+  __shared__ KScratch S;
+  const int lane = threadIdx.x;
+  const int half = (kp.J - 1) / 2;
+  for (int64_t s = blockIdx.x; s < nsorted; s += gridDim.x) {
+    const int64_t k = perm[s];
+    const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
+    const int nk_full = dev_nk(g.wproj, kp, false);
+    const int nk = nk_full > kp.smax ? kp.smax : nk_full;
+    double dropped;
+    const int hp = wkernel_row(g.wproj, nk, kp, S, &dropped);
+    const int h = (nk - 1) / 2;
+    const int np = 2 * hp + 1;
+    const int T = np + kp.J - 1;
+    const int Tm = (int)((meta[s] >> 16) & 0xff);
+    // Kaiser-Bessel taps phi(f - d), d = -half..half
+    const double fu = g.ub - floor(g.ub + 0.5);
+    const double fv = g.vb - floor(g.vb + 0.5);
+    if (lane < 2 * kp.J) {
+      const int d = (lane % kp.J) - half;
+      const double f = lane < kp.J ? fu : fv;
+      const double t = f - (double)d;
+      const double z = 1.0 - ((2.0 * t) / (double)kp.J) * ((2.0 * t) / (double)kp.J);
+      const double val = z >= 0.0 ? dev_i0(kp.beta * sqrt(z)) / kp.i0beta : 0.0;
+      if (lane < kp.J) S.ku[lane % kp.J] = val;
+      else S.kv[lane % kp.J] = val;
+    }
+    __syncthreads();
+    // t2[m][au] = sum_n kern[m][n] ku[au - n], kern = kept centre square of S.c
+    for (int idx = lane; idx < np * T; idx += 64) {
+      const int m = idx / T, au = idx - m * T;
+      double re = 0.0, im = 0.0;
+      for (int nn = 0; nn < np; ++nn) {
+        const int dd = au - nn;
+        if (dd >= 0 && dd < kp.J) {
+          const double2 c = S.c[(m + h - hp) * nk + (nn + h - hp)];
+          re += c.x * S.ku[dd];
+          im += c.y * S.ku[dd];
+        }
+      }
+      S.t2[idx] = make_double2(re, im);
+    }
+    __syncthreads();
+    const int64_t vb = wis[row_wi[s]].voff + voff[s];
+    if (T == Tm) {
+      for (int idx = lane; idx < T * T; idx += 64) {
+        const int av = idx / T, au = idx - av * T;
+        double re = 0.0, im = 0.0;
+        for (int m = 0; m < np; ++m) {
+          const int dd = av - m;
+          if (dd >= 0 && dd < kp.J) {
+            const double2 x = S.t2[m * T + au];
+            re += S.kv[dd] * x.x;
+            im += S.kv[dd] * x.y;
+          }
+        }
+        store_val<STORE>(vals, vb + idx, re, im);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_rowsym(const double* uvw, int64_t n, double scale, double gsx, double gsy,
+                         const double* mids, int P, const double* cents, int Kx, int Ky,
+                         int tile, const KernelParams& kp, uint64_t* keys, float* dropped,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)(n < 262144 ? n : 262144);
+  hipLaunchKernelGGL(k_rowsym, dim3(blocks), dim3(64), 0, s, uvw, n, scale, gsx, gsy, mids, P,
+                     cents, Kx, Ky, tile, kp, keys, dropped);
+  return hipGetLastError();
+}
+
+hipError_t launch_gbuild(const double* uvw, int64_t nsorted, const int32_t* perm,
+                         const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
+                         const WorkItem* wi, double scale, double gsx, double gsy,
+                         const double* mids, int P, const double* cents,
+                         const KernelParams& kp, void* vals, wf_store store, hipStream_t s) {
+  if (nsorted <= 0) return hipSuccess;
+  const int blocks = (int)(nsorted < 262144 ? nsorted : 262144);
+  switch (store) {
+    case WF_STORE_F32:
+      hipLaunchKernelGGL(k_gbuild<WF_STORE_F32>, dim3(blocks), dim3(64), 0, s, uvw, nsorted,
+                         perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
+                         vals);
+      break;
+    case WF_STORE_F16:
+      hipLaunchKernelGGL(k_gbuild<WF_STORE_F16>, dim3(blocks), dim3(64), 0, s, uvw, nsorted,
+                         perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
+                         vals);
+      break;
+    default:
+      hipLaunchKernelGGL(k_gbuild<WF_STORE_BF16>, dim3(blocks), dim3(64), 0, s, uvw, nsorted,
+                         perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
+                         vals);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace wf

@@ -1,0 +1,272 @@
+// Row and column passes of F and F^dag with the image-domain work fused in
+// (Sect. 3.2, eq. 6; Sect. 3.3, eq. 8):
+//   forward rows : x (.) Z_p, zero-pad to Kx, FFT of the ny image rows      -> A
+//   forward cols : zero-pad to Ky, FFT of every column                     -> X
+//   inverse cols : inverse FFT of every column, keep the ny image rows     -> A
+//                  (and clear Y behind the read, ready for the next gridding)
+//   inverse rows : inverse FFT of the ny rows, crop to nx, (.) conj(Z_p),
+//                  store or accumulate the sum over w-layers (eq. 7)
+// Z_p = grid correction x w-layer: s_i s_j exp(-2 pi i w_p (n-1)) / n with the phase
+// computed in FP64 (n - 1 = -(l^2+m^2)/(1+n) avoids cancellation), reduced to
+// [-1/2, 1/2) cycles in FP64 and only then rounded to FP32 for sincospi.
+#include "fft_lds.h"
+#include "wf_internal.h"
+
+namespace wf {
+
+__device__ __forceinline__ float2 zvalue(int i, int j, int nx, int ny, double cell, double wp,
+                                         float sxi, float syj) {
+  const double l = (double)(i - nx / 2) * cell;
+  const double m = (double)(j - ny / 2) * cell;
+  const double r2 = l * l + m * m;
+  const double n = sqrt(1.0 - r2);
+  const double d = -r2 / (1.0 + n);
+  double cyc = -wp * d;
+  cyc -= rint(cyc);
+  float s, c;
+  sincospif((float)(2.0 * cyc), &s, &c);
+  const float a = sxi * syj / (float)n;
+  return make_float2(a * c, a * s);
+}
+
+template <int N>
+constexpr int row_threads() {
+  return N / 16 < 64 ? 64 : (N / 16 > 1024 ? 1024 : N / 16);
+}
+template <int N>
+constexpr int col_width() {
+  return (16384 / N) > 16 ? 16 : (16384 / N);
+}
+template <int N>
+constexpr int col_threads() {
+  return (col_width<N>() * N) / 16 < 64 ? 64
+         : ((col_width<N>() * N) / 16 > 1024 ? 1024 : (col_width<N>() * N) / 16);
+}
+
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_fwd_rows(const float* __restrict__ img,
+                                                 float2* __restrict__ A,
+                                                 const float2* __restrict__ tw,
+                                                 const float* __restrict__ sx,
+                                                 const float* __restrict__ sy, int nx, int ny,
+                                                 double cell, double wp) {
+  extern __shared__ float2 buf[];
+  const int j = blockIdx.x;
+  const float syj = sy[j];
+  for (int t = threadIdx.x; t < N - nx; t += NT) buf[nx / 2 + t] = make_float2(0.f, 0.f);
+  const float* row = img + (int64_t)j * nx;
+  for (int i = threadIdx.x; i < nx; i += NT) {
+    const float v = row[i];
+    const float2 z = zvalue(i, j, nx, ny, cell, wp, sx[i], syj);
+    buf[(i - nx / 2) & (N - 1)] = make_float2(v * z.x, v * z.y);
+  }
+  __syncthreads();
+  fft_lines<N, NT, 1, false>(buf, N, tw);
+  for (int q = threadIdx.x; q < N; q += NT) A[strip_index(j, q, ny)] = buf[q];
+}
+
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_inv_rows(const float2* __restrict__ A,
+                                                 void* __restrict__ out,
+                                                 const float2* __restrict__ tw,
+                                                 const float* __restrict__ sx,
+                                                 const float* __restrict__ sy, int nx, int ny,
+                                                 double cell, double wp, int mode) {
+  extern __shared__ float2 buf[];
+  const int j = blockIdx.x;
+  for (int q = threadIdx.x; q < N; q += NT) buf[q] = A[strip_index(j, q, ny)];
+  __syncthreads();
+  fft_lines<N, NT, 1, true>(buf, N, tw);
+  const float syj = sy[j];
+  for (int i = threadIdx.x; i < nx; i += NT) {
+    const float2 v = buf[(i - nx / 2) & (N - 1)];
+    const float2 z = zvalue(i, j, nx, ny, cell, wp, sx[i], syj);
+    const float2 r = cmulc(v, z);
+    const int64_t o = (int64_t)j * nx + i;
+    if (mode < 2) {
+      float2* po = reinterpret_cast<float2*>(out) + o;
+      if (mode == 1) {
+        const float2 p = *po;
+        *po = make_float2(p.x + r.x, p.y + r.y);
+      } else {
+        *po = r;
+      }
+    } else {
+      float* po = reinterpret_cast<float*>(out) + o;
+      *po = (mode == 3) ? (*po + r.x) : r.x;
+    }
+  }
+}
+
+// Column passes: CW adjacent columns of one strip per workgroup, lines padded by one
+// element in LDS so that the strip-order global accesses (column index fastest) hit
+// distinct banks.
+template <int N, int NT, int CW>
+__global__ __launch_bounds__(NT) void k_fwd_cols(const float2* __restrict__ A,
+                                                 float2* __restrict__ X,
+                                                 const float2* __restrict__ tw, int ny) {
+  extern __shared__ float2 buf[];
+  constexpr int S = N + 1;
+  const int g = xcd_remap(blockIdx.x, gridDim.x);
+  const int q0 = g * CW;
+  const int strip = q0 >> 4, c0 = q0 & (SW - 1);
+  const int nz = N - ny;
+  for (int t = threadIdx.x; t < CW * nz; t += NT) {
+    const int c = t / nz, r = t - c * nz;
+    buf[c * S + ny / 2 + r] = make_float2(0.f, 0.f);
+  }
+  const float2* src = A + ((int64_t)strip * ny) * SW + c0;
+  for (int t = threadIdx.x; t < CW * ny; t += NT) {
+    const int jr = t / CW, c = t - jr * CW;
+    buf[c * S + ((jr - ny / 2) & (N - 1))] = src[(int64_t)jr * SW + c];
+  }
+  __syncthreads();
+  fft_lines<N, NT, CW, false>(buf, S, tw);
+  float2* dst = X + ((int64_t)strip * N) * SW + c0;
+  for (int t = threadIdx.x; t < CW * N; t += NT) {
+    const int qv = t / CW, c = t - qv * CW;
+    dst[(int64_t)qv * SW + c] = buf[c * S + qv];
+  }
+}
+
+template <int N, int NT, int CW>
+__global__ __launch_bounds__(NT) void k_inv_cols(float2* __restrict__ Y, float2* __restrict__ A,
+                                                 const float2* __restrict__ tw, int ny) {
+  extern __shared__ float2 buf[];
+  constexpr int S = N + 1;
+  const int g = xcd_remap(blockIdx.x, gridDim.x);
+  const int q0 = g * CW;
+  const int strip = q0 >> 4, c0 = q0 & (SW - 1);
+  float2* src = Y + ((int64_t)strip * N) * SW + c0;
+  for (int t = threadIdx.x; t < CW * N; t += NT) {
+    const int qv = t / CW, c = t - qv * CW;
+    float2* p = src + (int64_t)qv * SW + c;
+    buf[c * S + qv] = *p;
+    *p = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_lines<N, NT, CW, true>(buf, S, tw);
+  float2* dst = A + ((int64_t)strip * ny) * SW + c0;
+  for (int t = threadIdx.x; t < CW * ny; t += NT) {
+    const int jr = t / CW, c = t - jr * CW;
+    dst[(int64_t)jr * SW + c] = buf[c * S + ((jr - ny / 2) & (N - 1))];
+  }
+}
+
+__global__ void k_strip_to_rowmajor(const float2* __restrict__ src, float2* __restrict__ dst,
+                                    int R, int Q) {
+  const int64_t n = (int64_t)R * Q;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(t / Q), q = (int)(t - (int64_t)r * Q);
+    dst[t] = src[strip_index(r, q, R)];
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename K>
+static hipError_t set_lds(K kern, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+#define WF_FOR_SIZES(X) \
+  X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
+
+hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const float* sx,
+                           const float* sy, int nx, int ny, int Kx, double cell, double wp,
+                           hipStream_t s) {
+  switch (Kx) {
+#define C(N)                                                                              \
+  case N: {                                                                               \
+    constexpr int NT = row_threads<N>();                                                  \
+    const size_t lds = (size_t)N * sizeof(float2);                                        \
+    hipError_t e = set_lds(k_fwd_rows<N, NT>, lds);                                       \
+    if (e != hipSuccess) return e;                                                        \
+    hipLaunchKernelGGL((k_fwd_rows<N, NT>), dim3(ny), dim3(NT), lds, s, img, A, tw, sx,  \
+                       sy, nx, ny, cell, wp);                                             \
+    return hipGetLastError();                                                             \
+  }
+    WF_FOR_SIZES(C)
+#undef C
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const float* sx,
+                           const float* sy, int nx, int ny, int Kx, double cell, double wp,
+                           int mode, hipStream_t s) {
+  switch (Kx) {
+#define C(N)                                                                              \
+  case N: {                                                                               \
+    constexpr int NT = row_threads<N>();                                                  \
+    const size_t lds = (size_t)N * sizeof(float2);                                        \
+    hipError_t e = set_lds(k_inv_rows<N, NT>, lds);                                       \
+    if (e != hipSuccess) return e;                                                        \
+    hipLaunchKernelGGL((k_inv_rows<N, NT>), dim3(ny), dim3(NT), lds, s, A, out, tw, sx,  \
+                       sy, nx, ny, cell, wp, mode);                                       \
+    return hipGetLastError();                                                             \
+  }
+    WF_FOR_SIZES(C)
+#undef C
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fwd_cols(const float2* A, float2* X, const float2* tw, int ny, int Kx,
+                           int Ky, hipStream_t s) {
+  switch (Ky) {
+#define C(N)                                                                              \
+  case N: {                                                                               \
+    constexpr int CW = col_width<N>();                                                    \
+    constexpr int NT = col_threads<N>();                                                  \
+    if (Kx % CW != 0) return hipErrorInvalidValue;                                        \
+    const size_t lds = (size_t)CW * (N + 1) * sizeof(float2);                             \
+    hipError_t e = set_lds(k_fwd_cols<N, NT, CW>, lds);                                   \
+    if (e != hipSuccess) return e;                                                        \
+    hipLaunchKernelGGL((k_fwd_cols<N, NT, CW>), dim3(Kx / CW), dim3(NT), lds, s, A, X,   \
+                       tw, ny);                                                           \
+    return hipGetLastError();                                                             \
+  }
+    WF_FOR_SIZES(C)
+#undef C
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_inv_cols(float2* Y, float2* A, const float2* tw, int ny, int Kx, int Ky,
+                           hipStream_t s) {
+  switch (Ky) {
+#define C(N)                                                                              \
+  case N: {                                                                               \
+    constexpr int CW = col_width<N>();                                                    \
+    constexpr int NT = col_threads<N>();                                                  \
+    if (Kx % CW != 0) return hipErrorInvalidValue;                                        \
+    const size_t lds = (size_t)CW * (N + 1) * sizeof(float2);                             \
+    hipError_t e = set_lds(k_inv_cols<N, NT, CW>, lds);                                   \
+    if (e != hipSuccess) return e;                                                        \
+    hipLaunchKernelGGL((k_inv_cols<N, NT, CW>), dim3(Kx / CW), dim3(NT), lds, s, Y, A,   \
+                       tw, ny);                                                           \
+    return hipGetLastError();                                                             \
+  }
+    WF_FOR_SIZES(C)
+#undef C
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_strip_to_rowmajor(const float2* src, float2* dst, int R, int Q,
+                                    hipStream_t s) {
+  const int64_t n = (int64_t)R * Q;
+  const int blocks = (int)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
+  hipLaunchKernelGGL(k_strip_to_rowmajor, dim3(blocks), dim3(256), 0, s, src, dst, R, Q);
+  return hipGetLastError();
+}
+
+}  // namespace wf

@@ -1,0 +1,167 @@
+// Internal declarations of the widefield operator library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "wf.h"
+
+namespace wf {
+
+// Complex grids are stored in strips of SW adjacent columns: element (row r, column q)
+// of an R x Q complex array lives at ((q / SW) * R + r) * SW + q % SW.  A 128-byte
+// line then holds one row of one strip, so row passes touch whole lines and column
+// passes read each strip as one contiguous block.
+constexpr int SW = 16;
+
+__host__ __device__ inline int64_t strip_index(int r, int q, int R) {
+  return ((int64_t)(q >> 4) * R + r) * SW + (q & (SW - 1));
+}
+
+// One unit of work of the fused G^dag G, de-gridding and gridding kernels: a run of
+// consecutive sorted rows of one bin whose patch centres fall in one grid tile.  The
+// kernel accumulates into an LDS window of side W = tile + 2 halo whose origin on the
+// periodic grid is (u0, v0) (possibly negative or past the edge; wrapped mod K).
+struct WorkItem {
+  int64_t voff;   // index (complex units) of the first value of the first row
+  int32_t row0;   // first sorted row
+  int32_t nrows;  // rows in this item
+  int32_t u0, v0; // window origin
+  int32_t bin;
+  int32_t pad;
+};
+static_assert(sizeof(WorkItem) == 32, "WorkItem layout");
+
+// Per-row metadata word: window-local patch origin and patch side.
+__host__ __device__ inline uint32_t pack_meta(int lu0, int lv0, int T) {
+  return (uint32_t)lu0 | ((uint32_t)lv0 << 8) | ((uint32_t)T << 16);
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Parameters of the residual-w kernel and interpolation kernel, shared by the build
+// kernels.
+struct KernelParams {
+  double Lx, Ly;      // field sides nx*cell, ny*cell
+  double oLx, oLy;    // padded field sides
+  double alpha;       // sampling margin
+  double eps;         // dropped energy
+  double beta;        // Kaiser-Bessel shape
+  double i0beta;      // I0(beta)
+  int J;              // Kaiser-Bessel support
+  int smax;           // kernel side cap
+  int o;              // oversampling
+};
+
+struct ChanOp {
+  double freq = 0, scale = 0;
+  int64_t vis_off = 0;   // offset of this channel's rows in the caller's vis vector
+  int64_t nrows = 0;
+  int P = 0;
+  std::vector<double> centroids;
+  std::vector<int64_t> bin_row0, bin_nrows;
+  std::vector<int32_t> bin_wi0, bin_nwi;
+  int64_t ntaps = 0;
+  int64_t nwork = 0;
+  DevBuf meta, voff, perm, vals, work;
+  wf_plan_info info{};
+};
+
+struct Profiler {
+  bool enabled = false;
+  std::vector<hipEvent_t> ev;   // pairs
+  size_t used = 0;
+  int64_t launches = 0;
+  double total_ms = 0;
+};
+
+constexpr int NPROF = 5;
+
+}  // namespace wf
+
+struct wf_op {
+  wf_options opt;
+  wf_image_shape shape;
+  int Kx = 0, Ky = 0;
+  int tile = 64, halo = 10, win = 84;
+  int device = 0;
+  wf::KernelParams kp;
+  std::vector<wf::ChanOp> chans;
+  int64_t total_rows = 0;
+  wf::DevBuf X, Y, A, twx, twy, sx, sy;
+  wf::Profiler prof[wf::NPROF];
+};
+
+namespace wf {
+
+// ------------------------------------------------------------------ kernel launchers
+// (defined in the .hip translation units; all asynchronous on `s`)
+
+hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const float* sx,
+                           const float* sy, int nx, int ny, int Kx, double cell, double wp,
+                           hipStream_t s);
+hipError_t launch_fwd_cols(const float2* A, float2* X, const float2* tw, int ny, int Kx,
+                           int Ky, hipStream_t s);
+hipError_t launch_inv_cols(float2* Y, float2* A, const float2* tw, int ny, int Kx, int Ky,
+                           hipStream_t s);
+// mode 0: out complex, overwrite; 1: complex, accumulate; 2: real part, overwrite;
+// 3: real part, accumulate
+hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const float* sx,
+                           const float* sy, int nx, int ny, int Kx, double cell, double wp,
+                           int mode, hipStream_t s);
+
+hipError_t launch_gtg(const WorkItem* wi, int nwi, const uint32_t* meta, const uint32_t* voff,
+                      const void* vals, wf_store store, const float2* X, float2* Y, int Kx,
+                      int Ky, int win, hipStream_t s);
+hipError_t launch_degrid(const WorkItem* wi, int nwi, const uint32_t* meta,
+                         const uint32_t* voff, const int32_t* perm, const void* vals,
+                         wf_store store, const float2* X, float2* vis, int Kx, int Ky,
+                         hipStream_t s);
+hipError_t launch_grid(const WorkItem* wi, int nwi, const uint32_t* meta, const uint32_t* voff,
+                       const int32_t* perm, const void* vals, wf_store store,
+                       const float2* vis, float2* Y, int Kx, int Ky, int win, hipStream_t s);
+hipError_t launch_strip_to_rowmajor(const float2* src, float2* dst, int R, int Q,
+                                    hipStream_t s);
+
+// Build kernels (FP64).  Symbolic pass over rows in caller order: bin, grid position,
+// residual kernel side after thresholding, sort key.
+hipError_t launch_rowsym(const double* uvw, int64_t n, double scale, double gsx, double gsy,
+                         const double* mids, int P, const double* cents, int Kx, int Ky,
+                         int tile, const KernelParams& kp, uint64_t* keys, float* dropped,
+                         hipStream_t s);
+// Value pass over sorted rows: writes each row's T*T values.
+hipError_t launch_gbuild(const double* uvw, int64_t nsorted, const int32_t* perm,
+                         const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
+                         const WorkItem* wi, double scale, double gsx, double gsy,
+                         const double* mids, int P, const double* cents,
+                         const KernelParams& kp, void* vals, wf_store store, hipStream_t s);
+
+// ------------------------------------------------------------------ host helpers
+double i0_series(double x);
+double kb_phihat(double nu, int J, double beta);
+
+struct PlanResult {
+  int P = 1;
+  int p_wsclean = 1;
+  int p_star = 1;
+  wf_strategy strategy = WF_PRECOMP_G;
+  double k_est = 0, mem_model = 0, cost_model = 0;
+  std::vector<double> centroids;
+};
+
+// Sect. 3.4 planner on the host (eq. 5, eq. 9 GPU form, eq. 10, Fig. 2).
+int plan_channel(const double* w_all, int64_t M, const wf_image_shape& shape,
+                 const wf_options& opt, uint64_t budget, PlanResult* out, std::string* err);
+std::vector<double> kmeans_1d(std::vector<double> wsub, int P);
+int nk_rule(double wproj, const KernelParams& kp, bool capped);
+
+// Stable LSD radix sort of (key, idx) by key bits [lo_bit, 64).
+void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<int32_t>& idx, int lo_bit);
+
+}  // namespace wf

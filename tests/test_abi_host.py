@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every function
+that include/wf.h declares, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2605_26347_amd import _lib, default_options
+from paper_2605_26347_amd._lib import WfImageShape, WfOptions
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "wf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wf_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, n
+
+
+def test_default_options():
+    o = default_options()
+    assert (o.J, o.oversample, o.smax, o.nbins, o.store) == (7, 2, 15, 0, 0)
+    assert abs(o.beta - 2.34 * 7) < 1e-12 and o.eps_w == 1e-6
+    assert o.plan_fraction == 0.01 and o.budget_fraction == 0.65
+
+
+def _build(uvw, freqs, nx=64, ny=64, cell=1e-4, chan_rows=None, **kw):
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    o = default_options(**kw)
+    uvw = np.ascontiguousarray(uvw, dtype=np.float64)
+    fr = np.ascontiguousarray(freqs, dtype=np.float64)
+    cr = None if chan_rows is None else np.ascontiguousarray(chan_rows, dtype=np.int64)
+    st = lib.wf_build_operator(uvw.ctypes.data_as(ctypes.c_void_p), uvw.shape[0],
+                               None if cr is None else cr.ctypes.data_as(ctypes.c_void_p),
+                               fr.ctypes.data_as(ctypes.c_void_p), fr.size,
+                               WfImageShape(nx, ny, cell), 1 << 30, ctypes.byref(o), None,
+                               ctypes.byref(h))
+    return st, lib.wf_last_error().decode(), h
+
+
+UVW = np.random.default_rng(0).normal(0, 100, (50, 3))
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(nx=48), "powers of two"),
+    (dict(nx=4, ny=4), "powers of two"),
+    (dict(cell=0.0), "cell"),
+    (dict(cell=0.02), "too wide"),
+    (dict(J=6), "J must be odd"),
+    (dict(smax=17), "smax"),
+    (dict(J=9, smax=15), "patch side"),
+    (dict(nbins=300), "nbins"),
+    (dict(oversample=3), "oversample"),
+    (dict(tile=48), "tile"),
+])
+def test_invalid_arguments(kw, frag):
+    st, msg, h = _build(UVW, [1e9], **kw)
+    assert st == _lib.WF_EINVAL and frag in msg and not h.value
+
+
+def test_invalid_rows_and_freqs():
+    st, msg, _ = _build(UVW, [1e9, 1.2e9], chan_rows=[20, 20])
+    assert st == _lib.WF_EINVAL and "sum" in msg
+    st, msg, _ = _build(UVW, [-1e9])
+    assert st == _lib.WF_EINVAL and "frequencies" in msg
+    bad = UVW.copy()
+    bad[3, 1] = np.nan
+    st, msg, _ = _build(bad, [1e9])
+    assert st == _lib.WF_EINVAL and "non-finite" in msg
+
+
+def test_null_handle_calls():
+    lib = _lib.load()
+    assert lib.wf_psf_apply(None, None, None, None) == _lib.WF_EINVAL
+    assert lib.wf_destroy(None) == _lib.WF_EINVAL
+    assert b"null" in lib.wf_last_error()
