@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the widefield Phi^dag Phi apply on one MI355X.
+
+Workload: 4096^2 image over a 3 degree field, 50M visibilities of the 64-antenna
+array over 16 h at 1.28 GHz, w-bin count chosen by the planner (eq. 10) under 288 GB.
+One step = one Re{Phi^dag Phi x} apply over all w-bins (the operator the
+forward-backward iteration of eq. 4 consumes), inputs resident in HBM.
+
+Two forms are built and timed: G stored as complex FP16 with FP32 accumulation and
+FP32 FFTs (the mixed form, reported as `value`) and G stored as complex FP32.
+Printed: one JSON line with applies/s, Gvis/s, the mixed/FP32 speedup, the roofline
+of the dominant kernel (fused G^dag G, HIP events on its stream during the timed
+region) and the FP64 oracle's throughput on a bounded CPU sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Φ†Φ applies/s, Gvis/s (4096², 50M vis): mixed vs FP32 at ≤1e-3 rel err"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--nvis", type=int, default=50_000_000)
+    ap.add_argument("--fov", type=float, default=3.0)
+    ap.add_argument("--budget", type=float, default=288e9)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--forms", default="f16,f32")
+    return ap.parse_args()
+
+
+def gtg_bytes(info, store):
+    """Algorithmic bytes of the fused G^dag G kernel over one apply: every stored value
+    of G once (b_v per tap), the per-row metadata (patch origin word + value offset) and
+    the work-item records.  Grid reads and writes are not counted (lower bound)."""
+    bv = 8 if store == "f32" else 4
+    return bv * info["ntaps"] + 8 * info["nrows"] + 32 * info["nwork"]
+
+
+def time_form(obs, store, args, torch):
+    from paper_2605_26347_amd import Operator
+    t0 = time.time()
+    op = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad,
+                  memory_budget=args.budget, store=store)
+    tb = time.time() - t0
+    info = op.plan(0)
+    log(f"{store}: built in {tb:.1f} s: P={info['nbins']} (P*={info['p_star']}, "
+        f"P_WSClean={info['p_wsclean']}), taps={info['ntaps']:.3e}, "
+        f"G={info['mem_g_bytes'] / 1e9:.1f} GB, work items={info['nwork']}, "
+        f"capped={info['capped_fraction']:.4f}")
+    x = torch.from_numpy(obs.sky.astype(np.float32)[None]).to("cuda:0")
+    out = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        op.psf_apply_re(x, out)
+    torch.cuda.synchronize()
+    op.profile_enable(0, True)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record(stream)
+    for i in range(args.steps):
+        op.psf_apply_re(x, out)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = start.elapsed_time(end) / args.steps
+    nl, kms = op.profile_read(0)
+    op.profile_enable(0, False)
+    log(f"{store}: {ms:.3f} ms/apply (wall {1e3 * wall / args.steps:.3f}), "
+        f"G^dag G {kms / max(nl, 1):.3f} ms/launch over {nl} launches")
+    res = dict(ms=ms, info=info, build_s=tb, gtg_launches=nl, gtg_ms_total=kms,
+               out=out.clone(), store=store)
+    op.close()
+    del op
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(obs, P_gpu):
+    """FP64 oracle on a bounded sample: one full-size w-layer (two 8192^2 FFTs and the
+    layer's w-modulation) and the sparse products of a 50k-row sample of that layer;
+    scaled to a full apply as P * t_layer_fft + M * t_row."""
+    import threadpoolctl
+    from oracle import OracleOperator, OperatorParams
+    from oracle.operator import C_LIGHT
+    nsamp = 50_000
+    rng = np.random.default_rng(11)
+    rows = np.sort(rng.choice(obs.uvw_m.shape[0], nsamp, replace=False))
+    prm = OperatorParams(obs.nx, obs.ny, obs.cell_rad)
+    # centroids from the oracle's own planner-sized k-means on the full data's subset
+    orc_full_w = obs.uvw_m[:, 2] * (obs.freqs_hz[0] / C_LIGHT)
+    from oracle import wbins
+    mask = wbins.plan_subset_mask(orc_full_w.size, 0.01, 0)
+    cents = wbins.kmeans_1d(orc_full_w[mask], P_gpu)
+    orc = OracleOperator(obs.uvw_m[rows], obs.freqs_hz[0], prm, centroids=cents)
+    x = obs.sky
+    info = threadpoolctl.threadpool_info()
+    cores = max([i.get("num_threads", 1) for i in info] + [1])
+    p = int(np.argmax([r.size for r in orc.bin_rows]))
+    t0 = time.perf_counter()
+    z = orc.zp(p)
+    X = orc.fwd_fft(z * x)
+    t1 = time.perf_counter()
+    Y = orc.gtg(p, X)
+    t2 = time.perf_counter()
+    _ = np.conj(z) * orc.inv_fft_crop(Y)
+    t3 = time.perf_counter()
+    t_fft = (t1 - t0) + (t3 - t2)
+    t_row = (t2 - t1) / orc.bin_rows[p].size
+    M = obs.uvw_m.shape[0]
+    t_apply = P_gpu * t_fft + M * t_row
+    log(f"cpu oracle: layer FFT+modulation {t_fft:.2f} s, {1e6 * t_row:.2f} us/row "
+        f"({orc.bin_rows[p].size} rows) -> {t_apply:.0f} s per full apply")
+    return {"value": 1.0 / t_apply, "unit": "applies/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": (f"one full-size w-layer (4096^2 image, 8192^2 FFTs) plus the G^dag G "
+                       f"products of the {orc.bin_rows[p].size} rows of that layer within a "
+                       f"seeded {nsamp}-row sample, scaled to P={P_gpu} layers and "
+                       f"{M} rows: P*t_layer + M*t_row"),
+            "seconds": t3 - t0}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the operator "
+              "shards by w-bin across GPUs only in design", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import wfsynth as ws
+    t0 = time.time()
+    obs = ws.precision_form(n=args.n, nvis=args.nvis, fov_deg=args.fov)
+    log(f"inputs: {obs.uvw_m.shape[0]} rows, {obs.nx}^2 image, {time.time() - t0:.1f} s")
+    forms = args.forms.split(",")
+    res = {}
+    for f in forms:
+        res[f] = time_form(obs, f, args, torch)
+    head = res[forms[0]]
+    M = obs.uvw_m.shape[0]
+    aps = 1e3 / head["ms"]
+    acc = {}
+    if "f32" in res:
+        ref = res["f32"]["out"]
+        for f in forms:
+            if f != "f32":
+                d = (res[f]["out"] - ref).norm() / ref.norm()
+                acc[f"{f}_vs_f32"] = float(d)
+    nl = head["gtg_launches"]
+    kms = head["gtg_ms_total"] / max(nl, 1)
+    bytes_per_apply = gtg_bytes(head["info"], head["store"])
+    P = head["info"]["nbins"]
+    per_launch = bytes_per_apply / max(P, 1)
+    achieved = per_launch / (kms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": aps, "unit": "applies/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Re{{Phi^dag Phi x}}, {obs.nx}^2 image, {M} visibilities, "
+                               f"3 deg field, 64-antenna array 16 h, 1.28 GHz",
+                   "store": head["store"], "nbins": P, "image": obs.nx, "nvis": M},
+        "gvis_per_s": aps * M / 1e9,
+        "forms": {f: {"ms": r["ms"], "applies_per_s": 1e3 / r["ms"],
+                      "gvis_per_s": 1e3 / r["ms"] * M / 1e9, "nbins": r["info"]["nbins"],
+                      "ntaps": r["info"]["ntaps"], "build_s": r["build_s"],
+                      "g_bytes": r["info"]["mem_g_bytes"]} for f, r in res.items()},
+        "accuracy": acc,
+        "roofline": {"bound": "hbm", "kernel": "fused G^dag G (k_gtg)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": per_launch, "ms_per_launch": kms,
+                     "share_of_step": kms * P / head["ms"]},
+    }
+    if "f32" in res and forms[0] != "f32":
+        line["speedup_mixed_vs_f32"] = res["f32"]["ms"] / head["ms"]
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(obs, P)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

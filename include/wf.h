@@ -66,7 +66,7 @@ typedef struct {
   double beta;             /* Kaiser-Bessel shape, default 2.34 J                     */
   int32_t oversample;      /* grid oversampling o (Sect. 3.2), must be 2              */
   double alpha;            /* w-kernel sampling margin over the chirp band, default 2 */
-  int32_t smax;            /* largest residual-kernel side (odd, <= 15), default 15   */
+  int32_t smax;            /* largest residual-kernel side (odd, <= 31), default 31   */
   double eps_w;            /* kernel energy dropped by the hard threshold, 1e-6       */
   int32_t nbins;           /* 0: planner chooses P (eq. 10); > 0 forces P (<= 255)    */
   wf_strategy strategy;    /* WF_AUTO: decision tree                                  */

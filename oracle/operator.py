@@ -37,7 +37,7 @@ class OperatorParams:
     beta: float = 2.34 * 7
     o: int = 2
     alpha: float = 2.0
-    smax: int = 15
+    smax: int = 31
     eps: float = 1e-6
 
 

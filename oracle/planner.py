@@ -53,7 +53,7 @@ def cost(P: int, K: float, nx: int, ny: int, o: int = 2) -> float:
     return 2.0 * (10.0 * Np * math.log2(math.sqrt(Np)) * P + 6.0 * K)
 
 
-def k_of_p(wsub, M: int, P: int, nx, ny, cell, J=7, o=2, alpha=2.0, smax=15):
+def k_of_p(wsub, M: int, P: int, nx, ny, cell, J=7, o=2, alpha=2.0, smax=31):
     """(K(P) estimate scaled to M rows, fraction of subset rows with n_k <= smax, centroids)."""
     c = wbins.kmeans_1d(wsub, P)
     b = wbins.assign_bins(wsub, c)
@@ -65,7 +65,7 @@ def k_of_p(wsub, M: int, P: int, nx, ny, cell, J=7, o=2, alpha=2.0, smax=15):
     return K, ok, c
 
 
-def plan(w_lambda, nx, ny, cell, memory_budget, store="f32", J=7, o=2, alpha=2.0, smax=15,
+def plan(w_lambda, nx, ny, cell, memory_budget, store="f32", J=7, o=2, alpha=2.0, smax=31,
          plan_fraction=0.01, budget_fraction=0.65, seed=0, m_H=None, p_max=None):
     """Decision tree of Sect. 3.4.  w_lambda: all rows' w in wavelengths.
     m_H: optional callable P -> bytes of the holographic matrix.  Returns a dict."""

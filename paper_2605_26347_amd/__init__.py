@@ -136,10 +136,10 @@ class Operator:
     def get_row(self, row, chan=0):
         """(T, qu0, qv0, bin, values complex64 [T, T]) of one stored row of G."""
         T, qu, qv, b = (ctypes.c_int32() for _ in range(4))
-        buf = np.zeros(2 * 32 * 32, dtype=np.float32)
+        buf = np.zeros(2 * 64 * 64, dtype=np.float32)
         check(self._lib.wf_get_row(self._h, chan, ctypes.c_int64(row), ctypes.byref(T),
                                    ctypes.byref(qu), ctypes.byref(qv), ctypes.byref(b),
-                                   buf.ctypes.data_as(ctypes.c_void_p), 32 * 32), "wf_get_row")
+                                   buf.ctypes.data_as(ctypes.c_void_p), 64 * 64), "wf_get_row")
         t = T.value
         vals = buf[:2 * t * t].view(np.complex64).reshape(t, t).copy()
         return t, qu.value, qv.value, b.value, vals

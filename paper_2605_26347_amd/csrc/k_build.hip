@@ -24,16 +24,17 @@
 
 namespace wf {
 
-constexpr int MAXNK = 15;
-constexpr int MAXT = 21 + 8;  // room for J up to 15 with smax 15
+constexpr int MAXNK = 31;
+constexpr int MAXT = 37;      // J - 1 + smax <= 37
+constexpr int NSORT = 1024;   // power of two >= MAXNK^2
 
 struct KScratch {
   double2 c[MAXNK * MAXNK];        // samples, then kernel
   double2 t[MAXNK * MAXNK];        // DFT intermediate
-  double e[256];                   // energies (sorted)
+  double e[NSORT];                 // energies (sorted)
   double2 roots[MAXNK];            // exp(-2 pi i m / nk)
   double2 t2[MAXNK * MAXT];        // convolution intermediate
-  double ku[16], kv[16];           // Kaiser-Bessel taps
+  double ku[16], kv[16];           // Kaiser-Bessel taps (J <= 15)
 };
 
 __device__ __forceinline__ double dev_i0(double x) {
@@ -175,8 +176,11 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
     S.c[idx] = make_double2(re * inv, im * inv);
   }
   __syncthreads();
-  // energies, ascending bitonic sort over 256 slots (+inf padding)
-  for (int i = lane; i < 256; i += 64) {
+  // energies, ascending bitonic sort over NS slots (NS = next power of two >= nk^2,
+  // +inf padding)
+  int NS = 16;
+  while (NS < nn2) NS <<= 1;
+  for (int i = lane; i < NS; i += 64) {
     if (i < nn2) {
       const double2 v = S.c[i];
       S.e[i] = v.x * v.x + v.y * v.y;
@@ -185,9 +189,9 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
     }
   }
   __syncthreads();
-  for (int k = 2; k <= 256; k <<= 1) {
+  for (int k = 2; k <= NS; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = lane; i < 256; i += 64) {
+      for (int i = lane; i < NS; i += 64) {
         const int ixj = i ^ j;
         if (ixj > i) {
           const bool up = (i & k) == 0;
@@ -201,12 +205,15 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
       __syncthreads();
     }
   }
-  // inclusive prefix sums: lane holds slots 4 lane .. 4 lane + 3
-  double loc[4];
+  // inclusive prefix sums: lane holds slots pl*lane .. pl*lane + pl - 1
+  constexpr int PLMAX = NSORT / 64;
+  const int pl = NS >= 64 ? NS / 64 : 1;
+  double loc[PLMAX];
   double run = 0.0;
-  for (int q = 0; q < 4; ++q) {
-    const int i = 4 * lane + q;
-    const double v = (i < nn2) ? S.e[i] : 0.0;
+#pragma unroll
+  for (int q = 0; q < PLMAX; ++q) {
+    const int i = pl * lane + q;
+    const double v = (q < pl && i < nn2) ? S.e[i] : 0.0;
     run += v;
     loc[q] = run;
   }
@@ -220,9 +227,10 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
   const double tot = __shfl(scan, 63, 64);
   const double thr = kp.eps * tot;
   int cnt = 0;
-  for (int q = 0; q < 4; ++q) {
-    const int i = 4 * lane + q;
-    if (i < nn2 && offs + loc[q] <= thr) ++cnt;
+#pragma unroll
+  for (int q = 0; q < PLMAX; ++q) {
+    const int i = pl * lane + q;
+    if (q < pl && i < nn2 && offs + loc[q] <= thr) ++cnt;
   }
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
   int jdrop = cnt < nn2 - 1 ? cnt : nn2 - 1;
@@ -274,8 +282,9 @@ __global__ __launch_bounds__(64) void k_rowsym(const double* __restrict__ uvw, i
       const int64_t rvm = ((rv % Ky) + Ky) % Ky;
       const uint64_t tu = (uint64_t)(rum / tile), lu = (uint64_t)(rum % tile);
       const uint64_t tv = (uint64_t)(rvm / tile), lv = (uint64_t)(rvm % tile);
-      keys[k] = ((uint64_t)g.p << 56) | (tv << 46) | (tu << 36) | ((uint64_t)T << 31) |
-                (lv << 24) | (lu << 17);
+      // key: bin 8 | tile v 10 | tile u 10 | patch side 6 | local v 7 | local u 7 | 16 zero
+      keys[k] = ((uint64_t)g.p << 56) | (tv << 46) | (tu << 36) | ((uint64_t)T << 30) |
+                (lv << 23) | (lu << 16);
       const float df = (float)dropped;
       dropped_out[k] = (nk_full > kp.smax) ? -df - 1e-30f : df;
     }
@@ -309,7 +318,8 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
                                                double gsx, double gsy,
                                                const double* __restrict__ mids, int P,
                                                const double* __restrict__ cents,
-                                               KernelParams kp, void* __restrict__ vals) {
+                                               KernelParams kp, void* __restrict__ vals,
+                                               int* __restrict__ mismatch) {
 #pragma clang fp contract(off)
   __shared__ KScratch S;
   const int lane = threadIdx.x;
@@ -368,6 +378,8 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
         }
         store_val<STORE>(vals, vb + idx, re, im);
       }
+    } else if (lane == 0) {
+      atomicAdd(mismatch, 1);
     }
     __syncthreads();
   }
@@ -388,24 +400,25 @@ hipError_t launch_gbuild(const double* uvw, int64_t nsorted, const int32_t* perm
                          const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
                          const WorkItem* wi, double scale, double gsx, double gsy,
                          const double* mids, int P, const double* cents,
-                         const KernelParams& kp, void* vals, wf_store store, hipStream_t s) {
+                         const KernelParams& kp, void* vals, wf_store store, int* mismatch,
+                         hipStream_t s) {
   if (nsorted <= 0) return hipSuccess;
   const int blocks = (int)(nsorted < 262144 ? nsorted : 262144);
   switch (store) {
     case WF_STORE_F32:
       hipLaunchKernelGGL(k_gbuild<WF_STORE_F32>, dim3(blocks), dim3(64), 0, s, uvw, nsorted,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals);
+                         vals, mismatch);
       break;
     case WF_STORE_F16:
       hipLaunchKernelGGL(k_gbuild<WF_STORE_F16>, dim3(blocks), dim3(64), 0, s, uvw, nsorted,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals);
+                         vals, mismatch);
       break;
     default:
       hipLaunchKernelGGL(k_gbuild<WF_STORE_BF16>, dim3(blocks), dim3(64), 0, s, uvw, nsorted,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals);
+                         vals, mismatch);
       break;
   }
   return hipGetLastError();

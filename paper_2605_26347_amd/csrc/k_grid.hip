@@ -3,7 +3,7 @@
 //
 // Rows are sorted by (bin, grid tile, patch side) and cut into work items; a
 // workgroup owns one work item and a wavefront processes one row at a time with its
-// 64 lanes spread over the row's T x T patch (T <= 21 -> at most 7 taps per lane).
+// 64 lanes spread over the row's T x T patch (T <= 37 -> at most 22 taps per lane).
 //   fused G^dag G : y_k = sum_q g_k[q] X[q] (gather from the grid, wave reduction),
 //                   then conj(g_k) y_k is added into an LDS window of the tile plus
 //                   its halo (LDS atomics); G is read from HBM once.  The window is
@@ -20,7 +20,7 @@ namespace wf {
 
 constexpr int GWAVES = 8;          // wavefronts per workgroup
 constexpr int GNT = GWAVES * 64;
-constexpr int MAXK = 7;            // ceil(21*21 / 64)
+constexpr int MAXK = 22;           // ceil(37*37 / 64)
 
 template <int STORE>
 __device__ __forceinline__ float2 load_val(const void* __restrict__ vals, int64_t i) {
@@ -52,9 +52,11 @@ __device__ __forceinline__ float2 row_gather(const void* __restrict__ vals, int6
   const float invT = 1.0f / (float)T;
   float sx = 0.f, sy = 0.f;
 #pragma unroll
+  for (int k = 0; k < MAXK; ++k) li[k] = -1;
+#pragma unroll
   for (int k = 0; k < MAXK; ++k) {
+    if (64 * k >= TT) break;  // wave-uniform
     const int t = lane + 64 * k;
-    li[k] = -1;
     if (t < TT) {
       const int a = (int)(((float)t + 0.5f) * invT);
       const int b = t - a * T;
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(GNT) void k_gtg(const WorkItem* __restrict__ wis,
     s.y = wave_sum(s.y);
 #pragma unroll
     for (int k = 0; k < MAXK; ++k) {
+      if (64 * k >= T * T) break;  // wave-uniform
       if (li[k] >= 0) {
         // conj(g) * y
         const float rx = g[k].x * s.x + g[k].y * s.y;
@@ -177,6 +180,7 @@ __global__ __launch_bounds__(GNT) void k_grid(const WorkItem* __restrict__ wis,
                       false);
 #pragma unroll
     for (int k = 0; k < MAXK; ++k) {
+      if (64 * k >= T * T) break;  // wave-uniform
       if (li[k] >= 0) {
         const float rx = g[k].x * s.x + g[k].y * s.y;
         const float ry = g[k].x * s.y - g[k].y * s.x;

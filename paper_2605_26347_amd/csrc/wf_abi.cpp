@@ -215,7 +215,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
 
   std::vector<int32_t> idx(M);
   std::iota(idx.begin(), idx.end(), 0);
-  radix_sort_pairs(keys, idx, 17);
+  radix_sort_pairs(keys, idx, 16);
 
   // work items: runs of one (bin, tile), split for load balance
   const int64_t maxrows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
@@ -233,8 +233,8 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     const uint64_t k = keys[sidx];
     const int bin = (int)(k >> 56);
     const int tv = (int)((k >> 46) & 1023), tu = (int)((k >> 36) & 1023);
-    const int T = (int)((k >> 31) & 31);
-    const int lv = (int)((k >> 24) & 127), lu = (int)((k >> 17) & 127);
+    const int T = (int)((k >> 30) & 63);
+    const int lv = (int)((k >> 23) & 127), lu = (int)((k >> 16) & 127);
     const uint64_t grp = k >> 36;
     if (grp != cur || wis.back().nrows >= maxrows || taps_in + T * T > maxtaps) {
       WorkItem wi{};
@@ -267,8 +267,11 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   ch.ntaps = taps_total;
   ch.nwork = (int64_t)wis.size();
   const int b_v = opt.store == WF_STORE_F32 ? 8 : 4;
-  DevBuf drowwi;
+  DevBuf drowwi, dmis;
   tmp.b.push_back(&drowwi);
+  tmp.b.push_back(&dmis);
+  if ((st = dalloc(dmis, sizeof(int))) != WF_OK) return st;
+  WF_HIP(hipMemsetAsync(dmis.p, 0, sizeof(int), s));
   if ((st = dalloc(ch.meta, sizeof(uint32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
   if ((st = dalloc(ch.voff, sizeof(uint32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
   if ((st = dalloc(ch.perm, sizeof(int32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
@@ -287,8 +290,13 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
                        (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
                        (const int32_t*)drowwi.p, (const WorkItem*)ch.work.p, ch.scale, gsx,
                        gsy, (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
-                       ch.vals.p, opt.store, s));
+                       ch.vals.p, opt.store, (int*)dmis.p, s));
+  int mismatch = 0;
+  WF_HIP(hipMemcpyAsync(&mismatch, dmis.p, sizeof(int), hipMemcpyDeviceToHost, s));
   WF_HIP(hipStreamSynchronize(s));
+  if (mismatch != 0)
+    return fail(WF_EINVAL, std::to_string(mismatch) +
+                               " rows changed patch side between the symbolic and value passes");
 
   wf_plan_info& in = ch.info;
   in.nchan = (int32_t)op->chans.size();
@@ -396,7 +404,7 @@ void wf_default_options(wf_options* o) {
   o->beta = 2.34 * 7;
   o->oversample = 2;
   o->alpha = 2.0;
-  o->smax = 15;
+  o->smax = 31;
   o->eps_w = 1e-6;
   o->nbins = 0;
   o->strategy = WF_AUTO;
@@ -430,10 +438,10 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
     else wf_default_options(&opt);
     if (opt.oversample != 2) return fail(WF_EINVAL, "oversample must be 2");
     if (opt.J < 3 || opt.J > 15 || (opt.J % 2) == 0) return fail(WF_EINVAL, "J must be odd in [3,15]");
-    if (opt.smax < 1 || opt.smax > 15 || (opt.smax % 2) == 0)
-      return fail(WF_EINVAL, "smax must be odd in [1,15]");
-    if (opt.J - 1 + opt.smax > 21)
-      return fail(WF_EINVAL, "patch side J - 1 + smax must not exceed 21");
+    if (opt.smax < 1 || opt.smax > 31 || (opt.smax % 2) == 0)
+      return fail(WF_EINVAL, "smax must be odd in [1,31]");
+    if (opt.J - 1 + opt.smax > 37)
+      return fail(WF_EINVAL, "patch side J - 1 + smax must not exceed 37");
     if (opt.nbins < 0 || opt.nbins > 255) return fail(WF_EINVAL, "nbins must be in [0,255]");
     if (!(opt.beta > 0) || !(opt.alpha > 0) || !(opt.eps_w >= 0) || opt.eps_w >= 1)
       return fail(WF_EINVAL, "bad beta / alpha / eps_w");
@@ -467,7 +475,7 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
     op->shape = shape;
     op->Kx = 2 * shape.nx;
     op->Ky = 2 * shape.ny;
-    int tile = opt.tile > 0 ? opt.tile : 64;
+    int tile = opt.tile > 0 ? opt.tile : 32;
     if (!is_pow2(tile) || tile < 8 || tile > 128)
       return fail(WF_EINVAL, "tile must be a power of two in [8,128]");
     tile = std::min({tile, op->Kx, op->Ky});

@@ -140,7 +140,8 @@ hipError_t launch_gbuild(const double* uvw, int64_t nsorted, const int32_t* perm
                          const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
                          const WorkItem* wi, double scale, double gsx, double gsy,
                          const double* mids, int P, const double* cents,
-                         const KernelParams& kp, void* vals, wf_store store, hipStream_t s);
+                         const KernelParams& kp, void* vals, wf_store store, int* mismatch,
+                         hipStream_t s);
 
 // ------------------------------------------------------------------ host helpers
 double i0_series(double x);

@@ -16,7 +16,7 @@ def rel(a, b):
 def oracle_for(obs, nbins, chan=0, uvw=None, **kw):
     prm = OperatorParams(obs.nx, obs.ny, obs.cell_rad,
                          J=kw.get("J", 7), beta=kw.get("beta", 2.34 * kw.get("J", 7)),
-                         alpha=kw.get("alpha", 2.0), smax=kw.get("smax", 15),
+                         alpha=kw.get("alpha", 2.0), smax=kw.get("smax", 31),
                          eps=kw.get("eps_w", 1e-6))
     u = obs.uvw_m if uvw is None else uvw
     return OracleOperator(u, obs.freqs_hz[chan], prm, nbins=nbins, seed=kw.get("seed", 0),

@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_default_options():
     o = default_options()
-    assert (o.J, o.oversample, o.smax, o.nbins, o.store) == (7, 2, 15, 0, 0)
+    assert (o.J, o.oversample, o.smax, o.nbins, o.store) == (7, 2, 31, 0, 0)
     assert abs(o.beta - 2.34 * 7) < 1e-12 and o.eps_w == 1e-6
     assert o.plan_fraction == 0.01 and o.budget_fraction == 0.65
 
@@ -59,8 +59,8 @@ UVW = np.random.default_rng(0).normal(0, 100, (50, 3))
     (dict(cell=0.0), "cell"),
     (dict(cell=0.02), "too wide"),
     (dict(J=6), "J must be odd"),
-    (dict(smax=17), "smax"),
-    (dict(J=9, smax=15), "patch side"),
+    (dict(smax=33), "smax"),
+    (dict(J=9, smax=31), "patch side"),
     (dict(nbins=300), "nbins"),
     (dict(oversample=3), "oversample"),
     (dict(tile=48), "tile"),
