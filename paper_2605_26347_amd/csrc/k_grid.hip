@@ -1,15 +1,21 @@
 // Sparse products with the de-gridding matrix G_p (Sect. 3.2, eq. 6) and its adjoint
 // (Sect. 3.3, eq. 8).
 //
-// Rows are sorted by (bin, grid tile, patch side) and cut into work items; a
-// workgroup owns one work item and a wavefront processes one row at a time with its
-// 64 lanes spread over the row's T x T patch (T <= 37 -> at most 22 taps per lane).
-//   fused G^dag G : y_k = sum_q g_k[q] X[q] (gather from the grid, wave reduction),
-//                   then conj(g_k) y_k is added into an LDS window of the tile plus
-//                   its halo (LDS atomics); G is read from HBM once.  The window is
-//                   flushed with global atomics into Y, skipping untouched cells.
-//   de-gridding   : the gather half, y written to the caller's visibility order.
-//   gridding      : the scatter half, y read from the caller's visibility order.
+// Rows are sorted by (bin, grid tile, patch side, patch origin) and cut into work
+// items that hold one patch-size class; a workgroup owns one work item and each of its
+// wavefronts walks a contiguous segment of the item's rows, its 64 lanes spread over a
+// row's T x T patch (MK taps per lane).  Consecutive rows with the same patch origin
+// and side (a "run": visibilities falling in one grid cell) share their grid cells, so
+//   * the grid values X of the run's patch are gathered once per run,
+//   * conj(g_k) y_k is accumulated in registers over the run and added into the LDS
+//     window of the tile (plus halo) once per run,
+// and the stored values of G are streamed from HBM exactly once.  A row's sum
+// y_k = sum_t g_k[t] X[t] is reduced across the wavefront with DPP within each
+// 16-lane row and four readlanes, which leaves y_k wave-uniform.  At the end the
+// window is added into Y with global atomics (untouched cells skipped).
+//   fused G^dag G : gather + reduce + accumulate (Phi^dag Phi);
+//   de-gridding   : gather + reduce, y written to the caller's visibility order (Phi);
+//   gridding      : y read from the caller's order, accumulate (Phi^dag).
 // Values are stored as complex FP32, FP16 or BF16; all arithmetic is FP32.
 #include <hip/hip_fp16.h>
 
@@ -20,58 +26,117 @@ namespace wf {
 
 constexpr int GWAVES = 8;          // wavefronts per workgroup
 constexpr int GNT = GWAVES * 64;
-constexpr int MAXK = 22;           // ceil(37*37 / 64)
+
+// Stored values are loaded in their raw form (float2, or one 32-bit word holding two
+// 16-bit halves) and widened to FP32 only where they are used, so that the loads of a
+// row can all be in flight together.
+template <int STORE>
+struct RawT {
+  using type = uint32_t;
+};
+template <>
+struct RawT<WF_STORE_F32> {
+  using type = float2;
+};
 
 template <int STORE>
-__device__ __forceinline__ float2 load_val(const void* __restrict__ vals, int64_t i) {
+__device__ __forceinline__ typename RawT<STORE>::type load_raw(const void* __restrict__ vals,
+                                                               int64_t i) {
   if constexpr (STORE == WF_STORE_F32) {
     return reinterpret_cast<const float2*>(vals)[i];
+  } else {
+    return reinterpret_cast<const uint32_t*>(vals)[i];
+  }
+}
+
+template <int STORE>
+__device__ __forceinline__ float2 widen(typename RawT<STORE>::type r) {
+  if constexpr (STORE == WF_STORE_F32) {
+    return r;
   } else if constexpr (STORE == WF_STORE_F16) {
-    const __half2 h = reinterpret_cast<const __half2*>(vals)[i];
+    __half2 h;
+    __builtin_memcpy(&h, &r, 4);
     return __half22float2(h);
   } else {
-    const uint32_t b = reinterpret_cast<const uint32_t*>(vals)[i];
-    return make_float2(__uint_as_float(b << 16), __uint_as_float(b & 0xffff0000u));
+    return make_float2(__uint_as_float(r << 16), __uint_as_float(r & 0xffff0000u));
   }
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Sum over the wavefront, returned wave-uniform: DPP butterflies inside each row of 16
+// lanes (quad xor 1, quad xor 2, half-row mirror, row mirror), then the four row sums.
+__device__ __forceinline__ float wave_sum_uniform(float v) {
+  v += __builtin_amdgcn_update_dpp(0.f, v, 0xb1, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0.f, v, 0x4e, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0.f, v, 0x141, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0.f, v, 0x140, 0xf, 0xf, false);
+  const int b = __float_as_int(v);
+  return (__int_as_float(__builtin_amdgcn_readlane(b, 0)) +
+          __int_as_float(__builtin_amdgcn_readlane(b, 16))) +
+         (__int_as_float(__builtin_amdgcn_readlane(b, 32)) +
+          __int_as_float(__builtin_amdgcn_readlane(b, 48)));
 }
 
-// Gather y = sum_t g[t] X[cell(t)] over one row; keeps the row's values and LDS
-// window indices in registers for a following scatter.
-template <int STORE>
-__device__ __forceinline__ float2 row_gather(const void* __restrict__ vals, int64_t vb, int T,
-                                             int lu0, int lv0, int u0, int v0, int Kx, int Ky,
-                                             const float2* __restrict__ X, float2 (&g)[MAXK],
-                                             int (&li)[MAXK], int W, int lane, bool need_x) {
-  const int TT = T * T;
-  const float invT = 1.0f / (float)T;
-  float sx = 0.f, sy = 0.f;
+struct RunGeom {
+  int T, TT, lu0, lv0;
+};
+
+__device__ __forceinline__ RunGeom decode(uint32_t m) {
+  RunGeom r;
+  r.lu0 = m & 0xff;
+  r.lv0 = (m >> 8) & 0xff;
+  r.T = (m >> 16) & 0xff;
+  r.TT = r.T * r.T;
+  return r;
+}
+
+// Patch coordinates (a = row, b = column) of tap t; exact for t < 2^13, T <= 64.
+__device__ __forceinline__ void tap_ab(int t, int T, float invT, int& a, int& b) {
+  a = (int)(((float)t + 0.5f) * invT);
+  b = t - a * T;
+}
+
+// Load the grid values of a run's patch (one per lane and tap slot).
+template <int MK>
+__device__ __forceinline__ void load_patch_x(const RunGeom& r, int u0, int v0, int Kx, int Ky,
+                                             const float2* __restrict__ X, int lane,
+                                             float2 (&xr)[MK]) {
+  const float invT = 1.0f / (float)r.T;
+  // branch-free: lanes past the patch read its last cell and zero the value
 #pragma unroll
-  for (int k = 0; k < MAXK; ++k) li[k] = -1;
-#pragma unroll
-  for (int k = 0; k < MAXK; ++k) {
-    if (64 * k >= TT) break;  // wave-uniform
+  for (int k = 0; k < MK; ++k) {
     const int t = lane + 64 * k;
-    if (t < TT) {
-      const int a = (int)(((float)t + 0.5f) * invT);
-      const int b = t - a * T;
-      g[k] = load_val<STORE>(vals, vb + t);
-      li[k] = (lv0 + a) * W + (lu0 + b);
-      if (need_x) {
-        const int gu = (u0 + lu0 + b) & (Kx - 1);
-        const int gv = (v0 + lv0 + a) & (Ky - 1);
-        const float2 x = X[strip_index(gv, gu, Ky)];
-        sx += g[k].x * x.x - g[k].y * x.y;
-        sy += g[k].x * x.y + g[k].y * x.x;
-      }
+    const int tc = t < r.TT ? t : r.TT - 1;
+    int a, b;
+    tap_ab(tc, r.T, invT, a, b);
+    const int gu = (u0 + r.lu0 + b) & (Kx - 1);
+    const int gv = (v0 + r.lv0 + a) & (Ky - 1);
+    xr[k] = X[strip_index(gv, gu, Ky)];
+  }
+#pragma unroll
+  for (int k = 0; k < MK; ++k)
+    if (lane + 64 * k >= r.TT) xr[k] = make_float2(0.f, 0.f);
+}
+
+// Add a run's register accumulator into the LDS window.
+template <int MK>
+__device__ __forceinline__ void scatter_run(const RunGeom& r, int W, int lane,
+                                            const float2 (&ac)[MK], float* accf) {
+  const float invT = 1.0f / (float)r.T;
+#pragma unroll
+  for (int k = 0; k < MK; ++k) {
+    const int t = lane + 64 * k;
+    if (t < r.TT) {
+      int a, b;
+      tap_ab(t, r.T, invT, a, b);
+      const int li = (r.lv0 + a) * W + (r.lu0 + b);
+      atomicAdd(accf + 2 * li, ac[k].x);
+      atomicAdd(accf + 2 * li + 1, ac[k].y);
     }
   }
-  return make_float2(sx, sy);
+}
+
+__device__ __forceinline__ void window_zero(float2* acc, int W) {
+  for (int c = threadIdx.x; c < W * W; c += GNT) acc[c] = make_float2(0.f, 0.f);
 }
 
 __device__ __forceinline__ void window_flush(const float2* acc, int W, int u0, int v0, int Kx,
@@ -89,108 +154,119 @@ __device__ __forceinline__ void window_flush(const float2* acc, int W, int u0, i
   }
 }
 
-template <int STORE>
-__global__ __launch_bounds__(GNT) void k_gtg(const WorkItem* __restrict__ wis,
-                                             const uint32_t* __restrict__ meta,
-                                             const uint32_t* __restrict__ voff,
-                                             const void* __restrict__ vals,
-                                             const float2* __restrict__ X,
-                                             float2* __restrict__ Y, int Kx, int Ky, int W) {
-  extern __shared__ float2 acc[];
-  const WorkItem wi = wis[xcd_remap(blockIdx.x, gridDim.x)];
-  for (int c = threadIdx.x; c < W * W; c += GNT) acc[c] = make_float2(0.f, 0.f);
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float* accf = reinterpret_cast<float*>(acc);
-  for (int r = wave; r < wi.nrows; r += GWAVES) {
-    const int row = wi.row0 + r;
-    const uint32_t m = meta[row];
-    const int lu0 = m & 0xff, lv0 = (m >> 8) & 0xff, T = (m >> 16) & 0xff;
-    const int64_t vb = wi.voff + voff[row];
-    float2 g[MAXK];
-    int li[MAXK];
-    float2 s = row_gather<STORE>(vals, vb, T, lu0, lv0, wi.u0, wi.v0, Kx, Ky, X, g, li, W,
-                                 lane, true);
-    s.x = wave_sum(s.x);
-    s.y = wave_sum(s.y);
-#pragma unroll
-    for (int k = 0; k < MAXK; ++k) {
-      if (64 * k >= T * T) break;  // wave-uniform
-      if (li[k] >= 0) {
-        // conj(g) * y
-        const float rx = g[k].x * s.x + g[k].y * s.y;
-        const float ry = g[k].x * s.y - g[k].y * s.x;
-        atomicAdd(accf + 2 * li[k], rx);
-        atomicAdd(accf + 2 * li[k] + 1, ry);
-      }
-    }
-  }
-  __syncthreads();
-  window_flush(acc, W, wi.u0, wi.v0, Kx, Ky, Y);
-}
-
-template <int STORE>
-__global__ __launch_bounds__(GNT) void k_degrid(const WorkItem* __restrict__ wis,
-                                                const uint32_t* __restrict__ meta,
-                                                const uint32_t* __restrict__ voff,
-                                                const int32_t* __restrict__ perm,
-                                                const void* __restrict__ vals,
-                                                const float2* __restrict__ X,
-                                                float2* __restrict__ vis, int Kx, int Ky) {
-  const WorkItem wi = wis[xcd_remap(blockIdx.x, gridDim.x)];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r = wave; r < wi.nrows; r += GWAVES) {
-    const int row = wi.row0 + r;
-    const uint32_t m = meta[row];
-    const int lu0 = m & 0xff, lv0 = (m >> 8) & 0xff, T = (m >> 16) & 0xff;
-    const int64_t vb = wi.voff + voff[row];
-    float2 g[MAXK];
-    int li[MAXK];
-    float2 s = row_gather<STORE>(vals, vb, T, lu0, lv0, wi.u0, wi.v0, Kx, Ky, X, g, li, 256,
-                                 lane, true);
-    s.x = wave_sum(s.x);
-    s.y = wave_sum(s.y);
-    if (lane == 0) vis[perm[row]] = s;
-  }
-}
-
-template <int STORE>
-__global__ __launch_bounds__(GNT) void k_grid(const WorkItem* __restrict__ wis,
+// MODE 0: fused G^dag G; 1: de-gridding; 2: gridding.
+template <int STORE, int MK, int MODE>
+__global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
                                               const uint32_t* __restrict__ meta,
                                               const uint32_t* __restrict__ voff,
                                               const int32_t* __restrict__ perm,
                                               const void* __restrict__ vals,
-                                              const float2* __restrict__ vis,
-                                              float2* __restrict__ Y, int Kx, int Ky, int W) {
+                                              const float2* __restrict__ X,
+                                              float2* __restrict__ Y,
+                                              float2* __restrict__ vis, int Kx, int Ky,
+                                              int W) {
   extern __shared__ float2 acc[];
   const WorkItem wi = wis[xcd_remap(blockIdx.x, gridDim.x)];
-  for (int c = threadIdx.x; c < W * W; c += GNT) acc[c] = make_float2(0.f, 0.f);
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr bool GATHER = MODE != 2;
+  constexpr bool SCATTER = MODE != 1;
+  if constexpr (SCATTER) {
+    window_zero(acc, W);
+    __syncthreads();
+  }
   float* accf = reinterpret_cast<float*>(acc);
-  for (int r = wave; r < wi.nrows; r += GWAVES) {
-    const int row = wi.row0 + r;
-    const uint32_t m = meta[row];
-    const int lu0 = m & 0xff, lv0 = (m >> 8) & 0xff, T = (m >> 16) & 0xff;
-    const int64_t vb = wi.voff + voff[row];
-    const float2 s = vis[perm[row]];
-    float2 g[MAXK];
-    int li[MAXK];
-    row_gather<STORE>(vals, vb, T, lu0, lv0, wi.u0, wi.v0, Kx, Ky, nullptr, g, li, W, lane,
-                      false);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int seg = (wi.nrows + GWAVES - 1) / GWAVES;
+  const int r0 = wave * seg;
+  const int r1 = min(wi.nrows, r0 + seg);
+  float2 xr[MK], ac[MK];
+  RunGeom rg{};
+  uint32_t cur = 0xffffffffu;
+  using Raw = typename RawT<STORE>::type;
+  if (r0 >= r1) {
+    if constexpr (SCATTER) {
+      __syncthreads();
+      window_flush(acc, W, wi.u0, wi.v0, Kx, Ky, Y);
+    }
+    return;
+  }
+  // Software pipeline: row metadata comes through the scalar cache two rows ahead, value
+  // offsets are the running sum of T^2 inside the item, a new run's grid values are
+  // requested first and the next row's values right after, so that waiting for the
+  // current row leaves the prefetch in flight.
+  const uint32_t* __restrict__ mrow = meta + wi.row0;
+  uint32_t m_cur = mrow[r0];
+  uint32_t m_nxt = (r0 + 1 < r1) ? mrow[r0 + 1] : 0u;
+  int64_t vb = wi.voff + (int64_t)voff[wi.row0 + r0];
+  Raw gn[MK];
+  {
+    const int Tn = (int)((m_cur >> 16) & 0xff);
+    const int lastt = Tn * Tn - 1;
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k) {
-      if (64 * k >= T * T) break;  // wave-uniform
-      if (li[k] >= 0) {
-        const float rx = g[k].x * s.x + g[k].y * s.y;
-        const float ry = g[k].x * s.y - g[k].y * s.x;
-        atomicAdd(accf + 2 * li[k], rx);
-        atomicAdd(accf + 2 * li[k] + 1, ry);
+    for (int k = 0; k < MK; ++k) gn[k] = load_raw<STORE>(vals, vb + min(lane + 64 * k, lastt));
+  }
+  for (int r = r0; r < r1; ++r) {
+    const int row = wi.row0 + r;
+    const uint32_t m = m_cur;
+    m_cur = m_nxt;
+    m_nxt = (r + 2 < r1) ? mrow[r + 2] : 0u;
+    Raw graw[MK];
+#pragma unroll
+    for (int k = 0; k < MK; ++k) graw[k] = gn[k];
+    const int Tm = (int)((m >> 16) & 0xff);
+    vb += (int64_t)Tm * Tm;
+    if (m != cur) {
+      if constexpr (SCATTER) {
+        if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
+      }
+      cur = m;
+      rg = decode(m);
+      if constexpr (GATHER) load_patch_x<MK>(rg, wi.u0, wi.v0, Kx, Ky, X, lane, xr);
+#pragma unroll
+      for (int k = 0; k < MK; ++k) ac[k] = make_float2(0.f, 0.f);
+    }
+    if (r + 1 < r1) {  // prefetch the next row (branch-free, clamped in-bounds loads)
+      const int Tn = (int)((m_cur >> 16) & 0xff);
+      const int lastt = Tn * Tn - 1;
+#pragma unroll
+      for (int k = 0; k < MK; ++k) gn[k] = load_raw<STORE>(vals, vb + min(lane + 64 * k, lastt));
+    }
+    float2 g[MK];
+    const int TTm = Tm * Tm;
+#pragma unroll
+    for (int k = 0; k < MK; ++k)
+      g[k] = (lane + 64 * k < TTm) ? widen<STORE>(graw[k]) : make_float2(0.f, 0.f);
+    float yx, yy;
+    if constexpr (GATHER) {
+      float sx = 0.f, sy = 0.f;
+#pragma unroll
+      for (int k = 0; k < MK; ++k) {
+        sx += g[k].x * xr[k].x - g[k].y * xr[k].y;
+        sy += g[k].x * xr[k].y + g[k].y * xr[k].x;
+      }
+      yx = wave_sum_uniform(sx);
+      yy = wave_sum_uniform(sy);
+      if constexpr (MODE == 1) {
+        if (lane == 0) vis[perm[row]] = make_float2(yx, yy);
+      }
+    } else {
+      const float2 y = vis[perm[row]];
+      yx = y.x;
+      yy = y.y;
+    }
+    if constexpr (SCATTER) {
+#pragma unroll
+      for (int k = 0; k < MK; ++k) {  // += conj(g) y
+        ac[k].x += g[k].x * yx + g[k].y * yy;
+        ac[k].y += g[k].x * yy - g[k].y * yx;
       }
     }
   }
-  __syncthreads();
-  window_flush(acc, W, wi.u0, wi.v0, Kx, Ky, Y);
+  if constexpr (SCATTER) {
+    if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
+    __syncthreads();
+    window_flush(acc, W, wi.u0, wi.v0, Kx, Ky, Y);
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -202,78 +278,77 @@ static hipError_t set_lds(K kern, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_gtg(const WorkItem* wi, int nwi, const uint32_t* meta, const uint32_t* voff,
-                      const void* vals, wf_store store, const float2* X, float2* Y, int Kx,
-                      int Ky, int win, hipStream_t s) {
-  if (nwi <= 0) return hipSuccess;
-  const size_t lds = (size_t)win * win * sizeof(float2);
-  hipError_t e;
-  switch (store) {
-    case WF_STORE_F32:
-      if ((e = set_lds(k_gtg<WF_STORE_F32>, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_gtg<WF_STORE_F32>, dim3(nwi), dim3(GNT), lds, s, wi, meta, voff,
-                         vals, X, Y, Kx, Ky, win);
-      break;
-    case WF_STORE_F16:
-      if ((e = set_lds(k_gtg<WF_STORE_F16>, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_gtg<WF_STORE_F16>, dim3(nwi), dim3(GNT), lds, s, wi, meta, voff,
-                         vals, X, Y, Kx, Ky, win);
-      break;
-    default:
-      if ((e = set_lds(k_gtg<WF_STORE_BF16>, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_gtg<WF_STORE_BF16>, dim3(nwi), dim3(GNT), lds, s, wi, meta, voff,
-                         vals, X, Y, Kx, Ky, win);
-      break;
-  }
+template <int STORE, int MK, int MODE>
+static hipError_t launch_one(const WorkItem* wi, int nwi, const uint32_t* meta,
+                             const uint32_t* voff, const int32_t* perm, const void* vals,
+                             const float2* X, float2* Y, float2* vis, int Kx, int Ky, int win,
+                             hipStream_t s) {
+  const size_t lds = MODE == 1 ? 0 : (size_t)win * win * sizeof(float2);
+  hipError_t e = set_lds(k_rows<STORE, MK, MODE>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_rows<STORE, MK, MODE>), dim3(nwi), dim3(GNT), lds, s, wi, meta, voff,
+                     perm, vals, X, Y, vis, Kx, Ky, win);
   return hipGetLastError();
 }
 
-hipError_t launch_degrid(const WorkItem* wi, int nwi, const uint32_t* meta,
+template <int STORE, int MODE>
+static hipError_t launch_cls(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
+                             const uint32_t* voff, const int32_t* perm, const void* vals,
+                             const float2* X, float2* Y, float2* vis, int Kx, int Ky, int win,
+                             hipStream_t s) {
+#define WF_ONE(MK) \
+  launch_one<STORE, MK, MODE>(wi, nwi, meta, voff, perm, vals, X, Y, vis, Kx, Ky, win, s)
+  switch (cls) {
+    case 0: return WF_ONE(2);
+    case 1: return WF_ONE(4);
+    case 2: return WF_ONE(7);
+    case 3: return WF_ONE(12);
+    case 4: return WF_ONE(16);
+    default: return WF_ONE(22);
+  }
+#undef WF_ONE
+}
+
+template <int MODE>
+static hipError_t launch_mode(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
+                              const uint32_t* voff, const int32_t* perm, const void* vals,
+                              wf_store store, const float2* X, float2* Y, float2* vis, int Kx,
+                              int Ky, int win, hipStream_t s) {
+  if (nwi <= 0) return hipSuccess;
+  switch (store) {
+    case WF_STORE_F32:
+      return launch_cls<WF_STORE_F32, MODE>(cls, wi, nwi, meta, voff, perm, vals, X, Y, vis,
+                                            Kx, Ky, win, s);
+    case WF_STORE_F16:
+      return launch_cls<WF_STORE_F16, MODE>(cls, wi, nwi, meta, voff, perm, vals, X, Y, vis,
+                                            Kx, Ky, win, s);
+    default:
+      return launch_cls<WF_STORE_BF16, MODE>(cls, wi, nwi, meta, voff, perm, vals, X, Y, vis,
+                                             Kx, Ky, win, s);
+  }
+}
+
+hipError_t launch_gtg(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
+                      const uint32_t* voff, const void* vals, wf_store store, const float2* X,
+                      float2* Y, int Kx, int Ky, int win, hipStream_t s) {
+  return launch_mode<0>(cls, wi, nwi, meta, voff, nullptr, vals, store, X, Y, nullptr, Kx, Ky,
+                        win, s);
+}
+
+hipError_t launch_degrid(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
                          const uint32_t* voff, const int32_t* perm, const void* vals,
                          wf_store store, const float2* X, float2* vis, int Kx, int Ky,
                          hipStream_t s) {
-  if (nwi <= 0) return hipSuccess;
-  switch (store) {
-    case WF_STORE_F32:
-      hipLaunchKernelGGL(k_degrid<WF_STORE_F32>, dim3(nwi), dim3(GNT), 0, s, wi, meta, voff,
-                         perm, vals, X, vis, Kx, Ky);
-      break;
-    case WF_STORE_F16:
-      hipLaunchKernelGGL(k_degrid<WF_STORE_F16>, dim3(nwi), dim3(GNT), 0, s, wi, meta, voff,
-                         perm, vals, X, vis, Kx, Ky);
-      break;
-    default:
-      hipLaunchKernelGGL(k_degrid<WF_STORE_BF16>, dim3(nwi), dim3(GNT), 0, s, wi, meta, voff,
-                         perm, vals, X, vis, Kx, Ky);
-      break;
-  }
-  return hipGetLastError();
+  return launch_mode<1>(cls, wi, nwi, meta, voff, perm, vals, store, X, nullptr, vis, Kx, Ky,
+                        0, s);
 }
 
-hipError_t launch_grid(const WorkItem* wi, int nwi, const uint32_t* meta, const uint32_t* voff,
-                       const int32_t* perm, const void* vals, wf_store store,
-                       const float2* vis, float2* Y, int Kx, int Ky, int win, hipStream_t s) {
-  if (nwi <= 0) return hipSuccess;
-  const size_t lds = (size_t)win * win * sizeof(float2);
-  hipError_t e;
-  switch (store) {
-    case WF_STORE_F32:
-      if ((e = set_lds(k_grid<WF_STORE_F32>, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_grid<WF_STORE_F32>, dim3(nwi), dim3(GNT), lds, s, wi, meta, voff,
-                         perm, vals, vis, Y, Kx, Ky, win);
-      break;
-    case WF_STORE_F16:
-      if ((e = set_lds(k_grid<WF_STORE_F16>, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_grid<WF_STORE_F16>, dim3(nwi), dim3(GNT), lds, s, wi, meta, voff,
-                         perm, vals, vis, Y, Kx, Ky, win);
-      break;
-    default:
-      if ((e = set_lds(k_grid<WF_STORE_BF16>, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_grid<WF_STORE_BF16>, dim3(nwi), dim3(GNT), lds, s, wi, meta, voff,
-                         perm, vals, vis, Y, Kx, Ky, win);
-      break;
-  }
-  return hipGetLastError();
+hipError_t launch_grid(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
+                       const uint32_t* voff, const int32_t* perm, const void* vals,
+                       wf_store store, const float2* vis, float2* Y, int Kx, int Ky, int win,
+                       hipStream_t s) {
+  return launch_mode<2>(cls, wi, nwi, meta, voff, perm, vals, store, nullptr, Y,
+                        const_cast<float2*>(vis), Kx, Ky, win, s);
 }
 
 }  // namespace wf

@@ -217,18 +217,19 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   std::iota(idx.begin(), idx.end(), 0);
   radix_sort_pairs(keys, idx, 16);
 
-  // work items: runs of one (bin, tile), split for load balance
+  // work items: runs of one (bin, tile, patch class), split for load balance; within a
+  // bin the items are then grouped by patch class (one launch per class)
   const int64_t maxrows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
   const int64_t maxtaps = 1 << 20;
-  std::vector<WorkItem> wis;
+  std::vector<WorkItem> wis0;
+  std::vector<int> wcls;
   std::vector<uint32_t> meta(M), voff(M);
   std::vector<int32_t> row_wi(M);
   ch.bin_row0.assign(ch.P, 0);
   ch.bin_nrows.assign(ch.P, 0);
-  ch.bin_wi0.assign(ch.P, 0);
-  ch.bin_nwi.assign(ch.P, 0);
   int64_t taps_total = 0, taps_in = 0;
   uint64_t cur = ~0ull;
+  int curcls = -1;
   for (int64_t sidx = 0; sidx < M; ++sidx) {
     const uint64_t k = keys[sidx];
     const int bin = (int)(k >> 56);
@@ -236,7 +237,9 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     const int T = (int)((k >> 30) & 63);
     const int lv = (int)((k >> 23) & 127), lu = (int)((k >> 16) & 127);
     const uint64_t grp = k >> 36;
-    if (grp != cur || wis.back().nrows >= maxrows || taps_in + T * T > maxtaps) {
+    const int cls = tap_class(T);
+    if (grp != cur || cls != curcls || wis0.back().nrows >= maxrows ||
+        taps_in + T * T > maxtaps) {
       WorkItem wi{};
       wi.voff = taps_total;
       wi.row0 = (int32_t)sidx;
@@ -244,25 +247,47 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
       wi.u0 = tu * tile - halo;
       wi.v0 = tv * tile - halo;
       wi.bin = bin;
-      if (wis.empty() || wis.back().bin != bin) {
-        ch.bin_wi0[bin] = (int32_t)wis.size();
-        ch.bin_row0[bin] = sidx;
-      }
-      wis.push_back(wi);
+      if (wis0.empty() || wis0.back().bin != bin) ch.bin_row0[bin] = sidx;
+      wis0.push_back(wi);
+      wcls.push_back(cls);
       cur = grp;
+      curcls = cls;
       taps_in = 0;
     }
-    WorkItem& wi = wis.back();
+    WorkItem& wi = wis0.back();
     voff[sidx] = (uint32_t)taps_in;
     const int off = (T - 1) / 2;
     meta[sidx] = pack_meta(lu + halo - off, lv + halo - off, T);
-    row_wi[sidx] = (int32_t)(wis.size() - 1);
+    row_wi[sidx] = (int32_t)(wis0.size() - 1);
     wi.nrows++;
     taps_in += (int64_t)T * T;
     taps_total += (int64_t)T * T;
     ch.bin_nrows[bin]++;
-    ch.bin_nwi[bin] = (int32_t)(wis.size() - ch.bin_wi0[bin]);
   }
+  // group by (bin, class), keeping tile order inside each group
+  std::vector<int32_t> order(wis0.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    if (wis0[x].bin != wis0[y].bin) return wis0[x].bin < wis0[y].bin;
+    return wcls[x] < wcls[y];
+  });
+  std::vector<WorkItem> wis(wis0.size());
+  std::vector<int32_t> newidx(wis0.size());
+  ch.bin_wi0.assign(ch.P, 0);
+  ch.bin_nwi.assign(ch.P, 0);
+  ch.cls_wi0.assign((size_t)ch.P * NCLS, 0);
+  ch.cls_nwi.assign((size_t)ch.P * NCLS, 0);
+  for (size_t i = 0; i < order.size(); ++i) {
+    const WorkItem& w = wis0[order[i]];
+    wis[i] = w;
+    newidx[order[i]] = (int32_t)i;
+    const int b = w.bin, c = wcls[order[i]];
+    if (ch.bin_nwi[b] == 0) ch.bin_wi0[b] = (int32_t)i;
+    ch.bin_nwi[b]++;
+    if (ch.cls_nwi[b * NCLS + c] == 0) ch.cls_wi0[b * NCLS + c] = (int32_t)i;
+    ch.cls_nwi[b * NCLS + c]++;
+  }
+  for (int64_t sidx = 0; sidx < M; ++sidx) row_wi[sidx] = newidx[row_wi[sidx]];
   std::vector<uint64_t>().swap(keys);
   ch.ntaps = taps_total;
   ch.nwork = (int64_t)wis.size();
@@ -379,10 +404,14 @@ wf_status psf_common(wf_op* op, const float* d_img, float* d_out, void* stream, 
       if ((st = layer_forward(op, x, wp, s)) != WF_OK) return st;
       {
         ProfScope ps(&op->prof[0], s);
-        WF_HIP(launch_gtg((const WorkItem*)ch.work.p + ch.bin_wi0[p], ch.bin_nwi[p],
-                          (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p, ch.vals.p,
-                          op->opt.store, (const float2*)op->X.p, (float2*)op->Y.p, op->Kx,
-                          op->Ky, op->win, s));
+        for (int c = 0; c < NCLS; ++c) {
+          const int n = ch.cls_nwi[p * NCLS + c];
+          if (n == 0) continue;
+          WF_HIP(launch_gtg(c, (const WorkItem*)ch.work.p + ch.cls_wi0[p * NCLS + c], n,
+                            (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p, ch.vals.p,
+                            op->opt.store, (const float2*)op->X.p, (float2*)op->Y.p, op->Kx,
+                            op->Ky, op->win, s));
+        }
       }
       const int mode = (re ? 2 : 0) + (first ? 0 : 1);
       if ((st = layer_adjoint(op, out, wp, mode, s)) != WF_OK) return st;
@@ -555,11 +584,15 @@ wf_status wf_forward(wf_op* op, const float* d_img, float* d_vis, void* stream) 
     for (int p = 0; p < ch.P; ++p) {
       if (ch.bin_nrows[p] == 0) continue;
       if ((st = layer_forward(op, d_img + c * npix, ch.centroids[p], s)) != WF_OK) return st;
-      WF_HIP(launch_degrid((const WorkItem*)ch.work.p + ch.bin_wi0[p], ch.bin_nwi[p],
-                           (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
-                           (const int32_t*)ch.perm.p, ch.vals.p, op->opt.store,
-                           (const float2*)op->X.p, (float2*)d_vis + ch.vis_off, op->Kx,
-                           op->Ky, s));
+      for (int c = 0; c < NCLS; ++c) {
+        const int n = ch.cls_nwi[p * NCLS + c];
+        if (n == 0) continue;
+        WF_HIP(launch_degrid(c, (const WorkItem*)ch.work.p + ch.cls_wi0[p * NCLS + c], n,
+                             (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
+                             (const int32_t*)ch.perm.p, ch.vals.p, op->opt.store,
+                             (const float2*)op->X.p, (float2*)d_vis + ch.vis_off, op->Kx,
+                             op->Ky, s));
+      }
     }
   }
   return WF_OK;
@@ -578,11 +611,15 @@ wf_status wf_adjoint(wf_op* op, const float* d_vis, float* d_img, void* stream) 
     bool first = true;
     for (int p = 0; p < ch.P; ++p) {
       if (ch.bin_nrows[p] == 0) continue;
-      WF_HIP(launch_grid((const WorkItem*)ch.work.p + ch.bin_wi0[p], ch.bin_nwi[p],
-                         (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
-                         (const int32_t*)ch.perm.p, ch.vals.p, op->opt.store,
-                         (const float2*)d_vis + ch.vis_off, (float2*)op->Y.p, op->Kx, op->Ky,
-                         op->win, s));
+      for (int c = 0; c < NCLS; ++c) {
+        const int n = ch.cls_nwi[p * NCLS + c];
+        if (n == 0) continue;
+        WF_HIP(launch_grid(c, (const WorkItem*)ch.work.p + ch.cls_wi0[p * NCLS + c], n,
+                           (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
+                           (const int32_t*)ch.perm.p, ch.vals.p, op->opt.store,
+                           (const float2*)d_vis + ch.vis_off, (float2*)op->Y.p, op->Kx,
+                           op->Ky, op->win, s));
+      }
       if ((st = layer_adjoint(op, out, ch.centroids[p], first ? 0 : 1, s)) != WF_OK) return st;
       first = false;
     }

@@ -35,6 +35,14 @@ struct WorkItem {
 };
 static_assert(sizeof(WorkItem) == 32, "WorkItem layout");
 
+// Patch-size classes of the row kernels: class c covers T*T <= 64 * cls_taps(c) taps,
+// i.e. patch sides up to 11, 15, 21, 27, 31, 37.
+constexpr int NCLS = 6;
+__host__ __device__ inline int tap_class(int T) {
+  const int k = (T * T + 63) / 64;
+  return k <= 2 ? 0 : k <= 4 ? 1 : k <= 7 ? 2 : k <= 12 ? 3 : k <= 16 ? 4 : 5;
+}
+
 // Per-row metadata word: window-local patch origin and patch side.
 __host__ __device__ inline uint32_t pack_meta(int lu0, int lv0, int T) {
   return (uint32_t)lu0 | ((uint32_t)lv0 << 8) | ((uint32_t)T << 16);
@@ -67,6 +75,7 @@ struct ChanOp {
   std::vector<double> centroids;
   std::vector<int64_t> bin_row0, bin_nrows;
   std::vector<int32_t> bin_wi0, bin_nwi;
+  std::vector<int32_t> cls_wi0, cls_nwi;   // [bin * NCLS + class]
   int64_t ntaps = 0;
   int64_t nwork = 0;
   DevBuf meta, voff, perm, vals, work;
@@ -116,16 +125,18 @@ hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const f
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
                            int mode, hipStream_t s);
 
-hipError_t launch_gtg(const WorkItem* wi, int nwi, const uint32_t* meta, const uint32_t* voff,
-                      const void* vals, wf_store store, const float2* X, float2* Y, int Kx,
-                      int Ky, int win, hipStream_t s);
-hipError_t launch_degrid(const WorkItem* wi, int nwi, const uint32_t* meta,
+// Row kernels over the work items of one patch-size class `cls`.
+hipError_t launch_gtg(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
+                      const uint32_t* voff, const void* vals, wf_store store, const float2* X,
+                      float2* Y, int Kx, int Ky, int win, hipStream_t s);
+hipError_t launch_degrid(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
                          const uint32_t* voff, const int32_t* perm, const void* vals,
                          wf_store store, const float2* X, float2* vis, int Kx, int Ky,
                          hipStream_t s);
-hipError_t launch_grid(const WorkItem* wi, int nwi, const uint32_t* meta, const uint32_t* voff,
-                       const int32_t* perm, const void* vals, wf_store store,
-                       const float2* vis, float2* Y, int Kx, int Ky, int win, hipStream_t s);
+hipError_t launch_grid(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
+                       const uint32_t* voff, const int32_t* perm, const void* vals,
+                       wf_store store, const float2* vis, float2* Y, int Kx, int Ky, int win,
+                       hipStream_t s);
 hipError_t launch_strip_to_rowmajor(const float2* src, float2* dst, int R, int Q,
                                     hipStream_t s);
 
