@@ -6,6 +6,11 @@
 //                  (and clear Y behind the read, ready for the next gridding)
 //   inverse rows : inverse FFT of the ny rows, crop to nx, (.) conj(Z_p),
 //                  store or accumulate the sum over w-layers (eq. 7)
+// Pruning to the bin's active uv support (the discrete Fourier modes its rows touch, plus
+// a one-tile halo): the forward column pass writes X only inside needed tiles, the inverse
+// column pass reads (and clears) Y only there, and both row passes touch only the column
+// strips that hold needed tiles; everything else is known to be unused or zero.  Null
+// masks mean the full grid.
 // Z_p = grid correction x w-layer: s_i s_j exp(-2 pi i w_p (n-1)) / n with the phase
 // computed in FP64 (n - 1 = -(l^2+m^2)/(1+n) avoids cancellation), reduced to
 // [-1/2, 1/2) cycles in FP64 and only then rounded to FP32 for sincospi.
@@ -29,6 +34,20 @@ __device__ __forceinline__ float2 zvalue(int i, int j, int nx, int ny, double ce
   return make_float2(a * c, a * s);
 }
 
+__device__ __forceinline__ bool bit_set(const uint32_t* __restrict__ m, int i) {
+  return (m[i >> 5] >> (i & 31)) & 1u;
+}
+
+// Geometry of the pruning masks: tile bitmap [Ky/tile][Kx/tile] and strip bitmap
+// [Kx/16], both as packed 32-bit words.
+struct Masks {
+  const uint32_t* strip;  // null: all strips needed
+  const uint32_t* tile;   // null: all tiles needed
+  const int32_t* groups;  // null: column groups 0..n-1
+  int tiles_x;
+  int tsh;                // log2(tile)
+};
+
 template <int N>
 constexpr int row_threads() {
   return N / 16 < 64 ? 64 : (N / 16 > 1024 ? 1024 : N / 16);
@@ -49,7 +68,8 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const float* __restrict__ img,
                                                  const float2* __restrict__ tw,
                                                  const float* __restrict__ sx,
                                                  const float* __restrict__ sy, int nx, int ny,
-                                                 double cell, double wp) {
+                                                 double cell, double wp,
+                                                 const uint32_t* __restrict__ smask) {
   extern __shared__ float2 buf[];
   const int j = blockIdx.x;
   const float syj = sy[j];
@@ -62,7 +82,8 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const float* __restrict__ img,
   }
   __syncthreads();
   fft_lines<N, NT, 1, false>(buf, N, tw);
-  for (int q = threadIdx.x; q < N; q += NT) A[strip_index(j, q, ny)] = buf[q];
+  for (int q = threadIdx.x; q < N; q += NT)
+    if (!smask || bit_set(smask, q >> 4)) A[strip_index(j, q, ny)] = buf[q];
 }
 
 template <int N, int NT>
@@ -71,10 +92,13 @@ __global__ __launch_bounds__(NT) void k_inv_rows(const float2* __restrict__ A,
                                                  const float2* __restrict__ tw,
                                                  const float* __restrict__ sx,
                                                  const float* __restrict__ sy, int nx, int ny,
-                                                 double cell, double wp, int mode) {
+                                                 double cell, double wp, int mode,
+                                                 const uint32_t* __restrict__ smask) {
   extern __shared__ float2 buf[];
   const int j = blockIdx.x;
-  for (int q = threadIdx.x; q < N; q += NT) buf[q] = A[strip_index(j, q, ny)];
+  for (int q = threadIdx.x; q < N; q += NT)
+    buf[q] = (!smask || bit_set(smask, q >> 4)) ? A[strip_index(j, q, ny)]
+                                                : make_float2(0.f, 0.f);
   __syncthreads();
   fft_lines<N, NT, 1, true>(buf, N, tw);
   const float syj = sy[j];
@@ -104,10 +128,12 @@ __global__ __launch_bounds__(NT) void k_inv_rows(const float2* __restrict__ A,
 template <int N, int NT, int CW>
 __global__ __launch_bounds__(NT) void k_fwd_cols(const float2* __restrict__ A,
                                                  float2* __restrict__ X,
-                                                 const float2* __restrict__ tw, int ny) {
+                                                 const float2* __restrict__ tw, int ny,
+                                                 Masks mk) {
   extern __shared__ float2 buf[];
   constexpr int S = N + 1;
-  const int g = xcd_remap(blockIdx.x, gridDim.x);
+  const int gi = xcd_remap(blockIdx.x, gridDim.x);
+  const int g = mk.groups ? mk.groups[gi] : gi;
   const int q0 = g * CW;
   const int strip = q0 >> 4, c0 = q0 & (SW - 1);
   const int nz = N - ny;
@@ -125,24 +151,31 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(const float2* __restrict__ A,
   float2* dst = X + ((int64_t)strip * N) * SW + c0;
   for (int t = threadIdx.x; t < CW * N; t += NT) {
     const int qv = t / CW, c = t - qv * CW;
-    dst[(int64_t)qv * SW + c] = buf[c * S + qv];
+    if (!mk.tile || bit_set(mk.tile, (qv >> mk.tsh) * mk.tiles_x + ((q0 + c) >> mk.tsh)))
+      dst[(int64_t)qv * SW + c] = buf[c * S + qv];
   }
 }
 
 template <int N, int NT, int CW>
 __global__ __launch_bounds__(NT) void k_inv_cols(float2* __restrict__ Y, float2* __restrict__ A,
-                                                 const float2* __restrict__ tw, int ny) {
+                                                 const float2* __restrict__ tw, int ny,
+                                                 Masks mk) {
   extern __shared__ float2 buf[];
   constexpr int S = N + 1;
-  const int g = xcd_remap(blockIdx.x, gridDim.x);
+  const int gi = xcd_remap(blockIdx.x, gridDim.x);
+  const int g = mk.groups ? mk.groups[gi] : gi;
   const int q0 = g * CW;
   const int strip = q0 >> 4, c0 = q0 & (SW - 1);
   float2* src = Y + ((int64_t)strip * N) * SW + c0;
   for (int t = threadIdx.x; t < CW * N; t += NT) {
     const int qv = t / CW, c = t - qv * CW;
     float2* p = src + (int64_t)qv * SW + c;
-    buf[c * S + qv] = *p;
-    *p = make_float2(0.f, 0.f);
+    if (!mk.tile || bit_set(mk.tile, (qv >> mk.tsh) * mk.tiles_x + ((q0 + c) >> mk.tsh))) {
+      buf[c * S + qv] = *p;
+      *p = make_float2(0.f, 0.f);
+    } else {
+      buf[c * S + qv] = make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
   fft_lines<N, NT, CW, true>(buf, S, tw);
@@ -177,7 +210,7 @@ static hipError_t set_lds(K kern, size_t bytes) {
 
 hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const float* sx,
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
-                           hipStream_t s) {
+                           const uint32_t* smask, hipStream_t s) {
   switch (Kx) {
 #define C(N)                                                                              \
   case N: {                                                                               \
@@ -186,7 +219,7 @@ hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const 
     hipError_t e = set_lds(k_fwd_rows<N, NT>, lds);                                       \
     if (e != hipSuccess) return e;                                                        \
     hipLaunchKernelGGL((k_fwd_rows<N, NT>), dim3(ny), dim3(NT), lds, s, img, A, tw, sx,  \
-                       sy, nx, ny, cell, wp);                                             \
+                       sy, nx, ny, cell, wp, smask);                                      \
     return hipGetLastError();                                                             \
   }
     WF_FOR_SIZES(C)
@@ -198,7 +231,7 @@ hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const 
 
 hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const float* sx,
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
-                           int mode, hipStream_t s) {
+                           int mode, const uint32_t* smask, hipStream_t s) {
   switch (Kx) {
 #define C(N)                                                                              \
   case N: {                                                                               \
@@ -207,7 +240,7 @@ hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const f
     hipError_t e = set_lds(k_inv_rows<N, NT>, lds);                                       \
     if (e != hipSuccess) return e;                                                        \
     hipLaunchKernelGGL((k_inv_rows<N, NT>), dim3(ny), dim3(NT), lds, s, A, out, tw, sx,  \
-                       sy, nx, ny, cell, wp, mode);                                       \
+                       sy, nx, ny, cell, wp, mode, smask);                                \
     return hipGetLastError();                                                             \
   }
     WF_FOR_SIZES(C)
@@ -218,7 +251,7 @@ hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const f
 }
 
 hipError_t launch_fwd_cols(const float2* A, float2* X, const float2* tw, int ny, int Kx,
-                           int Ky, hipStream_t s) {
+                           int Ky, const ColPrune* pr, hipStream_t s) {
   switch (Ky) {
 #define C(N)                                                                              \
   case N: {                                                                               \
@@ -228,8 +261,15 @@ hipError_t launch_fwd_cols(const float2* A, float2* X, const float2* tw, int ny,
     const size_t lds = (size_t)CW * (N + 1) * sizeof(float2);                             \
     hipError_t e = set_lds(k_fwd_cols<N, NT, CW>, lds);                                   \
     if (e != hipSuccess) return e;                                                        \
-    hipLaunchKernelGGL((k_fwd_cols<N, NT, CW>), dim3(Kx / CW), dim3(NT), lds, s, A, X,   \
-                       tw, ny);                                                           \
+    Masks mk{nullptr, nullptr, nullptr, 1, 0};                                            \
+    int ng = Kx / CW;                                                                     \
+    if (pr) {                                                                             \
+      mk = Masks{pr->strip, pr->tile, pr->groups, pr->tiles_x, pr->tsh};                  \
+      ng = pr->ngroups;                                                                   \
+    }                                                                                     \
+    if (ng == 0) return hipSuccess;                                                       \
+    hipLaunchKernelGGL((k_fwd_cols<N, NT, CW>), dim3(ng), dim3(NT), lds, s, A, X, tw, ny, \
+                       mk);                                                               \
     return hipGetLastError();                                                             \
   }
     WF_FOR_SIZES(C)
@@ -240,7 +280,7 @@ hipError_t launch_fwd_cols(const float2* A, float2* X, const float2* tw, int ny,
 }
 
 hipError_t launch_inv_cols(float2* Y, float2* A, const float2* tw, int ny, int Kx, int Ky,
-                           hipStream_t s) {
+                           const ColPrune* pr, hipStream_t s) {
   switch (Ky) {
 #define C(N)                                                                              \
   case N: {                                                                               \
@@ -250,8 +290,15 @@ hipError_t launch_inv_cols(float2* Y, float2* A, const float2* tw, int ny, int K
     const size_t lds = (size_t)CW * (N + 1) * sizeof(float2);                             \
     hipError_t e = set_lds(k_inv_cols<N, NT, CW>, lds);                                   \
     if (e != hipSuccess) return e;                                                        \
-    hipLaunchKernelGGL((k_inv_cols<N, NT, CW>), dim3(Kx / CW), dim3(NT), lds, s, Y, A,   \
-                       tw, ny);                                                           \
+    Masks mk{nullptr, nullptr, nullptr, 1, 0};                                            \
+    int ng = Kx / CW;                                                                     \
+    if (pr) {                                                                             \
+      mk = Masks{pr->strip, pr->tile, pr->groups, pr->tiles_x, pr->tsh};                  \
+      ng = pr->ngroups;                                                                   \
+    }                                                                                     \
+    if (ng == 0) return hipSuccess;                                                       \
+    hipLaunchKernelGGL((k_inv_cols<N, NT, CW>), dim3(ng), dim3(NT), lds, s, Y, A, tw, ny, \
+                       mk);                                                               \
     return hipGetLastError();                                                             \
   }
     WF_FOR_SIZES(C)

@@ -231,11 +231,11 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
 #pragma unroll
       for (int k = 0; k < MK; ++k) gn[k] = load_raw<STORE>(vals, vb + min(lane + 64 * k, lastt));
     }
+    // lanes past the patch hold a copy of its last value: their grid values are zero
+    // (gather) and their accumulators are never added into the window (scatter)
     float2 g[MK];
-    const int TTm = Tm * Tm;
 #pragma unroll
-    for (int k = 0; k < MK; ++k)
-      g[k] = (lane + 64 * k < TTm) ? widen<STORE>(graw[k]) : make_float2(0.f, 0.f);
+    for (int k = 0; k < MK; ++k) g[k] = widen<STORE>(graw[k]);
     float yx, yy;
     if constexpr (GATHER) {
       float sx = 0.f, sy = 0.f;

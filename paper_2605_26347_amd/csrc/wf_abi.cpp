@@ -87,6 +87,7 @@ void destroy_op(wf_op* op) {
     dfree(c.perm);
     dfree(c.vals);
     dfree(c.work);
+    dfree(c.prune);
   }
   dfree(op->X);
   dfree(op->Y);
@@ -288,6 +289,75 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     ch.cls_nwi[b * NCLS + c]++;
   }
   for (int64_t sidx = 0; sidx < M; ++sidx) row_wi[sidx] = newidx[row_wi[sidx]];
+
+  // active uv support per bin: tiles holding rows, dilated to cover the LDS windows'
+  // halo, the column strips under them and the column groups of the column passes
+  {
+    const int tx = Kx / tile, ty = Ky / tile;
+    int tsh = 0;
+    while ((1 << tsh) < tile) ++tsh;
+    const int dil = (halo + tile - 1) / tile;
+    const int nstrip = Kx / SW;
+    const int cw = col_width_for(Ky);
+    const int ngroup_all = Kx / cw;
+    const size_t wt = ((size_t)tx * ty + 31) / 32, ws = ((size_t)nstrip + 31) / 32;
+    std::vector<uint32_t> hbuf;
+    ch.pr_strip.assign(ch.P, 0);
+    ch.pr_tile.assign(ch.P, 0);
+    ch.pr_groups.assign(ch.P, 0);
+    ch.pr_ngroups.assign(ch.P, 0);
+    ch.active_tile_frac.assign(ch.P, 0.0);
+    std::vector<uint8_t> act((size_t)tx * ty), need((size_t)tx * ty);
+    for (int p = 0; p < ch.P; ++p) {
+      std::fill(act.begin(), act.end(), 0);
+      std::fill(need.begin(), need.end(), 0);
+      for (int i = 0; i < ch.bin_nwi[p]; ++i) {
+        const WorkItem& w = wis[ch.bin_wi0[p] + i];
+        const int tu = (w.u0 + halo) / tile, tv = (w.v0 + halo) / tile;
+        act[(size_t)tv * tx + tu] = 1;
+      }
+      for (int tv = 0; tv < ty; ++tv)
+        for (int tu = 0; tu < tx; ++tu) {
+          if (!act[(size_t)tv * tx + tu]) continue;
+          for (int dv = -dil; dv <= dil; ++dv)
+            for (int du = -dil; du <= dil; ++du)
+              need[(size_t)(((tv + dv) % ty + ty) % ty) * tx + ((tu + du) % tx + tx) % tx] = 1;
+        }
+      std::vector<uint32_t> tb(wt, 0), sb(ws, 0);
+      int64_t nneed = 0;
+      std::vector<uint8_t> colneed(tx, 0);
+      for (size_t i = 0; i < need.size(); ++i)
+        if (need[i]) {
+          tb[i >> 5] |= 1u << (i & 31);
+          colneed[i % tx] = 1;
+          ++nneed;
+        }
+      ch.active_tile_frac[p] = (double)nneed / (double)need.size();
+      for (int st2 = 0; st2 < nstrip; ++st2) {
+        const int c0 = (st2 * SW) >> tsh, c1 = ((st2 + 1) * SW - 1) >> tsh;
+        bool any = false;
+        for (int c = c0; c <= c1; ++c) any = any || colneed[c];
+        if (any) sb[st2 >> 5] |= 1u << (st2 & 31);
+      }
+      std::vector<uint32_t> gl;
+      for (int g = 0; g < ngroup_all; ++g) {
+        const int st2 = (g * cw) / SW;
+        if ((sb[st2 >> 5] >> (st2 & 31)) & 1u) gl.push_back((uint32_t)g);
+      }
+      ch.pr_strip[p] = hbuf.size() * 4;
+      hbuf.insert(hbuf.end(), sb.begin(), sb.end());
+      ch.pr_tile[p] = hbuf.size() * 4;
+      hbuf.insert(hbuf.end(), tb.begin(), tb.end());
+      ch.pr_groups[p] = hbuf.size() * 4;
+      hbuf.insert(hbuf.end(), gl.begin(), gl.end());
+      ch.pr_ngroups[p] = (int32_t)gl.size();
+    }
+    if ((st = dalloc(ch.prune, sizeof(uint32_t) * std::max<size_t>(hbuf.size(), 1))) != WF_OK)
+      return st;
+    WF_HIP(hipMemcpyAsync(ch.prune.p, hbuf.data(), sizeof(uint32_t) * hbuf.size(),
+                          hipMemcpyHostToDevice, s));
+    WF_HIP(hipStreamSynchronize(s));
+  }
   std::vector<uint64_t>().swap(keys);
   ch.ntaps = taps_total;
   ch.nwork = (int64_t)wis.size();
@@ -352,36 +422,54 @@ wf_status check_op(const wf_op* op) {
   return WF_OK;
 }
 
-// One w-layer's forward half: X_p = F Z_p x.
-wf_status layer_forward(wf_op* op, const float* x, double wp, hipStream_t s) {
+// Pruning masks of (channel, bin); pr = null selects the full grid.
+ColPrune prune_of(const wf_op* op, const ChanOp& ch, int p) {
+  ColPrune pr;
+  const char* b = (const char*)ch.prune.p;
+  pr.strip = (const uint32_t*)(b + ch.pr_strip[p]);
+  pr.tile = (const uint32_t*)(b + ch.pr_tile[p]);
+  pr.groups = (const int32_t*)(b + ch.pr_groups[p]);
+  pr.ngroups = ch.pr_ngroups[p];
+  pr.tiles_x = op->Kx / op->tile;
+  int tsh = 0;
+  while ((1 << tsh) < op->tile) ++tsh;
+  pr.tsh = tsh;
+  return pr;
+}
+
+// One w-layer's forward half: X_p = F Z_p x (only inside the bin's support if pr).
+wf_status layer_forward(wf_op* op, const float* x, double wp, const ColPrune* pr,
+                        hipStream_t s) {
   const int nx = op->shape.nx, ny = op->shape.ny;
   {
     ProfScope ps(&op->prof[1], s);
     WF_HIP(launch_fwd_rows(x, (float2*)op->A.p, (const float2*)op->twx.p,
                            (const float*)op->sx.p, (const float*)op->sy.p, nx, ny, op->Kx,
-                           op->shape.cell_rad, wp, s));
+                           op->shape.cell_rad, wp, pr ? pr->strip : nullptr, s));
   }
   {
     ProfScope ps(&op->prof[2], s);
     WF_HIP(launch_fwd_cols((const float2*)op->A.p, (float2*)op->X.p, (const float2*)op->twy.p,
-                           ny, op->Kx, op->Ky, s));
+                           ny, op->Kx, op->Ky, pr, s));
   }
   return WF_OK;
 }
 
-// One w-layer's adjoint half from the gridded Y: out (+)= Z_p^dag F^dag Y (Y is cleared).
-wf_status layer_adjoint(wf_op* op, void* out, double wp, int mode, hipStream_t s) {
+// One w-layer's adjoint half from the gridded Y: out (+)= Z_p^dag F^dag Y (Y is cleared
+// where it was read; outside the bin's support it is zero already).
+wf_status layer_adjoint(wf_op* op, void* out, double wp, int mode, const ColPrune* pr,
+                        hipStream_t s) {
   const int nx = op->shape.nx, ny = op->shape.ny;
   {
     ProfScope ps(&op->prof[3], s);
     WF_HIP(launch_inv_cols((float2*)op->Y.p, (float2*)op->A.p, (const float2*)op->twy.p, ny,
-                           op->Kx, op->Ky, s));
+                           op->Kx, op->Ky, pr, s));
   }
   {
     ProfScope ps(&op->prof[4], s);
     WF_HIP(launch_inv_rows((const float2*)op->A.p, out, (const float2*)op->twx.p,
                            (const float*)op->sx.p, (const float*)op->sy.p, nx, ny, op->Kx,
-                           op->shape.cell_rad, wp, mode, s));
+                           op->shape.cell_rad, wp, mode, pr ? pr->strip : nullptr, s));
   }
   return WF_OK;
 }
@@ -401,7 +489,8 @@ wf_status psf_common(wf_op* op, const float* d_img, float* d_out, void* stream, 
     for (int p = 0; p < ch.P; ++p) {
       if (ch.bin_nrows[p] == 0) continue;
       const double wp = ch.centroids[p];
-      if ((st = layer_forward(op, x, wp, s)) != WF_OK) return st;
+      const ColPrune pr = prune_of(op, ch, p);
+      if ((st = layer_forward(op, x, wp, &pr, s)) != WF_OK) return st;
       {
         ProfScope ps(&op->prof[0], s);
         for (int c = 0; c < NCLS; ++c) {
@@ -414,7 +503,7 @@ wf_status psf_common(wf_op* op, const float* d_img, float* d_out, void* stream, 
         }
       }
       const int mode = (re ? 2 : 0) + (first ? 0 : 1);
-      if ((st = layer_adjoint(op, out, wp, mode, s)) != WF_OK) return st;
+      if ((st = layer_adjoint(op, out, wp, mode, &pr, s)) != WF_OK) return st;
       first = false;
     }
     if (first) WF_HIP(hipMemsetAsync(out, 0, npix * (re ? 4 : 8), s));
@@ -583,7 +672,9 @@ wf_status wf_forward(wf_op* op, const float* d_img, float* d_vis, void* stream) 
     ChanOp& ch = op->chans[c];
     for (int p = 0; p < ch.P; ++p) {
       if (ch.bin_nrows[p] == 0) continue;
-      if ((st = layer_forward(op, d_img + c * npix, ch.centroids[p], s)) != WF_OK) return st;
+      const ColPrune pr = prune_of(op, ch, p);
+      if ((st = layer_forward(op, d_img + c * npix, ch.centroids[p], &pr, s)) != WF_OK)
+        return st;
       for (int c = 0; c < NCLS; ++c) {
         const int n = ch.cls_nwi[p * NCLS + c];
         if (n == 0) continue;
@@ -620,7 +711,9 @@ wf_status wf_adjoint(wf_op* op, const float* d_vis, float* d_img, void* stream) 
                            (const float2*)d_vis + ch.vis_off, (float2*)op->Y.p, op->Kx,
                            op->Ky, op->win, s));
       }
-      if ((st = layer_adjoint(op, out, ch.centroids[p], first ? 0 : 1, s)) != WF_OK) return st;
+      const ColPrune pr = prune_of(op, ch, p);
+      if ((st = layer_adjoint(op, out, ch.centroids[p], first ? 0 : 1, &pr, s)) != WF_OK)
+        return st;
       first = false;
     }
     if (first) WF_HIP(hipMemsetAsync(out, 0, npix * 8, s));
@@ -734,7 +827,8 @@ wf_status wf_layer_grid(wf_op* op, int32_t chan, int32_t bin, const float* d_img
   WF_HIP(hipSetDevice(op->device));
   hipStream_t s = (hipStream_t)stream;
   const int64_t npix = (int64_t)op->shape.nx * op->shape.ny;
-  if ((st = layer_forward(op, d_img + chan * npix, ch.centroids[bin], s)) != WF_OK) return st;
+  if ((st = layer_forward(op, d_img + chan * npix, ch.centroids[bin], nullptr, s)) != WF_OK)
+    return st;
   WF_HIP(launch_strip_to_rowmajor((const float2*)op->X.p, (float2*)d_grid, op->Ky, op->Kx, s));
   return WF_OK;
 }

@@ -48,6 +48,21 @@ __host__ __device__ inline uint32_t pack_meta(int lu0, int lv0, int T) {
   return (uint32_t)lu0 | ((uint32_t)lv0 << 8) | ((uint32_t)T << 16);
 }
 
+// Active uv support of one bin for the column passes: tiles that hold rows, dilated by
+// one tile (the LDS windows reach into neighbours), the column strips under them, and the
+// column groups (col_width columns each) that cover those strips.
+struct ColPrune {
+  const uint32_t* strip;   // [Kx/16] bits
+  const uint32_t* tile;    // [Ky/tile][Kx/tile] bits
+  const int32_t* groups;   // active column-group indices
+  int ngroups;
+  int tiles_x;
+  int tsh;                 // log2(tile)
+};
+
+// Columns per workgroup of the column passes for a column length of Ky.
+inline int col_width_for(int Ky) { return (16384 / Ky) > 16 ? 16 : (16384 / Ky); }
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -79,6 +94,10 @@ struct ChanOp {
   int64_t ntaps = 0;
   int64_t nwork = 0;
   DevBuf meta, voff, perm, vals, work;
+  DevBuf prune;                            // per bin: strip bits, tile bits, groups
+  std::vector<size_t> pr_strip, pr_tile, pr_groups;  // byte offsets into prune per bin
+  std::vector<int32_t> pr_ngroups;
+  std::vector<double> active_tile_frac;
   wf_plan_info info{};
 };
 
@@ -112,18 +131,19 @@ namespace wf {
 // ------------------------------------------------------------------ kernel launchers
 // (defined in the .hip translation units; all asynchronous on `s`)
 
+// Pruning arguments may be null (full grid).
 hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const float* sx,
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
-                           hipStream_t s);
+                           const uint32_t* smask, hipStream_t s);
 hipError_t launch_fwd_cols(const float2* A, float2* X, const float2* tw, int ny, int Kx,
-                           int Ky, hipStream_t s);
+                           int Ky, const ColPrune* pr, hipStream_t s);
 hipError_t launch_inv_cols(float2* Y, float2* A, const float2* tw, int ny, int Kx, int Ky,
-                           hipStream_t s);
+                           const ColPrune* pr, hipStream_t s);
 // mode 0: out complex, overwrite; 1: complex, accumulate; 2: real part, overwrite;
 // 3: real part, accumulate
 hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const float* sx,
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
-                           int mode, hipStream_t s);
+                           int mode, const uint32_t* smask, hipStream_t s);
 
 // Row kernels over the work items of one patch-size class `cls`.
 hipError_t launch_gtg(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
