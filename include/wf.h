@@ -75,7 +75,7 @@ typedef struct {
   double budget_fraction;  /* share of memory_budget for the sparse matrix, 0.65      */
   uint64_t seed;           /* SplitMix64 state for the subset draw                    */
   int32_t tile;            /* grid tile side of the fused G^dag G kernel (0 = auto)   */
-  int32_t max_rows_per_item; /* work-item split for load balance (0 = auto)           */
+  int32_t max_rows_per_item; /* rows per work item, <= 1024 (0 = auto: 1024)           */
 } wf_options;
 
 /* Fill *opt with the defaults listed above. */

@@ -117,11 +117,14 @@ __device__ __forceinline__ void load_patch_x(const RunGeom& r, int u0, int v0, i
     if (lane + 64 * k >= r.TT) xr[k] = make_float2(0.f, 0.f);
 }
 
-// Add a run's register accumulator into the LDS window.
+// Add a run's register accumulator into the LDS window.  The window is stored as two
+// planes (real parts, then imaginary parts) so that the consecutive cells of a patch row
+// fall in consecutive banks.
 template <int MK>
 __device__ __forceinline__ void scatter_run(const RunGeom& r, int W, int lane,
                                             const float2 (&ac)[MK], float* accf) {
   const float invT = 1.0f / (float)r.T;
+  float* acci = accf + W * W;
 #pragma unroll
   for (int k = 0; k < MK; ++k) {
     const int t = lane + 64 * k;
@@ -129,20 +132,20 @@ __device__ __forceinline__ void scatter_run(const RunGeom& r, int W, int lane,
       int a, b;
       tap_ab(t, r.T, invT, a, b);
       const int li = (r.lv0 + a) * W + (r.lu0 + b);
-      atomicAdd(accf + 2 * li, ac[k].x);
-      atomicAdd(accf + 2 * li + 1, ac[k].y);
+      atomicAdd(accf + li, ac[k].x);
+      atomicAdd(acci + li, ac[k].y);
     }
   }
 }
 
-__device__ __forceinline__ void window_zero(float2* acc, int W) {
-  for (int c = threadIdx.x; c < W * W; c += GNT) acc[c] = make_float2(0.f, 0.f);
+__device__ __forceinline__ void window_zero(float* accf, int W) {
+  for (int c = threadIdx.x; c < 2 * W * W; c += GNT) accf[c] = 0.f;
 }
 
-__device__ __forceinline__ void window_flush(const float2* acc, int W, int u0, int v0, int Kx,
+__device__ __forceinline__ void window_flush(const float* accf, int W, int u0, int v0, int Kx,
                                              int Ky, float2* __restrict__ Y) {
   for (int c = threadIdx.x; c < W * W; c += GNT) {
-    const float2 v = acc[c];
+    const float2 v = make_float2(accf[c], accf[W * W + c]);
     if (v.x != 0.f || v.y != 0.f) {
       const int a = c / W, b = c - a * W;
       const int gu = (u0 + b) & (Kx - 1);
@@ -165,15 +168,16 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
                                               float2* __restrict__ Y,
                                               float2* __restrict__ vis, int Kx, int Ky,
                                               int W) {
-  extern __shared__ float2 acc[];
-  const WorkItem wi = wis[xcd_remap(blockIdx.x, gridDim.x)];
+  extern __shared__ float accf[];
+  // Items are ordered largest first and dealt round-robin over the XCDs by the hardware,
+  // which spreads the dense uv core (many items) evenly and schedules longest first.
+  const WorkItem wi = wis[blockIdx.x];
   constexpr bool GATHER = MODE != 2;
   constexpr bool SCATTER = MODE != 1;
   if constexpr (SCATTER) {
-    window_zero(acc, W);
+    window_zero(accf, W);
     __syncthreads();
   }
-  float* accf = reinterpret_cast<float*>(acc);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int seg = (wi.nrows + GWAVES - 1) / GWAVES;
@@ -186,86 +190,112 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   if (r0 >= r1) {
     if constexpr (SCATTER) {
       __syncthreads();
-      window_flush(acc, W, wi.u0, wi.v0, Kx, Ky, Y);
+      window_flush(accf, W, wi.u0, wi.v0, Kx, Ky, Y);
     }
     return;
   }
-  // Software pipeline: row metadata comes through the scalar cache two rows ahead, value
-  // offsets are the running sum of T^2 inside the item, a new run's grid values are
-  // requested first and the next row's values right after, so that waiting for the
-  // current row leaves the prefetch in flight.
-  const uint32_t* __restrict__ mrow = meta + wi.row0;
-  uint32_t m_cur = mrow[r0];
-  uint32_t m_nxt = (r0 + 1 < r1) ? mrow[r0 + 1] : 0u;
-  int64_t vb = wi.voff + (int64_t)voff[wi.row0 + r0];
-  Raw gn[MK];
-  {
-    const int Tn = (int)((m_cur >> 16) & 0xff);
-    const int lastt = Tn * Tn - 1;
+  // Software pipeline, D rows deep.  The metadata of the wavefront's whole segment (at
+  // most 128 rows: items hold at most 1024 rows) sits in two VGPRs, lane i holding rows
+  // r0 + i and r0 + 64 + i, and is read back with readlane, so the loop never waits on
+  // the LDS/scalar counter that the window atomics use.  Value offsets are the running
+  // sum of T^2 inside the item; the values of row r + D are requested (after a new run's
+  // grid values) before row r is reduced.
+  constexpr int D = MK <= 4 ? 4 : (MK <= 7 ? 2 : 1);
+  const int nseg = r1 - r0;
+  const uint32_t* __restrict__ mrow = meta + wi.row0 + r0;
+  const uint32_t mv0 = mrow[min(lane, nseg - 1)];
+  const uint32_t mv1 = mrow[min(64 + lane, nseg - 1)];
+  auto meta_of = [&](int r) -> uint32_t {
+    const int i = r - r0;
+    return (uint32_t)__builtin_amdgcn_readlane((int)(i < 64 ? mv0 : mv1), i & 63);
+  };
+  Raw buf[D][MK];
+  uint32_t mb[D];
+  int rp = r0;                                        // next row to request
+  int64_t vbp = wi.voff + (int64_t)voff[wi.row0 + r0];  // its value offset
+  uint32_t mp = meta_of(r0);                          // its metadata
 #pragma unroll
-    for (int k = 0; k < MK; ++k) gn[k] = load_raw<STORE>(vals, vb + min(lane + 64 * k, lastt));
-  }
-  for (int r = r0; r < r1; ++r) {
-    const int row = wi.row0 + r;
-    const uint32_t m = m_cur;
-    m_cur = m_nxt;
-    m_nxt = (r + 2 < r1) ? mrow[r + 2] : 0u;
-    Raw graw[MK];
-#pragma unroll
-    for (int k = 0; k < MK; ++k) graw[k] = gn[k];
-    const int Tm = (int)((m >> 16) & 0xff);
-    vb += (int64_t)Tm * Tm;
-    if (m != cur) {
-      if constexpr (SCATTER) {
-        if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
-      }
-      cur = m;
-      rg = decode(m);
-      if constexpr (GATHER) load_patch_x<MK>(rg, wi.u0, wi.v0, Kx, Ky, X, lane, xr);
-#pragma unroll
-      for (int k = 0; k < MK; ++k) ac[k] = make_float2(0.f, 0.f);
-    }
-    if (r + 1 < r1) {  // prefetch the next row (branch-free, clamped in-bounds loads)
-      const int Tn = (int)((m_cur >> 16) & 0xff);
+  for (int d = 0; d < D; ++d) {
+    mb[d] = 0u;
+    if (rp < r1) {
+      const int Tn = (int)((mp >> 16) & 0xff);
       const int lastt = Tn * Tn - 1;
 #pragma unroll
-      for (int k = 0; k < MK; ++k) gn[k] = load_raw<STORE>(vals, vb + min(lane + 64 * k, lastt));
+      for (int k = 0; k < MK; ++k)
+        buf[d][k] = load_raw<STORE>(vals, vbp + min(lane + 64 * k, lastt));
+      mb[d] = mp;
+      vbp += (int64_t)Tn * Tn;
+      ++rp;
+      mp = rp < r1 ? meta_of(rp) : 0u;
     }
-    // lanes past the patch hold a copy of its last value: their grid values are zero
-    // (gather) and their accumulators are never added into the window (scatter)
-    float2 g[MK];
+  }
+  for (int rb = r0; rb < r1; rb += D) {
 #pragma unroll
-    for (int k = 0; k < MK; ++k) g[k] = widen<STORE>(graw[k]);
-    float yx, yy;
-    if constexpr (GATHER) {
-      float sx = 0.f, sy = 0.f;
+    for (int d = 0; d < D; ++d) {
+      const int r = rb + d;
+      if (r >= r1) break;
+      const int row = wi.row0 + r;
+      const uint32_t m = mb[d];
+      Raw graw[MK];
 #pragma unroll
-      for (int k = 0; k < MK; ++k) {
-        sx += g[k].x * xr[k].x - g[k].y * xr[k].y;
-        sy += g[k].x * xr[k].y + g[k].y * xr[k].x;
+      for (int k = 0; k < MK; ++k) graw[k] = buf[d][k];
+      if (m != cur) {
+        if constexpr (SCATTER) {
+          if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
+        }
+        cur = m;
+        rg = decode(m);
+        if constexpr (GATHER) load_patch_x<MK>(rg, wi.u0, wi.v0, Kx, Ky, X, lane, xr);
+#pragma unroll
+        for (int k = 0; k < MK; ++k) ac[k] = make_float2(0.f, 0.f);
       }
-      yx = wave_sum_uniform(sx);
-      yy = wave_sum_uniform(sy);
-      if constexpr (MODE == 1) {
-        if (lane == 0) vis[perm[row]] = make_float2(yx, yy);
-      }
-    } else {
-      const float2 y = vis[perm[row]];
-      yx = y.x;
-      yy = y.y;
-    }
-    if constexpr (SCATTER) {
+      if (rp < r1) {  // request row rp = r + D (branch-free, clamped in-bounds loads)
+        const int Tn = (int)((mp >> 16) & 0xff);
+        const int lastt = Tn * Tn - 1;
 #pragma unroll
-      for (int k = 0; k < MK; ++k) {  // += conj(g) y
-        ac[k].x += g[k].x * yx + g[k].y * yy;
-        ac[k].y += g[k].x * yy - g[k].y * yx;
+        for (int k = 0; k < MK; ++k)
+          buf[d][k] = load_raw<STORE>(vals, vbp + min(lane + 64 * k, lastt));
+        mb[d] = mp;
+        vbp += (int64_t)Tn * Tn;
+        ++rp;
+        mp = rp < r1 ? meta_of(rp) : 0u;
+      }
+      // lanes past the patch hold a copy of its last value: their grid values are zero
+      // (gather) and their accumulators are never added into the window (scatter)
+      float2 g[MK];
+#pragma unroll
+      for (int k = 0; k < MK; ++k) g[k] = widen<STORE>(graw[k]);
+      float yx, yy;
+      if constexpr (GATHER) {
+        float sx = 0.f, sy = 0.f;
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+          sx += g[k].x * xr[k].x - g[k].y * xr[k].y;
+          sy += g[k].x * xr[k].y + g[k].y * xr[k].x;
+        }
+        yx = wave_sum_uniform(sx);
+        yy = wave_sum_uniform(sy);
+        if constexpr (MODE == 1) {
+          if (lane == 0) vis[perm[row]] = make_float2(yx, yy);
+        }
+      } else {
+        const float2 y = vis[perm[row]];
+        yx = y.x;
+        yy = y.y;
+      }
+      if constexpr (SCATTER) {
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {  // += conj(g) y
+          ac[k].x += g[k].x * yx + g[k].y * yy;
+          ac[k].y += g[k].x * yy - g[k].y * yx;
+        }
       }
     }
   }
   if constexpr (SCATTER) {
     if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
     __syncthreads();
-    window_flush(acc, W, wi.u0, wi.v0, Kx, Ky, Y);
+    window_flush(accf, W, wi.u0, wi.v0, Kx, Ky, Y);
   }
 }
 

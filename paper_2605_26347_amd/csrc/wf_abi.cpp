@@ -220,6 +220,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
 
   // work items: runs of one (bin, tile, patch class), split for load balance; within a
   // bin the items are then grouped by patch class (one launch per class)
+  // (the row kernels hold a wavefront's metadata for at most 128 rows in registers)
   const int64_t maxrows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
   const int64_t maxtaps = 1 << 20;
   std::vector<WorkItem> wis0;
@@ -265,12 +266,19 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     taps_total += (int64_t)T * T;
     ch.bin_nrows[bin]++;
   }
-  // group by (bin, class), keeping tile order inside each group
+  // group by (bin, class); inside a group the largest items (most taps) come first so
+  // that the hardware's in-order dispatch schedules longest work first
+  std::vector<int64_t> wtaps(wis0.size());
+  for (size_t i = 0; i < wis0.size(); ++i) {
+    const int64_t end = (i + 1 < wis0.size()) ? wis0[i + 1].voff : taps_total;
+    wtaps[i] = end - wis0[i].voff;
+  }
   std::vector<int32_t> order(wis0.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
     if (wis0[x].bin != wis0[y].bin) return wis0[x].bin < wis0[y].bin;
-    return wcls[x] < wcls[y];
+    if (wcls[x] != wcls[y]) return wcls[x] < wcls[y];
+    return wtaps[x] > wtaps[y];
   });
   std::vector<WorkItem> wis(wis0.size());
   std::vector<int32_t> newidx(wis0.size());
@@ -561,6 +569,8 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
     if (opt.J - 1 + opt.smax > 37)
       return fail(WF_EINVAL, "patch side J - 1 + smax must not exceed 37");
     if (opt.nbins < 0 || opt.nbins > 255) return fail(WF_EINVAL, "nbins must be in [0,255]");
+    if (opt.max_rows_per_item < 0 || opt.max_rows_per_item > 1024)
+      return fail(WF_EINVAL, "max_rows_per_item must be in [0,1024]");
     if (!(opt.beta > 0) || !(opt.alpha > 0) || !(opt.eps_w >= 0) || opt.eps_w >= 1)
       return fail(WF_EINVAL, "bad beta / alpha / eps_w");
     if (!(opt.plan_fraction > 0) || opt.plan_fraction > 1 || !(opt.budget_fraction > 0) ||
