@@ -76,6 +76,8 @@ typedef struct {
   uint64_t seed;           /* SplitMix64 state for the subset draw                    */
   int32_t tile;            /* grid tile side of the fused G^dag G kernel (0 = auto)   */
   int32_t max_rows_per_item; /* rows per work item, <= 1024 (0 = auto: 1024)           */
+  int32_t branches;        /* concurrent branches of an apply, <= 16 (0 = auto: one per
+                              channel up to 4; a single channel runs on one branch)   */
 } wf_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -136,6 +138,8 @@ typedef struct {
   double capped_fraction;   /* rows whose kernel side was capped at smax               */
   double max_dropped_energy;/* largest per-row dropped kernel energy fraction           */
   double build_seconds;     /* wall time of the build of this channel                  */
+  int32_t max_rows_per_item;/* rows per work item of the current split                 */
+  int32_t branch;           /* branch that writes this channel's output                */
 } wf_plan_info;
 
 /* Plan and matrix statistics of channel chan (Sect. 3.4 quantities). */
@@ -165,6 +169,67 @@ wf_status wf_layer_grid(wf_op* op, int32_t chan, int32_t bin, const float* d_img
  * returns the number of launches and their summed duration in ms (synchronising). */
 wf_status wf_profile_enable(wf_op* op, int32_t kernel_id, int32_t enable);
 wf_status wf_profile_read(wf_op* op, int32_t kernel_id, int64_t* launches, double* total_ms);
+
+/* ------------------------------------------------------------------ batched form
+ * The channels of a wideband operator are independent operators (Sect. 2; the paper
+ * runs one worker pool per frequency).  An apply issues its (channel, bin) layers on
+ * `branches` concurrent HIP streams forked from and joined back into the caller's
+ * stream; each branch owns a set of work grids (2 Kx Ky + ny Kx complex FP32 values,
+ * plus an nx ny accumulator when a single channel's bins are split over branches).
+ * Channels are placed on branches largest first (by measured time after wf_autotune,
+ * else by stored values and FFT work).  Results equal the one-branch apply up to the
+ * order of FP32 additions. */
+
+/* Set the number of branches (1..16).  Allocates the extra branches' grids; with one
+ * channel and n > 1 the channel's bins are split over the branches and the partial sums
+ * are added in the caller's stream.  Invalidates graphs captured earlier. */
+wf_status wf_set_branches(wf_op* op, int32_t branches);
+
+typedef enum {
+  WF_APPLY_FORWARD = 0,   /* wf_forward      */
+  WF_APPLY_ADJOINT = 1,   /* wf_adjoint      */
+  WF_APPLY_PSF = 2,       /* wf_psf_apply    */
+  WF_APPLY_PSF_RE = 3     /* wf_psf_apply_re */
+} wf_apply_kind;
+
+typedef struct wf_graph wf_graph;
+
+/* Capture one apply of `kind` with fixed device buffers d_in / d_out (as for the
+ * matching apply call) into an instantiated HIP graph: all channels, bins, branches and
+ * per-channel stamps of the sweep become one graph launch.  hip_stream must be a
+ * created (non-NULL) stream; it is used for the capture only.  The graph refers to the
+ * operator's grids: it must not run concurrently with another apply of the same
+ * handle, and it becomes invalid (wf_graph_launch returns WF_EINVAL) after
+ * wf_set_branches or wf_autotune.  Profiling is off inside the graph. */
+wf_status wf_graph_capture(wf_op* op, wf_apply_kind kind, const float* d_in, float* d_out,
+                           void* hip_stream, wf_graph** out);
+/* Launch a captured apply on hip_stream (any stream of the operator's device). */
+wf_status wf_graph_launch(wf_graph* g, void* hip_stream);
+/* Release a graph; graphs of a handle are destroyed before the handle itself. */
+wf_status wf_graph_destroy(wf_graph* g);
+
+/* Per-channel completion latency.  When enabled, every apply (eager or a graph captured
+ * while enabled) writes the device wall clock at its start and after each channel's
+ * last kernel.  wf_read_latency synchronises the device and writes, for the last apply
+ * that ran, the milliseconds from its start to each channel's completion into host
+ * ms[nchan] (cap >= nchan); channels without rows report their zero fill. */
+wf_status wf_latency_enable(wf_op* op, int32_t enable);
+wf_status wf_read_latency(wf_op* op, double* ms, int32_t cap);
+
+typedef struct {
+  int32_t branches;        /* branch count chosen                                     */
+  int32_t retuned_chans;   /* channels whose work-item size changed                   */
+  double sweep_ms_before;  /* Re{Phi^dag Phi} sweep (all channels) before tuning      */
+  double sweep_ms_after;   /* ... and after                                           */
+} wf_tune_info;
+
+/* Autotuner: by timing Re{Phi^dag Phi} applies on d_img (real FP32 [nchan][ny][nx])
+ * into the caller's scratch d_out (same shape), choose per channel the rows per work
+ * item (256, 512 or 1024: only the work-item split of the stored rows changes, never
+ * their values) and then the branch count (1, 2, 4, and 8 when nchan >= 8).  reps timed
+ * applies per candidate (>= 1).  Synchronous; invalidates graphs captured earlier. */
+wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_stream,
+                      int32_t reps, wf_tune_info* info);
 
 /* Release all device and host memory of the handle (synchronises its device). */
 wf_status wf_destroy(wf_op* op);

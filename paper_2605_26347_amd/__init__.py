@@ -13,11 +13,12 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import WfImageShape, WfOptions, WfPlanInfo, check, STORE, STRATEGY
+from ._lib import (WfImageShape, WfOptions, WfPlanInfo, WfTuneInfo, check, APPLY, STORE,
+                   STRATEGY)
 
 _lib.load()
 
-__all__ = ["Operator", "default_options"]
+__all__ = ["Operator", "Graph", "default_options"]
 
 
 def default_options(**kw) -> WfOptions:
@@ -165,10 +166,65 @@ class Operator:
               "wf_profile_read")
         return n.value, ms.value
 
+    # ------------------------------------------------------------------ batched form
+    def set_branches(self, n):
+        """Run applies on n concurrent branches (streams with their own work grids)."""
+        check(self._lib.wf_set_branches(self._h, int(n)), "wf_set_branches")
+
+    def capture(self, kind, inp, out, stream):
+        """Capture one apply ('forward', 'adjoint', 'psf', 'psf_re') with fixed buffers
+        into a HIP graph; stream must be a created torch.cuda.Stream."""
+        g = ctypes.c_void_p()
+        check(self._lib.wf_graph_capture(self._h, APPLY[kind], ctypes.c_void_p(inp.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()),
+                                         _stream_handle(stream), ctypes.byref(g)),
+              "wf_graph_capture")
+        return Graph(self, g)
+
+    def latency_enable(self, enable=True):
+        check(self._lib.wf_latency_enable(self._h, int(enable)), "wf_latency_enable")
+
+    def read_latency(self):
+        """ms from the start of the last apply to each channel's completion."""
+        out = np.zeros(self.nchan, dtype=np.float64)
+        check(self._lib.wf_read_latency(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                        self.nchan), "wf_read_latency")
+        return out
+
+    def autotune(self, img, out, reps=3, stream=None) -> dict:
+        info = WfTuneInfo()
+        check(self._lib.wf_autotune(self._h, ctypes.c_void_p(img.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream),
+                                    int(reps), ctypes.byref(info)), "wf_autotune")
+        return {k: getattr(info, k) for k, _ in WfTuneInfo._fields_}
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             self._lib.wf_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """An apply captured into a HIP graph (see wf_graph_capture in include/wf.h)."""
+
+    def __init__(self, op, handle):
+        self._op = op          # keeps the operator alive while the graph exists
+        self._lib = op._lib
+        self._g = handle
+
+    def launch(self, stream=None):
+        check(self._lib.wf_graph_launch(self._g, _stream_handle(stream)), "wf_graph_launch")
+
+    def close(self):
+        if getattr(self, "_g", None) and self._g.value:
+            self._lib.wf_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -25,7 +25,8 @@ class WfOptions(ctypes.Structure):
                 ("nbins", ctypes.c_int32), ("strategy", ctypes.c_int32),
                 ("store", ctypes.c_int32), ("plan_fraction", ctypes.c_double),
                 ("budget_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("tile", ctypes.c_int32), ("max_rows_per_item", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("max_rows_per_item", ctypes.c_int32),
+                ("branches", ctypes.c_int32)]
 
 
 class WfPlanInfo(ctypes.Structure):
@@ -37,7 +38,16 @@ class WfPlanInfo(ctypes.Structure):
                 ("nwork", ctypes.c_int64), ("k_estimate", ctypes.c_double),
                 ("mem_g_bytes", ctypes.c_double), ("mem_model_bytes", ctypes.c_double),
                 ("cost_model", ctypes.c_double), ("capped_fraction", ctypes.c_double),
-                ("max_dropped_energy", ctypes.c_double), ("build_seconds", ctypes.c_double)]
+                ("max_dropped_energy", ctypes.c_double), ("build_seconds", ctypes.c_double),
+                ("max_rows_per_item", ctypes.c_int32), ("branch", ctypes.c_int32)]
+
+
+class WfTuneInfo(ctypes.Structure):
+    _fields_ = [("branches", ctypes.c_int32), ("retuned_chans", ctypes.c_int32),
+                ("sweep_ms_before", ctypes.c_double), ("sweep_ms_after", ctypes.c_double)]
+
+
+APPLY = {"forward": 0, "adjoint": 1, "psf": 2, "psf_re": 3}
 
 
 _P = ctypes.c_void_p
@@ -59,6 +69,13 @@ SIGNATURES = {
     "wf_layer_grid": (_I32, [_P, _I32, _I32, _P, _P, _P]),
     "wf_profile_enable": (_I32, [_P, _I32, _I32]),
     "wf_profile_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "wf_set_branches": (_I32, [_P, _I32]),
+    "wf_graph_capture": (_I32, [_P, _I32, _P, _P, _P, ctypes.POINTER(_P)]),
+    "wf_graph_launch": (_I32, [_P, _P]),
+    "wf_graph_destroy": (_I32, [_P]),
+    "wf_latency_enable": (_I32, [_P, _I32]),
+    "wf_read_latency": (_I32, [_P, _P, _I32]),
+    "wf_autotune": (_I32, [_P, _P, _P, _P, _I32, ctypes.POINTER(WfTuneInfo)]),
     "wf_destroy": (_I32, [_P]),
     "wf_last_error": (ctypes.c_char_p, []),
 }

@@ -26,6 +26,7 @@ SOURCES = {
     "k_fft.hip": [],
     "k_grid.hip": [],
     "k_build.hip": ["-ffp-contract=off"],
+    "k_util.hip": [],
     "host_plan.cpp": ["-ffp-contract=off"],
     "wf_abi.cpp": [],
 }

@@ -14,6 +14,9 @@
 // Z_p = grid correction x w-layer: s_i s_j exp(-2 pi i w_p (n-1)) / n with the phase
 // computed in FP64 (n - 1 = -(l^2+m^2)/(1+n) avoids cancellation), reduced to
 // [-1/2, 1/2) cycles in FP64 and only then rounded to FP32 for sincospi.
+#include <mutex>
+#include <vector>
+
 #include "fft_lds.h"
 #include "wf_internal.h"
 
@@ -198,11 +201,28 @@ __global__ void k_strip_to_rowmajor(const float2* __restrict__ src, float2* __re
 
 // ------------------------------------------------------------------ launchers
 
+// Raise a kernel's dynamic LDS limit once per (kernel, device, size), so that launches
+// issued later (also inside a stream capture) make no attribute call.
 template <typename K>
 static hipError_t set_lds(K kern, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  struct Done {
+    const void* k;
+    int dev;
+    size_t bytes;
+  };
+  static std::mutex mu;
+  static std::vector<Done> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const void* k = reinterpret_cast<const void*>(kern);
+  std::lock_guard<std::mutex> lock(mu);
+  for (const Done& d : done)
+    if (d.k == k && d.dev == dev && d.bytes >= bytes) return hipSuccess;
+  e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) done.push_back(Done{k, dev, bytes});
+  return e;
 }
 
 #define WF_FOR_SIZES(X) \

@@ -15,6 +15,14 @@
 
 using namespace wf;
 
+struct wf_graph {
+  wf_op* op;
+  int device;
+  uint64_t gen;      // operator generation at capture
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
 namespace {
 
 thread_local std::string g_err;
@@ -77,6 +85,8 @@ float half_bits_to_float(uint16_t h) {
   return f;
 }
 
+void release_branch(Branch& B, bool own_stream);
+
 void destroy_op(wf_op* op) {
   if (!op) return;
   (void)hipSetDevice(op->device);
@@ -89,9 +99,9 @@ void destroy_op(wf_op* op) {
     dfree(c.work);
     dfree(c.prune);
   }
-  dfree(op->X);
-  dfree(op->Y);
-  dfree(op->A);
+  for (size_t b = 0; b < op->br.size(); ++b) release_branch(op->br[b], b > 0);
+  if (op->fork) (void)hipEventDestroy(op->fork);
+  dfree(op->stamps);
   dfree(op->twx);
   dfree(op->twy);
   dfree(op->sx);
@@ -124,7 +134,7 @@ struct ProfScope {
   hipStream_t s;
   hipEvent_t b = nullptr, e = nullptr;
   ProfScope(Profiler* prof, hipStream_t st) : p(prof), s(st) {
-    if (!p->enabled) return;
+    if (!p || !p->enabled) return;
     if (p->used + 2 > p->ev.size()) {
       for (int i = 0; i < 64; ++i) {
         hipEvent_t ev;
@@ -142,6 +152,72 @@ struct ProfScope {
     if (b) (void)hipEventRecord(e, s);
   }
 };
+
+// Split the channel's row groups into work items of at most maxrows rows and 2^20
+// values (the row kernels keep a wavefront's metadata for at most 128 rows in
+// registers), then order them by (bin, patch class) -- one launch per class -- with the
+// largest items of a launch first so that the hardware's in-order dispatch starts the
+// longest work first.  trow: patch side of each sorted row.  Writes each row's value
+// offset inside its item (voff) and, if row_wi is given, its item index.
+void split_items(ChanOp& ch, const uint8_t* trow, int64_t maxrows, std::vector<WorkItem>& wis,
+                 uint32_t* voff, int32_t* row_wi) {
+  const int64_t maxtaps = 1 << 20;
+  std::vector<WorkItem> w0;
+  std::vector<int> wcls;
+  std::vector<int64_t> wtaps;
+  for (const RowGroup& g : ch.groups) {
+    int64_t abs = g.voff, taps_in = 0;
+    for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) {
+      const int64_t t2 = (int64_t)trow[r] * trow[r];
+      if (r == g.row0 || w0.back().nrows >= maxrows || taps_in + t2 > maxtaps) {
+        WorkItem wi{};
+        wi.voff = abs;
+        wi.row0 = (int32_t)r;
+        wi.nrows = 0;
+        wi.u0 = g.u0;
+        wi.v0 = g.v0;
+        wi.bin = g.bin;
+        w0.push_back(wi);
+        wcls.push_back(g.cls);
+        wtaps.push_back(0);
+        taps_in = 0;
+      }
+      voff[r] = (uint32_t)taps_in;
+      if (row_wi) row_wi[r] = (int32_t)(w0.size() - 1);
+      w0.back().nrows++;
+      wtaps.back() += t2;
+      taps_in += t2;
+      abs += t2;
+    }
+  }
+  std::vector<int32_t> order(w0.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    if (w0[x].bin != w0[y].bin) return w0[x].bin < w0[y].bin;
+    if (wcls[x] != wcls[y]) return wcls[x] < wcls[y];
+    return wtaps[x] > wtaps[y];
+  });
+  wis.assign(w0.size(), WorkItem{});
+  std::vector<int32_t> newidx(w0.size());
+  ch.bin_wi0.assign(ch.P, 0);
+  ch.bin_nwi.assign(ch.P, 0);
+  ch.cls_wi0.assign((size_t)ch.P * NCLS, 0);
+  ch.cls_nwi.assign((size_t)ch.P * NCLS, 0);
+  for (size_t i = 0; i < order.size(); ++i) {
+    const WorkItem& w = w0[order[i]];
+    wis[i] = w;
+    newidx[order[i]] = (int32_t)i;
+    const int b = w.bin, c = wcls[order[i]];
+    if (ch.bin_nwi[b] == 0) ch.bin_wi0[b] = (int32_t)i;
+    ch.bin_nwi[b]++;
+    if (ch.cls_nwi[b * NCLS + c] == 0) ch.cls_wi0[b * NCLS + c] = (int32_t)i;
+    ch.cls_nwi[b * NCLS + c]++;
+  }
+  if (row_wi)
+    for (int64_t r = 0; r < ch.nrows; ++r) row_wi[r] = newidx[row_wi[r]];
+  ch.max_rows = (int32_t)maxrows;
+  ch.nwork = (int64_t)wis.size();
+}
 
 wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double freq,
                         int64_t vis_off, uint64_t budget, hipStream_t s) {
@@ -218,18 +294,16 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   std::iota(idx.begin(), idx.end(), 0);
   radix_sort_pairs(keys, idx, 16);
 
-  // work items: runs of one (bin, tile, patch class), split for load balance; within a
-  // bin the items are then grouped by patch class (one launch per class)
-  // (the row kernels hold a wavefront's metadata for at most 128 rows in registers)
-  const int64_t maxrows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
-  const int64_t maxtaps = 1 << 20;
-  std::vector<WorkItem> wis0;
-  std::vector<int> wcls;
+  // rows grouped in runs of one (bin, tile, patch class); the work items split the
+  // groups (split_items)
   std::vector<uint32_t> meta(M), voff(M);
+  std::vector<uint8_t> trow(M);
   std::vector<int32_t> row_wi(M);
   ch.bin_row0.assign(ch.P, 0);
   ch.bin_nrows.assign(ch.P, 0);
-  int64_t taps_total = 0, taps_in = 0;
+  ch.bin_taps.assign(ch.P, 0);
+  ch.groups.clear();
+  int64_t taps_total = 0;
   uint64_t cur = ~0ull;
   int curcls = -1;
   for (int64_t sidx = 0; sidx < M; ++sidx) {
@@ -240,63 +314,32 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     const int lv = (int)((k >> 23) & 127), lu = (int)((k >> 16) & 127);
     const uint64_t grp = k >> 36;
     const int cls = tap_class(T);
-    if (grp != cur || cls != curcls || wis0.back().nrows >= maxrows ||
-        taps_in + T * T > maxtaps) {
-      WorkItem wi{};
-      wi.voff = taps_total;
-      wi.row0 = (int32_t)sidx;
-      wi.nrows = 0;
-      wi.u0 = tu * tile - halo;
-      wi.v0 = tv * tile - halo;
-      wi.bin = bin;
-      if (wis0.empty() || wis0.back().bin != bin) ch.bin_row0[bin] = sidx;
-      wis0.push_back(wi);
-      wcls.push_back(cls);
+    if (grp != cur || cls != curcls) {
+      RowGroup g{};
+      g.voff = taps_total;
+      g.row0 = (int32_t)sidx;
+      g.nrows = 0;
+      g.u0 = tu * tile - halo;
+      g.v0 = tv * tile - halo;
+      g.bin = bin;
+      g.cls = cls;
+      if (ch.groups.empty() || ch.groups.back().bin != bin) ch.bin_row0[bin] = sidx;
+      ch.groups.push_back(g);
       cur = grp;
       curcls = cls;
-      taps_in = 0;
     }
-    WorkItem& wi = wis0.back();
-    voff[sidx] = (uint32_t)taps_in;
     const int off = (T - 1) / 2;
     meta[sidx] = pack_meta(lu + halo - off, lv + halo - off, T);
-    row_wi[sidx] = (int32_t)(wis0.size() - 1);
-    wi.nrows++;
-    taps_in += (int64_t)T * T;
+    trow[sidx] = (uint8_t)T;
+    ch.groups.back().nrows++;
     taps_total += (int64_t)T * T;
     ch.bin_nrows[bin]++;
+    ch.bin_taps[bin] += (int64_t)T * T;
   }
-  // group by (bin, class); inside a group the largest items (most taps) come first so
-  // that the hardware's in-order dispatch schedules longest work first
-  std::vector<int64_t> wtaps(wis0.size());
-  for (size_t i = 0; i < wis0.size(); ++i) {
-    const int64_t end = (i + 1 < wis0.size()) ? wis0[i + 1].voff : taps_total;
-    wtaps[i] = end - wis0[i].voff;
-  }
-  std::vector<int32_t> order(wis0.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    if (wis0[x].bin != wis0[y].bin) return wis0[x].bin < wis0[y].bin;
-    if (wcls[x] != wcls[y]) return wcls[x] < wcls[y];
-    return wtaps[x] > wtaps[y];
-  });
-  std::vector<WorkItem> wis(wis0.size());
-  std::vector<int32_t> newidx(wis0.size());
-  ch.bin_wi0.assign(ch.P, 0);
-  ch.bin_nwi.assign(ch.P, 0);
-  ch.cls_wi0.assign((size_t)ch.P * NCLS, 0);
-  ch.cls_nwi.assign((size_t)ch.P * NCLS, 0);
-  for (size_t i = 0; i < order.size(); ++i) {
-    const WorkItem& w = wis0[order[i]];
-    wis[i] = w;
-    newidx[order[i]] = (int32_t)i;
-    const int b = w.bin, c = wcls[order[i]];
-    if (ch.bin_nwi[b] == 0) ch.bin_wi0[b] = (int32_t)i;
-    ch.bin_nwi[b]++;
-    if (ch.cls_nwi[b * NCLS + c] == 0) ch.cls_wi0[b * NCLS + c] = (int32_t)i;
-    ch.cls_nwi[b * NCLS + c]++;
-  }
-  for (int64_t sidx = 0; sidx < M; ++sidx) row_wi[sidx] = newidx[row_wi[sidx]];
+  std::vector<WorkItem> wis;
+  ch.max_rows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
+  split_items(ch, trow.data(), ch.max_rows, wis, voff.data(), row_wi.data());
+  std::vector<uint8_t>().swap(trow);
 
   // active uv support per bin: tiles holding rows, dilated to cover the LDS windows'
   // halo, the column strips under them and the column groups of the column passes
@@ -315,18 +358,17 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     ch.pr_groups.assign(ch.P, 0);
     ch.pr_ngroups.assign(ch.P, 0);
     ch.active_tile_frac.assign(ch.P, 0.0);
-    std::vector<uint8_t> act((size_t)tx * ty), need((size_t)tx * ty);
+    std::vector<uint8_t> act((size_t)ch.P * tx * ty, 0), need((size_t)tx * ty);
+    for (const RowGroup& g : ch.groups) {
+      const int tu = (g.u0 + halo) / tile, tv = (g.v0 + halo) / tile;
+      act[((size_t)g.bin * ty + tv) * tx + tu] = 1;
+    }
     for (int p = 0; p < ch.P; ++p) {
-      std::fill(act.begin(), act.end(), 0);
       std::fill(need.begin(), need.end(), 0);
-      for (int i = 0; i < ch.bin_nwi[p]; ++i) {
-        const WorkItem& w = wis[ch.bin_wi0[p] + i];
-        const int tu = (w.u0 + halo) / tile, tv = (w.v0 + halo) / tile;
-        act[(size_t)tv * tx + tu] = 1;
-      }
+      const uint8_t* ap = act.data() + (size_t)p * tx * ty;
       for (int tv = 0; tv < ty; ++tv)
         for (int tu = 0; tu < tx; ++tu) {
-          if (!act[(size_t)tv * tx + tu]) continue;
+          if (!ap[(size_t)tv * tx + tu]) continue;
           for (int dv = -dil; dv <= dil; ++dv)
             for (int du = -dil; du <= dil; ++du)
               need[(size_t)(((tv + dv) % ty + ty) % ty) * tx + ((tu + du) % tx + tx) % tx] = 1;
@@ -422,6 +464,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   in.max_dropped_energy = maxdrop;
   in.build_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  in.max_rows_per_item = ch.max_rows;
   return WF_OK;
 }
 
@@ -445,77 +488,390 @@ ColPrune prune_of(const wf_op* op, const ChanOp& ch, int p) {
   return pr;
 }
 
+// Work grids and stream of one branch for the current call.
+struct Lane {
+  float2* X;
+  float2* Y;
+  float2* A;
+  float* acc;
+  hipStream_t s;
+};
+
+Lane lane_of(wf_op* op, int b, hipStream_t caller) {
+  Branch& B = op->br[b];
+  return Lane{(float2*)B.X.p, (float2*)B.Y.p, (float2*)B.A.p, (float*)B.acc.p,
+              b == 0 ? caller : B.s};
+}
+
+Profiler* prof_of(wf_op* op, int k) { return op->capturing ? nullptr : &op->prof[k]; }
+
 // One w-layer's forward half: X_p = F Z_p x (only inside the bin's support if pr).
-wf_status layer_forward(wf_op* op, const float* x, double wp, const ColPrune* pr,
-                        hipStream_t s) {
+wf_status layer_forward(wf_op* op, const Lane& L, const float* x, double wp,
+                        const ColPrune* pr) {
   const int nx = op->shape.nx, ny = op->shape.ny;
   {
-    ProfScope ps(&op->prof[1], s);
-    WF_HIP(launch_fwd_rows(x, (float2*)op->A.p, (const float2*)op->twx.p,
-                           (const float*)op->sx.p, (const float*)op->sy.p, nx, ny, op->Kx,
-                           op->shape.cell_rad, wp, pr ? pr->strip : nullptr, s));
+    ProfScope ps(prof_of(op, 1), L.s);
+    WF_HIP(launch_fwd_rows(x, L.A, (const float2*)op->twx.p, (const float*)op->sx.p,
+                           (const float*)op->sy.p, nx, ny, op->Kx, op->shape.cell_rad, wp,
+                           pr ? pr->strip : nullptr, L.s));
   }
   {
-    ProfScope ps(&op->prof[2], s);
-    WF_HIP(launch_fwd_cols((const float2*)op->A.p, (float2*)op->X.p, (const float2*)op->twy.p,
-                           ny, op->Kx, op->Ky, pr, s));
+    ProfScope ps(prof_of(op, 2), L.s);
+    WF_HIP(launch_fwd_cols(L.A, L.X, (const float2*)op->twy.p, ny, op->Kx, op->Ky, pr, L.s));
   }
   return WF_OK;
 }
 
 // One w-layer's adjoint half from the gridded Y: out (+)= Z_p^dag F^dag Y (Y is cleared
 // where it was read; outside the bin's support it is zero already).
-wf_status layer_adjoint(wf_op* op, void* out, double wp, int mode, const ColPrune* pr,
-                        hipStream_t s) {
+wf_status layer_adjoint(wf_op* op, const Lane& L, void* out, double wp, int mode,
+                        const ColPrune* pr) {
   const int nx = op->shape.nx, ny = op->shape.ny;
   {
-    ProfScope ps(&op->prof[3], s);
-    WF_HIP(launch_inv_cols((float2*)op->Y.p, (float2*)op->A.p, (const float2*)op->twy.p, ny,
-                           op->Kx, op->Ky, pr, s));
+    ProfScope ps(prof_of(op, 3), L.s);
+    WF_HIP(launch_inv_cols(L.Y, L.A, (const float2*)op->twy.p, ny, op->Kx, op->Ky, pr, L.s));
   }
   {
-    ProfScope ps(&op->prof[4], s);
-    WF_HIP(launch_inv_rows((const float2*)op->A.p, out, (const float2*)op->twx.p,
-                           (const float*)op->sx.p, (const float*)op->sy.p, nx, ny, op->Kx,
-                           op->shape.cell_rad, wp, mode, pr ? pr->strip : nullptr, s));
+    ProfScope ps(prof_of(op, 4), L.s);
+    WF_HIP(launch_inv_rows(L.A, out, (const float2*)op->twx.p, (const float*)op->sx.p,
+                           (const float*)op->sy.p, nx, ny, op->Kx, op->shape.cell_rad, wp,
+                           mode, pr ? pr->strip : nullptr, L.s));
   }
   return WF_OK;
 }
 
-wf_status psf_common(wf_op* op, const float* d_img, float* d_out, void* stream, bool re) {
-  wf_status st = check_op(op);
-  if (st != WF_OK) return st;
-  if (!d_img || !d_out) return fail(WF_EINVAL, "null image pointer");
-  WF_HIP(hipSetDevice(op->device));
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t npix = (int64_t)op->shape.nx * op->shape.ny;
-  for (size_t c = 0; c < op->chans.size(); ++c) {
-    ChanOp& ch = op->chans[c];
-    const float* x = d_img + c * npix;
-    void* out = re ? (void*)(d_out + c * npix) : (void*)(d_out + 2 * c * npix);
+bool valid_kind(int kind) { return kind >= WF_APPLY_FORWARD && kind <= WF_APPLY_PSF_RE; }
+
+int64_t npix_of(const wf_op* op) { return (int64_t)op->shape.nx * op->shape.ny; }
+
+// Floats of one channel's image output of an apply (not used by the forward apply).
+int64_t out_floats(const wf_op* op, int kind) {
+  return npix_of(op) * (kind == WF_APPLY_PSF_RE ? 1 : 2);
+}
+
+// Channel c's part of the caller's input and output buffers.
+const float* chan_in(const wf_op* op, int kind, const float* in, int c) {
+  return kind == WF_APPLY_ADJOINT ? in + 2 * op->chans[c].vis_off : in + c * npix_of(op);
+}
+float* chan_out(const wf_op* op, int kind, float* out, int c) {
+  if (kind == WF_APPLY_FORWARD) return out + 2 * op->chans[c].vis_off;
+  return out + c * out_floats(op, kind);
+}
+
+// Bin p of one channel: that w-layer's share of the apply.  first: the layer opens the
+// channel's image sum in out (overwrite) instead of adding to it.
+wf_status bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
+                    const float* in, float* out, bool first) {
+  wf_status st;
+  const ColPrune pr = prune_of(op, ch, p);
+  const double wp = ch.centroids[p];
+  const WorkItem* wk = (const WorkItem*)ch.work.p;
+  if (kind == WF_APPLY_FORWARD) {
+    if ((st = layer_forward(op, L, in, wp, &pr)) != WF_OK) return st;
+    for (int c = 0; c < NCLS; ++c) {
+      const int n = ch.cls_nwi[p * NCLS + c];
+      if (n == 0) continue;
+      WF_HIP(launch_degrid(c, wk + ch.cls_wi0[p * NCLS + c], n, (const uint32_t*)ch.meta.p,
+                           (const uint32_t*)ch.voff.p, (const int32_t*)ch.perm.p, ch.vals.p,
+                           op->opt.store, L.X, (float2*)out, op->Kx, op->Ky, L.s));
+    }
+    return WF_OK;
+  }
+  if (kind == WF_APPLY_ADJOINT) {
+    for (int c = 0; c < NCLS; ++c) {
+      const int n = ch.cls_nwi[p * NCLS + c];
+      if (n == 0) continue;
+      WF_HIP(launch_grid(c, wk + ch.cls_wi0[p * NCLS + c], n, (const uint32_t*)ch.meta.p,
+                         (const uint32_t*)ch.voff.p, (const int32_t*)ch.perm.p, ch.vals.p,
+                         op->opt.store, (const float2*)in, L.Y, op->Kx, op->Ky, op->win, L.s));
+    }
+    return layer_adjoint(op, L, out, wp, first ? 0 : 1, &pr);
+  }
+  if ((st = layer_forward(op, L, in, wp, &pr)) != WF_OK) return st;
+  {
+    ProfScope ps(prof_of(op, 0), L.s);
+    for (int c = 0; c < NCLS; ++c) {
+      const int n = ch.cls_nwi[p * NCLS + c];
+      if (n == 0) continue;
+      WF_HIP(launch_gtg(c, wk + ch.cls_wi0[p * NCLS + c], n, (const uint32_t*)ch.meta.p,
+                        (const uint32_t*)ch.voff.p, ch.vals.p, op->opt.store, L.X, L.Y,
+                        op->Kx, op->Ky, op->win, L.s));
+    }
+  }
+  const int mode = (kind == WF_APPLY_PSF_RE ? 2 : 0) + (first ? 0 : 1);
+  return layer_adjoint(op, L, out, wp, mode, &pr);
+}
+
+// All non-empty bins of channel c on one lane, written directly to the channel's output.
+wf_status run_channel(wf_op* op, int kind, int c, const Lane& L, const float* in, float* out) {
+  const ChanOp& ch = op->chans[c];
+  const float* ci = chan_in(op, kind, in, c);
+  float* co = chan_out(op, kind, out, c);
+  bool first = true;
+  wf_status st;
+  for (int p = 0; p < ch.P; ++p) {
+    if (ch.bin_nrows[p] == 0) continue;
+    if ((st = bin_apply(op, kind, L, ch, p, ci, co, first)) != WF_OK) return st;
+    first = false;
+  }
+  if (first && kind != WF_APPLY_FORWARD)
+    WF_HIP(launch_fill_zero(co, out_floats(op, kind), L.s));
+  return WF_OK;
+}
+
+// A whole apply: fork the branches off the caller's stream, issue every segment, join,
+// add the partial sums of split channels, and stamp each channel's completion.
+wf_status run_apply(wf_op* op, int kind, const float* in, float* out, hipStream_t s) {
+  wf_status st;
+  const int nchan = (int)op->chans.size();
+  unsigned long long* stamps = op->stamping ? (unsigned long long*)op->stamps.p : nullptr;
+  if (stamps) WF_HIP(launch_stamp(stamps + nchan, s));
+  const int nb = op->nbranch;
+  if (nb > 1) {
+    WF_HIP(hipEventRecord(op->fork, s));
+    for (int b = 1; b < nb; ++b) WF_HIP(hipStreamWaitEvent(op->br[b].s, op->fork, 0));
+  }
+  std::vector<int> nseg(nchan, 0);
+  for (const Segment& g : op->segs) nseg[g.chan]++;
+  for (const Segment& g : op->segs) {
+    const Lane L = lane_of(op, g.branch, s);
+    const ChanOp& ch = op->chans[g.chan];
+    const float* ci = chan_in(op, kind, in, g.chan);
+    // forward: every bin writes its own rows, so all segments write in place
+    float* co = (g.direct || kind == WF_APPLY_FORWARD) ? chan_out(op, kind, out, g.chan) : L.acc;
     bool first = true;
-    for (int p = 0; p < ch.P; ++p) {
-      if (ch.bin_nrows[p] == 0) continue;
-      const double wp = ch.centroids[p];
-      const ColPrune pr = prune_of(op, ch, p);
-      if ((st = layer_forward(op, x, wp, &pr, s)) != WF_OK) return st;
-      {
-        ProfScope ps(&op->prof[0], s);
-        for (int c = 0; c < NCLS; ++c) {
-          const int n = ch.cls_nwi[p * NCLS + c];
-          if (n == 0) continue;
-          WF_HIP(launch_gtg(c, (const WorkItem*)ch.work.p + ch.cls_wi0[p * NCLS + c], n,
-                            (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p, ch.vals.p,
-                            op->opt.store, (const float2*)op->X.p, (float2*)op->Y.p, op->Kx,
-                            op->Ky, op->win, s));
-        }
-      }
-      const int mode = (re ? 2 : 0) + (first ? 0 : 1);
-      if ((st = layer_adjoint(op, out, wp, mode, &pr, s)) != WF_OK) return st;
+    for (int p : g.bins) {
+      if ((st = bin_apply(op, kind, L, ch, p, ci, co, first)) != WF_OK) return st;
       first = false;
     }
-    if (first) WF_HIP(hipMemsetAsync(out, 0, npix * (re ? 4 : 8), s));
+    if (stamps && nseg[g.chan] == 1) WF_HIP(launch_stamp(stamps + g.chan, L.s));
   }
+  for (int c = 0; c < nchan; ++c) {
+    if (nseg[c] != 0) continue;
+    if (kind != WF_APPLY_FORWARD)
+      WF_HIP(launch_fill_zero(chan_out(op, kind, out, c), out_floats(op, kind), s));
+    if (stamps) WF_HIP(launch_stamp(stamps + c, s));
+  }
+  if (nb > 1)
+    for (int b = 1; b < nb; ++b) {
+      WF_HIP(hipEventRecord(op->br[b].done, op->br[b].s));
+      WF_HIP(hipStreamWaitEvent(s, op->br[b].done, 0));
+    }
+  if (kind != WF_APPLY_FORWARD)
+    for (const Segment& g : op->segs)
+      if (!g.direct)
+        WF_HIP(launch_add_into(chan_out(op, kind, out, g.chan),
+                               (const float*)op->br[g.branch].acc.p, out_floats(op, kind), s));
+  if (stamps)
+    for (int c = 0; c < nchan; ++c)
+      if (nseg[c] > 1) WF_HIP(launch_stamp(stamps + c, s));
+  return WF_OK;
+}
+
+wf_status apply_entry(wf_op* op, int kind, const float* in, float* out, void* stream) {
+  wf_status st = check_op(op);
+  if (st != WF_OK) return st;
+  if (!in || !out) return fail(WF_EINVAL, "null pointer");
+  WF_HIP(hipSetDevice(op->device));
+  return run_apply(op, kind, in, out, (hipStream_t)stream);
+}
+
+// Rough device cost of one bin (bytes moved): stored values plus the FFT passes over
+// the bin's active support.
+double bin_cost(const wf_op* op, const ChanOp& ch, int p) {
+  const double bv = op->opt.store == WF_STORE_F32 ? 8.0 : 4.0;
+  const double grid = 8.0 * op->Kx * op->Ky;
+  return bv * (double)ch.bin_taps[p] + grid * (0.5 + 3.0 * ch.active_tile_frac[p]);
+}
+
+// Place the (channel, bin) layers on branches: channels largest first onto the least
+// loaded branch; a single channel splits its bins the same way.  Segments are issued
+// round-robin over the branches so that every branch starts at once.
+void assign_segments(wf_op* op) {
+  const int nchan = (int)op->chans.size();
+  const int req = std::max(1, (int)op->opt.branches);
+  op->segs.clear();
+  for (auto& ch : op->chans) ch.info.branch = 0;
+  if (nchan == 1 && req > 1) {
+    const ChanOp& ch = op->chans[0];
+    std::vector<int> bins;
+    for (int p = 0; p < ch.P; ++p)
+      if (ch.bin_nrows[p] > 0) bins.push_back(p);
+    std::stable_sort(bins.begin(), bins.end(),
+                     [&](int a, int b) { return bin_cost(op, ch, a) > bin_cost(op, ch, b); });
+    const int nb = std::max(1, std::min<int>(req, (int)bins.size()));
+    std::vector<double> load(nb, 0.0);
+    std::vector<std::vector<int>> own(nb);
+    for (int p : bins) {
+      const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      own[b].push_back(p);
+      load[b] += bin_cost(op, ch, p);
+    }
+    for (int b = 0; b < nb; ++b) {
+      if (own[b].empty()) continue;
+      std::sort(own[b].begin(), own[b].end());
+      Segment g;
+      g.chan = 0;
+      g.branch = b;
+      g.direct = (b == 0);
+      g.bins = own[b];
+      op->segs.push_back(g);
+    }
+    op->nbranch = nb;
+    return;
+  }
+  bool measured = true;
+  std::vector<int> chans;
+  for (int c = 0; c < nchan; ++c)
+    if (op->chans[c].nrows > 0) {
+      chans.push_back(c);
+      measured = measured && op->chans[c].measured_ms > 0;
+    }
+  std::vector<double> cost(nchan, 0.0);
+  for (int c : chans) {
+    const ChanOp& ch = op->chans[c];
+    if (measured) {
+      cost[c] = ch.measured_ms;
+    } else {
+      for (int p = 0; p < ch.P; ++p)
+        if (ch.bin_nrows[p] > 0) cost[c] += bin_cost(op, ch, p);
+    }
+  }
+  std::stable_sort(chans.begin(), chans.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  const int nb = std::max(1, std::min<int>(req, (int)chans.size()));
+  std::vector<double> load(nb, 0.0);
+  std::vector<std::vector<int>> own(nb);
+  for (int c : chans) {
+    const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    own[b].push_back(c);
+    load[b] += cost[c];
+  }
+  size_t depth = 0;
+  for (auto& o : own) depth = std::max(depth, o.size());
+  for (size_t k = 0; k < depth; ++k)
+    for (int b = 0; b < nb; ++b) {
+      if (k >= own[b].size()) continue;
+      const int c = own[b][k];
+      const ChanOp& ch = op->chans[c];
+      Segment g;
+      g.chan = c;
+      g.branch = b;
+      g.direct = true;
+      for (int p = 0; p < ch.P; ++p)
+        if (ch.bin_nrows[p] > 0) g.bins.push_back(p);
+      op->segs.push_back(g);
+      op->chans[c].info.branch = b;
+    }
+  op->nbranch = nb;
+}
+
+void release_branch(Branch& B, bool own_stream) {
+  dfree(B.X);
+  dfree(B.Y);
+  dfree(B.A);
+  dfree(B.acc);
+  if (own_stream && B.s) (void)hipStreamDestroy(B.s);
+  if (B.done) (void)hipEventDestroy(B.done);
+  B.s = nullptr;
+  B.done = nullptr;
+}
+
+// Allocate the grids (and streams) of branches [0, op->nbranch) and the accumulators the
+// segments need; release branches beyond.  The caller has synchronised the device.
+wf_status ensure_branches(wf_op* op) {
+  const int nb = op->nbranch;
+  const size_t grid = sizeof(float2) * (size_t)op->Kx * op->Ky;
+  const size_t arow = sizeof(float2) * (size_t)op->shape.ny * op->Kx;
+  for (size_t b = nb; b < op->br.size(); ++b) release_branch(op->br[b], b > 0);
+  if ((int)op->br.size() > nb) op->br.resize(nb);
+  if ((int)op->br.size() < nb) op->br.resize(nb);
+  std::vector<bool> need_acc(nb, false);
+  for (const Segment& g : op->segs)
+    if (!g.direct) need_acc[g.branch] = true;
+  wf_status st;
+  for (int b = 0; b < nb; ++b) {
+    Branch& B = op->br[b];
+    if (b > 0 && !B.s) WF_HIP(hipStreamCreateWithFlags(&B.s, hipStreamNonBlocking));
+    if (b > 0 && !B.done) WF_HIP(hipEventCreateWithFlags(&B.done, hipEventDisableTiming));
+    if (!B.X.p) {
+      if ((st = dalloc(B.X, grid)) != WF_OK) return st;
+      if ((st = dalloc(B.Y, grid)) != WF_OK) return st;
+      if ((st = dalloc(B.A, arow)) != WF_OK) return st;
+      WF_HIP(hipMemset(B.Y.p, 0, grid));
+    }
+    if (need_acc[b] && !B.acc.p) {
+      if ((st = dalloc(B.acc, sizeof(float2) * (size_t)npix_of(op))) != WF_OK) return st;
+    } else if (!need_acc[b] && B.acc.p) {
+      dfree(B.acc);
+    }
+  }
+  if (nb > 1 && !op->fork) WF_HIP(hipEventCreateWithFlags(&op->fork, hipEventDisableTiming));
+  WF_HIP(hipDeviceSynchronize());
+  return WF_OK;
+}
+
+wf_status set_branches(wf_op* op, int n) {
+  WF_HIP(hipDeviceSynchronize());
+  op->opt.branches = n;
+  assign_segments(op);
+  op->generation++;
+  return ensure_branches(op);
+}
+
+// Re-split channel c's stored rows into work items of at most maxrows rows.  Only the
+// item table and the rows' offsets inside their items change; the values stay put.
+wf_status retune_channel(wf_op* op, int c, int32_t maxrows) {
+  ChanOp& ch = op->chans[c];
+  if (ch.nrows == 0 || ch.max_rows == maxrows) return WF_OK;
+  const int64_t M = ch.nrows;
+  WF_HIP(hipDeviceSynchronize());
+  std::vector<uint32_t> meta(M), voff(M);
+  WF_HIP(hipMemcpy(meta.data(), ch.meta.p, sizeof(uint32_t) * M, hipMemcpyDeviceToHost));
+  std::vector<uint8_t> trow(M);
+  for (int64_t r = 0; r < M; ++r) trow[r] = (uint8_t)((meta[r] >> 16) & 0xff);
+  std::vector<uint32_t>().swap(meta);
+  std::vector<WorkItem> wis;
+  split_items(ch, trow.data(), maxrows, wis, voff.data(), nullptr);
+  if (ch.work.bytes < sizeof(WorkItem) * wis.size()) {
+    dfree(ch.work);
+    wf_status st = dalloc(ch.work, sizeof(WorkItem) * wis.size());
+    if (st != WF_OK) return st;
+  }
+  WF_HIP(hipMemcpy(ch.voff.p, voff.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice));
+  WF_HIP(hipMemcpy(ch.work.p, wis.data(), sizeof(WorkItem) * wis.size(),
+                   hipMemcpyHostToDevice));
+  ch.info.nwork = ch.nwork;
+  ch.info.max_rows_per_item = ch.max_rows;
+  op->generation++;
+  return WF_OK;
+}
+
+// Mean duration in ms of `reps` runs of fn on stream s, after one untimed run.
+template <class F>
+wf_status time_runs(hipStream_t s, int reps, F&& fn, double* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  WF_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(WF_EHIP, "hipEventCreate failed");
+  }
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  wf_status st = fn();
+  if (st != WF_OK) return st;
+  WF_HIP(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; ++i)
+    if ((st = fn()) != WF_OK) return st;
+  WF_HIP(hipEventRecord(e1, s));
+  WF_HIP(hipEventSynchronize(e1));
+  float t = 0;
+  WF_HIP(hipEventElapsedTime(&t, e0, e1));
+  *ms = (double)t / reps;
   return WF_OK;
 }
 
@@ -540,6 +896,7 @@ void wf_default_options(wf_options* o) {
   o->seed = 0;
   o->tile = 0;
   o->max_rows_per_item = 0;
+  o->branches = 0;
 }
 
 const char* wf_last_error(void) { return g_err.c_str(); }
@@ -571,6 +928,8 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
     if (opt.nbins < 0 || opt.nbins > 255) return fail(WF_EINVAL, "nbins must be in [0,255]");
     if (opt.max_rows_per_item < 0 || opt.max_rows_per_item > 1024)
       return fail(WF_EINVAL, "max_rows_per_item must be in [0,1024]");
+    if (opt.branches < 0 || opt.branches > 16)
+      return fail(WF_EINVAL, "branches must be in [0,16]");
     if (!(opt.beta > 0) || !(opt.alpha > 0) || !(opt.eps_w >= 0) || opt.eps_w >= 1)
       return fail(WF_EINVAL, "bad beta / alpha / eps_w");
     if (!(opt.plan_fraction > 0) || opt.plan_fraction > 1 || !(opt.budget_fraction > 0) ||
@@ -635,14 +994,16 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
       sy[j] = (float)(1.0 / kb_phihat((double)(j - ny / 2) / Ky, opt.J, opt.beta));
     auto twx = twiddles(Kx), twy = twiddles(Ky);
     wf_status st;
-    if ((st = dalloc(op->X, sizeof(float2) * (size_t)Kx * Ky)) != WF_OK) return st;
-    if ((st = dalloc(op->Y, sizeof(float2) * (size_t)Kx * Ky)) != WF_OK) return st;
-    if ((st = dalloc(op->A, sizeof(float2) * (size_t)ny * Kx)) != WF_OK) return st;
+    op->br.resize(1);
+    Branch& B0 = op->br[0];
+    if ((st = dalloc(B0.X, sizeof(float2) * (size_t)Kx * Ky)) != WF_OK) return st;
+    if ((st = dalloc(B0.Y, sizeof(float2) * (size_t)Kx * Ky)) != WF_OK) return st;
+    if ((st = dalloc(B0.A, sizeof(float2) * (size_t)ny * Kx)) != WF_OK) return st;
     if ((st = dalloc(op->twx, sizeof(float2) * Kx)) != WF_OK) return st;
     if ((st = dalloc(op->twy, sizeof(float2) * Ky)) != WF_OK) return st;
     if ((st = dalloc(op->sx, sizeof(float) * nx)) != WF_OK) return st;
     if ((st = dalloc(op->sy, sizeof(float) * ny)) != WF_OK) return st;
-    WF_HIP(hipMemsetAsync(op->Y.p, 0, op->Y.bytes, s));
+    WF_HIP(hipMemsetAsync(B0.Y.p, 0, B0.Y.bytes, s));
     WF_HIP(hipMemcpyAsync(op->twx.p, twx.data(), sizeof(float2) * Kx, hipMemcpyHostToDevice, s));
     WF_HIP(hipMemcpyAsync(op->twy.p, twy.data(), sizeof(float2) * Ky, hipMemcpyHostToDevice, s));
     WF_HIP(hipMemcpyAsync(op->sx.p, sx.data(), sizeof(float) * nx, hipMemcpyHostToDevice, s));
@@ -661,6 +1022,10 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
     }
     for (auto& ch : op->chans) ch.info.nchan = nchan;
     WF_HIP(hipStreamSynchronize(s));
+    if ((st = set_branches(op, opt.branches > 0 ? opt.branches
+                                                : (nchan > 1 ? std::min(nchan, 4) : 1))) !=
+        WF_OK)
+      return st;
     *out = op;
     guard.op = nullptr;
     return WF_OK;
@@ -672,71 +1037,19 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
 }
 
 wf_status wf_forward(wf_op* op, const float* d_img, float* d_vis, void* stream) {
-  wf_status st = check_op(op);
-  if (st != WF_OK) return st;
-  if (!d_img || !d_vis) return fail(WF_EINVAL, "null pointer");
-  WF_HIP(hipSetDevice(op->device));
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t npix = (int64_t)op->shape.nx * op->shape.ny;
-  for (size_t c = 0; c < op->chans.size(); ++c) {
-    ChanOp& ch = op->chans[c];
-    for (int p = 0; p < ch.P; ++p) {
-      if (ch.bin_nrows[p] == 0) continue;
-      const ColPrune pr = prune_of(op, ch, p);
-      if ((st = layer_forward(op, d_img + c * npix, ch.centroids[p], &pr, s)) != WF_OK)
-        return st;
-      for (int c = 0; c < NCLS; ++c) {
-        const int n = ch.cls_nwi[p * NCLS + c];
-        if (n == 0) continue;
-        WF_HIP(launch_degrid(c, (const WorkItem*)ch.work.p + ch.cls_wi0[p * NCLS + c], n,
-                             (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
-                             (const int32_t*)ch.perm.p, ch.vals.p, op->opt.store,
-                             (const float2*)op->X.p, (float2*)d_vis + ch.vis_off, op->Kx,
-                             op->Ky, s));
-      }
-    }
-  }
-  return WF_OK;
+  return apply_entry(op, WF_APPLY_FORWARD, d_img, d_vis, stream);
 }
 
 wf_status wf_adjoint(wf_op* op, const float* d_vis, float* d_img, void* stream) {
-  wf_status st = check_op(op);
-  if (st != WF_OK) return st;
-  if (!d_img || !d_vis) return fail(WF_EINVAL, "null pointer");
-  WF_HIP(hipSetDevice(op->device));
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t npix = (int64_t)op->shape.nx * op->shape.ny;
-  for (size_t c = 0; c < op->chans.size(); ++c) {
-    ChanOp& ch = op->chans[c];
-    void* out = (void*)(d_img + 2 * c * npix);
-    bool first = true;
-    for (int p = 0; p < ch.P; ++p) {
-      if (ch.bin_nrows[p] == 0) continue;
-      for (int c = 0; c < NCLS; ++c) {
-        const int n = ch.cls_nwi[p * NCLS + c];
-        if (n == 0) continue;
-        WF_HIP(launch_grid(c, (const WorkItem*)ch.work.p + ch.cls_wi0[p * NCLS + c], n,
-                           (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
-                           (const int32_t*)ch.perm.p, ch.vals.p, op->opt.store,
-                           (const float2*)d_vis + ch.vis_off, (float2*)op->Y.p, op->Kx,
-                           op->Ky, op->win, s));
-      }
-      const ColPrune pr = prune_of(op, ch, p);
-      if ((st = layer_adjoint(op, out, ch.centroids[p], first ? 0 : 1, &pr, s)) != WF_OK)
-        return st;
-      first = false;
-    }
-    if (first) WF_HIP(hipMemsetAsync(out, 0, npix * 8, s));
-  }
-  return WF_OK;
+  return apply_entry(op, WF_APPLY_ADJOINT, d_vis, d_img, stream);
 }
 
 wf_status wf_psf_apply(wf_op* op, const float* d_img, float* d_out, void* stream) {
-  return psf_common(op, d_img, d_out, stream, false);
+  return apply_entry(op, WF_APPLY_PSF, d_img, d_out, stream);
 }
 
 wf_status wf_psf_apply_re(wf_op* op, const float* d_img, float* d_out, void* stream) {
-  return psf_common(op, d_img, d_out, stream, true);
+  return apply_entry(op, WF_APPLY_PSF_RE, d_img, d_out, stream);
 }
 
 wf_status wf_get_plan(const wf_op* op, int32_t chan, wf_plan_info* out) {
@@ -837,9 +1150,10 @@ wf_status wf_layer_grid(wf_op* op, int32_t chan, int32_t bin, const float* d_img
   WF_HIP(hipSetDevice(op->device));
   hipStream_t s = (hipStream_t)stream;
   const int64_t npix = (int64_t)op->shape.nx * op->shape.ny;
-  if ((st = layer_forward(op, d_img + chan * npix, ch.centroids[bin], nullptr, s)) != WF_OK)
+  const Lane L = lane_of(op, 0, s);
+  if ((st = layer_forward(op, L, d_img + chan * npix, ch.centroids[bin], nullptr)) != WF_OK)
     return st;
-  WF_HIP(launch_strip_to_rowmajor((const float2*)op->X.p, (float2*)d_grid, op->Ky, op->Kx, s));
+  WF_HIP(launch_strip_to_rowmajor(L.X, (float2*)d_grid, op->Ky, op->Kx, s));
   return WF_OK;
 }
 
@@ -872,6 +1186,179 @@ wf_status wf_profile_read(wf_op* op, int32_t kernel_id, int64_t* launches, doubl
   if (launches) *launches = p.launches;
   if (total_ms) *total_ms = p.total_ms;
   return WF_OK;
+}
+
+wf_status wf_set_branches(wf_op* op, int32_t branches) {
+  wf_status st = check_op(op);
+  if (st != WF_OK) return st;
+  if (branches < 1 || branches > 16) return fail(WF_EINVAL, "branches must be in [1,16]");
+  WF_HIP(hipSetDevice(op->device));
+  return set_branches(op, branches);
+}
+
+wf_status wf_graph_capture(wf_op* op, wf_apply_kind kind, const float* d_in, float* d_out,
+                           void* hip_stream, wf_graph** out) {
+  wf_status st = check_op(op);
+  if (st != WF_OK) return st;
+  if (!out) return fail(WF_EINVAL, "out is null");
+  *out = nullptr;
+  if (!valid_kind(kind)) return fail(WF_EINVAL, "bad apply kind");
+  if (!d_in || !d_out) return fail(WF_EINVAL, "null pointer");
+  if (!hip_stream) return fail(WF_EINVAL, "graph capture needs a created (non-NULL) stream");
+  WF_HIP(hipSetDevice(op->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  WF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  op->capturing = true;
+  st = run_apply(op, kind, d_in, d_out, s);
+  op->capturing = false;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != WF_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(WF_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(WF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+  }
+  wf_graph* r = new (std::nothrow) wf_graph{op, op->device, op->generation, g, x};
+  if (!r) {
+    (void)hipGraphExecDestroy(x);
+    (void)hipGraphDestroy(g);
+    return fail(WF_ENOMEM, "host allocation failed");
+  }
+  *out = r;
+  return WF_OK;
+}
+
+wf_status wf_graph_launch(wf_graph* g, void* hip_stream) {
+  if (!g || !g->op) return fail(WF_EINVAL, "null graph");
+  if (g->gen != g->op->generation)
+    return fail(WF_EINVAL, "the operator's work items or branches changed since the capture");
+  WF_HIP(hipSetDevice(g->op->device));
+  WF_HIP(hipGraphLaunch(g->exec, (hipStream_t)hip_stream));
+  return WF_OK;
+}
+
+wf_status wf_graph_destroy(wf_graph* g) {
+  if (!g) return fail(WF_EINVAL, "null graph");
+  (void)hipSetDevice(g->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return WF_OK;
+}
+
+wf_status wf_latency_enable(wf_op* op, int32_t enable) {
+  wf_status st = check_op(op);
+  if (st != WF_OK) return st;
+  WF_HIP(hipSetDevice(op->device));
+  if (enable && !op->stamps.p) {
+    const size_t bytes = sizeof(unsigned long long) * (op->chans.size() + 1);
+    if ((st = dalloc(op->stamps, bytes)) != WF_OK) return st;
+    WF_HIP(hipMemset(op->stamps.p, 0, bytes));
+    WF_HIP(hipDeviceSynchronize());
+  }
+  // the stamp buffer stays allocated: graphs captured while enabled keep writing it
+  op->stamping = enable != 0;
+  return WF_OK;
+}
+
+wf_status wf_read_latency(wf_op* op, double* ms, int32_t cap) {
+  try {
+    wf_status st = check_op(op);
+    if (st != WF_OK) return st;
+    const int nchan = (int)op->chans.size();
+    if (!ms || cap < nchan) return fail(WF_EINVAL, "capacity too small");
+    if (!op->stamps.p) return fail(WF_EINVAL, "latency stamps are not enabled");
+    WF_HIP(hipSetDevice(op->device));
+    WF_HIP(hipDeviceSynchronize());
+    std::vector<unsigned long long> t(nchan + 1);
+    WF_HIP(hipMemcpy(t.data(), op->stamps.p, sizeof(unsigned long long) * (nchan + 1),
+                     hipMemcpyDeviceToHost));
+    int khz = 0;
+    WF_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, op->device));
+    if (khz <= 0) return fail(WF_EHIP, "device wall-clock rate unavailable");
+    for (int c = 0; c < nchan; ++c)
+      ms[c] = (double)((long long)(t[c] - t[nchan])) / (double)khz;
+    return WF_OK;
+  } catch (const std::exception& e) {
+    return fail(WF_ENOMEM, e.what());
+  }
+}
+
+wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_stream,
+                      int32_t reps, wf_tune_info* info) {
+  try {
+    wf_status st = check_op(op);
+    if (st != WF_OK) return st;
+    if (!d_img || !d_out || reps < 1) return fail(WF_EINVAL, "bad autotune arguments");
+    WF_HIP(hipSetDevice(op->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int kind = WF_APPLY_PSF_RE;
+    auto sweep = [&]() { return run_apply(op, kind, d_img, d_out, s); };
+    double before = 0;
+    if ((st = time_runs(s, reps, sweep, &before)) != WF_OK) return st;
+    int retuned = 0;
+    const int32_t cand_rows[3] = {256, 512, 1024};
+    for (int c = 0; c < (int)op->chans.size(); ++c) {
+      ChanOp& ch = op->chans[c];
+      if (ch.nrows == 0) continue;
+      const int32_t orig = ch.max_rows;
+      int32_t best = orig;
+      double best_ms = 1e300;
+      for (int32_t mr : cand_rows) {
+        if ((st = retune_channel(op, c, mr)) != WF_OK) return st;
+        const Lane L = lane_of(op, 0, s);
+        double t = 0;
+        st = time_runs(s, reps, [&]() { return run_channel(op, kind, c, L, d_img, d_out); }, &t);
+        if (st != WF_OK) return st;
+        if (t < best_ms) {
+          best_ms = t;
+          best = mr;
+        }
+      }
+      if ((st = retune_channel(op, c, best)) != WF_OK) return st;
+      ch.measured_ms = best_ms;
+      if (best != orig) ++retuned;
+    }
+    const int nchan = (int)op->chans.size();
+    std::vector<int> cands = {1, 2, 4};
+    if (nchan == 1) cands = {1, 2, 3, 4};
+    if (nchan >= 8) cands.push_back(8);
+    int best_nb = 1;
+    double best_ms = 1e300;
+    for (int nb : cands) {
+      if (nchan > 1 && nb > nchan) continue;
+      if ((st = set_branches(op, nb)) != WF_OK) return st;
+      double t = 0;
+      if ((st = time_runs(s, reps, sweep, &t)) != WF_OK) return st;
+      if (t < best_ms) {
+        best_ms = t;
+        best_nb = nb;
+      }
+    }
+    if ((st = set_branches(op, best_nb)) != WF_OK) return st;
+    double after = 0;
+    if ((st = time_runs(s, reps, sweep, &after)) != WF_OK) return st;
+    if (info) {
+      info->branches = op->nbranch;
+      info->retuned_chans = retuned;
+      info->sweep_ms_before = before;
+      info->sweep_ms_after = after;
+    }
+    return WF_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(WF_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(WF_EINVAL, e.what());
+  }
 }
 
 wf_status wf_destroy(wf_op* op) {

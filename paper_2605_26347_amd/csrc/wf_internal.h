@@ -82,6 +82,15 @@ struct KernelParams {
   int o;              // oversampling
 };
 
+// A run of consecutive sorted rows of one (bin, tile, patch class); work items are
+// pieces of one group.
+struct RowGroup {
+  int64_t voff;   // index (complex units) of the group's first value
+  int32_t row0, nrows;
+  int32_t u0, v0; // LDS window origin of the tile
+  int32_t bin, cls;
+};
+
 struct ChanOp {
   double freq = 0, scale = 0;
   int64_t vis_off = 0;   // offset of this channel's rows in the caller's vis vector
@@ -91,6 +100,10 @@ struct ChanOp {
   std::vector<int64_t> bin_row0, bin_nrows;
   std::vector<int32_t> bin_wi0, bin_nwi;
   std::vector<int32_t> cls_wi0, cls_nwi;   // [bin * NCLS + class]
+  std::vector<int64_t> bin_taps;           // stored values per bin
+  std::vector<RowGroup> groups;            // in sorted-row order
+  int32_t max_rows = 1024;                 // rows per work item of the current split
+  double measured_ms = 0;                  // last timed apply of this channel (0 = none)
   int64_t ntaps = 0;
   int64_t nwork = 0;
   DevBuf meta, voff, perm, vals, work;
@@ -111,6 +124,25 @@ struct Profiler {
 
 constexpr int NPROF = 5;
 
+// One concurrent branch of an apply: its own stream and work grids (branch 0 runs on the
+// caller's stream and owns the operator's first set of grids).  acc receives the partial
+// image sum of a channel whose bins are split over several branches.
+struct Branch {
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+  DevBuf X, Y, A, acc;
+};
+
+// Work of one branch for one channel: a list of its non-empty bins.  A direct segment
+// writes the channel's output itself; the others accumulate into their branch's acc,
+// added into the output after the join.
+struct Segment {
+  int chan = 0;
+  int branch = 0;
+  bool direct = true;
+  std::vector<int> bins;
+};
+
 }  // namespace wf
 
 struct wf_op {
@@ -122,8 +154,16 @@ struct wf_op {
   wf::KernelParams kp;
   std::vector<wf::ChanOp> chans;
   int64_t total_rows = 0;
-  wf::DevBuf X, Y, A, twx, twy, sx, sy;
+  wf::DevBuf twx, twy, sx, sy;
   wf::Profiler prof[wf::NPROF];
+  std::vector<wf::Branch> br;        // br[0]: the operator's own grids
+  int nbranch = 1;                   // branches the segments use
+  std::vector<wf::Segment> segs;     // issue order of the applies
+  hipEvent_t fork = nullptr;
+  wf::DevBuf stamps;                 // [nchan + 1] wall-clock stamps, when enabled
+  bool stamping = false;
+  bool capturing = false;
+  uint64_t generation = 0;           // bumped when work items or branches change
 };
 
 namespace wf {
@@ -157,6 +197,9 @@ hipError_t launch_grid(int cls, const WorkItem* wi, int nwi, const uint32_t* met
                        const uint32_t* voff, const int32_t* perm, const void* vals,
                        wf_store store, const float2* vis, float2* Y, int Kx, int Ky, int win,
                        hipStream_t s);
+hipError_t launch_fill_zero(void* p, int64_t nfloats, hipStream_t s);
+hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
+hipError_t launch_add_into(float* out, const float* in, int64_t nfloats, hipStream_t s);
 hipError_t launch_strip_to_rowmajor(const float2* src, float2* dst, int R, int Q,
                                     hipStream_t s);
 

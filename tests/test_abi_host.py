@@ -33,6 +33,7 @@ def test_default_options():
     assert (o.J, o.oversample, o.smax, o.nbins, o.store) == (7, 2, 31, 0, 0)
     assert abs(o.beta - 2.34 * 7) < 1e-12 and o.eps_w == 1e-6
     assert o.plan_fraction == 0.01 and o.budget_fraction == 0.65
+    assert o.branches == 0 and o.max_rows_per_item == 0
 
 
 def _build(uvw, freqs, nx=64, ny=64, cell=1e-4, chan_rows=None, **kw):
@@ -64,6 +65,7 @@ UVW = np.random.default_rng(0).normal(0, 100, (50, 3))
     (dict(nbins=300), "nbins"),
     (dict(oversample=3), "oversample"),
     (dict(tile=48), "tile"),
+    (dict(branches=17), "branches"),
 ])
 def test_invalid_arguments(kw, frag):
     st, msg, h = _build(UVW, [1e9], **kw)
@@ -86,3 +88,16 @@ def test_null_handle_calls():
     assert lib.wf_psf_apply(None, None, None, None) == _lib.WF_EINVAL
     assert lib.wf_destroy(None) == _lib.WF_EINVAL
     assert b"null" in lib.wf_last_error()
+
+
+def test_null_handle_batched_calls():
+    lib = _lib.load()
+    g = ctypes.c_void_p()
+    assert lib.wf_set_branches(None, 2) == _lib.WF_EINVAL
+    assert lib.wf_graph_capture(None, 3, None, None, None, ctypes.byref(g)) == _lib.WF_EINVAL
+    assert not g.value
+    assert lib.wf_graph_launch(None, None) == _lib.WF_EINVAL
+    assert lib.wf_graph_destroy(None) == _lib.WF_EINVAL
+    assert lib.wf_latency_enable(None, 1) == _lib.WF_EINVAL
+    assert lib.wf_read_latency(None, None, 0) == _lib.WF_EINVAL
+    assert lib.wf_autotune(None, None, None, None, 1, None) == _lib.WF_EINVAL
