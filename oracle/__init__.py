@@ -23,6 +23,9 @@ of the widefield radio-interferometric measurement model"):
                     FP64, matrix-free over row chunks.
 * ``planner``    -- WSClean bin bound (eq. 5), memory model (eq. 9, GPU byte form),
                     cost model (eq. 10) and the decision tree (Sect. 3.4, Fig. 2).
+* ``mlp``        -- (not in the paper) FP64 forward, backward and Adam step of the
+                    network that predicts residual-w kernels, its input definition and
+                    its training targets (thresholded exact kernels).
 
 Pins (tests/test_oracle_*.py): brute-force direct sum, adjointness to 1e-12,
 Hermitian positive semi-definiteness, w-stacking exactness on quantised w,
