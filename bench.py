@@ -47,9 +47,14 @@ def parse():
     ap.add_argument("--forms", default="f16,f32")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", default="precision", choices=["precision", "batched"],
+    ap.add_argument("--workload", default="precision",
+                    choices=["precision", "batched", "learned"],
                     help="precision: one channel 4096^2 / 50M rows (default); batched: "
-                         "16 channels 2048^2 / 48M rows, autotuned, one graph per sweep")
+                         "16 channels 2048^2 / 48M rows, autotuned, one graph per sweep; "
+                         "learned: G of 20M rows on 4096^2 / 16 bins built with the "
+                         "residual-kernel network vs the exact construction")
+    ap.add_argument("--train-examples", type=int, default=1_000_000)
+    ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--store", default="f16", help="value storage of the batched form")
     return ap.parse_args()
 
@@ -265,6 +270,86 @@ def bench_batched(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def bench_learned(args, torch):
+    """Learned form: the residual-kernel network trained on 1M exact kernels (residual w
+    of the 64-antenna array binned at 16 bins, fields of 1-4 degrees), then G of 20M rows
+    on a 4096^2 / 3 degree image with 16 bins built with the network (exact fallback where
+    its predicted error exceeds 1e-3 or the kernel side exceeds 15) and without it."""
+    import wfsynth as ws
+    from paper_2605_26347_amd import Network, Operator
+    t0 = time.time()
+    obs = ws.learned_form()
+    M = obs.uvw_m.shape[0]
+    log(f"inputs: {M} rows, {obs.nx}^2, {time.time() - t0:.1f} s")
+    mk = dict(memory_budget=args.budget, nbins=16, store="f32")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    op_e = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad, **mk)
+    torch.cuda.synchronize()
+    t_exact = time.time() - t0
+    pe = op_e.plan(0)
+    cents = op_e.centroids(0)
+    w = obs.uvw_m[:, 2] * (obs.freqs_hz[0] / 299792458.0)
+    wp = w - cents[np.searchsorted(0.5 * (cents[1:] + cents[:-1]), w, side="left")]
+    w_, L_, fu_, fv_ = ws.kernel_examples(wp, args.train_examples)
+    dev = [torch.from_numpy(a).to("cuda:0") for a in (w_, L_, fu_, fv_)]
+    t0 = time.time()
+    x, nk = Network.inputs(*dev)
+    t = Network.targets(dev[0], dev[1])
+    keep = (nk <= 15).nonzero().squeeze(1)
+    x, t = x[keep].contiguous(), t[keep].contiguous()
+    torch.cuda.synchronize()
+    t_targets = time.time() - t0
+    net = Network(seed=5)
+    t0 = time.time()
+    hist = net.train(x, t, batch=4096, epochs=args.epochs, lr0=2e-3, lr_end=1e-6, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    log(f"training: {x.shape[0]} kernels (of {args.train_examples}) in {t_train:.1f} s "
+        f"(targets {t_targets:.2f} s); kernel loss {hist[0, 0]:.2e} -> {hist[-1, 0]:.2e}")
+    # held-out accuracy of the network itself
+    hv = ws.kernel_examples(wp, 100_000, seed=99)
+    hd = [torch.from_numpy(a).to("cuda:0") for a in hv]
+    xv, nkv = Network.inputs(*hd)
+    tv = Network.targets(hd[0], hd[1])
+    kv = (nkv <= 15).nonzero().squeeze(1)
+    pv = net.infer(xv[kv].contiguous(), bf16=2)
+    ev = ((pv[:, :450] - tv[kv]).norm(dim=1) / tv[kv].norm(dim=1)).cpu().numpy()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    op_s = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad, surrogate=net,
+                    surrogate_tol=1e-3, **mk)
+    torch.cuda.synchronize()
+    t_sur = time.time() - t0
+    ps = op_s.plan(0)
+    xs = torch.from_numpy(obs.sky.astype(np.float32)[None]).to("cuda:0")
+    ref = op_e.psf_apply(xs)
+    got = op_s.psf_apply(xs)
+    err = float((got - ref).norm() / ref.norm())
+    log(f"build: exact {t_exact:.2f} s (channel {pe['build_seconds']:.2f} s), network "
+        f"{t_sur:.2f} s (channel {ps['build_seconds']:.2f} s); network rows "
+        f"{ps['surrogate_fraction']:.3f}; Phi^dag Phi rel vs exact {err:.2e}")
+    line = {
+        "metric": "G build time, 4096² / 20M vis / 16 bins: residual-kernel network + exact "
+                  "fallback vs exact",
+        "value": ps["build_seconds"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * ps["build_seconds"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"G of {M} visibilities, {obs.nx}^2 image, 3 deg field, "
+                               f"16 w-bins, FP32 values", "nvis": M, "nbins": 16},
+        "build_s": {"exact": pe["build_seconds"], "network": ps["build_seconds"],
+                    "exact_wall": t_exact, "network_wall": t_sur},
+        "network_rows": ps["surrogate_fraction"],
+        "fallback_fraction": 1.0 - ps["surrogate_fraction"],
+        "psf_rel_vs_exact": err,
+        "train": {"examples": int(x.shape[0]), "epochs": args.epochs, "seconds": t_train,
+                  "kernel_loss_first": float(hist[0, 0]), "kernel_loss_last": float(hist[-1, 0])},
+        "heldout_rel_err": {"p50": float(np.median(ev)), "p90": float(np.percentile(ev, 90)),
+                            "p99": float(np.percentile(ev, 99))},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -275,6 +360,9 @@ def main():
     import wfsynth as ws
     if args.workload == "batched":
         bench_batched(args, torch)
+        return
+    if args.workload == "learned":
+        bench_learned(args, torch)
         return
     t0 = time.time()
     obs = ws.precision_form(n=args.n, nvis=args.nvis, fov_deg=args.fov)

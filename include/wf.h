@@ -40,6 +40,7 @@ extern "C" {
 #endif
 
 typedef struct wf_op wf_op;
+typedef struct wf_mlp wf_mlp;
 
 typedef enum {
   WF_OK = 0,
@@ -78,6 +79,11 @@ typedef struct {
   int32_t max_rows_per_item; /* rows per work item, <= 1024 (0 = auto: 1024)           */
   int32_t branches;        /* concurrent branches of an apply, <= 16 (0 = auto: one per
                               channel up to 4; a single channel runs on one branch)   */
+  const wf_mlp* surrogate; /* NULL: exact residual kernels.  Otherwise rows whose
+                              kernel the network predicts with log10 error at most
+                              log10(surrogate_tol) use the prediction (square fields;
+                              the network must outlive the build call only)          */
+  double surrogate_tol;    /* predicted relative L2 error bound, default 1e-3          */
 } wf_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -140,6 +146,7 @@ typedef struct {
   double build_seconds;     /* wall time of the build of this channel                  */
   int32_t max_rows_per_item;/* rows per work item of the current split                 */
   int32_t branch;           /* branch that writes this channel's output                */
+  double surrogate_fraction;/* rows whose residual kernel came from the network        */
 } wf_plan_info;
 
 /* Plan and matrix statistics of channel chan (Sect. 3.4 quantities). */
@@ -230,6 +237,71 @@ typedef struct {
  * applies per candidate (>= 1).  Synchronous; invalidates graphs captured earlier. */
 wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_stream,
                       int32_t reps, wf_tune_info* info);
+
+/* ------------------------------------------------------------------ learned kernels
+ * Not in the paper.  A multilayer perceptron predicts the thresholded residual-w kernel
+ * of Sect. 3.1 (the w-projection kernel built from the tapered chirp, Fig. 1) so that
+ * the build of G can skip the exact construction where the network is accurate; the
+ * exact construction is the fallback and the judge.
+ *  Inputs (WF_MLP_IN per row, FP32): w_proj (o L)^2 / 4, L / (4 degrees in radians),
+ *    the row's u and v offsets from its nearest grid cell (cells, [-1/2, 1/2)), n_k / 15
+ *    with n_k the uncapped kernel side of the bandwidth rule; L = nx cell (square field).
+ *  Outputs (WF_MLP_OUT per row, FP32): the kernel centred in a 15 x 15 window,
+ *    row-major over (s_v, s_u), (re, im) per tap, then the predicted log10 of the
+ *    relative L2 error of those 450 outputs.
+ *  Network: 5 -> 4 hidden layers of 256 with exact GELU -> 451, trained in FP32 (Adam)
+ *    by the library's matrix-core kernels; inference in BF16 with FP32 accumulation
+ *    (first layer in FP32).  Flat parameters: per layer W [in][out] row-major, then b.
+ *  Loss of a batch of B rows: (1/B) sum [ |p - t|^2 over the 450 kernel outputs +
+ *    (e - log10(max(r, 1e-8)))^2 ], r = |p - t| / |t| held constant; the error output
+ *    trains its own weights only.
+ * All pointers named d_* are device memory of the network's device. */
+#define WF_MLP_IN 5
+#define WF_MLP_OUT 451
+
+/* Create a network with seeded uniform(+-1/sqrt(fan_in)) weights and zero biases on the
+ * current device. */
+wf_status wf_mlp_create(uint64_t seed, wf_mlp** out);
+wf_status wf_mlp_destroy(wf_mlp* m);
+/* Number of parameters (314,819). */
+int64_t wf_mlp_num_params(void);
+/* Copy the flat FP32 parameters to / from host memory (n = wf_mlp_num_params()).
+ * Setting them resets the Adam state.  Synchronous. */
+wf_status wf_mlp_get_params(const wf_mlp* m, float* host, int64_t n);
+wf_status wf_mlp_set_params(wf_mlp* m, const float* host, int64_t n);
+
+/* Training inputs d_x [n][WF_MLP_IN] and uncapped kernel sides d_nk [n] (may be NULL)
+ * for examples (d_w: w_proj in wavelengths, d_L: field side nx cell, d_fu, d_fv: cell
+ * offsets), all FP64 [n]; opt supplies alpha and the oversampling (NULL: defaults). */
+wf_status wf_mlp_inputs(const double* d_w, const double* d_L, const double* d_fu,
+                        const double* d_fv, int64_t n, const wf_options* opt, float* d_x,
+                        int32_t* d_nk, void* hip_stream);
+/* Training targets d_t [n][450]: the exact thresholded kernels (the construction the
+ * operator build uses), centred in the 15 x 15 window; zeros where n_k > 15. */
+wf_status wf_mlp_targets(const double* d_w, const double* d_L, int64_t n,
+                         const wf_options* opt, float* d_t, void* hip_stream);
+
+/* Loss and gradient of one batch (batch <= 65536 rows of d_x, d_t): writes the two loss
+ * terms to d_loss[2] and, if d_grad is not NULL, the flat gradient [num_params]. */
+wf_status wf_mlp_loss_grad(wf_mlp* m, const float* d_x, const float* d_t, int32_t batch,
+                           float* d_grad, float* d_loss, void* hip_stream);
+/* One Adam step (b1 0.9, b2 0.999, eps 1e-8) with the gradient of the last
+ * wf_mlp_loss_grad call. */
+wf_status wf_mlp_adam_step(wf_mlp* m, float lr, void* hip_stream);
+/* Train over n examples for `epochs` epochs of floor(n / batch) minibatches each (a
+ * seeded SplitMix64 shuffle per epoch), learning rate cosine-annealed from lr0 to
+ * lr_end.  d_hist (may be NULL) receives per epoch the sums over its minibatches of the
+ * two loss terms, [epochs][2].  Asynchronous on hip_stream apart from the shuffles. */
+wf_status wf_mlp_train(wf_mlp* m, const float* d_x, const float* d_t, int64_t n,
+                       int32_t batch, int32_t epochs, double lr0, double lr_end,
+                       uint64_t seed, float* d_hist, void* hip_stream);
+/* Outputs d_out [n][WF_MLP_OUT] for inputs d_x [n][WF_MLP_IN].  bf16 = 0: the FP32
+ * training kernels; 1: the BF16 inference kernel with plain BF16 operands (relative
+ * output error near 1e-3); 2: the BF16 inference kernel with split operands (high part
+ * + BF16 residual, three BF16 products per step, FP32-level error) -- the form the
+ * operator build uses. */
+wf_status wf_mlp_infer(wf_mlp* m, const float* d_x, int64_t n, int32_t bf16,
+                       float* d_out, void* hip_stream);
 
 /* Release all device and host memory of the handle (synchronises its device). */
 wf_status wf_destroy(wf_op* op);

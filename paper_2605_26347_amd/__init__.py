@@ -18,7 +18,7 @@ from ._lib import (WfImageShape, WfOptions, WfPlanInfo, WfTuneInfo, check, APPLY
 
 _lib.load()
 
-__all__ = ["Operator", "Graph", "default_options"]
+__all__ = ["Operator", "Graph", "Network", "default_options"]
 
 
 def default_options(**kw) -> WfOptions:
@@ -29,6 +29,8 @@ def default_options(**kw) -> WfOptions:
             v = STORE[v] if isinstance(v, str) else int(v)
         elif k == "strategy":
             v = STRATEGY[v] if isinstance(v, str) else int(v)
+        elif k == "surrogate":
+            v = None if v is None else (v._h.value if isinstance(v, Network) else int(v))
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
@@ -225,6 +227,108 @@ class Graph:
         if getattr(self, "_g", None) and self._g.value:
             self._lib.wf_graph_destroy(self._g)
             self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Network:
+    """Residual-kernel network (include/wf.h, learned kernels): FP32 training and BF16
+    inference on the GPU.  Tensors are torch tensors on the current HIP device."""
+
+    NIN, NOUT = 5, 451
+
+    def __init__(self, seed=5):
+        self._lib = _lib.load()
+        self._h = ctypes.c_void_p()
+        check(self._lib.wf_mlp_create(ctypes.c_uint64(seed), ctypes.byref(self._h)),
+              "wf_mlp_create")
+
+    @staticmethod
+    def num_params():
+        return int(_lib.load().wf_mlp_num_params())
+
+    def get_params(self):
+        out = np.zeros(self.num_params(), dtype=np.float32)
+        check(self._lib.wf_mlp_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                          out.size), "wf_mlp_get_params")
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        check(self._lib.wf_mlp_set_params(self._h, theta.ctypes.data_as(ctypes.c_void_p),
+                                          theta.size), "wf_mlp_set_params")
+
+    @staticmethod
+    def inputs(w, L, fu, fv, stream=None, **opts):
+        """Network inputs [n, 5] and uncapped kernel sides [n] from float64 tensors."""
+        import torch
+        n = w.numel()
+        x = torch.empty((n, 5), dtype=torch.float32, device=w.device)
+        nk = torch.empty(n, dtype=torch.int32, device=w.device)
+        o = default_options(**opts)
+        check(_lib.load().wf_mlp_inputs(*(ctypes.c_void_p(t.data_ptr()) for t in (w, L, fu, fv)),
+                                        n, ctypes.byref(o), ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(nk.data_ptr()), _stream_handle(stream)),
+              "wf_mlp_inputs")
+        return x, nk
+
+    @staticmethod
+    def targets(w, L, stream=None, **opts):
+        """Exact thresholded kernels [n, 450] (zeros where the side exceeds 15)."""
+        import torch
+        n = w.numel()
+        t = torch.empty((n, 450), dtype=torch.float32, device=w.device)
+        o = default_options(**opts)
+        check(_lib.load().wf_mlp_targets(ctypes.c_void_p(w.data_ptr()),
+                                         ctypes.c_void_p(L.data_ptr()), n, ctypes.byref(o),
+                                         ctypes.c_void_p(t.data_ptr()), _stream_handle(stream)),
+              "wf_mlp_targets")
+        return t
+
+    def loss_grad(self, x, t, stream=None):
+        import torch
+        g = torch.empty(self.num_params(), dtype=torch.float32, device=x.device)
+        loss = torch.empty(2, dtype=torch.float32, device=x.device)
+        check(self._lib.wf_mlp_loss_grad(self._h, ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(t.data_ptr()), x.shape[0],
+                                         ctypes.c_void_p(g.data_ptr()),
+                                         ctypes.c_void_p(loss.data_ptr()),
+                                         _stream_handle(stream)), "wf_mlp_loss_grad")
+        return loss, g
+
+    def adam_step(self, lr, stream=None):
+        check(self._lib.wf_mlp_adam_step(self._h, ctypes.c_float(lr), _stream_handle(stream)),
+              "wf_mlp_adam_step")
+
+    def train(self, x, t, batch=4096, epochs=10, lr0=1e-3, lr_end=1e-5, seed=5, stream=None):
+        """Returns the per-epoch mean (kernel loss, error-output loss)."""
+        import torch
+        hist = torch.zeros((max(epochs, 1), 2), dtype=torch.float32, device=x.device)
+        check(self._lib.wf_mlp_train(self._h, ctypes.c_void_p(x.data_ptr()),
+                                     ctypes.c_void_p(t.data_ptr()), x.shape[0], batch, epochs,
+                                     lr0, lr_end, ctypes.c_uint64(seed),
+                                     ctypes.c_void_p(hist.data_ptr()), _stream_handle(stream)),
+              "wf_mlp_train")
+        return hist[:epochs].cpu().numpy() / max(x.shape[0] // batch, 1)
+
+    def infer(self, x, bf16=2, out=None, stream=None):
+        """bf16: 0 FP32 kernels, 1 plain BF16, 2 split BF16 (the build's form)."""
+        import torch
+        if out is None:
+            out = torch.empty((x.shape[0], self.NOUT), dtype=torch.float32, device=x.device)
+        check(self._lib.wf_mlp_infer(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                     int(bf16), ctypes.c_void_p(out.data_ptr()),
+                                     _stream_handle(stream)), "wf_mlp_infer")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.wf_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:

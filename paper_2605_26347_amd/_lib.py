@@ -26,7 +26,8 @@ class WfOptions(ctypes.Structure):
                 ("store", ctypes.c_int32), ("plan_fraction", ctypes.c_double),
                 ("budget_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("tile", ctypes.c_int32), ("max_rows_per_item", ctypes.c_int32),
-                ("branches", ctypes.c_int32)]
+                ("branches", ctypes.c_int32), ("surrogate", ctypes.c_void_p),
+                ("surrogate_tol", ctypes.c_double)]
 
 
 class WfPlanInfo(ctypes.Structure):
@@ -39,7 +40,8 @@ class WfPlanInfo(ctypes.Structure):
                 ("mem_g_bytes", ctypes.c_double), ("mem_model_bytes", ctypes.c_double),
                 ("cost_model", ctypes.c_double), ("capped_fraction", ctypes.c_double),
                 ("max_dropped_energy", ctypes.c_double), ("build_seconds", ctypes.c_double),
-                ("max_rows_per_item", ctypes.c_int32), ("branch", ctypes.c_int32)]
+                ("max_rows_per_item", ctypes.c_int32), ("branch", ctypes.c_int32),
+                ("surrogate_fraction", ctypes.c_double)]
 
 
 class WfTuneInfo(ctypes.Structure):
@@ -76,6 +78,17 @@ SIGNATURES = {
     "wf_latency_enable": (_I32, [_P, _I32]),
     "wf_read_latency": (_I32, [_P, _P, _I32]),
     "wf_autotune": (_I32, [_P, _P, _P, _P, _I32, ctypes.POINTER(WfTuneInfo)]),
+    "wf_mlp_create": (_I32, [ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "wf_mlp_destroy": (_I32, [_P]),
+    "wf_mlp_num_params": (_I64, []),
+    "wf_mlp_get_params": (_I32, [_P, _P, _I64]),
+    "wf_mlp_set_params": (_I32, [_P, _P, _I64]),
+    "wf_mlp_inputs": (_I32, [_P, _P, _P, _P, _I64, ctypes.POINTER(WfOptions), _P, _P, _P]),
+    "wf_mlp_targets": (_I32, [_P, _P, _I64, ctypes.POINTER(WfOptions), _P, _P]),
+    "wf_mlp_loss_grad": (_I32, [_P, _P, _P, _I32, _P, _P, _P]),
+    "wf_mlp_adam_step": (_I32, [_P, ctypes.c_float, _P]),
+    "wf_mlp_train": (_I32, [_P, _P, _P, _I64, _I32, _I32, _D, _D, ctypes.c_uint64, _P, _P]),
+    "wf_mlp_infer": (_I32, [_P, _P, _I64, _I32, _P, _P]),
     "wf_destroy": (_I32, [_P]),
     "wf_last_error": (ctypes.c_char_p, []),
 }

@@ -27,6 +27,8 @@ SOURCES = {
     "k_grid.hip": [],
     "k_build.hip": ["-ffp-contract=off"],
     "k_util.hip": [],
+    "k_mlp.hip": [],
+    "wf_mlp.cpp": [],
     "host_plan.cpp": ["-ffp-contract=off"],
     "wf_abi.cpp": [],
 }

@@ -20,6 +20,9 @@
 
 #include <float.h>
 
+#include <algorithm>
+
+#include "mlp_defs.h"
 #include "wf_internal.h"
 
 namespace wf {
@@ -115,6 +118,8 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+__device__ int wkernel_threshold(int nk, double eps, KScratch& S, double* dropped);
+
 // Exact residual kernel of side nk with threshold; workgroup = one wavefront.
 // Leaves the masked kernel in S.c (nk x nk, [s_v][s_u]); returns h' (kept half-side).
 __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratch& S,
@@ -176,6 +181,18 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
     S.c[idx] = make_double2(re * inv, im * inv);
   }
   __syncthreads();
+  return wkernel_threshold(nk, kp.eps, S, dropped);
+}
+
+// Energy threshold of a kernel in S.c (nk x nk): drop the smallest entries holding at
+// most eps of the energy (ties within 1e-9 relative of the smallest kept energy are
+// kept), zero them in S.c, and return the half-side of the smallest centred square that
+// holds every kept entry.  Workgroup = one wavefront.
+__device__ int wkernel_threshold(int nk, double eps, KScratch& S, double* dropped) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x;
+  const int nn2 = nk * nk;
+  const int h = (nk - 1) / 2;
   // energies, ascending bitonic sort over NS slots (NS = next power of two >= nk^2,
   // +inf padding)
   int NS = 16;
@@ -225,7 +242,7 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
   }
   const double offs = scan - run;
   const double tot = __shfl(scan, 63, 64);
-  const double thr = kp.eps * tot;
+  const double thr = eps * tot;
   int cnt = 0;
 #pragma unroll
   for (int q = 0; q < PLMAX; ++q) {
@@ -259,21 +276,47 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
   return hp;
 }
 
-__global__ __launch_bounds__(64) void k_rowsym(const double* __restrict__ uvw, int64_t n,
-                                               double scale, double gsx, double gsy,
-                                               const double* __restrict__ mids, int P,
-                                               const double* __restrict__ cents, int Kx,
+// Rows whose kernel comes from the network: side at most the prediction window and the
+// cap, not a plain delta, and a predicted log10 error at most logtol.
+__device__ __forceinline__ bool use_prediction(const float* pr, int nk_full,
+                                               const KernelParams& kp, float logtol) {
+  return pr && nk_full > 1 && nk_full <= MLP_SIDE && nk_full <= kp.smax &&
+         pr[MLP_KOUT] <= logtol;
+}
+
+// Kernel of side nk from the network's prediction: the centre nk x nk of the predicted
+// window, thresholded like the exact kernel.
+__device__ int predicted_kernel(const float* pr, int nk, const KernelParams& kp, KScratch& S,
+                                double* dropped) {
+  const int a = (MLP_SIDE - nk) / 2;
+  for (int idx = threadIdx.x; idx < nk * nk; idx += 64) {
+    const int sv = idx / nk, su = idx - sv * nk;
+    const int j = (sv + a) * MLP_SIDE + (su + a);
+    S.c[idx] = make_double2((double)pr[2 * j], (double)pr[2 * j + 1]);
+  }
+  __syncthreads();
+  return wkernel_threshold(nk, kp.eps, S, dropped);
+}
+
+__global__ __launch_bounds__(64) void k_rowsym(const double* __restrict__ uvw, int64_t r0,
+                                               int64_t r1, double scale, double gsx,
+                                               double gsy, const double* __restrict__ mids,
+                                               int P, const double* __restrict__ cents, int Kx,
                                                int Ky, int tile, KernelParams kp,
                                                uint64_t* __restrict__ keys,
-                                               float* __restrict__ dropped_out) {
+                                               float* __restrict__ dropped_out, Surrogate sg) {
 #pragma clang fp contract(off)
   __shared__ KScratch S;
-  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+  for (int64_t k = r0 + blockIdx.x; k < r1; k += gridDim.x) {
     const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
     const int nk_full = dev_nk(g.wproj, kp, false);
     const int nk = nk_full > kp.smax ? kp.smax : nk_full;
     double dropped;
-    const int hp = wkernel_row(g.wproj, nk, kp, S, &dropped);
+    const float* pr = sg.pred ? sg.pred + (k - r0) * MLP_OUT : nullptr;
+    const bool usep = use_prediction(pr, nk_full, kp, sg.logtol);
+    const int hp = usep ? predicted_kernel(pr, nk, kp, S, &dropped)
+                        : wkernel_row(g.wproj, nk, kp, S, &dropped);
+    if (usep && threadIdx.x == 0 && sg.used) atomicAdd(sg.used, 1);
     if (threadIdx.x == 0) {
       const int T = 2 * hp + 1 + kp.J - 1;
       const int64_t ru = (int64_t)floor(g.ub + 0.5);
@@ -309,8 +352,8 @@ __device__ __forceinline__ void store_val(void* vals, int64_t i, double re, doub
 }
 
 template <int STORE>
-__global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, int64_t nsorted,
-                                               const int32_t* __restrict__ perm,
+__global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, int64_t s0,
+                                               int64_t s1, const int32_t* __restrict__ perm,
                                                const uint32_t* __restrict__ meta,
                                                const uint32_t* __restrict__ voff,
                                                const int32_t* __restrict__ row_wi,
@@ -319,18 +362,21 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
                                                const double* __restrict__ mids, int P,
                                                const double* __restrict__ cents,
                                                KernelParams kp, void* __restrict__ vals,
-                                               int* __restrict__ mismatch) {
+                                               int* __restrict__ mismatch, Surrogate sg) {
 #pragma clang fp contract(off)
   __shared__ KScratch S;
   const int lane = threadIdx.x;
   const int half = (kp.J - 1) / 2;
-  for (int64_t s = blockIdx.x; s < nsorted; s += gridDim.x) {
+  for (int64_t s = s0 + blockIdx.x; s < s1; s += gridDim.x) {
     const int64_t k = perm[s];
     const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
     const int nk_full = dev_nk(g.wproj, kp, false);
     const int nk = nk_full > kp.smax ? kp.smax : nk_full;
     double dropped;
-    const int hp = wkernel_row(g.wproj, nk, kp, S, &dropped);
+    const float* pr = sg.pred ? sg.pred + (s - s0) * MLP_OUT : nullptr;
+    const bool usep = use_prediction(pr, nk_full, kp, sg.logtol);
+    const int hp = usep ? predicted_kernel(pr, nk, kp, S, &dropped)
+                        : wkernel_row(g.wproj, nk, kp, S, &dropped);
     const int h = (nk - 1) / 2;
     const int np = 2 * hp + 1;
     const int T = np + kp.J - 1;
@@ -385,42 +431,146 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
   }
 }
 
-hipError_t launch_rowsym(const double* uvw, int64_t n, double scale, double gsx, double gsy,
-                         const double* mids, int P, const double* cents, int Kx, int Ky,
-                         int tile, const KernelParams& kp, uint64_t* keys, float* dropped,
-                         hipStream_t s) {
+// Network inputs of rows [r0, r0 + nr) in caller order (perm null) or of sorted rows
+// perm[r0 ..] (field side L, square field).
+__global__ __launch_bounds__(256) void k_row_inputs(const double* __restrict__ uvw,
+                                                    const int32_t* __restrict__ perm, int64_t r0,
+                                                    int64_t nr, double scale, double gsx,
+                                                    double gsy, const double* __restrict__ mids,
+                                                    int P, const double* __restrict__ cents,
+                                                    KernelParams kp, double L,
+                                                    float* __restrict__ x) {
+#pragma clang fp contract(off)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nr;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = r0 + i;
+    const int64_t k = perm ? (int64_t)perm[s] : s;
+    const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
+    const int nk_full = dev_nk(g.wproj, kp, false);
+    const double fu = g.ub - floor(g.ub + 0.5);
+    const double fv = g.vb - floor(g.vb + 0.5);
+    mlp_inputs(g.wproj, L, kp.o, fu, fv, nk_full, x + i * MLP_IN);
+  }
+}
+
+__device__ __forceinline__ KernelParams with_field(KernelParams kp, double L) {
+  kp.Lx = L;
+  kp.Ly = L;
+  kp.oLx = (double)kp.o * L;
+  kp.oLy = (double)kp.o * L;
+  return kp;
+}
+
+// Training inputs of examples (w_proj, field side L, cell offsets).
+__global__ __launch_bounds__(256) void k_train_inputs(const double* __restrict__ w,
+                                                      const double* __restrict__ L,
+                                                      const double* __restrict__ fu,
+                                                      const double* __restrict__ fv, int64_t n,
+                                                      KernelParams kp, float* __restrict__ x,
+                                                      int32_t* __restrict__ nk_out) {
+#pragma clang fp contract(off)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const KernelParams q = with_field(kp, L[i]);
+    const int nk = dev_nk(w[i], q, false);
+    mlp_inputs(w[i], L[i], q.o, fu[i], fv[i], nk, x + i * MLP_IN);
+    if (nk_out) nk_out[i] = nk;
+  }
+}
+
+// Training targets: the thresholded exact kernel of each example centred in the 15 x 15
+// window (zeros when its side exceeds 15).  One wavefront per example.
+__global__ __launch_bounds__(64) void k_exact_targets(const double* __restrict__ w,
+                                                      const double* __restrict__ L, int64_t n,
+                                                      KernelParams kp, float* __restrict__ t) {
+#pragma clang fp contract(off)
+  __shared__ KScratch S;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const KernelParams q = with_field(kp, L[i]);
+    const int nk = dev_nk(w[i], q, false);
+    if (nk <= MLP_SIDE) {
+      double dropped;
+      (void)wkernel_row(w[i], nk, q, S, &dropped);
+    }
+    const int a = (MLP_SIDE - nk) / 2;
+    for (int j = threadIdx.x; j < MLP_SIDE * MLP_SIDE; j += 64) {
+      const int sv = j / MLP_SIDE - a, su = j % MLP_SIDE - a;
+      double2 v = make_double2(0.0, 0.0);
+      if (nk <= MLP_SIDE && sv >= 0 && sv < nk && su >= 0 && su < nk) v = S.c[sv * nk + su];
+      t[i * MLP_KOUT + 2 * j] = (float)v.x;
+      t[i * MLP_KOUT + 2 * j + 1] = (float)v.y;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_rowsym(const double* uvw, int64_t r0, int64_t r1, double scale, double gsx,
+                         double gsy, const double* mids, int P, const double* cents, int Kx,
+                         int Ky, int tile, const KernelParams& kp, uint64_t* keys,
+                         float* dropped, const Surrogate& sg, hipStream_t s) {
+  const int64_t n = r1 - r0;
   if (n <= 0) return hipSuccess;
   const int blocks = (int)(n < 262144 ? n : 262144);
-  hipLaunchKernelGGL(k_rowsym, dim3(blocks), dim3(64), 0, s, uvw, n, scale, gsx, gsy, mids, P,
-                     cents, Kx, Ky, tile, kp, keys, dropped);
+  hipLaunchKernelGGL(k_rowsym, dim3(blocks), dim3(64), 0, s, uvw, r0, r1, scale, gsx, gsy, mids,
+                     P, cents, Kx, Ky, tile, kp, keys, dropped, sg);
   return hipGetLastError();
 }
 
-hipError_t launch_gbuild(const double* uvw, int64_t nsorted, const int32_t* perm,
+hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_t* perm,
                          const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
                          const WorkItem* wi, double scale, double gsx, double gsy,
                          const double* mids, int P, const double* cents,
                          const KernelParams& kp, void* vals, wf_store store, int* mismatch,
-                         hipStream_t s) {
-  if (nsorted <= 0) return hipSuccess;
-  const int blocks = (int)(nsorted < 262144 ? nsorted : 262144);
+                         const Surrogate& sg, hipStream_t s) {
+  const int64_t n = s1 - s0;
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)(n < 262144 ? n : 262144);
   switch (store) {
     case WF_STORE_F32:
-      hipLaunchKernelGGL(k_gbuild<WF_STORE_F32>, dim3(blocks), dim3(64), 0, s, uvw, nsorted,
+      hipLaunchKernelGGL(k_gbuild<WF_STORE_F32>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, mismatch);
+                         vals, mismatch, sg);
       break;
     case WF_STORE_F16:
-      hipLaunchKernelGGL(k_gbuild<WF_STORE_F16>, dim3(blocks), dim3(64), 0, s, uvw, nsorted,
+      hipLaunchKernelGGL(k_gbuild<WF_STORE_F16>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, mismatch);
+                         vals, mismatch, sg);
       break;
     default:
-      hipLaunchKernelGGL(k_gbuild<WF_STORE_BF16>, dim3(blocks), dim3(64), 0, s, uvw, nsorted,
+      hipLaunchKernelGGL(k_gbuild<WF_STORE_BF16>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, mismatch);
+                         vals, mismatch, sg);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_row_inputs(const double* uvw, const int32_t* perm, int64_t r0, int64_t nr,
+                             double scale, double gsx, double gsy, const double* mids, int P,
+                             const double* cents, const KernelParams& kp, double L, float* x,
+                             hipStream_t s) {
+  if (nr <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((nr + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_row_inputs, dim3((unsigned)nb), dim3(256), 0, s, uvw, perm, r0, nr,
+                     scale, gsx, gsy, mids, P, cents, kp, L, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_train_inputs(const double* w, const double* L, const double* fu,
+                               const double* fv, int64_t n, const KernelParams& kp, float* x,
+                               int32_t* nk, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_train_inputs, dim3((unsigned)nb), dim3(256), 0, s, w, L, fu, fv, n, kp,
+                     x, nk);
+  return hipGetLastError();
+}
+
+hipError_t launch_exact_targets(const double* w, const double* L, int64_t n,
+                                const KernelParams& kp, float* t, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)(n < 262144 ? n : 262144);
+  hipLaunchKernelGGL(k_exact_targets, dim3(blocks), dim3(64), 0, s, w, L, n, kp, t);
   return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "mlp_defs.h"
 #include "wf_internal.h"
 
 using namespace wf;
@@ -23,7 +24,7 @@ struct wf_graph {
   hipGraphExec_t exec;
 };
 
-namespace {
+namespace wf {
 
 thread_local std::string g_err;
 
@@ -31,15 +32,6 @@ wf_status fail(wf_status s, const std::string& m) {
   g_err = m;
   return s;
 }
-
-#define WF_HIP(call)                                                                 \
-  do {                                                                               \
-    hipError_t e_ = (call);                                                          \
-    if (e_ != hipSuccess)                                                            \
-      return fail(WF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
-  } while (0)
-
-constexpr double C_LIGHT = 299792458.0;
 
 wf_status dalloc(DevBuf& b, size_t bytes) {
   b.bytes = bytes;
@@ -62,6 +54,12 @@ void dfree(DevBuf& b) {
   b.p = nullptr;
   b.bytes = 0;
 }
+
+}  // namespace wf
+
+namespace {
+
+constexpr double C_LIGHT = 299792458.0;
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -268,9 +266,50 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
                         hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(dcents.p, ch.centroids.data(), sizeof(double) * ch.P,
                         hipMemcpyHostToDevice, s));
-  WF_HIP(launch_rowsym((const double*)duvw.p, M, ch.scale, gsx, gsy, (const double*)dmids.p,
-                       ch.P, (const double*)dcents.p, Kx, Ky, tile, op->kp,
-                       (uint64_t*)dkeys.p, (float*)ddrop.p, s));
+  // residual kernels from the network where it is trusted: inputs and BF16 inference over
+  // chunks of rows, once in caller order (symbolic pass) and once in sorted order (values)
+  const wf_mlp* mlp = opt.surrogate;
+  const float logtol = mlp ? (float)std::log10(opt.surrogate_tol) : 0.f;
+  const double Lfield = op->shape.nx * op->shape.cell_rad;
+  const int64_t CH = std::min<int64_t>(std::max<int64_t>(M, 1), 1 << 20);
+  DevBuf dx, dpred, dused;
+  tmp.b.push_back(&dx);
+  tmp.b.push_back(&dpred);
+  tmp.b.push_back(&dused);
+  if (mlp) {
+    if ((st = dalloc(dx, sizeof(float) * MLP_IN * CH)) != WF_OK) return st;
+    if ((st = dalloc(dpred, sizeof(float) * MLP_OUT * CH)) != WF_OK) return st;
+    if ((st = dalloc(dused, sizeof(int))) != WF_OK) return st;
+    WF_HIP(hipMemsetAsync(dused.p, 0, sizeof(int), s));
+  }
+  auto surrogate_pass = [&](const int32_t* order, auto&& launch) -> wf_status {
+    if (!mlp) return launch(0, M, Surrogate{});
+    for (int64_t r0 = 0; r0 < M; r0 += CH) {
+      const int64_t n = std::min<int64_t>(CH, M - r0);
+      WF_HIP(launch_row_inputs((const double*)duvw.p, order, r0, n, ch.scale, gsx, gsy,
+                               (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
+                               Lfield, (float*)dx.p, s));
+      wf_status e = mlp_infer_bf16(mlp, (const float*)dx.p, n, true, (float*)dpred.p, s);
+      if (e != WF_OK) return e;
+      Surrogate sg;
+      sg.pred = (const float*)dpred.p;
+      sg.logtol = logtol;
+      sg.used = order ? nullptr : (int*)dused.p;
+      if ((e = launch(r0, r0 + n, sg)) != WF_OK) return e;
+    }
+    return WF_OK;
+  };
+  st = surrogate_pass(nullptr, [&](int64_t r0, int64_t r1, const Surrogate& sg) -> wf_status {
+    WF_HIP(launch_rowsym((const double*)duvw.p, r0, r1, ch.scale, gsx, gsy,
+                         (const double*)dmids.p, ch.P, (const double*)dcents.p, Kx, Ky, tile,
+                         op->kp, (uint64_t*)dkeys.p, (float*)ddrop.p, sg, s));
+    return WF_OK;
+  });
+  if (st != WF_OK) return st;
+  int nused = 0;
+  if (mlp) {
+    WF_HIP(hipMemcpyAsync(&nused, dused.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  }
   std::vector<uint64_t> keys(M);
   std::vector<float> dropped(M);
   WF_HIP(hipMemcpyAsync(keys.data(), dkeys.p, sizeof(uint64_t) * M, hipMemcpyDeviceToHost, s));
@@ -431,11 +470,20 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   WF_HIP(hipMemcpyAsync(drowwi.p, row_wi.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(ch.work.p, wis.data(), sizeof(WorkItem) * wis.size(),
                         hipMemcpyHostToDevice, s));
-  WF_HIP(launch_gbuild((const double*)duvw.p, M, (const int32_t*)ch.perm.p,
-                       (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
-                       (const int32_t*)drowwi.p, (const WorkItem*)ch.work.p, ch.scale, gsx,
-                       gsy, (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
-                       ch.vals.p, opt.store, (int*)dmis.p, s));
+  st = surrogate_pass((const int32_t*)ch.perm.p,
+                      [&](int64_t s0, int64_t s1, const Surrogate& sg) -> wf_status {
+                        WF_HIP(launch_gbuild((const double*)duvw.p, s0, s1,
+                                             (const int32_t*)ch.perm.p,
+                                             (const uint32_t*)ch.meta.p,
+                                             (const uint32_t*)ch.voff.p,
+                                             (const int32_t*)drowwi.p,
+                                             (const WorkItem*)ch.work.p, ch.scale, gsx, gsy,
+                                             (const double*)dmids.p, ch.P,
+                                             (const double*)dcents.p, op->kp, ch.vals.p,
+                                             opt.store, (int*)dmis.p, sg, s));
+                        return WF_OK;
+                      });
+  if (st != WF_OK) return st;
   int mismatch = 0;
   WF_HIP(hipMemcpyAsync(&mismatch, dmis.p, sizeof(int), hipMemcpyDeviceToHost, s));
   WF_HIP(hipStreamSynchronize(s));
@@ -465,6 +513,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   in.build_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   in.max_rows_per_item = ch.max_rows;
+  in.surrogate_fraction = M ? (double)nused / (double)M : 0.0;
   return WF_OK;
 }
 
@@ -897,6 +946,8 @@ void wf_default_options(wf_options* o) {
   o->tile = 0;
   o->max_rows_per_item = 0;
   o->branches = 0;
+  o->surrogate = nullptr;
+  o->surrogate_tol = 1e-3;
 }
 
 const char* wf_last_error(void) { return g_err.c_str(); }
@@ -930,6 +981,10 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
       return fail(WF_EINVAL, "max_rows_per_item must be in [0,1024]");
     if (opt.branches < 0 || opt.branches > 16)
       return fail(WF_EINVAL, "branches must be in [0,16]");
+    if (opt.surrogate && !(opt.surrogate_tol > 0))
+      return fail(WF_EINVAL, "surrogate_tol must be positive");
+    if (opt.surrogate && shape.nx != shape.ny)
+      return fail(WF_ENOTSUP, "the kernel network is defined for square fields only");
     if (!(opt.beta > 0) || !(opt.alpha > 0) || !(opt.eps_w >= 0) || opt.eps_w >= 1)
       return fail(WF_EINVAL, "bad beta / alpha / eps_w");
     if (!(opt.plan_fraction > 0) || opt.plan_fraction > 1 || !(opt.budget_fraction > 0) ||

@@ -166,6 +166,20 @@ struct wf_op {
   uint64_t generation = 0;           // bumped when work items or branches change
 };
 
+// Residual-kernel network: FP32 parameters with Adam state, per-batch activations, and
+// the transposed BF16 weights of the inference kernel (refreshed when the parameters
+// change).
+struct wf_mlp {
+  int device = 0;
+  wf::DevBuf params, grad, m, v;
+  mutable wf::DevBuf wt;          // BF16 [2][3 x 256 x 256 + 512 x 256] (high, residual)
+  mutable bool wt_dirty = true;
+  int64_t t = 0;                  // Adam steps taken
+  int bcap = 0;                   // batch capacity of the buffers below
+  wf::DevBuf xb, tb, P, dP, dA, dB, idx, loss;
+  wf::DevBuf H[4], Z[4];
+};
+
 namespace wf {
 
 // ------------------------------------------------------------------ kernel launchers
@@ -203,21 +217,70 @@ hipError_t launch_add_into(float* out, const float* in, int64_t nfloats, hipStre
 hipError_t launch_strip_to_rowmajor(const float2* src, float2* dst, int R, int Q,
                                     hipStream_t s);
 
-// Build kernels (FP64).  Symbolic pass over rows in caller order: bin, grid position,
-// residual kernel side after thresholding, sort key.
-hipError_t launch_rowsym(const double* uvw, int64_t n, double scale, double gsx, double gsy,
-                         const double* mids, int P, const double* cents, int Kx, int Ky,
-                         int tile, const KernelParams& kp, uint64_t* keys, float* dropped,
-                         hipStream_t s);
-// Value pass over sorted rows: writes each row's T*T values.
-hipError_t launch_gbuild(const double* uvw, int64_t nsorted, const int32_t* perm,
+// Kernels predicted by the residual-kernel network for a chunk of rows (null pred: every
+// row exact).  pred [rows of the chunk][451]; rows whose predicted log10 error exceeds
+// logtol, or whose side is out of the network's range, use the exact construction.
+struct Surrogate {
+  const float* pred = nullptr;
+  float logtol = -3.f;
+  int* used = nullptr;          // counts rows built from the prediction (may be null)
+};
+
+// Build kernels (FP64).  Symbolic pass over rows [r0, r1) in caller order: bin, grid
+// position, residual kernel side after thresholding, sort key.
+hipError_t launch_rowsym(const double* uvw, int64_t r0, int64_t r1, double scale, double gsx,
+                         double gsy, const double* mids, int P, const double* cents, int Kx,
+                         int Ky, int tile, const KernelParams& kp, uint64_t* keys,
+                         float* dropped, const Surrogate& sg, hipStream_t s);
+// Value pass over sorted rows [s0, s1): writes each row's T*T values.
+hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_t* perm,
                          const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
                          const WorkItem* wi, double scale, double gsx, double gsy,
                          const double* mids, int P, const double* cents,
                          const KernelParams& kp, void* vals, wf_store store, int* mismatch,
-                         hipStream_t s);
+                         const Surrogate& sg, hipStream_t s);
+// Network inputs of rows [r0, r0 + nr) (caller order, or sorted order through perm).
+hipError_t launch_row_inputs(const double* uvw, const int32_t* perm, int64_t r0, int64_t nr,
+                             double scale, double gsx, double gsy, const double* mids, int P,
+                             const double* cents, const KernelParams& kp, double L, float* x,
+                             hipStream_t s);
+// Training inputs and exact training targets of (w_proj, field side) examples.
+hipError_t launch_train_inputs(const double* w, const double* L, const double* fu,
+                               const double* fv, int64_t n, const KernelParams& kp, float* x,
+                               int32_t* nk, hipStream_t s);
+hipError_t launch_exact_targets(const double* w, const double* L, int64_t n,
+                                const KernelParams& kp, float* t, hipStream_t s);
+
+// Residual-kernel network kernels.
+hipError_t launch_mlp_gemm(bool ta, bool tb, int epi, const float* A, int lda, const float* B,
+                           int ldb, float* C, int ldc, float* Z, const float* bias, int M,
+                           int N, int K, hipStream_t s);
+hipError_t launch_mlp_gelu_bwd(float* dH, const float* Z, int64_t n, hipStream_t s);
+hipError_t launch_mlp_colsum(const float* D, int ld, int rows, int N, float* db,
+                             hipStream_t s);
+hipError_t launch_mlp_loss(const float* P, const float* T, float* dP, int B, float* loss,
+                           hipStream_t s);
+hipError_t launch_mlp_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                           float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_mlp_gather(const float* X, int cx, const float* T, int ct,
+                             const int32_t* idx, int B, float* xb, float* tb, hipStream_t s);
+hipError_t launch_mlp_prep_bf16(const float* params, uint16_t* wt, hipStream_t s);
+hipError_t launch_mlp_infer_bf16(const float* x, int64_t n, const float* params,
+                                 const uint16_t* wt, bool split, float* out, hipStream_t s);
 
 // ------------------------------------------------------------------ host helpers
+// Record the thread-local error message of the ABI and return the status.
+wf_status fail(wf_status s, const std::string& m);
+wf_status dalloc(DevBuf& b, size_t bytes);
+void dfree(DevBuf& b);
+
+#define WF_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::wf::fail(WF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
 double i0_series(double x);
 double kb_phihat(double nu, int J, double beta);
 
@@ -235,6 +298,10 @@ int plan_channel(const double* w_all, int64_t M, const wf_image_shape& shape,
                  const wf_options& opt, uint64_t budget, PlanResult* out, std::string* err);
 std::vector<double> kmeans_1d(std::vector<double> wsub, int P);
 int nk_rule(double wproj, const KernelParams& kp, bool capped);
+
+// BF16 inference of the residual-kernel network (out [n][451]); split: hi/lo operands.
+wf_status mlp_infer_bf16(const wf_mlp* m, const float* x, int64_t n, bool split, float* out,
+                         hipStream_t s);
 
 // Stable LSD radix sort of (key, idx) by key bits [lo_bit, 64).
 void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<int32_t>& idx, int lo_bit);

@@ -101,3 +101,14 @@ def test_null_handle_batched_calls():
     assert lib.wf_latency_enable(None, 1) == _lib.WF_EINVAL
     assert lib.wf_read_latency(None, None, 0) == _lib.WF_EINVAL
     assert lib.wf_autotune(None, None, None, None, 1, None) == _lib.WF_EINVAL
+
+
+def test_network_host_calls():
+    lib = _lib.load()
+    assert lib.wf_mlp_num_params() == 5 * 256 + 256 + 3 * (256 * 256 + 256) + 256 * 451 + 451
+    assert lib.wf_mlp_destroy(None) == _lib.WF_EINVAL
+    assert lib.wf_mlp_get_params(None, None, 0) == _lib.WF_EINVAL
+    assert lib.wf_mlp_infer(None, None, 0, 1, None, None) == _lib.WF_EINVAL
+    assert lib.wf_mlp_train(None, None, None, 0, 1, 1, 1e-3, 1e-5, 0, None, None) == _lib.WF_EINVAL
+    o = default_options()
+    assert o.surrogate is None and o.surrogate_tol == 1e-3

@@ -1,0 +1,175 @@
+"""Residual-kernel network through the C ABI against the FP64 network reference
+(oracle/mlp.py) and the FP64 exact kernels: inputs and training targets, the FP32
+forward pass (1e-5), the BF16 inference kernel, per-tensor gradients (1e-4), an Adam
+step, training, and an operator whose G is built from the trained network (Phi^dag Phi
+within 1e-3 of the exact FP64 oracle)."""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import wfsynth as ws
+from gpu_common import rel, oracle_for, gpu_operator, to_dev
+from oracle import mlp as omlp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _net():
+    from paper_2605_26347_amd import Network
+    return Network
+
+
+def _examples(n, seed, wscale=1.0):
+    r = np.random.default_rng(seed)
+    L = np.radians(r.choice([1.0, 2.0, 3.0, 4.0], n))
+    # the side rule gives n_k = 2 ceil(|w| (2L)^2 / n') + 1: |w| (2L)^2 up to 9 covers
+    # sides up to 19 (about a fifth beyond the 15 window)
+    w = r.uniform(-1, 1, n) * wscale * 9.0 / (2 * L) ** 2
+    w[:3] = 0.0
+    fu = r.uniform(-0.5, 0.5, n)
+    fv = r.uniform(-0.5, 0.5, n)
+    return w, L, fu, fv
+
+
+def test_inputs_and_targets_match_oracle():
+    Net = _net()
+    w, L, fu, fv = _examples(400, 1)
+    x, nk = Net.inputs(*(to_dev(a) for a in (w, L, fu, fv)))
+    t = Net.targets(to_dev(w), to_dev(L)).cpu().numpy()
+    xo, nko = omlp.features(w, L, fu, fv)
+    assert np.array_equal(nk.cpu().numpy(), nko)
+    assert np.allclose(x.cpu().numpy(), xo, rtol=1e-6, atol=1e-7)
+    nrep = 0
+    for i in range(w.size):
+        ref = omlp.kernel_target(w[i], L[i])
+        if ref is None:
+            assert np.all(t[i] == 0)
+            continue
+        nrep += 1
+        assert np.abs(t[i] - ref).max() <= 2e-7 * max(1.0, np.abs(ref).max()), i
+    say(f"[gpu] targets: {nrep} of {w.size} representable")
+    assert 100 < nrep < w.size
+
+
+@pytest.fixture(scope="module")
+def params():
+    th = omlp.init(7)
+    th += np.random.default_rng(8).normal(0, 0.02, th.size)   # non-zero biases too
+    return th
+
+
+def test_forward_fp32_and_bf16(params):
+    Net = _net()
+    net = Net(seed=1)
+    net.set_params(params.astype(np.float32))
+    assert np.array_equal(net.get_params(), params.astype(np.float32))
+    w, L, fu, fv = _examples(300, 2)        # 300 rows: ragged 64-row tiles
+    xo, _ = omlp.features(w, L, fu, fv)
+    x = to_dev(xo.astype(np.float32))
+    ref, _ = omlp.forward(params.astype(np.float32).astype(np.float64),
+                          xo.astype(np.float32).astype(np.float64))
+    p32 = net.infer(x, bf16=0).cpu().numpy()
+    e32 = rel(p32, ref)
+    p16 = net.infer(x, bf16=1).cpu().numpy()
+    e16 = rel(p16, ref)
+    psp = net.infer(x, bf16=2).cpu().numpy()
+    esp = rel(psp, ref)
+    say(f"[gpu] forward rel: fp32 {e32:.2e}, bf16 {e16:.2e}, split bf16 {esp:.2e}")
+    assert e32 <= 1e-5
+    assert e16 <= 2e-2
+    assert esp <= 2e-5
+
+
+def test_gradients_and_adam_match_oracle(params):
+    Net = _net()
+    net = Net(seed=1)
+    th = params.astype(np.float32)
+    net.set_params(th)
+    r = np.random.default_rng(4)
+    B = 200
+    xo = r.normal(0, 1, (B, 5)).astype(np.float32)
+    to = r.normal(0, 0.1, (B, 450)).astype(np.float32)
+    loss, g = net.loss_grad(to_dev(xo), to_dev(to))
+    lk, le, go = omlp.loss_grad(th.astype(np.float64), xo.astype(np.float64),
+                                to.astype(np.float64))
+    loss = loss.cpu().numpy()
+    assert abs(loss[0] - lk) <= 1e-5 * lk and abs(loss[1] - le) <= 1e-4 * le
+    g = g.cpu().numpy()
+    sizes = omlp.SIZES
+    o = 0
+    for i, (a, b) in enumerate(zip(sizes[:-1], sizes[1:])):
+        for name, n in (("W", a * b), ("b", b)):
+            e = rel(g[o:o + n], go[o:o + n])
+            say(f"[gpu] grad layer {i} {name}: {e:.2e}")
+            assert e <= 1e-4, (i, name, e)
+            o += n
+    net.adam_step(1e-3)
+    th1, _, _ = omlp.adam(th.astype(np.float64), g.astype(np.float64), np.zeros(th.size),
+                          np.zeros(th.size), 1, 1e-3)
+    assert np.abs(net.get_params() - th1).max() <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """A network trained on exact kernels of fields 1-4 degrees (residual w of each field
+    spanning kernel sides up to ~19)."""
+    Net = _net()
+    w, L, fu, fv = _examples(1_300_000, 11, wscale=7.0 / 9.0)
+    wd, Ld = to_dev(w), to_dev(L)
+    x, nk = Net.inputs(wd, Ld, to_dev(fu), to_dev(fv))
+    t = Net.targets(wd, Ld)
+    keep = (nk <= 15).nonzero().squeeze(1)
+    x, t = x[keep].contiguous(), t[keep].contiguous()
+    net = Net(seed=5)
+    t0 = time.time()
+    hist = net.train(x, t, batch=4096, epochs=100, lr0=2e-3, lr_end=1e-6, seed=3)
+    torch.cuda.synchronize()
+    say(f"[gpu] trained on {x.shape[0]} kernels in {time.time() - t0:.1f} s; "
+        f"kernel loss {hist[0, 0]:.2e} -> {hist[-1, 0]:.2e}, error-output loss "
+        f"{hist[0, 1]:.2e} -> {hist[-1, 1]:.2e}")
+    return net, hist
+
+
+def test_training_reduces_loss(trained):
+    _, hist = trained
+    assert hist[-1, 0] < 0.05 * hist[0, 0]
+    assert hist[-1, 1] < hist[0, 1]
+
+
+def test_surrogate_build_matches_exact_oracle(trained):
+    """G built with the network where it predicts an error <= 1e-3 (exact elsewhere):
+    Phi^dag Phi within 1e-3 of the FP64 oracle built with exact kernels, and the network
+    takes over part of the kernel construction."""
+    net, _ = trained
+    obs = ws.widefield(n=128, nvis=24_000, fov_deg=3.0, npoints=40, nblobs=3,
+                       blob_sigma=(1.0, 3.0))
+    t0 = time.time()
+    op_e = gpu_operator(obs, 4)
+    torch.cuda.synchronize()
+    te = time.time() - t0
+    t0 = time.time()
+    op_s = gpu_operator(obs, 4, surrogate=net)
+    torch.cuda.synchronize()
+    ts = time.time() - t0
+    frac = op_s.plan()["surrogate_fraction"]
+    orc = oracle_for(obs, 4)
+    x = obs.sky.astype(np.float32)
+    ref = orc.psf(x.astype(np.float64))
+    es = rel(op_s.psf_apply(to_dev(x[None])).cpu().numpy()[0], ref)
+    ee = rel(op_e.psf_apply(to_dev(x[None])).cpu().numpy()[0], ref)
+    say(f"[gpu] surrogate rows {frac:.3f}; psf rel: surrogate {es:.2e}, exact {ee:.2e}; "
+        f"build {ts:.2f} s vs exact {te:.2f} s")
+    assert frac > 0.2
+    assert es <= 1e-3
+    # rows the network takes must be exactly those of side <= 15 it trusts: a looser
+    # tolerance can only add rows
+    op_l = gpu_operator(obs, 4, surrogate=net, surrogate_tol=0.5)
+    assert op_l.plan()["surrogate_fraction"] >= frac

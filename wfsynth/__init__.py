@@ -199,6 +199,27 @@ def precision_form(n: int = 4096, nvis: int = 50_000_000, fov_deg: float = 3.0,
                        n, n, cell, s)
 
 
+def learned_form(n: int = 4096, nvis: int = 20_000_000, fov_deg: float = 3.0,
+                 sky: bool = True) -> Observation:
+    """4096^2 over 3 degrees, 20M rows: a seeded subset of the 16 h sample set of the
+    64-antenna array (the precision form's tracks)."""
+    o = precision_form(n, 50_000_000, fov_deg, sky)
+    uvw = o.uvw_m[seeded_subset(o.uvw_m.shape[0], nvis, SEED_SAMPLING + 7)]
+    return Observation("learned", np.ascontiguousarray(uvw), o.freqs_hz, n, n, o.cell_rad,
+                       o.sky)
+
+
+def kernel_examples(wproj_pool: np.ndarray, n: int, seed: int = SEED_MLP,
+                    fovs_deg=(1.0, 2.0, 3.0, 4.0)):
+    """Training examples of the residual-kernel network: residual w drawn (seeded, with
+    replacement) from a pool, field side uniform over fovs_deg (as nx cell, radians),
+    cell offsets uniform in [-1/2, 1/2).  Returns (w, L, fu, fv) float64 arrays."""
+    rng = np.random.default_rng(seed)
+    w = np.asarray(wproj_pool, dtype=np.float64)[rng.integers(0, len(wproj_pool), n)]
+    L = np.radians(rng.choice(np.asarray(fovs_deg, dtype=np.float64), n))
+    return w, L, rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n)
+
+
 def batched_counts(nchan: int = 16, total: int = 48_000_000, lo: float = 0.5e6,
                    hi: float = 6e6, seed: int = SEED_SAMPLING) -> np.ndarray:
     """Seeded log-uniform per-channel counts in [lo, hi], rescaled (clamped,
