@@ -285,17 +285,46 @@ __device__ __forceinline__ bool use_prediction(const float* pr, int nk_full,
 }
 
 // Kernel of side nk from the network's prediction: the centre nk x nk of the predicted
-// window, thresholded like the exact kernel.
+// window, cut to the smallest centred square whose outside holds at most eps of the
+// energy (whole square rings are dropped; no sort, unlike the exact kernel's per-entry
+// threshold, whose zeroed entries the network has learned as near-zero outputs).
 __device__ int predicted_kernel(const float* pr, int nk, const KernelParams& kp, KScratch& S,
                                 double* dropped) {
+#pragma clang fp contract(off)
   const int a = (MLP_SIDE - nk) / 2;
+  const int h = (nk - 1) / 2;
+  double ring[MLP_SIDE / 2 + 1];
+#pragma unroll
+  for (int r = 0; r <= MLP_SIDE / 2; ++r) ring[r] = 0.0;
   for (int idx = threadIdx.x; idx < nk * nk; idx += 64) {
     const int sv = idx / nk, su = idx - sv * nk;
     const int j = (sv + a) * MLP_SIDE + (su + a);
-    S.c[idx] = make_double2((double)pr[2 * j], (double)pr[2 * j + 1]);
+    const double re = (double)pr[2 * j], im = (double)pr[2 * j + 1];
+    S.c[idx] = make_double2(re, im);
+    const int rv = sv > h ? sv - h : h - sv;
+    const int ru = su > h ? su - h : h - su;
+    const int r = rv > ru ? rv : ru;
+    const double e = re * re + im * im;
+#pragma unroll
+    for (int q = 0; q <= MLP_SIDE / 2; ++q)
+      if (q == r) ring[q] += e;
   }
+  double tot = 0.0;
+#pragma unroll
+  for (int q = 0; q <= MLP_SIDE / 2; ++q) {
+    ring[q] = wave_sum_d(ring[q]);
+    tot += ring[q];
+  }
+  int hp = h;
+  double outside = 0.0;
+  for (int q = h; q > 0; --q) {
+    if (outside + ring[q] > kp.eps * tot) break;
+    outside += ring[q];
+    hp = q - 1;
+  }
+  *dropped = tot > 0.0 ? outside / tot : 0.0;
   __syncthreads();
-  return wkernel_threshold(nk, kp.eps, S, dropped);
+  return hp;
 }
 
 __global__ __launch_bounds__(64) void k_rowsym(const double* __restrict__ uvw, int64_t r0,
