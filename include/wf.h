@@ -54,7 +54,12 @@ typedef enum {
 typedef enum { WF_STORE_F32 = 0, WF_STORE_F16 = 1, WF_STORE_BF16 = 2 } wf_store;
 
 /* Strategy of Sect. 3.4 / Fig. 2: (a) precomputed G, (b) precomputed holographic H,
- * (c) G computed on the fly.  WF_AUTO runs the decision tree. */
+ * (c) G computed on the fly.  WF_AUTO runs the decision tree: (a) when G fits the
+ * budget, else (b) when H fits (its exact size is known after the symbolic pass), else
+ * WF_EBUDGET -- (c) is not built (WF_ENOTSUP when requested).  A holographic operator
+ * stores H_p = G_p^dag G_p as dense stencils per active 32 x 32 grid tile (side
+ * 2 Tmax - 1, Tmax the largest patch side reaching the tile) and applies Phi^dag Phi
+ * only: wf_forward / wf_adjoint / wf_get_row return WF_ENOTSUP for it.  Needs tile <= 32. */
 typedef enum { WF_AUTO = 0, WF_PRECOMP_G = 1, WF_PRECOMP_H = 2, WF_ONTHEFLY = 3 } wf_strategy;
 
 typedef struct {
@@ -147,6 +152,7 @@ typedef struct {
   int32_t max_rows_per_item;/* rows per work item of the current split                 */
   int32_t branch;           /* branch that writes this channel's output                */
   double surrogate_fraction;/* rows whose residual kernel came from the network        */
+  double mem_h_bytes;       /* device bytes of the holographic stencils (strategy (b))  */
 } wf_plan_info;
 
 /* Plan and matrix statistics of channel chan (Sect. 3.4 quantities). */

@@ -41,7 +41,7 @@ class WfPlanInfo(ctypes.Structure):
                 ("cost_model", ctypes.c_double), ("capped_fraction", ctypes.c_double),
                 ("max_dropped_energy", ctypes.c_double), ("build_seconds", ctypes.c_double),
                 ("max_rows_per_item", ctypes.c_int32), ("branch", ctypes.c_int32),
-                ("surrogate_fraction", ctypes.c_double)]
+                ("surrogate_fraction", ctypes.c_double), ("mem_h_bytes", ctypes.c_double)]
 
 
 class WfTuneInfo(ctypes.Structure):

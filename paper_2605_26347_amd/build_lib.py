@@ -28,6 +28,7 @@ SOURCES = {
     "k_build.hip": ["-ffp-contract=off"],
     "k_util.hip": [],
     "k_mlp.hip": [],
+    "k_holo.hip": [],
     "wf_mlp.cpp": [],
     "host_plan.cpp": ["-ffp-contract=off"],
     "wf_abi.cpp": [],

@@ -240,8 +240,12 @@ int plan_channel(const double* w_all, int64_t M, const wf_image_shape& shape,
   out->cost_model = tab[Pbar - 1].cost;
   out->strategy = WF_PRECOMP_H;
   out->centroids = lloyd(S, Pbar);
-  if (err) *err = "precomputed G does not fit the memory budget (needs strategy (b) or (c))";
-  return 1;
+  // branch (b) when its exact size (known after the symbolic pass) fits, else (c)
+  if (opt.strategy == WF_PRECOMP_G) {
+    if (err) *err = "precomputed G does not fit the memory budget";
+    return 1;
+  }
+  return 0;
 }
 
 void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<int32_t>& idx, int lo_bit) {

@@ -391,7 +391,8 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
                                                const double* __restrict__ mids, int P,
                                                const double* __restrict__ cents,
                                                KernelParams kp, void* __restrict__ vals,
-                                               int* __restrict__ mismatch, Surrogate sg) {
+                                               int64_t vbase, int* __restrict__ mismatch,
+                                               Surrogate sg) {
 #pragma clang fp contract(off)
   __shared__ KScratch S;
   const int lane = threadIdx.x;
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
       S.t2[idx] = make_double2(re, im);
     }
     __syncthreads();
-    const int64_t vb = wis[row_wi[s]].voff + voff[s];
+    const int64_t vb = wis[row_wi[s]].voff + voff[s] - vbase;
     if (T == Tm) {
       for (int idx = lane; idx < T * T; idx += 64) {
         const int av = idx / T, au = idx - av * T;
@@ -549,8 +550,8 @@ hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_
                          const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
                          const WorkItem* wi, double scale, double gsx, double gsy,
                          const double* mids, int P, const double* cents,
-                         const KernelParams& kp, void* vals, wf_store store, int* mismatch,
-                         const Surrogate& sg, hipStream_t s) {
+                         const KernelParams& kp, void* vals, int64_t vbase, wf_store store,
+                         int* mismatch, const Surrogate& sg, hipStream_t s) {
   const int64_t n = s1 - s0;
   if (n <= 0) return hipSuccess;
   const int blocks = (int)(n < 262144 ? n : 262144);
@@ -558,17 +559,17 @@ hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_
     case WF_STORE_F32:
       hipLaunchKernelGGL(k_gbuild<WF_STORE_F32>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, mismatch, sg);
+                         vals, vbase, mismatch, sg);
       break;
     case WF_STORE_F16:
       hipLaunchKernelGGL(k_gbuild<WF_STORE_F16>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, mismatch, sg);
+                         vals, vbase, mismatch, sg);
       break;
     default:
       hipLaunchKernelGGL(k_gbuild<WF_STORE_BF16>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, mismatch, sg);
+                         vals, vbase, mismatch, sg);
       break;
   }
   return hipGetLastError();

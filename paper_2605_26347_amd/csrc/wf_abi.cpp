@@ -96,6 +96,8 @@ void destroy_op(wf_op* op) {
     dfree(c.vals);
     dfree(c.work);
     dfree(c.prune);
+    dfree(c.htiles);
+    dfree(c.hvals);
   }
   for (size_t b = 0; b < op->br.size(); ++b) release_branch(op->br[b], b > 0);
   if (op->fork) (void)hipEventDestroy(op->fork);
@@ -230,17 +232,16 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   for (int64_t k = 0; k < M; ++k) w[k] = uvw[3 * k + 2] * ch.scale;
   PlanResult pr;
   std::string perr;
+  if (opt.strategy == WF_ONTHEFLY)
+    return fail(WF_ENOTSUP, "the on-the-fly strategy (c) is not built");
   if (M > 0) {
-    if (plan_channel(w.data(), M, op->shape, opt, budget, &pr, &perr) != 0) {
-      return fail(WF_ENOTSUP, "channel " + std::to_string(c) + ": " + perr +
-                                  "; holographic and on-the-fly strategies are not built");
-    }
+    if (plan_channel(w.data(), M, op->shape, opt, budget, &pr, &perr) != 0)
+      return fail(WF_ENOTSUP, "channel " + std::to_string(c) + ": " + perr);
   } else {
     pr.P = 1;
     pr.centroids = {0.0};
   }
-  if (opt.strategy == WF_PRECOMP_H || opt.strategy == WF_ONTHEFLY)
-    return fail(WF_ENOTSUP, "only the precomputed-G strategy is built");
+  const bool holo = opt.strategy == WF_PRECOMP_H || pr.strategy == WF_PRECOMP_H;
   ch.P = pr.P;
   ch.centroids = pr.centroids;
   std::vector<double> mids(ch.P > 1 ? ch.P - 1 : 1, 0.0);
@@ -378,7 +379,6 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   std::vector<WorkItem> wis;
   ch.max_rows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
   split_items(ch, trow.data(), ch.max_rows, wis, voff.data(), row_wi.data());
-  std::vector<uint8_t>().swap(trow);
 
   // active uv support per bin: tiles holding rows, dilated to cover the LDS windows'
   // halo, the column strips under them and the column groups of the column passes
@@ -462,14 +462,143 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   if ((st = dalloc(ch.work, sizeof(WorkItem) * std::max<size_t>(wis.size(), 1))) != WF_OK)
     return st;
   if ((st = dalloc(drowwi, sizeof(int32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
-  if ((st = dalloc(ch.vals, (size_t)b_v * std::max<int64_t>(taps_total, 1))) != WF_OK)
-    return st;
   WF_HIP(hipMemcpyAsync(ch.meta.p, meta.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(ch.voff.p, voff.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(ch.perm.p, idx.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(drowwi.p, row_wi.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(ch.work.p, wis.data(), sizeof(WorkItem) * wis.size(),
                         hipMemcpyHostToDevice, s));
+  if (holo) {
+    // holographic matrix (Sect. 3.3): stencil tiles of every bin, accumulated from that
+    // bin's rows of G built one bin at a time in FP32; G itself is not kept
+    if (tile > 32) return fail(WF_EINVAL, "the holographic strategy needs tile <= 32");
+    const int tx = Kx / tile, ty = Ky / tile;
+    int tsh = 0;
+    while ((1 << tsh) < tile) ++tsh;
+    std::vector<HTile> ht;
+    std::vector<int32_t> slot((size_t)ch.P * tx * ty, -1);
+    std::vector<int> tmax((size_t)tx * ty);
+    ch.h_t0.assign(ch.P, 0);
+    ch.h_nt.assign(ch.P, 0);
+    ch.h_dmax.assign(ch.P, 0);
+    int64_t hv = 0, maxbin = 0;
+    size_t gi = 0;
+    for (int p = 0; p < ch.P; ++p) {
+      std::fill(tmax.begin(), tmax.end(), 0);
+      for (; gi < ch.groups.size() && ch.groups[gi].bin == p; ++gi) {
+        const RowGroup& g = ch.groups[gi];
+        int Tg = 0;
+        for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) Tg = std::max<int>(Tg, trow[r]);
+        const int tu = (g.u0 + halo) / tile, tv = (g.v0 + halo) / tile;
+        const int dil = (halo + tile - 1) / tile;   // patches stay within the LDS window
+        for (int dv = -dil; dv <= dil; ++dv)
+          for (int du = -dil; du <= dil; ++du) {
+            const size_t t = (size_t)(((tv + dv) % ty + ty) % ty) * tx + ((tu + du) % tx + tx) % tx;
+            tmax[t] = std::max(tmax[t], Tg);
+          }
+      }
+      ch.h_t0[p] = (int64_t)ht.size();
+      for (size_t t = 0; t < tmax.size(); ++t) {
+        if (!tmax[t]) continue;
+        HTile h;
+        h.tile = (int32_t)t;
+        h.D = 2 * tmax[t] - 1;
+        h.voff = hv;
+        slot[(size_t)p * tx * ty + t] = (int32_t)(ht.size() - ch.h_t0[p]);
+        ht.push_back(h);
+        hv += (int64_t)h.D * h.D * tile * tile;
+        ch.h_dmax[p] = std::max(ch.h_dmax[p], h.D);
+      }
+      ch.h_nt[p] = (int64_t)ht.size() - ch.h_t0[p];
+      maxbin = std::max(maxbin, ch.bin_taps[p]);
+    }
+    ch.h_values = hv;
+    // G is built for runs of whole row groups of one bin at a time, at most CHT values
+    std::vector<int64_t> gtaps(ch.groups.size());
+    int64_t maxgroup = 0;
+    for (size_t i = 0; i < ch.groups.size(); ++i) {
+      const int64_t end = i + 1 < ch.groups.size() ? ch.groups[i + 1].voff : taps_total;
+      gtaps[i] = end - ch.groups[i].voff;
+      maxgroup = std::max(maxgroup, gtaps[i]);
+    }
+    const int64_t cap = std::max<int64_t>(1 << 16, (int64_t)(0.1 * opt.budget_fraction *
+                                                              (double)budget / 8.0));
+    const int64_t CHT = std::max<int64_t>(maxgroup, std::min<int64_t>(maxbin, cap));
+    const double need = (double)b_v * hv + (opt.store == WF_STORE_F32 ? 0.0 : 8.0 * hv) +
+                        8.0 * CHT;
+    if (need > opt.budget_fraction * (double)budget)
+      return fail(WF_EBUDGET, "holographic matrix needs " + std::to_string(need / 1e9) +
+                                  " GB (on-the-fly strategy (c) is not built)");
+    DevBuf hacc, gtmp, dslot;
+    tmp.b.push_back(&gtmp);
+    tmp.b.push_back(&dslot);
+    if ((st = dalloc(hacc, sizeof(float2) * std::max<int64_t>(hv, 1))) != WF_OK) return st;
+    struct HGuard {
+      DevBuf* b;
+      bool keep = false;
+      ~HGuard() {
+        if (!keep) dfree(*b);
+      }
+    } hguard{&hacc};
+    if ((st = dalloc(gtmp, sizeof(float2) * std::max<int64_t>(CHT, 1))) != WF_OK) return st;
+    // work items in row order, so that a run of groups maps to a slice of them
+    std::vector<WorkItem> wrow(wis);
+    std::sort(wrow.begin(), wrow.end(),
+              [](const WorkItem& a, const WorkItem& b) { return a.row0 < b.row0; });
+    DevBuf dwrow;
+    tmp.b.push_back(&dwrow);
+    if ((st = dalloc(dwrow, sizeof(WorkItem) * std::max<size_t>(wrow.size(), 1))) != WF_OK)
+      return st;
+    WF_HIP(hipMemcpyAsync(dwrow.p, wrow.data(), sizeof(WorkItem) * wrow.size(),
+                          hipMemcpyHostToDevice, s));
+    if ((st = dalloc(dslot, sizeof(int32_t) * slot.size())) != WF_OK) return st;
+    if ((st = dalloc(ch.htiles, sizeof(HTile) * std::max<size_t>(ht.size(), 1))) != WF_OK)
+      return st;
+    WF_HIP(hipMemsetAsync(hacc.p, 0, hacc.bytes, s));
+    WF_HIP(hipMemcpyAsync(dslot.p, slot.data(), sizeof(int32_t) * slot.size(),
+                          hipMemcpyHostToDevice, s));
+    WF_HIP(hipMemcpyAsync(ch.htiles.p, ht.data(), sizeof(HTile) * ht.size(),
+                          hipMemcpyHostToDevice, s));
+    size_t wi_at = 0;
+    for (size_t ga = 0; ga < ch.groups.size();) {
+      const int p = ch.groups[ga].bin;
+      size_t gb = ga;
+      int64_t taps = 0;
+      while (gb < ch.groups.size() && ch.groups[gb].bin == p && taps + gtaps[gb] <= CHT)
+        taps += gtaps[gb++];
+      const int64_t s0 = ch.groups[ga].row0;
+      const int64_t s1 = (int64_t)ch.groups[gb - 1].row0 + ch.groups[gb - 1].nrows;
+      const int64_t vbase = ch.groups[ga].voff;
+      size_t wj = wi_at;
+      while (wj < wrow.size() && wrow[wj].row0 < s1) ++wj;
+      WF_HIP(launch_gbuild((const double*)duvw.p, s0, s1, (const int32_t*)ch.perm.p,
+                           (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
+                           (const int32_t*)drowwi.p, (const WorkItem*)ch.work.p, ch.scale, gsx,
+                           gsy, (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
+                           gtmp.p, vbase, WF_STORE_F32, (int*)dmis.p, Surrogate{}, s));
+      WF_HIP(launch_hbuild((const WorkItem*)dwrow.p + wi_at, (int)(wj - wi_at),
+                           (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
+                           (const float2*)gtmp.p, vbase,
+                           (const int32_t*)dslot.p + (size_t)p * tx * ty,
+                           (const HTile*)ch.htiles.p + ch.h_t0[p], tx, tsh, Kx, Ky,
+                           (float*)hacc.p, s));
+      wi_at = wj;
+      ga = gb;
+    }
+    if (opt.store == WF_STORE_F32) {
+      ch.hvals = hacc;
+      hguard.keep = true;
+    } else {
+      if ((st = dalloc(ch.hvals, sizeof(uint32_t) * std::max<int64_t>(hv, 1))) != WF_OK)
+        return st;
+      WF_HIP(launch_hpack((const float2*)hacc.p, (uint32_t*)ch.hvals.p, hv, opt.store, s));
+    }
+    WF_HIP(hipStreamSynchronize(s));
+    ch.holo = true;
+  }
+  if (!holo) {
+  if ((st = dalloc(ch.vals, (size_t)b_v * std::max<int64_t>(taps_total, 1))) != WF_OK)
+    return st;
   st = surrogate_pass((const int32_t*)ch.perm.p,
                       [&](int64_t s0, int64_t s1, const Surrogate& sg) -> wf_status {
                         WF_HIP(launch_gbuild((const double*)duvw.p, s0, s1,
@@ -480,10 +609,11 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
                                              (const WorkItem*)ch.work.p, ch.scale, gsx, gsy,
                                              (const double*)dmids.p, ch.P,
                                              (const double*)dcents.p, op->kp, ch.vals.p,
-                                             opt.store, (int*)dmis.p, sg, s));
+                                             0, opt.store, (int*)dmis.p, sg, s));
                         return WF_OK;
                       });
   if (st != WF_OK) return st;
+  }
   int mismatch = 0;
   WF_HIP(hipMemcpyAsync(&mismatch, dmis.p, sizeof(int), hipMemcpyDeviceToHost, s));
   WF_HIP(hipStreamSynchronize(s));
@@ -494,7 +624,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   wf_plan_info& in = ch.info;
   in.nchan = (int32_t)op->chans.size();
   in.nbins = ch.P;
-  in.strategy = WF_PRECOMP_G;
+  in.strategy = holo ? WF_PRECOMP_H : WF_PRECOMP_G;
   in.store = opt.store;
   in.Kx = Kx;
   in.Ky = Ky;
@@ -514,6 +644,14 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   in.max_rows_per_item = ch.max_rows;
   in.surrogate_fraction = M ? (double)nused / (double)M : 0.0;
+  in.mem_h_bytes = holo ? (double)b_v * ch.h_values + (double)ch.htiles.bytes : 0.0;
+  if (holo) {
+    // only the stencils serve the applies of a holographic operator
+    dfree(ch.meta);
+    dfree(ch.voff);
+    dfree(ch.perm);
+    dfree(ch.work);
+  }
   return WF_OK;
 }
 
@@ -637,7 +775,14 @@ wf_status bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
     return layer_adjoint(op, L, out, wp, first ? 0 : 1, &pr);
   }
   if ((st = layer_forward(op, L, in, wp, &pr)) != WF_OK) return st;
-  {
+  if (ch.holo) {
+    ProfScope ps(prof_of(op, 0), L.s);
+    int tsh = 0;
+    while ((1 << tsh) < op->tile) ++tsh;
+    WF_HIP(launch_happly((const HTile*)ch.htiles.p + ch.h_t0[p], (int)ch.h_nt[p], ch.h_dmax[p],
+                         ch.hvals.p, op->opt.store, L.X, L.Y, op->Kx / op->tile, tsh, op->Kx,
+                         op->Ky, L.s));
+  } else {
     ProfScope ps(prof_of(op, 0), L.s);
     for (int c = 0; c < NCLS; ++c) {
       const int n = ch.cls_nwi[p * NCLS + c];
@@ -721,6 +866,10 @@ wf_status apply_entry(wf_op* op, int kind, const float* in, float* out, void* st
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
   if (!in || !out) return fail(WF_EINVAL, "null pointer");
+  if (kind == WF_APPLY_FORWARD || kind == WF_APPLY_ADJOINT)
+    for (const auto& ch : op->chans)
+      if (ch.holo)
+        return fail(WF_ENOTSUP, "a holographic operator applies Phi^dag Phi only");
   WF_HIP(hipSetDevice(op->device));
   return run_apply(op, kind, in, out, (hipStream_t)stream);
 }
@@ -847,6 +996,7 @@ wf_status ensure_branches(wf_op* op) {
       if ((st = dalloc(B.Y, grid)) != WF_OK) return st;
       if ((st = dalloc(B.A, arow)) != WF_OK) return st;
       WF_HIP(hipMemset(B.Y.p, 0, grid));
+      WF_HIP(hipMemset(B.X.p, 0, grid));
     }
     if (need_acc[b] && !B.acc.p) {
       if ((st = dalloc(B.acc, sizeof(float2) * (size_t)npix_of(op))) != WF_OK) return st;
@@ -871,7 +1021,7 @@ wf_status set_branches(wf_op* op, int n) {
 // item table and the rows' offsets inside their items change; the values stay put.
 wf_status retune_channel(wf_op* op, int c, int32_t maxrows) {
   ChanOp& ch = op->chans[c];
-  if (ch.nrows == 0 || ch.max_rows == maxrows) return WF_OK;
+  if (ch.nrows == 0 || ch.max_rows == maxrows || ch.holo) return WF_OK;
   const int64_t M = ch.nrows;
   WF_HIP(hipDeviceSynchronize());
   std::vector<uint32_t> meta(M), voff(M);
@@ -1059,6 +1209,7 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
     if ((st = dalloc(op->sx, sizeof(float) * nx)) != WF_OK) return st;
     if ((st = dalloc(op->sy, sizeof(float) * ny)) != WF_OK) return st;
     WF_HIP(hipMemsetAsync(B0.Y.p, 0, B0.Y.bytes, s));
+    WF_HIP(hipMemsetAsync(B0.X.p, 0, B0.X.bytes, s));
     WF_HIP(hipMemcpyAsync(op->twx.p, twx.data(), sizeof(float2) * Kx, hipMemcpyHostToDevice, s));
     WF_HIP(hipMemcpyAsync(op->twy.p, twy.data(), sizeof(float2) * Ky, hipMemcpyHostToDevice, s));
     WF_HIP(hipMemcpyAsync(op->sx.p, sx.data(), sizeof(float) * nx, hipMemcpyHostToDevice, s));
@@ -1143,6 +1294,7 @@ wf_status wf_get_row(const wf_op* op, int32_t chan, int64_t row, int32_t* T, int
     if (chan < 0 || chan >= (int)op->chans.size()) return fail(WF_EINVAL, "bad channel");
     const ChanOp& ch = op->chans[chan];
     if (row < 0 || row >= ch.nrows) return fail(WF_EINVAL, "row out of range");
+    if (ch.holo) return fail(WF_ENOTSUP, "a holographic operator keeps no rows of G");
     WF_HIP(hipSetDevice(op->device));
     WF_HIP(hipDeviceSynchronize());
     std::vector<int32_t> perm(ch.nrows);

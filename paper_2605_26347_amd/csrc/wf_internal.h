@@ -91,6 +91,15 @@ struct RowGroup {
   int32_t bin, cls;
 };
 
+// One active grid tile of a bin's holographic matrix: dense stencil of side D, values
+// [D * D][tile * tile] from voff (complex units) on.
+struct HTile {
+  int32_t tile;   // tv * tiles_x + tu
+  int32_t D;
+  int64_t voff;
+};
+static_assert(sizeof(HTile) == 16, "HTile layout");
+
 struct ChanOp {
   double freq = 0, scale = 0;
   int64_t vis_off = 0;   // offset of this channel's rows in the caller's vis vector
@@ -106,6 +115,11 @@ struct ChanOp {
   double measured_ms = 0;                  // last timed apply of this channel (0 = none)
   int64_t ntaps = 0;
   int64_t nwork = 0;
+  bool holo = false;                       // strategy (b): H only
+  DevBuf htiles, hvals;                    // HTile [tiles of all bins], stencil values
+  std::vector<int64_t> h_t0, h_nt;         // per bin: first tile, tile count
+  std::vector<int32_t> h_dmax;             // per bin: largest stencil side
+  int64_t h_values = 0;                    // stored stencil values (complex)
   DevBuf meta, voff, perm, vals, work;
   DevBuf prune;                            // per bin: strip bits, tile bits, groups
   std::vector<size_t> pr_strip, pr_tile, pr_groups;  // byte offsets into prune per bin
@@ -214,6 +228,17 @@ hipError_t launch_grid(int cls, const WorkItem* wi, int nwi, const uint32_t* met
 hipError_t launch_fill_zero(void* p, int64_t nfloats, hipStream_t s);
 hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
 hipError_t launch_add_into(float* out, const float* in, int64_t nfloats, hipStream_t s);
+// Holographic matrix: accumulate the stencils of one bin from its work items (values g
+// of that bin from vbase on, FP32), pack FP32 stencils to FP16 / BF16, and apply.
+hipError_t launch_hbuild(const WorkItem* wi, int nwi, const uint32_t* meta, const uint32_t* voff,
+                         const float2* g, int64_t vbase, const int32_t* slot_of_tile,
+                         const HTile* ht, int tiles_x, int tsh, int Kx, int Ky, float* h,
+                         hipStream_t s);
+hipError_t launch_hpack(const float2* src, uint32_t* dst, int64_t n, wf_store store,
+                        hipStream_t s);
+hipError_t launch_happly(const HTile* ht, int ntiles, int Dmax, const void* hv, wf_store store,
+                         const float2* X, float2* Y, int tiles_x, int tsh, int Kx, int Ky,
+                         hipStream_t s);
 hipError_t launch_strip_to_rowmajor(const float2* src, float2* dst, int R, int Q,
                                     hipStream_t s);
 
@@ -232,13 +257,14 @@ hipError_t launch_rowsym(const double* uvw, int64_t r0, int64_t r1, double scale
                          double gsy, const double* mids, int P, const double* cents, int Kx,
                          int Ky, int tile, const KernelParams& kp, uint64_t* keys,
                          float* dropped, const Surrogate& sg, hipStream_t s);
-// Value pass over sorted rows [s0, s1): writes each row's T*T values.
+// Value pass over sorted rows [s0, s1): writes each row's T*T values at its value offset
+// minus vbase.
 hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_t* perm,
                          const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
                          const WorkItem* wi, double scale, double gsx, double gsy,
                          const double* mids, int P, const double* cents,
-                         const KernelParams& kp, void* vals, wf_store store, int* mismatch,
-                         const Surrogate& sg, hipStream_t s);
+                         const KernelParams& kp, void* vals, int64_t vbase, wf_store store,
+                         int* mismatch, const Surrogate& sg, hipStream_t s);
 // Network inputs of rows [r0, r0 + nr) (caller order, or sorted order through perm).
 hipError_t launch_row_inputs(const double* uvw, const int32_t* perm, int64_t r0, int64_t nr,
                              double scale, double gsx, double gsy, const double* mids, int P,
