@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="precision",
-                    choices=["precision", "batched", "learned"],
+                    choices=["precision", "batched", "learned", "holographic"],
                     help="precision: one channel 4096^2 / 50M rows (default); batched: "
                          "16 channels 2048^2 / 48M rows, autotuned, one graph per sweep; "
                          "learned: G of 20M rows on 4096^2 / 16 bins built with the "
@@ -270,6 +270,72 @@ def bench_batched(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def bench_holographic(args, torch):
+    """Holographic strategy where it pays: the central 512^2 of the precision form
+    (same cell, 0.375 degree field) with all 50M visibilities, ~48 per grid cell.
+    Phi^dag Phi with the stencils of H_p = G_p^dag G_p against the fused G^dag G."""
+    import wfsynth as ws
+    from paper_2605_26347_amd import Operator
+    full = ws.precision_form(n=4096, nvis=args.nvis, fov_deg=args.fov, sky=False)
+    n = 512
+    cell = full.cell_rad
+    M = full.uvw_m.shape[0]
+    x = torch.from_numpy(ws.gauss_image(n, 4).astype(np.float32)[None]).to("cuda:0")
+    res = {}
+    for strat in ("G", "H"):
+        t0 = time.time()
+        op = Operator(full.uvw_m, full.freqs_hz, n, n, cell, memory_budget=args.budget,
+                      store=args.store, strategy=strat)
+        torch.cuda.synchronize()
+        tb = time.time() - t0
+        info = op.plan(0)
+        out = torch.empty_like(x)
+        for _ in range(args.warmup):
+            op.psf_apply_re(x, out)
+        op.profile_enable(0, True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            op.psf_apply_re(x, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        nl, kms = op.profile_read(0)
+        op.profile_enable(0, False)
+        byts = info["mem_h_bytes"] if strat == "H" else info["mem_g_bytes"]
+        res[strat] = dict(ms=ms, build_s=tb, nbins=info["nbins"], bytes=byts,
+                          kernel_ms=kms / max(args.steps, 1), out=out.clone())
+        log(f"{strat}: P={info['nbins']} built {tb:.1f} s, {byts / 1e9:.2f} GB, "
+            f"{ms:.3f} ms/apply (G^dag G or H part {kms / max(args.steps, 1):.3f} ms)")
+        op.close()
+        del op
+        torch.cuda.empty_cache()
+    d = float((res["H"]["out"] - res["G"]["out"]).norm() / res["G"]["out"].norm())
+    kh = res["H"]["kernel_ms"]
+    line = {
+        "metric": "Φ†Φ applies/s with the holographic H vs the fused G†G (512² crop of the "
+                  "4096² / 3° field, 50M vis)",
+        "value": 1e3 / res["H"]["ms"], "unit": "applies/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["H"]["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Re{{Phi^dag Phi x}}, {n}^2 image at the 4096^2 / 3 deg cell, "
+                               f"{M} visibilities", "store": args.store,
+                   "nbins": res["H"]["nbins"]},
+        "G": {k: v for k, v in res["G"].items() if k != "out"},
+        "H": {k: v for k, v in res["H"].items() if k != "out"},
+        "speedup_H_vs_G": res["G"]["ms"] / res["H"]["ms"],
+        "H_vs_G_rel": d,
+        "roofline": {"bound": "hbm", "kernel": "k_happly (H stencils)",
+                     "achieved": res["H"]["bytes"] / (kh * 1e-3) / 1e9 if kh > 0 else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (res["H"]["bytes"] / (kh * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                     if kh > 0 else None, "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_learned(args, torch):
     """Learned form: the residual-kernel network trained on 1M exact kernels (residual w
     of the 64-antenna array binned at 16 bins, fields of 1-4 degrees), then G of 20M rows
@@ -363,6 +429,9 @@ def main():
         return
     if args.workload == "learned":
         bench_learned(args, torch)
+        return
+    if args.workload == "holographic":
+        bench_holographic(args, torch)
         return
     t0 = time.time()
     obs = ws.precision_form(n=args.n, nvis=args.nvis, fov_deg=args.fov)

@@ -59,7 +59,7 @@ typedef enum { WF_STORE_F32 = 0, WF_STORE_F16 = 1, WF_STORE_BF16 = 2 } wf_store;
  * WF_EBUDGET -- (c) is not built (WF_ENOTSUP when requested).  A holographic operator
  * stores H_p = G_p^dag G_p as dense stencils per active 32 x 32 grid tile (side
  * 2 Tmax - 1, Tmax the largest patch side reaching the tile) and applies Phi^dag Phi
- * only: wf_forward / wf_adjoint / wf_get_row return WF_ENOTSUP for it.  Needs tile <= 32. */
+ * only: wf_forward / wf_adjoint / wf_get_row return WF_ENOTSUP for it.  Needs tile 32. */
 typedef enum { WF_AUTO = 0, WF_PRECOMP_G = 1, WF_PRECOMP_H = 2, WF_ONTHEFLY = 3 } wf_strategy;
 
 typedef struct {

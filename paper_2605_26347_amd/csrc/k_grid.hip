@@ -138,18 +138,36 @@ __device__ __forceinline__ void scatter_run(const RunGeom& r, int W, int lane,
   }
 }
 
-__device__ __forceinline__ void window_zero(float* accf, int W) {
-  for (int c = threadIdx.x; c < 2 * W * W; c += GNT) accf[c] = 0.f;
+// The work item's bounding box of patch cells in its window (packed by the host as
+// origin u, origin v, width, height, 8 bits each): only these cells are cleared and
+// flushed, which matters when an item holds few rows.
+struct Box {
+  int u0, v0, w, h;
+};
+__device__ __forceinline__ Box box_of(int32_t packed) {
+  const uint32_t b = (uint32_t)packed;
+  return Box{(int)(b & 0xff), (int)((b >> 8) & 0xff), (int)((b >> 16) & 0xff), (int)(b >> 24)};
 }
 
-__device__ __forceinline__ void window_flush(const float* accf, int W, int u0, int v0, int Kx,
-                                             int Ky, float2* __restrict__ Y) {
-  for (int c = threadIdx.x; c < W * W; c += GNT) {
-    const float2 v = make_float2(accf[c], accf[W * W + c]);
+__device__ __forceinline__ void window_zero(float* accf, int W, const Box& bx) {
+  const int n = bx.w * bx.h;
+  for (int c = threadIdx.x; c < n; c += GNT) {
+    const int a = c / bx.w, b = c - a * bx.w;
+    const int o = (bx.v0 + a) * W + bx.u0 + b;
+    accf[o] = 0.f;
+    accf[W * W + o] = 0.f;
+  }
+}
+__device__ __forceinline__ void window_flush(const float* accf, int W, const Box& bx, int u0,
+                                             int v0, int Kx, int Ky, float2* __restrict__ Y) {
+  const int n = bx.w * bx.h;
+  for (int c = threadIdx.x; c < n; c += GNT) {
+    const int a = c / bx.w, b = c - a * bx.w;
+    const int o = (bx.v0 + a) * W + bx.u0 + b;
+    const float2 v = make_float2(accf[o], accf[W * W + o]);
     if (v.x != 0.f || v.y != 0.f) {
-      const int a = c / W, b = c - a * W;
-      const int gu = (u0 + b) & (Kx - 1);
-      const int gv = (v0 + a) & (Ky - 1);
+      const int gu = (u0 + bx.u0 + b) & (Kx - 1);
+      const int gv = (v0 + bx.v0 + a) & (Ky - 1);
       float2* p = Y + strip_index(gv, gu, Ky);
       unsafeAtomicAdd(&p->x, v.x);
       unsafeAtomicAdd(&p->y, v.y);
@@ -174,8 +192,9 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   const WorkItem wi = wis[blockIdx.x];
   constexpr bool GATHER = MODE != 2;
   constexpr bool SCATTER = MODE != 1;
+  const Box bx = box_of(wi.box);
   if constexpr (SCATTER) {
-    window_zero(accf, W);
+    window_zero(accf, W, bx);
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
@@ -190,7 +209,7 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   if (r0 >= r1) {
     if constexpr (SCATTER) {
       __syncthreads();
-      window_flush(accf, W, wi.u0, wi.v0, Kx, Ky, Y);
+      window_flush(accf, W, bx, wi.u0, wi.v0, Kx, Ky, Y);
     }
     return;
   }
@@ -295,7 +314,7 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   if constexpr (SCATTER) {
     if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
     __syncthreads();
-    window_flush(accf, W, wi.u0, wi.v0, Kx, Ky, Y);
+    window_flush(accf, W, bx, wi.u0, wi.v0, Kx, Ky, Y);
   }
 }
 

@@ -90,23 +90,36 @@ __global__ __launch_bounds__(256) void k_hpack(const float2* __restrict__ src,
   }
 }
 
+// Four consecutive stencil values (cells c .. c + 3 of one offset) as FP32 pairs.
 template <int STORE>
-__device__ __forceinline__ float2 hval(const void* __restrict__ v, int64_t i) {
+__device__ __forceinline__ void hval4(const void* __restrict__ v, int64_t i, float2 (&h)[4]) {
   if constexpr (STORE == WF_STORE_F32) {
-    return reinterpret_cast<const float2*>(v)[i];
-  } else if constexpr (STORE == WF_STORE_F16) {
-    const uint32_t r = reinterpret_cast<const uint32_t*>(v)[i];
-    __half2 hv;
-    __builtin_memcpy(&hv, &r, 4);
-    return __half22float2(hv);
+    const float4* p = reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(v) + i);
+    const float4 a = p[0], b = p[1];
+    h[0] = make_float2(a.x, a.y);
+    h[1] = make_float2(a.z, a.w);
+    h[2] = make_float2(b.x, b.y);
+    h[3] = make_float2(b.z, b.w);
   } else {
-    const uint32_t r = reinterpret_cast<const uint32_t*>(v)[i];
-    return make_float2(__uint_as_float(r << 16), __uint_as_float(r & 0xffff0000u));
+    const uint4 r = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint32_t*>(v) + i);
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (STORE == WF_STORE_F16) {
+        __half2 hv;
+        __builtin_memcpy(&hv, &w[j], 4);
+        h[j] = __half22float2(hv);
+      } else {
+        h[j] = make_float2(__uint_as_float(w[j] << 16), __uint_as_float(w[j] & 0xffff0000u));
+      }
+    }
   }
 }
 
 // Y += H X over the active tiles of one bin; one workgroup per tile, the X window
 // (tile + 2R cells per side, wrapped on the periodic grid) staged in LDS as two planes.
+// Thread t owns the four consecutive cells 4t .. 4t + 3 of the tile (one vector load of
+// stencil values per offset).  tile * tile == 4 * 256.
 template <int STORE>
 __global__ __launch_bounds__(256) void k_happly(const HTile* __restrict__ ht,
                                                 const void* __restrict__ hv,
@@ -128,39 +141,29 @@ __global__ __launch_bounds__(256) void k_happly(const HTile* __restrict__ ht,
     xi[i] = x.y;
   }
   __syncthreads();
-  constexpr int CPT = 4;   // cells per thread (tile <= 32)
-  float ar[CPT], ai[CPT];
-  int cu[CPT], cv[CPT];
-#pragma unroll
-  for (int j = 0; j < CPT; ++j) {
-    ar[j] = ai[j] = 0.f;
-    const int c = threadIdx.x + j * 256;
-    cu[j] = c & (tile - 1);
-    cv[j] = c >> tsh;
-  }
-  for (int dv = 0; dv < t.D; ++dv)
+  const int c0 = 4 * threadIdx.x;
+  const int cv = c0 >> tsh, cu = c0 & (tile - 1);
+  float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int dv = 0; dv < t.D; ++dv) {
+    const float* rr = xr + (cv + dv) * W + cu;
+    const float* ri = xi + (cv + dv) * W + cu;
+    const int64_t rowbase = t.voff + (int64_t)dv * t.D * ncell + c0;
     for (int du = 0; du < t.D; ++du) {
-      const int64_t base = t.voff + (int64_t)(dv * t.D + du) * ncell;
+      float2 h[4];
+      hval4<STORE>(hv, rowbase + (int64_t)du * ncell, h);
 #pragma unroll
-      for (int j = 0; j < CPT; ++j) {
-        const int c = threadIdx.x + j * 256;
-        if (c < ncell) {
-          const float2 hvv = hval<STORE>(hv, base + c);
-          const int o = (cv[j] + dv) * W + (cu[j] + du);
-          const float x0 = xr[o], x1 = xi[o];
-          ar[j] += hvv.x * x0 - hvv.y * x1;
-          ai[j] += hvv.x * x1 + hvv.y * x0;
-        }
+      for (int j = 0; j < 4; ++j) {
+        const float x0 = rr[du + j], x1 = ri[du + j];
+        ar[j] += h[j].x * x0 - h[j].y * x1;
+        ai[j] += h[j].x * x1 + h[j].y * x0;
       }
     }
+  }
 #pragma unroll
-  for (int j = 0; j < CPT; ++j) {
-    const int c = threadIdx.x + j * 256;
-    if (c < ncell) {
-      float2* p = Y + strip_index(tv * tile + cv[j], tu * tile + cu[j], Ky);
-      const float2 y = *p;
-      *p = make_float2(y.x + ar[j], y.y + ai[j]);
-    }
+  for (int j = 0; j < 4; ++j) {
+    float2* p = Y + strip_index(tv * tile + cv, tu * tile + cu + j, Ky);
+    const float2 y = *p;
+    *p = make_float2(y.x + ar[j], y.y + ai[j]);
   }
 }
 

@@ -159,17 +159,27 @@ struct ProfScope {
 // largest items of a launch first so that the hardware's in-order dispatch starts the
 // longest work first.  trow: patch side of each sorted row.  Writes each row's value
 // offset inside its item (voff) and, if row_wi is given, its item index.
-void split_items(ChanOp& ch, const uint8_t* trow, int64_t maxrows, std::vector<WorkItem>& wis,
-                 uint32_t* voff, int32_t* row_wi) {
+void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t maxrows,
+                 std::vector<WorkItem>& wis, uint32_t* voff, int32_t* row_wi) {
   const int64_t maxtaps = 1 << 20;
   std::vector<WorkItem> w0;
   std::vector<int> wcls;
   std::vector<int64_t> wtaps;
+  int bb[4] = {255, 255, 0, 0};   // running box of the last item: u0, v0, u1, v1
+  auto close_box = [&]() {
+    if (w0.empty()) return;
+    w0.back().box = (int32_t)((uint32_t)bb[0] | ((uint32_t)bb[1] << 8) |
+                              ((uint32_t)(bb[2] - bb[0]) << 16) |
+                              ((uint32_t)(bb[3] - bb[1]) << 24));
+  };
   for (const RowGroup& g : ch.groups) {
     int64_t abs = g.voff, taps_in = 0;
     for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) {
       const int64_t t2 = (int64_t)trow[r] * trow[r];
       if (r == g.row0 || w0.back().nrows >= maxrows || taps_in + t2 > maxtaps) {
+        close_box();
+        bb[0] = bb[1] = 255;
+        bb[2] = bb[3] = 0;
         WorkItem wi{};
         wi.voff = abs;
         wi.row0 = (int32_t)r;
@@ -182,6 +192,15 @@ void split_items(ChanOp& ch, const uint8_t* trow, int64_t maxrows, std::vector<W
         wtaps.push_back(0);
         taps_in = 0;
       }
+      {
+        const uint32_t m = meta[r];
+        const int lu0 = (int)(m & 0xff), lv0 = (int)((m >> 8) & 0xff);
+        const int T = (int)((m >> 16) & 0xff);
+        bb[0] = std::min(bb[0], lu0);
+        bb[1] = std::min(bb[1], lv0);
+        bb[2] = std::max(bb[2], lu0 + T);
+        bb[3] = std::max(bb[3], lv0 + T);
+      }
       voff[r] = (uint32_t)taps_in;
       if (row_wi) row_wi[r] = (int32_t)(w0.size() - 1);
       w0.back().nrows++;
@@ -190,6 +209,7 @@ void split_items(ChanOp& ch, const uint8_t* trow, int64_t maxrows, std::vector<W
       abs += t2;
     }
   }
+  close_box();
   std::vector<int32_t> order(w0.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
@@ -378,7 +398,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   }
   std::vector<WorkItem> wis;
   ch.max_rows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
-  split_items(ch, trow.data(), ch.max_rows, wis, voff.data(), row_wi.data());
+  split_items(ch, trow.data(), meta.data(), ch.max_rows, wis, voff.data(), row_wi.data());
 
   // active uv support per bin: tiles holding rows, dilated to cover the LDS windows'
   // halo, the column strips under them and the column groups of the column passes
@@ -471,7 +491,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   if (holo) {
     // holographic matrix (Sect. 3.3): stencil tiles of every bin, accumulated from that
     // bin's rows of G built one bin at a time in FP32; G itself is not kept
-    if (tile > 32) return fail(WF_EINVAL, "the holographic strategy needs tile <= 32");
+    if (tile != 32) return fail(WF_EINVAL, "the holographic strategy needs tile 32");
     const int tx = Kx / tile, ty = Ky / tile;
     int tsh = 0;
     while ((1 << tsh) < tile) ++tsh;
@@ -1028,9 +1048,8 @@ wf_status retune_channel(wf_op* op, int c, int32_t maxrows) {
   WF_HIP(hipMemcpy(meta.data(), ch.meta.p, sizeof(uint32_t) * M, hipMemcpyDeviceToHost));
   std::vector<uint8_t> trow(M);
   for (int64_t r = 0; r < M; ++r) trow[r] = (uint8_t)((meta[r] >> 16) & 0xff);
-  std::vector<uint32_t>().swap(meta);
   std::vector<WorkItem> wis;
-  split_items(ch, trow.data(), maxrows, wis, voff.data(), nullptr);
+  split_items(ch, trow.data(), meta.data(), maxrows, wis, voff.data(), nullptr);
   if (ch.work.bytes < sizeof(WorkItem) * wis.size()) {
     dfree(ch.work);
     wf_status st = dalloc(ch.work, sizeof(WorkItem) * wis.size());

@@ -31,7 +31,8 @@ struct WorkItem {
   int32_t nrows;  // rows in this item
   int32_t u0, v0; // window origin
   int32_t bin;
-  int32_t pad;
+  int32_t box;    // window-local bounding box of the rows' patches: u0 | v0 << 8 |
+                  // width << 16 | height << 24
 };
 static_assert(sizeof(WorkItem) == 32, "WorkItem layout");
 
