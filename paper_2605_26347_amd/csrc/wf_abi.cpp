@@ -1316,26 +1316,30 @@ wf_status wf_get_row(const wf_op* op, int32_t chan, int64_t row, int32_t* T, int
     if (ch.holo) return fail(WF_ENOTSUP, "a holographic operator keeps no rows of G");
     WF_HIP(hipSetDevice(op->device));
     WF_HIP(hipDeviceSynchronize());
-    std::vector<int32_t> perm(ch.nrows);
-    WF_HIP(hipMemcpy(perm.data(), ch.perm.p, sizeof(int32_t) * ch.nrows, hipMemcpyDeviceToHost));
-    int64_t s = -1;
-    for (int64_t i = 0; i < ch.nrows; ++i)
-      if (perm[i] == row) {
-        s = i;
-        break;
-      }
+    // host index of the stored rows, built on first use (and after a re-split)
+    DebugIndex& dx = ch.dbg;
+    if (dx.gen != op->generation + 1) {
+      std::vector<int32_t> perm(ch.nrows);
+      WF_HIP(hipMemcpy(perm.data(), ch.perm.p, sizeof(int32_t) * ch.nrows,
+                       hipMemcpyDeviceToHost));
+      dx.sorted_of.assign(ch.nrows, -1);
+      for (int64_t i = 0; i < ch.nrows; ++i) dx.sorted_of[perm[i]] = (int32_t)i;
+      dx.items.resize(ch.nwork);
+      WF_HIP(hipMemcpy(dx.items.data(), ch.work.p, sizeof(WorkItem) * ch.nwork,
+                       hipMemcpyDeviceToHost));
+      dx.item_of.assign(ch.nrows, 0);
+      for (int64_t i = 0; i < ch.nwork; ++i)
+        for (int32_t r = 0; r < dx.items[i].nrows; ++r)
+          dx.item_of[dx.items[i].row0 + r] = (int32_t)i;
+      dx.gen = op->generation + 1;
+    }
+    const int64_t s = dx.sorted_of[row];
     if (s < 0) return fail(WF_EINVAL, "row not found");
     uint32_t m, vo;
     WF_HIP(hipMemcpy(&m, (const uint32_t*)ch.meta.p + s, 4, hipMemcpyDeviceToHost));
     WF_HIP(hipMemcpy(&vo, (const uint32_t*)ch.voff.p + s, 4, hipMemcpyDeviceToHost));
-    std::vector<WorkItem> wis(ch.nwork);
-    WF_HIP(hipMemcpy(wis.data(), ch.work.p, sizeof(WorkItem) * ch.nwork, hipMemcpyDeviceToHost));
-    int64_t w = 0;
-    for (int64_t i = 0; i < ch.nwork; ++i)
-      if (s >= wis[i].row0 && s < wis[i].row0 + wis[i].nrows) {
-        w = i;
-        break;
-      }
+    const std::vector<WorkItem>& wis = dx.items;
+    const int64_t w = dx.item_of[s];
     const int t = (m >> 16) & 0xff, lu0 = m & 0xff, lv0 = (m >> 8) & 0xff;
     if (T) *T = t;
     if (qu0) *qu0 = (wis[w].u0 + lu0) & (op->Kx - 1);

@@ -101,6 +101,14 @@ struct HTile {
 };
 static_assert(sizeof(HTile) == 16, "HTile layout");
 
+// Host index of the stored rows for the diagnostic row reader (built on first use).
+struct DebugIndex {
+  uint64_t gen = 0;                        // operator generation + 1 when valid
+  std::vector<int32_t> sorted_of;          // caller row -> sorted row
+  std::vector<int32_t> item_of;            // sorted row -> work item
+  std::vector<WorkItem> items;
+};
+
 struct ChanOp {
   double freq = 0, scale = 0;
   int64_t vis_off = 0;   // offset of this channel's rows in the caller's vis vector
@@ -127,6 +135,7 @@ struct ChanOp {
   std::vector<int32_t> pr_ngroups;
   std::vector<double> active_tile_frac;
   wf_plan_info info{};
+  mutable DebugIndex dbg;
 };
 
 struct Profiler {
