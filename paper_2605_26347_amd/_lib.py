@@ -104,6 +104,9 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2605_26347_amd.build_lib` (no CPU fallback exists)")
+    # torch first: the library then binds to the HIP runtime torch has loaded (same
+    # soname), so that one runtime owns the device, the tensors' memory and the streams
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
