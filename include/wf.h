@@ -244,6 +244,24 @@ typedef struct {
 wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_stream,
                       int32_t reps, wf_tune_info* info);
 
+/* ------------------------------------------------------------------ forward-backward
+ * The operator's consumer (Sect. 2, eq. 4): x <- D(x + gamma (x_dirty - Re{Phi^dag Phi x}))
+ * with x_dirty = Re{Phi^dag y}, here with the non-learned denoiser D(z) = max(z - gamma
+ * lambda, 0), the prox of lambda ||x||_1 under positivity.  Images are real FP32
+ * [nchan][ny][nx] device buffers; the library keeps two work images of that size (and a
+ * complex one for the dirty image), allocated on first use. */
+
+/* x_dirty = Re{Phi^dag y}; d_vis complex FP32 [total rows].  Not for holographic
+ * operators (WF_ENOTSUP). */
+wf_status wf_dirty_image(wf_op* op, const float* d_vis, float* d_dirty, void* hip_stream);
+/* Largest eigenvalue of x -> Re{Phi^dag Phi x}, by `iters` power iterations from the
+ * normalised all-ones image (Rayleigh quotient of the last iterate, a lower bound);
+ * gamma < 2 / norm makes eq. 4 convergent.  Synchronous. */
+wf_status wf_op_norm(wf_op* op, int32_t iters, double* norm, void* hip_stream);
+/* `iters` forward-backward iterations on d_x in place (asynchronous). */
+wf_status wf_fb_iterate(wf_op* op, const float* d_dirty, float* d_x, int32_t iters,
+                        double gamma, double lambda, void* hip_stream);
+
 /* ------------------------------------------------------------------ learned kernels
  * Not in the paper.  A multilayer perceptron predicts the thresholded residual-w kernel
  * of Sect. 3.1 (the w-projection kernel built from the tapered chirp, Fig. 1) so that

@@ -168,6 +168,30 @@ class Operator:
               "wf_profile_read")
         return n.value, ms.value
 
+    # ------------------------------------------------------------------ forward-backward
+    def dirty_image(self, vis, out=None, stream=None):
+        """Re{Phi^dag y} as float32 [nchan, ny, nx]."""
+        import torch
+        if out is None:
+            out = torch.empty((self.nchan, self.ny, self.nx), dtype=torch.float32,
+                              device=vis.device)
+        self._call("wf_dirty_image", vis, out, stream)
+        return out
+
+    def op_norm(self, iters=50, stream=None):
+        """Largest eigenvalue of Re{Phi^dag Phi} by power iteration."""
+        v = ctypes.c_double()
+        check(self._lib.wf_op_norm(self._h, int(iters), ctypes.byref(v),
+                                   _stream_handle(stream)), "wf_op_norm")
+        return v.value
+
+    def fb_iterate(self, dirty, x, iters, gamma, lam, stream=None):
+        """iters forward-backward iterations (eq. 4) on x in place."""
+        check(self._lib.wf_fb_iterate(self._h, ctypes.c_void_p(dirty.data_ptr()),
+                                      ctypes.c_void_p(x.data_ptr()), int(iters), float(gamma),
+                                      float(lam), _stream_handle(stream)), "wf_fb_iterate")
+        return x
+
     # ------------------------------------------------------------------ batched form
     def set_branches(self, n):
         """Run applies on n concurrent branches (streams with their own work grids)."""

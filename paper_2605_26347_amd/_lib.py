@@ -78,6 +78,9 @@ SIGNATURES = {
     "wf_latency_enable": (_I32, [_P, _I32]),
     "wf_read_latency": (_I32, [_P, _P, _I32]),
     "wf_autotune": (_I32, [_P, _P, _P, _P, _I32, ctypes.POINTER(WfTuneInfo)]),
+    "wf_dirty_image": (_I32, [_P, _P, _P, _P]),
+    "wf_op_norm": (_I32, [_P, _I32, ctypes.POINTER(_D), _P]),
+    "wf_fb_iterate": (_I32, [_P, _P, _P, _I32, _D, _D, _P]),
     "wf_mlp_create": (_I32, [ctypes.c_uint64, ctypes.POINTER(_P)]),
     "wf_mlp_destroy": (_I32, [_P]),
     "wf_mlp_num_params": (_I64, []),
@@ -103,7 +106,7 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_2605_26347_amd.build_lib` (no CPU fallback exists)")
+                          "`python paper_2605_26347_amd/build_lib.py` (no CPU fallback exists)")
     # torch first: the library then binds to the HIP runtime torch has loaded (same
     # soname), so that one runtime owns the device, the tensors' memory and the streams
     import torch  # noqa: F401

@@ -1,6 +1,7 @@
 """Compile the HIP/C++ sources of the operator library into libwf.so (gfx950).
 
-Usage: python -m paper_2605_26347_amd.build_lib   (or call build()).
+Usage: python paper_2605_26347_amd/build_lib.py   (by path: importing the package would
+load the library it builds), or __graft_entry__.build().
 Each translation unit is compiled by hipcc in parallel, then linked as one shared
 library next to this file.  FP32 packed-math instructions are disabled for all device
 code; the FP64 build kernels are compiled without floating-point contraction so that

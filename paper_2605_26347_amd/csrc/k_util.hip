@@ -71,3 +71,99 @@ hipError_t launch_add_into(float* out, const float* in, int64_t nfloats, hipStre
 }
 
 }  // namespace wf
+
+// ------------------------------------------------------------------ forward-backward
+// (Sect. 2, eq. 4) elementwise steps and reductions of the FB driver.
+
+namespace wf {
+
+namespace {
+
+// x <- max(x + gamma (dirty - hx) - t, 0): gradient step of 1/2 ||Phi x - y||^2 followed
+// by the prox of t ||x||_1 under positivity.
+__global__ __launch_bounds__(256) void k_fb_step(float* __restrict__ x,
+                                                 const float* __restrict__ dirty,
+                                                 const float* __restrict__ hx, float gamma,
+                                                 float t, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = fmaxf(x[i] + gamma * (dirty[i] - hx[i]) - t, 0.f);
+}
+
+// *out += sum a[i] b[i] (out cleared by the caller); block sums in LDS, one atomic each.
+__global__ __launch_bounds__(256) void k_dot(const float* __restrict__ a,
+                                             const float* __restrict__ b, int64_t n,
+                                             float* __restrict__ out) {
+  __shared__ float part[256];
+  float s = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    s += a[i] * b[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, part[0]);
+}
+
+// dst = src / sqrt(*nrm2)
+__global__ __launch_bounds__(256) void k_normalize(float* __restrict__ dst,
+                                                   const float* __restrict__ src, int64_t n,
+                                                   const float* __restrict__ nrm2) {
+  const float s = rsqrtf(fmaxf(*nrm2, 1e-30f));
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i] * s;
+}
+
+__global__ __launch_bounds__(256) void k_fill_value(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_real_part(const float2* __restrict__ src,
+                                                   float* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i].x;
+}
+
+unsigned blocks_for(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+}
+
+}  // namespace
+
+hipError_t launch_fb_step(float* x, const float* dirty, const float* hx, float gamma, float t,
+                          int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fb_step, dim3(blocks_for(n)), dim3(256), 0, s, x, dirty, hx, gamma, t, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const float* a, const float* b, int64_t n, float* out, hipStream_t s) {
+  hipError_t e = launch_fill_zero(out, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dot, dim3(blocks_for(n)), dim3(256), 0, s, a, b, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(float* dst, const float* src, int64_t n, const float* nrm2,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize, dim3(blocks_for(n)), dim3(256), 0, s, dst, src, n, nrm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_value(float* p, int64_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_value, dim3(blocks_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_part(const float2* src, float* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_real_part, dim3(blocks_for(n)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace wf

@@ -102,6 +102,10 @@ void destroy_op(wf_op* op) {
   for (size_t b = 0; b < op->br.size(); ++b) release_branch(op->br[b], b > 0);
   if (op->fork) (void)hipEventDestroy(op->fork);
   dfree(op->stamps);
+  dfree(op->fb_h);
+  dfree(op->fb_x);
+  dfree(op->fb_c);
+  dfree(op->fb_red);
   dfree(op->twx);
   dfree(op->twy);
   dfree(op->sx);
@@ -1589,6 +1593,81 @@ wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_str
   } catch (const std::exception& e) {
     return fail(WF_EINVAL, e.what());
   }
+}
+
+// ------------------------------------------------------------------ forward-backward
+
+namespace {
+
+wf_status fb_buffers(wf_op* op, bool complex_too) {
+  const int64_t n = npix_of(op) * (int64_t)op->chans.size();
+  wf_status st;
+  if (!op->fb_h.p && (st = dalloc(op->fb_h, sizeof(float) * n)) != WF_OK) return st;
+  if (!op->fb_x.p && (st = dalloc(op->fb_x, sizeof(float) * n)) != WF_OK) return st;
+  if (!op->fb_red.p && (st = dalloc(op->fb_red, sizeof(float) * 4)) != WF_OK) return st;
+  if (complex_too && !op->fb_c.p && (st = dalloc(op->fb_c, sizeof(float2) * n)) != WF_OK)
+    return st;
+  return WF_OK;
+}
+
+}  // namespace
+
+wf_status wf_dirty_image(wf_op* op, const float* d_vis, float* d_dirty, void* stream) {
+  wf_status st = check_op(op);
+  if (st != WF_OK) return st;
+  if (!d_vis || !d_dirty) return fail(WF_EINVAL, "null pointer");
+  for (const auto& ch : op->chans)
+    if (ch.holo) return fail(WF_ENOTSUP, "a holographic operator has no Phi^dag");
+  WF_HIP(hipSetDevice(op->device));
+  if ((st = fb_buffers(op, true)) != WF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = run_apply(op, WF_APPLY_ADJOINT, d_vis, (float*)op->fb_c.p, s)) != WF_OK) return st;
+  WF_HIP(launch_real_part((const float2*)op->fb_c.p, d_dirty,
+                          npix_of(op) * (int64_t)op->chans.size(), s));
+  return WF_OK;
+}
+
+wf_status wf_op_norm(wf_op* op, int32_t iters, double* norm, void* stream) {
+  wf_status st = check_op(op);
+  if (st != WF_OK) return st;
+  if (iters < 1 || !norm) return fail(WF_EINVAL, "bad power-iteration arguments");
+  WF_HIP(hipSetDevice(op->device));
+  if ((st = fb_buffers(op, false)) != WF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = npix_of(op) * (int64_t)op->chans.size();
+  float* x = (float*)op->fb_x.p;
+  float* z = (float*)op->fb_h.p;
+  float* red = (float*)op->fb_red.p;
+  WF_HIP(launch_fill_value(x, n, (float)(1.0 / std::sqrt((double)n)), s));
+  for (int it = 0; it < iters; ++it) {
+    if ((st = run_apply(op, WF_APPLY_PSF_RE, x, z, s)) != WF_OK) return st;
+    if (it + 1 == iters) WF_HIP(launch_dot(x, z, n, red, s));
+    WF_HIP(launch_dot(z, z, n, red + 1, s));
+    WF_HIP(launch_normalize(x, z, n, red + 1, s));
+  }
+  float L = 0.f;
+  WF_HIP(hipMemcpyAsync(&L, red, sizeof(float), hipMemcpyDeviceToHost, s));
+  WF_HIP(hipStreamSynchronize(s));
+  *norm = L;
+  return WF_OK;
+}
+
+wf_status wf_fb_iterate(wf_op* op, const float* d_dirty, float* d_x, int32_t iters,
+                        double gamma, double lambda, void* stream) {
+  wf_status st = check_op(op);
+  if (st != WF_OK) return st;
+  if (!d_dirty || !d_x || iters < 0 || !(gamma > 0) || !(lambda >= 0))
+    return fail(WF_EINVAL, "bad forward-backward arguments");
+  WF_HIP(hipSetDevice(op->device));
+  if ((st = fb_buffers(op, false)) != WF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = npix_of(op) * (int64_t)op->chans.size();
+  for (int it = 0; it < iters; ++it) {
+    if ((st = run_apply(op, WF_APPLY_PSF_RE, d_x, (float*)op->fb_h.p, s)) != WF_OK) return st;
+    WF_HIP(launch_fb_step(d_x, d_dirty, (const float*)op->fb_h.p, (float)gamma,
+                          (float)(gamma * lambda), n, s));
+  }
+  return WF_OK;
 }
 
 wf_status wf_destroy(wf_op* op) {

@@ -188,6 +188,7 @@ struct wf_op {
   bool stamping = false;
   bool capturing = false;
   uint64_t generation = 0;           // bumped when work items or branches change
+  wf::DevBuf fb_h, fb_x, fb_c, fb_red;  // forward-backward work images and reductions
 };
 
 // Residual-kernel network: FP32 parameters with Adam state, per-batch activations, and
@@ -238,6 +239,15 @@ hipError_t launch_grid(int cls, const WorkItem* wi, int nwi, const uint32_t* met
 hipError_t launch_fill_zero(void* p, int64_t nfloats, hipStream_t s);
 hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
 hipError_t launch_add_into(float* out, const float* in, int64_t nfloats, hipStream_t s);
+// Forward-backward driver (eq. 4): x <- max(x + gamma (dirty - hx) - t, 0); *out = a.b;
+// dst = src / sqrt(*nrm2); fill with a value; real part of complex values.
+hipError_t launch_fb_step(float* x, const float* dirty, const float* hx, float gamma, float t,
+                          int64_t n, hipStream_t s);
+hipError_t launch_dot(const float* a, const float* b, int64_t n, float* out, hipStream_t s);
+hipError_t launch_normalize(float* dst, const float* src, int64_t n, const float* nrm2,
+                            hipStream_t s);
+hipError_t launch_fill_value(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_real_part(const float2* src, float* dst, int64_t n, hipStream_t s);
 // Holographic matrix: accumulate the stencils of one bin from its work items (values g
 // of that bin from vbase on, FP32), pack FP32 stencils to FP16 / BF16, and apply.
 hipError_t launch_hbuild(const WorkItem* wi, int nwi, const uint32_t* meta, const uint32_t* voff,
