@@ -102,10 +102,14 @@ def time_form(obs, store, args, torch):
     x = torch.from_numpy(obs.sky.astype(np.float32)[None]).to("cuda:0")
     out = torch.empty_like(x)
     stream = torch.cuda.current_stream()
+    # the library's autotuner picks the rows per work item and the number of concurrent
+    # branches (w-bins of the channel spread over streams) by timing applies
+    tune = op.autotune(x, out, reps=2)
+    info = op.plan(0)
+    log(f"{store}: autotune {tune}, rows per item {info['max_rows_per_item']}")
     for i in range(args.warmup):
         op.psf_apply_re(x, out)
     torch.cuda.synchronize()
-    op.profile_enable(0, True)
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -117,12 +121,38 @@ def time_form(obs, store, args, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     ms = start.elapsed_time(end) / args.steps
+    # the fused kernel on its own (one branch, so that no other kernel shares the GPU
+    # while its launches are timed), HIP events on its stream
+    op.set_branches(1)
+    for i in range(args.warmup):
+        op.psf_apply_re(x, out)
+    op.profile_enable(0, True)
+    for i in range(args.steps):
+        op.psf_apply_re(x, out)
     nl, kms = op.profile_read(0)
     op.profile_enable(0, False)
-    log(f"{store}: {ms:.3f} ms/apply (wall {1e3 * wall / args.steps:.3f}), "
-        f"G^dag G {kms / max(nl, 1):.3f} ms/launch over {nl} launches")
+    log(f"{store}: {ms:.3f} ms/apply (wall {1e3 * wall / args.steps:.3f}) on "
+        f"{tune['branches']} branches; G^dag G alone {kms / max(nl, 1):.3f} ms/launch over "
+        f"{nl} launches")
     res = dict(ms=ms, info=info, build_s=tb, gtg_launches=nl, gtg_ms_total=kms,
-               out=out.clone(), store=store)
+               out=out.clone(), store=store, tune=tune)
+    if store == args.forms.split(",")[0]:
+        # forward-backward iterations (eq. 4) on the same operator, tuned branches
+        op.set_branches(tune["branches"])
+        y = op.forward(x)
+        dirty = op.dirty_image(y)
+        L = op.op_norm(10)
+        xk = torch.zeros_like(x)
+        op.fb_iterate(dirty, xk, 1, 1.0 / L, 0.0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        op.fb_iterate(dirty, xk, 5, 1.0 / L, 0.0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res["fb_ms"] = e0.elapsed_time(e1) / 5
+        log(f"{store}: forward-backward iteration {res['fb_ms']:.3f} ms")
     op.close()
     del op
     torch.cuda.empty_cache()
@@ -479,10 +509,13 @@ def main():
                       "ntaps": r["info"]["ntaps"], "build_s": r["build_s"],
                       "g_bytes": r["info"]["mem_g_bytes"]} for f, r in res.items()},
         "accuracy": acc,
+        "autotune": head["tune"],
+        "fb_iteration_ms": head.get("fb_ms"),
         "roofline": {"bound": "hbm", "kernel": "fused G^dag G (k_gtg)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": per_launch, "ms_per_launch": kms,
+                     "timed": "one branch, HIP events around each launch on its stream",
                      "share_of_step": kms * P / head["ms"]},
     }
     if "f32" in res and forms[0] != "f32":
