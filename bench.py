@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="precision",
-                    choices=["precision", "batched", "learned", "holographic"],
+                    choices=["precision", "batched", "learned", "holographic", "counters"],
                     help="precision: one channel 4096^2 / 50M rows (default); batched: "
                          "16 channels 2048^2 / 48M rows, autotuned, one graph per sweep; "
                          "learned: G of 20M rows on 4096^2 / 16 bins built with the "
@@ -300,6 +300,32 @@ def bench_batched(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def counters_run(args, torch):
+    """Counter-collection run (under rocprofv3 --pmc): a plain 1 GiB device copy for
+    calibrating the byte counters, then exactly one Re{Phi^dag Phi} apply of the precision
+    form per storage form (one branch, default work items), so that the fused kernel's
+    counters summed over the run and divided by P are the bytes of one launch per bin."""
+    import wfsynth as ws
+    from paper_2605_26347_amd import Operator
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+    obs = ws.precision_form(n=args.n, nvis=args.nvis, fov_deg=args.fov)
+    x = torch.from_numpy(obs.sky.astype(np.float32)[None]).to("cuda:0")
+    for f in args.forms.split(","):
+        op = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad,
+                      memory_budget=args.budget, store=f)
+        out = op.psf_apply_re(x)
+        torch.cuda.synchronize()
+        log(f"counters: {f} P={op.plan(0)['nbins']} one apply done")
+        op.close()
+        del op, out
+        torch.cuda.empty_cache()
+
+
 def bench_holographic(args, torch):
     """Holographic strategy where it pays: the central 512^2 of the precision form
     (same cell, 0.375 degree field) with all 50M visibilities, ~48 per grid cell.
@@ -462,6 +488,9 @@ def main():
         return
     if args.workload == "holographic":
         bench_holographic(args, torch)
+        return
+    if args.workload == "counters":
+        counters_run(args, torch)
         return
     t0 = time.time()
     obs = ws.precision_form(n=args.n, nvis=args.nvis, fov_deg=args.fov)
