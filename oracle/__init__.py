@@ -21,6 +21,9 @@ of the widefield radio-interferometric measurement model"):
 * ``operator``   -- Phi = [G_p F Z_p]_p (eq. 6), its adjoint, Phi^dag Phi (eq. 7-8)
                     and the holographic matrix H_p = G_p^dag G_p (Sect. 3.3), all in
                     FP64, matrix-free over row chunks.
+* ``weighting``  -- Briggs robust data weights (published definition; the paper names
+                    the scheme in Sect. 2 without a formula); the operator itself takes
+                    per-row weights and flags (``OracleOperator(weights=, flags=)``).
 * ``planner``    -- WSClean bin bound (eq. 5), memory model (eq. 9, GPU byte form),
                     cost model (eq. 10) and the decision tree (Sect. 3.4, Fig. 2).
 * ``mlp``        -- (not in the paper) FP64 forward, backward and Adam step of the
@@ -31,7 +34,9 @@ Pins (tests/test_oracle_*.py): brute-force direct sum, adjointness to 1e-12,
 Hermitian positive semi-definiteness, w-stacking exactness on quantised w,
 residual-kernel convergence towards the true-w direct sum, closed forms (delta
 images, w = 0 PSF convolution), k-means against an exact dynamic programme, and
-hand-computed planner values.
+hand-computed planner values; weighted rows against the weighted direct sum, flags
+against building on the kept rows, Briggs weights against a hand-computed example and
+their natural / uniform limits.
 """
 from .kernels import (kb_phi, kb_phihat, grid_correction, chirp, nm1, i0_series)  # noqa: F401
 from .directsum import direct_forward, direct_adjoint, direct_matrix  # noqa: F401

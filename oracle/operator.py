@@ -12,6 +12,10 @@ Sect. 3.3, eq. 7-8: Phi^dag Phi = sum_p Z_p^dag F^dag G_p^dag G_p F Z_p, F^dag b
 unnormalised inverse DFT followed by the crop back to the image positions;
 H_p = G_p^dag G_p.
 Sect. 2, eq. 3: (u, v, w) are baseline components in wavelengths, u = u_m f / c.
+Sect. 2 (data weighting, flags): a per-measurement weight omega_k scales row k of the
+operator, Phi_W = diag(omega) Phi, so Phi_W^dag Phi_W = Phi^dag diag(omega^2) Phi; a
+flagged measurement is discarded before anything else (planning included) and its
+forward value is zero.
 """
 from __future__ import annotations
 
@@ -72,11 +76,22 @@ class OracleOperator:
     """FP64 widefield operator for one channel.
 
     uvw_m: [M, 3] metres; freq_hz: scalar.  Bins: either `centroids` (ascending) or
-    `nbins` (k-means on the planning subset drawn with `seed`, `plan_fraction`)."""
+    `nbins` (k-means on the planning subset drawn with `seed`, `plan_fraction`).
+    weights: [M] real or None (all ones), scaling the rows of G; flags: [M] bool or None,
+    True = discarded.  forward() returns all M values (zero where flagged) and adjoint()
+    takes all M (flagged entries ignored); internally only the kept rows exist."""
 
     def __init__(self, uvw_m, freq_hz, prm: OperatorParams, nbins=None, centroids=None,
-                 seed=0, plan_fraction=0.01, chunk=16384, cache_bytes=2 << 30):
+                 seed=0, plan_fraction=0.01, chunk=16384, cache_bytes=2 << 30,
+                 weights=None, flags=None):
         self.prm = prm
+        uvw_m = np.asarray(uvw_m, dtype=np.float64)
+        self.M_all = uvw_m.shape[0]
+        self.keep = (np.arange(self.M_all) if flags is None
+                     else np.nonzero(~np.asarray(flags, dtype=bool))[0])
+        uvw_m = uvw_m[self.keep]
+        self.omega = (None if weights is None
+                      else np.asarray(weights, dtype=np.float64)[self.keep])
         scale = freq_hz / C_LIGHT
         self.u = uvw_m[:, 0] * scale
         self.v = uvw_m[:, 1] * scale
@@ -151,6 +166,8 @@ class OracleOperator:
                 Ku = np.where(valid[None], tu[rows][:, ac], 0.0)       # [b, T, n']
                 Kv = np.where(valid[None], tv[rows][:, ac], 0.0)
                 g = Kv @ ker @ np.swapaxes(Ku, 1, 2)                    # [b, T, T]
+                if self.omega is not None:
+                    g = g * self.omega[idx[rows]][:, None, None]
                 out.append((idx[rows], rv[rows] - half - hp, ru[rows] - half - hp, g))
         nbytes = sum(o[3].nbytes for o in out)
         if self._cache_used + nbytes <= self.cache_bytes:
@@ -204,7 +221,7 @@ class OracleOperator:
 
     # ------------------------------------------------------------------ operators
     def forward(self, x):
-        """Phi x (eq. 3, eq. 6); x: [ny, nx] real or complex -> y [M] complex."""
+        """Phi x (eq. 3, eq. 6); x: [ny, nx] real or complex -> y [M_all] complex."""
         y = np.zeros(self.M, dtype=np.complex128)
         for p in range(self.P):
             if self.bin_rows[p].size == 0:
@@ -212,10 +229,13 @@ class OracleOperator:
             X = self.fwd_fft(self.zp(p) * x)
             rows, yp = self.degrid(p, X)
             y[rows] = yp
-        return y
+        full = np.zeros(self.M_all, dtype=np.complex128)
+        full[self.keep] = y
+        return full
 
     def adjoint(self, y):
-        """Phi^dag y; returns [ny, nx] complex."""
+        """Phi^dag y (y: [M_all]); returns [ny, nx] complex."""
+        y = np.asarray(y)[self.keep]
         out = np.zeros((self.prm.ny, self.prm.nx), dtype=np.complex128)
         for p in range(self.P):
             if self.bin_rows[p].size == 0:
