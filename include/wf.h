@@ -89,6 +89,18 @@ typedef struct {
                               log10(surrogate_tol) use the prediction (square fields;
                               the network must outlive the build call only)          */
   double surrogate_tol;    /* predicted relative L2 error bound, default 1e-3          */
+  const float* weights;    /* NULL: unit weights.  Otherwise host FP32 [total rows] in
+                              the [chan][row] order of the visibilities: row k of the
+                              operator is scaled by weights[k], Phi_W = diag(w) Phi, so
+                              Phi_W^dag Phi_W = Phi^dag diag(w^2) Phi (data weighting,
+                              Sect. 2).  Finite; scaled G values must fit the storage
+                              format (WF_EINVAL when FP16 would overflow).  Read during
+                              the build only.                                         */
+  const uint8_t* flags;    /* NULL: no flags.  Otherwise host [total rows], same order;
+                              non-zero discards the measurement (Sect. 3.5 input files)
+                              before planning: its row is never built, wf_forward
+                              writes 0 there and wf_adjoint ignores it.  Read during the
+                              build only.                                             */
 } wf_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -115,6 +127,28 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
                             uint64_t memory_budget_bytes, const wf_options* opt,
                             void* hip_stream, wf_op** out);
 
+/* Briggs robust weights for wf_options.weights.  The paper names density-aware data
+ * weighting (Sect. 2) without a formula; this is the published definition (D. S.
+ * Briggs, PhD thesis, 1995), per channel:
+ *   W_c  = sum of the natural weights w_k of the samples whose (u, v) -- or whose
+ *          conjugate (-u, -v), the image being real -- falls in Fourier cell c of the
+ *          image (du = 1 / (nx cell_rad), dv = 1 / (ny cell_rad); index
+ *          floor(u / du + 1/2) modulo nx, likewise v);
+ *   f^2  = (5 10^-robust)^2 sum_k w_k / sum_k w_k W_c(k);
+ *   w'_k = w_k / (1 + W_c(k) f^2)   (robust -> +inf: natural; -> -inf: uniform).
+ * out receives the operator weights sqrt(w'_k): the imaging weight multiplies each
+ * sample once in Phi^dag diag(w') y = Phi_W^dag Phi_W-style sums.
+ *  uvw_m, nrows, chan_rows, freqs_hz, nchan, shape: as for wf_build_operator.
+ *  natural  host FP32 [total rows] natural weights (NULL = ones; finite, >= 0).
+ *  flags    host [total rows] (NULL = none): flagged samples get 0 and are left out.
+ *  out      host FP32 [total rows].
+ * Device work (density gridding with FP64 atomics, reductions) on hip_stream;
+ * synchronous.  Errors: WF_EINVAL, WF_ENOMEM, WF_EHIP. */
+wf_status wf_briggs_weights(const double* uvw_m, int64_t nrows, const int64_t* chan_rows,
+                            const double* freqs_hz, int32_t nchan, wf_image_shape shape,
+                            double robust, const float* natural, const uint8_t* flags,
+                            float* out, void* hip_stream);
+
 /* y = Phi x (eq. 3, eq. 6).  d_img: real FP32 [nchan][ny][nx];
  * d_vis: complex FP32 [total rows] in [chan][row] caller order. */
 wf_status wf_forward(wf_op* op, const float* d_img, float* d_vis, void* hip_stream);
@@ -139,7 +173,7 @@ typedef struct {
   int32_t tile;             /* fused-kernel tile side                                  */
   int32_t p_wsclean;        /* ceil of eq. 5 over the field (search upper end)         */
   int32_t p_star;           /* minimiser of eq. 10                                      */
-  int64_t nrows;            /* rows of this channel                                    */
+  int64_t nrows;            /* rows of this channel that were built (not flagged)      */
   int64_t ntaps;            /* stored values of G (K of eq. 9)                          */
   int64_t nwork;            /* work items of the fused kernel                           */
   double k_estimate;        /* planner's K(P) estimate at the chosen P                  */
@@ -153,6 +187,7 @@ typedef struct {
   int32_t branch;           /* branch that writes this channel's output                */
   double surrogate_fraction;/* rows whose residual kernel came from the network        */
   double mem_h_bytes;       /* device bytes of the holographic stencils (strategy (b))  */
+  int64_t nflagged;         /* flagged rows of this channel (discarded)                 */
 } wf_plan_info;
 
 /* Plan and matrix statistics of channel chan (Sect. 3.4 quantities). */

@@ -18,7 +18,7 @@ from ._lib import (WfImageShape, WfOptions, WfPlanInfo, WfTuneInfo, check, APPLY
 
 _lib.load()
 
-__all__ = ["Operator", "Graph", "Network", "default_options"]
+__all__ = ["Operator", "Graph", "Network", "default_options", "briggs_weights"]
 
 
 def default_options(**kw) -> WfOptions:
@@ -31,10 +31,36 @@ def default_options(**kw) -> WfOptions:
             v = STRATEGY[v] if isinstance(v, str) else int(v)
         elif k == "surrogate":
             v = None if v is None else (v._h.value if isinstance(v, Network) else int(v))
+        elif k in ("weights", "flags"):
+            raise TypeError(f"{k} is an argument of Operator, not an option")
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
     return o
+
+
+def briggs_weights(uvw_m, freqs_hz, nx, ny, cell_rad, robust, chan_rows=None, natural=None,
+                   flags=None, stream=None):
+    """Briggs robust operator weights sqrt(w'_k) (include/wf.h, wf_briggs_weights),
+    float32 [total rows], computed on the device."""
+    lib = _lib.load()
+    uvw = np.ascontiguousarray(uvw_m, dtype=np.float64)
+    fr = np.ascontiguousarray(np.atleast_1d(freqs_hz), dtype=np.float64)
+    cr = None if chan_rows is None else np.ascontiguousarray(chan_rows, dtype=np.int64)
+    n = int(cr.sum()) if cr is not None else int(uvw.shape[0]) * int(fr.size)
+    nat = None if natural is None else np.ascontiguousarray(natural, dtype=np.float32)
+    fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.uint8)
+    for a, name in ((nat, "natural"), (fl, "flags")):
+        if a is not None and a.shape != (n,):
+            raise ValueError(f"{name} must have shape ({n},)")
+    out = np.empty(n, dtype=np.float32)
+    ptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    check(lib.wf_briggs_weights(ptr(uvw), ctypes.c_int64(uvw.shape[0]), ptr(cr), ptr(fr),
+                                ctypes.c_int32(fr.size), WfImageShape(int(nx), int(ny),
+                                                                      float(cell_rad)),
+                                float(robust), ptr(nat), ptr(fl), ptr(out),
+                                _stream_handle(stream)), "wf_briggs_weights")
+    return out
 
 
 def _stream_handle(stream):
@@ -50,11 +76,13 @@ class Operator:
     uvw_m      (nrows, 3) float64 metres (host array).
     freqs_hz   channel frequencies.
     chan_rows  optional per-channel row counts (channel c uses its own block of rows).
+    weights    optional float32 [total rows] data weights (row k of Phi scaled by them).
+    flags      optional bool / uint8 [total rows]; True discards the measurement.
     Options: see include/wf.h (J, beta, alpha, smax, eps_w, nbins, strategy, store, ...).
     """
 
     def __init__(self, uvw_m, freqs_hz, nx, ny, cell_rad, memory_budget=288e9,
-                 chan_rows=None, stream=None, **opts):
+                 chan_rows=None, stream=None, weights=None, flags=None, **opts):
         self._lib = _lib.load()
         self._h = ctypes.c_void_p()
         uvw = np.ascontiguousarray(uvw_m, dtype=np.float64)
@@ -66,6 +94,17 @@ class Operator:
         self.nx, self.ny = int(nx), int(ny)
         self.nrows_total = int(cr.sum()) if cr is not None else int(uvw.shape[0]) * self.nchan
         self.opts = default_options(**opts)
+        wts = fl = None
+        if weights is not None:
+            wts = np.ascontiguousarray(weights, dtype=np.float32)
+            if wts.shape != (self.nrows_total,):
+                raise ValueError(f"weights must have shape ({self.nrows_total},)")
+            self.opts.weights = wts.ctypes.data
+        if flags is not None:
+            fl = np.ascontiguousarray(flags, dtype=np.uint8)
+            if fl.shape != (self.nrows_total,):
+                raise ValueError(f"flags must have shape ({self.nrows_total},)")
+            self.opts.flags = fl.ctypes.data
         shape = WfImageShape(self.nx, self.ny, float(cell_rad))
         st = self._lib.wf_build_operator(
             uvw.ctypes.data_as(ctypes.c_void_p), ctypes.c_int64(uvw.shape[0]),
@@ -73,6 +112,8 @@ class Operator:
             fr.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(self.nchan), shape,
             ctypes.c_uint64(int(memory_budget)), ctypes.byref(self.opts),
             _stream_handle(stream), ctypes.byref(self._h))
+        self.opts.weights = None
+        self.opts.flags = None
         check(st, "wf_build_operator")
 
     # ------------------------------------------------------------------ applies

@@ -27,7 +27,8 @@ class WfOptions(ctypes.Structure):
                 ("budget_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("tile", ctypes.c_int32), ("max_rows_per_item", ctypes.c_int32),
                 ("branches", ctypes.c_int32), ("surrogate", ctypes.c_void_p),
-                ("surrogate_tol", ctypes.c_double)]
+                ("surrogate_tol", ctypes.c_double), ("weights", ctypes.c_void_p),
+                ("flags", ctypes.c_void_p)]
 
 
 class WfPlanInfo(ctypes.Structure):
@@ -41,7 +42,8 @@ class WfPlanInfo(ctypes.Structure):
                 ("cost_model", ctypes.c_double), ("capped_fraction", ctypes.c_double),
                 ("max_dropped_energy", ctypes.c_double), ("build_seconds", ctypes.c_double),
                 ("max_rows_per_item", ctypes.c_int32), ("branch", ctypes.c_int32),
-                ("surrogate_fraction", ctypes.c_double), ("mem_h_bytes", ctypes.c_double)]
+                ("surrogate_fraction", ctypes.c_double), ("mem_h_bytes", ctypes.c_double),
+                ("nflagged", ctypes.c_int64)]
 
 
 class WfTuneInfo(ctypes.Structure):
@@ -57,6 +59,8 @@ _I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 
 SIGNATURES = {
     "wf_default_options": (None, [ctypes.POINTER(WfOptions)]),
+    "wf_briggs_weights": (_I32, [_P, _I64, _P, _P, _I32, WfImageShape, ctypes.c_double, _P,
+                                 _P, _P, _P]),
     "wf_build_operator": (_I32, [_P, _I64, _P, _P, _I32, WfImageShape, ctypes.c_uint64,
                                  ctypes.POINTER(WfOptions), _P, ctypes.POINTER(_P)]),
     "wf_forward": (_I32, [_P, _P, _P, _P]),

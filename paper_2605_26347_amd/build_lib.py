@@ -30,6 +30,8 @@ SOURCES = {
     "k_util.hip": [],
     "k_mlp.hip": [],
     "k_holo.hip": [],
+    "k_weight.hip": ["-ffp-contract=off"],
+    "wf_weight.cpp": [],
     "wf_mlp.cpp": [],
     "host_plan.cpp": ["-ffp-contract=off"],
     "wf_abi.cpp": [],

@@ -392,7 +392,7 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
                                                const double* __restrict__ cents,
                                                KernelParams kp, void* __restrict__ vals,
                                                int64_t vbase, int* __restrict__ mismatch,
-                                               Surrogate sg) {
+                                               Surrogate sg, const float* __restrict__ wts) {
 #pragma clang fp contract(off)
   __shared__ KScratch S;
   const int lane = threadIdx.x;
@@ -440,6 +440,8 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
     }
     __syncthreads();
     const int64_t vb = wis[row_wi[s]].voff + voff[s] - vbase;
+    const double wk = wts ? (double)wts[k] : 1.0;   // data weight of the row
+    bool over = false;
     if (T == Tm) {
       for (int idx = lane; idx < T * T; idx += 64) {
         const int av = idx / T, au = idx - av * T;
@@ -452,11 +454,15 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
             im += S.kv[dd] * x.y;
           }
         }
+        re *= wk;
+        im *= wk;
+        if constexpr (STORE == WF_STORE_F16) over = over || fabs(re) > 65504.0 || fabs(im) > 65504.0;
         store_val<STORE>(vals, vb + idx, re, im);
       }
     } else if (lane == 0) {
       atomicAdd(mismatch, 1);
     }
+    if (over) atomicAdd(mismatch + 1, 1);
     __syncthreads();
   }
 }
@@ -551,7 +557,7 @@ hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_
                          const WorkItem* wi, double scale, double gsx, double gsy,
                          const double* mids, int P, const double* cents,
                          const KernelParams& kp, void* vals, int64_t vbase, wf_store store,
-                         int* mismatch, const Surrogate& sg, hipStream_t s) {
+                         int* mismatch, const Surrogate& sg, const float* wts, hipStream_t s) {
   const int64_t n = s1 - s0;
   if (n <= 0) return hipSuccess;
   const int blocks = (int)(n < 262144 ? n : 262144);
@@ -559,17 +565,17 @@ hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_
     case WF_STORE_F32:
       hipLaunchKernelGGL(k_gbuild<WF_STORE_F32>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, vbase, mismatch, sg);
+                         vals, vbase, mismatch, sg, wts);
       break;
     case WF_STORE_F16:
       hipLaunchKernelGGL(k_gbuild<WF_STORE_F16>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, vbase, mismatch, sg);
+                         vals, vbase, mismatch, sg, wts);
       break;
     default:
       hipLaunchKernelGGL(k_gbuild<WF_STORE_BF16>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
                          perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, vbase, mismatch, sg);
+                         vals, vbase, mismatch, sg, wts);
       break;
   }
   return hipGetLastError();

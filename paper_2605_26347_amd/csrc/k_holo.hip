@@ -68,15 +68,17 @@ __global__ __launch_bounds__(256) void k_hbuild(const WorkItem* __restrict__ wi,
   }
 }
 
-// FP32 stencils -> packed FP16 / BF16 pairs (round to nearest even).
+// FP32 stencils -> packed FP16 / BF16 pairs (round to nearest even); *overflow counts
+// values beyond the FP16 range.
 __global__ __launch_bounds__(256) void k_hpack(const float2* __restrict__ src,
                                                uint32_t* __restrict__ dst, int64_t n,
-                                               int store) {
+                                               int store, int* __restrict__ overflow) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const float2 v = src[i];
     uint32_t out;
     if (store == WF_STORE_F16) {
+      if (fabsf(v.x) > 65504.f || fabsf(v.y) > 65504.f) atomicAdd(overflow, 1);
       const __half2 hv = __floats2half2_rn(v.x, v.y);
       __builtin_memcpy(&out, &hv, 4);
     } else {
@@ -194,10 +196,11 @@ hipError_t launch_hbuild(const WorkItem* wi, int nwi, const uint32_t* meta, cons
 }
 
 hipError_t launch_hpack(const float2* src, uint32_t* dst, int64_t n, wf_store store,
-                        hipStream_t s) {
+                        int* overflow, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_hpack, dim3((unsigned)nb), dim3(256), 0, s, src, dst, n, (int)store);
+  hipLaunchKernelGGL(k_hpack, dim3((unsigned)nb), dim3(256), 0, s, src, dst, n, (int)store,
+                     overflow);
   return hipGetLastError();
 }
 

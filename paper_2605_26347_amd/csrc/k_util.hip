@@ -37,7 +37,22 @@ __global__ void __launch_bounds__(256) k_add_into(float* out, const float* in, i
     out[i] += in[i];
 }
 
+// out[idx[i]] = 0: the forward values of flagged (discarded) visibilities.
+__global__ void __launch_bounds__(256) k_scatter_zero(float2* out, const int32_t* idx,
+                                                      int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[idx[i]] = make_float2(0.f, 0.f);
+}
+
 }  // namespace
+
+hipError_t launch_scatter_zero(float2* out, const int32_t* idx, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_scatter_zero, dim3((unsigned)nb), dim3(256), 0, s, out, idx, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_zero(void* p, int64_t nfloats, hipStream_t s) {
   if (nfloats <= 0) return hipSuccess;

@@ -98,6 +98,7 @@ void destroy_op(wf_op* op) {
     dfree(c.prune);
     dfree(c.htiles);
     dfree(c.hvals);
+    dfree(c.flagged);
   }
   for (size_t b = 0; b < op->br.size(); ++b) release_branch(op->br[b], b > 0);
   if (op->fork) (void)hipEventDestroy(op->fork);
@@ -243,8 +244,17 @@ void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t 
   ch.nwork = (int64_t)wis.size();
 }
 
+// Data weights and flags of one channel (Sect. 2): the rows that are built and the
+// weight of each.
+struct RowSel {
+  const float* w = nullptr;          // weight per built row (null: ones)
+  const int32_t* keep = nullptr;     // built row -> caller row (null: identity)
+  std::vector<int32_t> flagged;      // caller rows that are discarded
+  int64_t nvis = 0;                  // caller rows of the channel
+};
+
 wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double freq,
-                        int64_t vis_off, uint64_t budget, hipStream_t s) {
+                        int64_t vis_off, uint64_t budget, const RowSel& sel, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   ChanOp& ch = op->chans[c];
   const wf_options& opt = op->opt;
@@ -252,6 +262,8 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   ch.scale = freq / C_LIGHT;
   ch.vis_off = vis_off;
   ch.nrows = M;
+  ch.nvis = sel.nvis;
+  ch.nflag = (int64_t)sel.flagged.size();
   std::vector<double> w(M);
   for (int64_t k = 0; k < M; ++k) w[k] = uvw[3 * k + 2] * ch.scale;
   PlanResult pr;
@@ -287,6 +299,17 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   if ((st = dalloc(dkeys, sizeof(uint64_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
   if ((st = dalloc(ddrop, sizeof(float) * std::max<int64_t>(M, 1))) != WF_OK) return st;
   WF_HIP(hipMemcpyAsync(duvw.p, uvw, sizeof(double) * 3 * M, hipMemcpyHostToDevice, s));
+  DevBuf dwts;
+  tmp.b.push_back(&dwts);
+  if (sel.w && M > 0) {
+    if ((st = dalloc(dwts, sizeof(float) * M)) != WF_OK) return st;
+    WF_HIP(hipMemcpyAsync(dwts.p, sel.w, sizeof(float) * M, hipMemcpyHostToDevice, s));
+  }
+  if (ch.nflag > 0) {
+    if ((st = dalloc(ch.flagged, sizeof(int32_t) * ch.nflag)) != WF_OK) return st;
+    WF_HIP(hipMemcpyAsync(ch.flagged.p, sel.flagged.data(), sizeof(int32_t) * ch.nflag,
+                          hipMemcpyHostToDevice, s));
+  }
   WF_HIP(hipMemcpyAsync(dmids.p, mids.data(), sizeof(double) * mids.size(),
                         hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(dcents.p, ch.centroids.data(), sizeof(double) * ch.P,
@@ -478,8 +501,8 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   DevBuf drowwi, dmis;
   tmp.b.push_back(&drowwi);
   tmp.b.push_back(&dmis);
-  if ((st = dalloc(dmis, sizeof(int))) != WF_OK) return st;
-  WF_HIP(hipMemsetAsync(dmis.p, 0, sizeof(int), s));
+  if ((st = dalloc(dmis, 2 * sizeof(int))) != WF_OK) return st;
+  WF_HIP(hipMemsetAsync(dmis.p, 0, 2 * sizeof(int), s));
   if ((st = dalloc(ch.meta, sizeof(uint32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
   if ((st = dalloc(ch.voff, sizeof(uint32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
   if ((st = dalloc(ch.perm, sizeof(int32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
@@ -599,7 +622,8 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
                            (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
                            (const int32_t*)drowwi.p, (const WorkItem*)ch.work.p, ch.scale, gsx,
                            gsy, (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
-                           gtmp.p, vbase, WF_STORE_F32, (int*)dmis.p, Surrogate{}, s));
+                           gtmp.p, vbase, WF_STORE_F32, (int*)dmis.p, Surrogate{},
+                           (const float*)dwts.p, s));
       WF_HIP(launch_hbuild((const WorkItem*)dwrow.p + wi_at, (int)(wj - wi_at),
                            (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
                            (const float2*)gtmp.p, vbase,
@@ -615,7 +639,8 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     } else {
       if ((st = dalloc(ch.hvals, sizeof(uint32_t) * std::max<int64_t>(hv, 1))) != WF_OK)
         return st;
-      WF_HIP(launch_hpack((const float2*)hacc.p, (uint32_t*)ch.hvals.p, hv, opt.store, s));
+      WF_HIP(launch_hpack((const float2*)hacc.p, (uint32_t*)ch.hvals.p, hv, opt.store,
+                          (int*)dmis.p + 1, s));
     }
     WF_HIP(hipStreamSynchronize(s));
     ch.holo = true;
@@ -633,17 +658,27 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
                                              (const WorkItem*)ch.work.p, ch.scale, gsx, gsy,
                                              (const double*)dmids.p, ch.P,
                                              (const double*)dcents.p, op->kp, ch.vals.p,
-                                             0, opt.store, (int*)dmis.p, sg, s));
+                                             0, opt.store, (int*)dmis.p, sg,
+                                             (const float*)dwts.p, s));
                         return WF_OK;
                       });
   if (st != WF_OK) return st;
   }
-  int mismatch = 0;
-  WF_HIP(hipMemcpyAsync(&mismatch, dmis.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  int mismatch[2] = {0, 0};
+  WF_HIP(hipMemcpyAsync(mismatch, dmis.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   WF_HIP(hipStreamSynchronize(s));
-  if (mismatch != 0)
-    return fail(WF_EINVAL, std::to_string(mismatch) +
+  if (mismatch[0] != 0)
+    return fail(WF_EINVAL, std::to_string(mismatch[0]) +
                                " rows changed patch side between the symbolic and value passes");
+  if (mismatch[1] != 0)
+    return fail(WF_EINVAL, "weighted values exceed the FP16 range: scale the weights down "
+                           "or store FP32 / BF16");
+  if (sel.keep && !holo) {
+    // visibilities are read and written in caller order: sorted row -> caller row
+    for (int64_t i = 0; i < M; ++i) idx[i] = sel.keep[idx[i]];
+    WF_HIP(hipMemcpyAsync(ch.perm.p, idx.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
+    WF_HIP(hipStreamSynchronize(s));
+  }
 
   wf_plan_info& in = ch.info;
   in.nchan = (int32_t)op->chans.size();
@@ -669,6 +704,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   in.max_rows_per_item = ch.max_rows;
   in.surrogate_fraction = M ? (double)nused / (double)M : 0.0;
   in.mem_h_bytes = holo ? (double)b_v * ch.h_values + (double)ch.htiles.bytes : 0.0;
+  in.nflagged = ch.nflag;
   if (holo) {
     // only the stencils serve the applies of a holographic operator
     dfree(ch.meta);
@@ -844,6 +880,11 @@ wf_status run_apply(wf_op* op, int kind, const float* in, float* out, hipStream_
   const int nchan = (int)op->chans.size();
   unsigned long long* stamps = op->stamping ? (unsigned long long*)op->stamps.p : nullptr;
   if (stamps) WF_HIP(launch_stamp(stamps + nchan, s));
+  if (kind == WF_APPLY_FORWARD)
+    for (const ChanOp& ch : op->chans)
+      if (ch.nflag > 0)
+        WF_HIP(launch_scatter_zero((float2*)out + ch.vis_off, (const int32_t*)ch.flagged.p,
+                                   ch.nflag, s));
   const int nb = op->nbranch;
   if (nb > 1) {
     WF_HIP(hipEventRecord(op->fork, s));
@@ -1178,6 +1219,10 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
         return fail(WF_EINVAL, "frequencies must be positive");
     for (int64_t k = 0; k < 3 * nrows; ++k)
       if (!std::isfinite(uvw_m[k])) return fail(WF_EINVAL, "non-finite uvw coordinate");
+    const int64_t nvis_total = chan_rows ? nrows : nrows * (int64_t)nchan;
+    if (opt.weights)
+      for (int64_t k = 0; k < nvis_total; ++k)
+        if (!std::isfinite(opt.weights[k])) return fail(WF_EINVAL, "non-finite weight");
     const int64_t per_chan_max = chan_rows ? 0 : nrows;
     if (per_chan_max > INT32_MAX) return fail(WF_EINVAL, "too many rows per channel");
     if (chan_rows)
@@ -1187,6 +1232,8 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
     OpGuard guard{new wf_op()};
     wf_op* op = guard.op;
     op->opt = opt;
+    op->opt.weights = nullptr;   // caller arrays, read during the build only
+    op->opt.flags = nullptr;
     op->shape = shape;
     op->Kx = 2 * shape.nx;
     op->Ky = 2 * shape.ny;
@@ -1243,8 +1290,33 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
     for (int c = 0; c < nchan; ++c) {
       const int64_t Mc = chan_rows ? chan_rows[c] : nrows;
       const double* u = chan_rows ? uvw_m + 3 * off : uvw_m;
-      if ((st = build_channel(op, c, u, Mc, freqs_hz[c], op->total_rows, memory_budget_bytes,
-                              s)) != WF_OK)
+      // flagged rows are dropped before planning; the others keep their weights
+      RowSel sel;
+      sel.nvis = Mc;
+      sel.w = opt.weights ? opt.weights + op->total_rows : nullptr;
+      std::vector<int32_t> keep;
+      std::vector<double> ukeep;
+      std::vector<float> wkeep;
+      int64_t Mb = Mc;
+      if (opt.flags) {
+        const uint8_t* f = opt.flags + op->total_rows;
+        for (int64_t k = 0; k < Mc; ++k) (f[k] ? sel.flagged : keep).push_back((int32_t)k);
+        if (!sel.flagged.empty()) {
+          Mb = (int64_t)keep.size();
+          ukeep.resize(3 * Mb);
+          for (int64_t i = 0; i < Mb; ++i)
+            for (int d = 0; d < 3; ++d) ukeep[3 * i + d] = u[3 * (int64_t)keep[i] + d];
+          if (sel.w) {
+            wkeep.resize(Mb);
+            for (int64_t i = 0; i < Mb; ++i) wkeep[i] = sel.w[keep[i]];
+            sel.w = wkeep.data();
+          }
+          sel.keep = keep.data();
+          u = ukeep.data();
+        }
+      }
+      if ((st = build_channel(op, c, u, Mb, freqs_hz[c], op->total_rows, memory_budget_bytes,
+                              sel, s)) != WF_OK)
         return st;
       op->total_rows += Mc;
       if (chan_rows) off += Mc;
@@ -1316,7 +1388,7 @@ wf_status wf_get_row(const wf_op* op, int32_t chan, int64_t row, int32_t* T, int
     if (st != WF_OK) return st;
     if (chan < 0 || chan >= (int)op->chans.size()) return fail(WF_EINVAL, "bad channel");
     const ChanOp& ch = op->chans[chan];
-    if (row < 0 || row >= ch.nrows) return fail(WF_EINVAL, "row out of range");
+    if (row < 0 || row >= ch.nvis) return fail(WF_EINVAL, "row out of range");
     if (ch.holo) return fail(WF_ENOTSUP, "a holographic operator keeps no rows of G");
     WF_HIP(hipSetDevice(op->device));
     WF_HIP(hipDeviceSynchronize());
@@ -1326,7 +1398,7 @@ wf_status wf_get_row(const wf_op* op, int32_t chan, int64_t row, int32_t* T, int
       std::vector<int32_t> perm(ch.nrows);
       WF_HIP(hipMemcpy(perm.data(), ch.perm.p, sizeof(int32_t) * ch.nrows,
                        hipMemcpyDeviceToHost));
-      dx.sorted_of.assign(ch.nrows, -1);
+      dx.sorted_of.assign(ch.nvis, -1);
       for (int64_t i = 0; i < ch.nrows; ++i) dx.sorted_of[perm[i]] = (int32_t)i;
       dx.items.resize(ch.nwork);
       WF_HIP(hipMemcpy(dx.items.data(), ch.work.p, sizeof(WorkItem) * ch.nwork,
@@ -1338,7 +1410,7 @@ wf_status wf_get_row(const wf_op* op, int32_t chan, int64_t row, int32_t* T, int
       dx.gen = op->generation + 1;
     }
     const int64_t s = dx.sorted_of[row];
-    if (s < 0) return fail(WF_EINVAL, "row not found");
+    if (s < 0) return fail(WF_EINVAL, "row is flagged (not built)");
     uint32_t m, vo;
     WF_HIP(hipMemcpy(&m, (const uint32_t*)ch.meta.p + s, 4, hipMemcpyDeviceToHost));
     WF_HIP(hipMemcpy(&vo, (const uint32_t*)ch.voff.p + s, 4, hipMemcpyDeviceToHost));

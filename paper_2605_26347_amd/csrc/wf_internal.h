@@ -112,7 +112,10 @@ struct DebugIndex {
 struct ChanOp {
   double freq = 0, scale = 0;
   int64_t vis_off = 0;   // offset of this channel's rows in the caller's vis vector
-  int64_t nrows = 0;
+  int64_t nrows = 0;     // rows built (flagged rows excluded)
+  int64_t nvis = 0;      // rows of the channel in the caller's vis vector
+  DevBuf flagged;        // int32 caller-order indices of the flagged rows
+  int64_t nflag = 0;
   int P = 0;
   std::vector<double> centroids;
   std::vector<int64_t> bin_row0, bin_nrows;
@@ -237,6 +240,21 @@ hipError_t launch_grid(int cls, const WorkItem* wi, int nwi, const uint32_t* met
                        wf_store store, const float2* vis, float2* Y, int Kx, int Ky, int win,
                        hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t nfloats, hipStream_t s);
+// out[idx[i]] = 0 for the n complex values listed (flagged visibilities).
+hipError_t launch_scatter_zero(float2* out, const int32_t* idx, int64_t n, hipStream_t s);
+// Briggs weighting: density of natural weights over the nx x ny Fourier cells (each
+// sample and its conjugate, FP64 atomics); sums[0] += sum w W_c(k), sums[1] += sum w;
+// out = sqrt(w / (1 + W_c(k) f2)).  w null: ones; flags non-zero: weight 0.
+hipError_t launch_density(const double* uvw, int64_t n, double scale, double du, double dv,
+                          int nx, int ny, const float* w, const uint8_t* flags, double* W,
+                          hipStream_t s);
+hipError_t launch_briggs_sums(const double* uvw, int64_t n, double scale, double du,
+                              double dv, int nx, int ny, const float* w,
+                              const uint8_t* flags, const double* W, double* sums,
+                              hipStream_t s);
+hipError_t launch_briggs_out(const double* uvw, int64_t n, double scale, double du, double dv,
+                             int nx, int ny, const float* w, const uint8_t* flags,
+                             const double* W, double f2, float* out, hipStream_t s);
 hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
 hipError_t launch_add_into(float* out, const float* in, int64_t nfloats, hipStream_t s);
 // Forward-backward driver (eq. 4): x <- max(x + gamma (dirty - hx) - t, 0); *out = a.b;
@@ -255,7 +273,7 @@ hipError_t launch_hbuild(const WorkItem* wi, int nwi, const uint32_t* meta, cons
                          const HTile* ht, int tiles_x, int tsh, int Kx, int Ky, float* h,
                          hipStream_t s);
 hipError_t launch_hpack(const float2* src, uint32_t* dst, int64_t n, wf_store store,
-                        hipStream_t s);
+                        int* overflow, hipStream_t s);
 hipError_t launch_happly(const HTile* ht, int ntiles, int Dmax, const void* hv, wf_store store,
                          const float2* X, float2* Y, int tiles_x, int tsh, int Kx, int Ky,
                          hipStream_t s);
@@ -278,13 +296,15 @@ hipError_t launch_rowsym(const double* uvw, int64_t r0, int64_t r1, double scale
                          int Ky, int tile, const KernelParams& kp, uint64_t* keys,
                          float* dropped, const Surrogate& sg, hipStream_t s);
 // Value pass over sorted rows [s0, s1): writes each row's T*T values at its value offset
-// minus vbase.
+// minus vbase, scaled by the row's data weight wts[perm[s]] (wts may be null: ones).
+// mismatch[0] counts rows whose patch side differs from the symbolic pass, mismatch[1]
+// rows with a value beyond the FP16 range (FP16 store only).
 hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_t* perm,
                          const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
                          const WorkItem* wi, double scale, double gsx, double gsy,
                          const double* mids, int P, const double* cents,
                          const KernelParams& kp, void* vals, int64_t vbase, wf_store store,
-                         int* mismatch, const Surrogate& sg, hipStream_t s);
+                         int* mismatch, const Surrogate& sg, const float* wts, hipStream_t s);
 // Network inputs of rows [r0, r0 + nr) (caller order, or sorted order through perm).
 hipError_t launch_row_inputs(const double* uvw, const int32_t* perm, int64_t r0, int64_t nr,
                              double scale, double gsx, double gsy, const double* mids, int P,

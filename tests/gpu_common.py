@@ -20,7 +20,8 @@ def oracle_for(obs, nbins, chan=0, uvw=None, **kw):
                          eps=kw.get("eps_w", 1e-6))
     u = obs.uvw_m if uvw is None else uvw
     return OracleOperator(u, obs.freqs_hz[chan], prm, nbins=nbins, seed=kw.get("seed", 0),
-                          plan_fraction=kw.get("plan_fraction", 0.01))
+                          plan_fraction=kw.get("plan_fraction", 0.01),
+                          weights=kw.get("weights"), flags=kw.get("flags"))
 
 
 def gpu_operator(obs, nbins, **kw):

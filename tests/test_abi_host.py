@@ -112,3 +112,36 @@ def test_network_host_calls():
     assert lib.wf_mlp_train(None, None, None, 0, 1, 1, 1e-3, 1e-5, 0, None, None) == _lib.WF_EINVAL
     o = default_options()
     assert o.surrogate is None and o.surrogate_tol == 1e-3
+
+
+def test_weight_and_briggs_host_checks():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    o = default_options()
+    w = np.ones(UVW.shape[0], dtype=np.float32)
+    w[7] = np.inf
+    o.weights = w.ctypes.data
+    uvw = np.ascontiguousarray(UVW)
+    fr = np.array([1e9])
+    st = lib.wf_build_operator(uvw.ctypes.data_as(ctypes.c_void_p), uvw.shape[0], None,
+                               fr.ctypes.data_as(ctypes.c_void_p), 1, WfImageShape(64, 64, 1e-4),
+                               1 << 30, ctypes.byref(o), None, ctypes.byref(h))
+    assert st == _lib.WF_EINVAL and b"weight" in lib.wf_last_error() and not h.value
+    with pytest.raises(TypeError):
+        default_options(weights=None)
+    out = np.zeros(uvw.shape[0], dtype=np.float32)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    nat = -np.ones(uvw.shape[0], dtype=np.float32)
+    assert lib.wf_briggs_weights(ptr(uvw), uvw.shape[0], None, ptr(fr), 1,
+                                 WfImageShape(64, 64, 1e-4), 0.0, ptr(nat), None, ptr(out),
+                                 None) == _lib.WF_EINVAL
+    assert b"natural" in lib.wf_last_error()
+    assert lib.wf_briggs_weights(ptr(uvw), uvw.shape[0], None, ptr(fr), 1,
+                                 WfImageShape(64, 64, 1e-4), float("nan"), None, None,
+                                 ptr(out), None) == _lib.WF_EINVAL
+    assert lib.wf_briggs_weights(ptr(uvw), uvw.shape[0], None, ptr(fr), 1,
+                                 WfImageShape(0, 64, 1e-4), 0.0, None, None, ptr(out),
+                                 None) == _lib.WF_EINVAL
+    # no rows: nothing to do, no device work
+    assert lib.wf_briggs_weights(None, 0, None, ptr(fr), 1, WfImageShape(64, 64, 1e-4), 0.0,
+                                 None, None, ptr(out), None) == _lib.WF_OK

@@ -12,7 +12,7 @@ baseline coordinates and projected onto (u,v,w) for an hour angle H and a
 declination delta.  The paper's own workload (simulated MeerKAT L-band, Sect. 5.1)
 is not available; these arrays stand in for it.
 
-Seeds: array 1, sampling 2, sky 3, probe 4, MLP 5.
+Seeds: array 1, sampling 2, sky 3, probe 4, MLP 5, data weights and flags 6.
 """
 from __future__ import annotations
 
@@ -26,6 +26,7 @@ LAT_DEG = -30.7
 DEC_DEG = -30.0
 
 SEED_ARRAY, SEED_SAMPLING, SEED_SKY, SEED_PROBE, SEED_MLP = 1, 2, 3, 4, 5
+SEED_DATA = 6
 
 
 # --------------------------------------------------------------------------- array
@@ -97,6 +98,28 @@ def seeded_subset(nrows: int, nkeep: int, seed: int) -> np.ndarray:
     idx = rng.choice(nrows, size=nkeep, replace=False)
     idx.sort()
     return idx.astype(np.int64)
+
+
+# --------------------------------------------------------------------------- data weights, flags
+
+def noise_sigma(nrows: int, seed: int = SEED_DATA) -> np.ndarray:
+    """Per-visibility noise standard deviations: log-normal around 1 (spread of
+    antenna system temperatures), float32."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.normal(0.0, 0.35, nrows)).astype(np.float32)
+
+
+def flag_runs(nrows: int, fraction: float, seed: int = SEED_DATA + 100,
+              mean_run: int = 40) -> np.ndarray:
+    """Boolean flag mask with about `fraction` of the rows set, in contiguous runs of
+    geometric length (mean mean_run rows), as time ranges or baselines are flagged."""
+    rng = np.random.default_rng(seed)
+    m = np.zeros(nrows, dtype=bool)
+    target = int(round(fraction * nrows))
+    while m.sum() < target:
+        a = int(rng.integers(0, nrows))
+        m[a:a + int(rng.geometric(1.0 / mean_run))] = True
+    return m
 
 
 # --------------------------------------------------------------------------- images
