@@ -56,10 +56,16 @@ typedef enum { WF_STORE_F32 = 0, WF_STORE_F16 = 1, WF_STORE_BF16 = 2 } wf_store;
 /* Strategy of Sect. 3.4 / Fig. 2: (a) precomputed G, (b) precomputed holographic H,
  * (c) G computed on the fly.  WF_AUTO runs the decision tree: (a) when G fits the
  * budget, else (b) when H fits (its exact size is known after the symbolic pass), else
- * WF_EBUDGET -- (c) is not built (WF_ENOTSUP when requested).  A holographic operator
- * stores H_p = G_p^dag G_p as dense stencils per active 32 x 32 grid tile (side
- * 2 Tmax - 1, Tmax the largest patch side reaching the tile) and applies Phi^dag Phi
- * only: wf_forward / wf_adjoint / wf_get_row return WF_ENOTSUP for it.  Needs tile 32. */
+ * (c); WF_EBUDGET when not even (c)'s row data fits.  A holographic operator stores
+ * H_p = G_p^dag G_p as dense stencils per active 32 x 32 grid tile (side 2 Tmax - 1,
+ * Tmax the largest patch side reaching the tile) and applies Phi^dag Phi only:
+ * wf_forward / wf_adjoint / wf_get_row return WF_ENOTSUP for it.  Needs tile 32.
+ * An on-the-fly operator keeps per row only its coordinates, weight and patch word
+ * (about 44 bytes) and rebuilds G chunk by chunk (runs of whole row groups of one bin,
+ * at most 2.5% of the budget share each) into a transient buffer of each branch at every
+ * apply, with the same FP64 value pass as the build of (a): its results equal those of
+ * (a) up to the order of FP32 atomic additions.  It uses exact kernels only (WF_ENOTSUP
+ * with a kernel network); wf_get_row returns WF_ENOTSUP for it. */
 typedef enum { WF_AUTO = 0, WF_PRECOMP_G = 1, WF_PRECOMP_H = 2, WF_ONTHEFLY = 3 } wf_strategy;
 
 typedef struct {
@@ -188,6 +194,7 @@ typedef struct {
   double surrogate_fraction;/* rows whose residual kernel came from the network        */
   double mem_h_bytes;       /* device bytes of the holographic stencils (strategy (b))  */
   int64_t nflagged;         /* flagged rows of this channel (discarded)                 */
+  double mem_transient_bytes;/* on-the-fly: value buffer of one branch (largest chunk)   */
 } wf_plan_info;
 
 /* Plan and matrix statistics of channel chan (Sect. 3.4 quantities). */
@@ -213,7 +220,7 @@ wf_status wf_layer_grid(wf_op* op, int32_t chan, int32_t bin, const float* d_img
 
 /* Diagnostic timing: when enabled, every launch of kernel `kernel_id` (0 = the fused
  * G^dag G kernel, 1 = forward row FFT, 2 = forward column FFT, 3 = inverse column FFT,
- * 4 = inverse row FFT) is bracketed by HIP events on its stream; wf_profile_read
+ * 4 = inverse row FFT, 5 = the on-the-fly value pass of G) is bracketed by HIP events on its stream; wf_profile_read
  * returns the number of launches and their summed duration in ms (synchronising). */
 wf_status wf_profile_enable(wf_op* op, int32_t kernel_id, int32_t enable);
 wf_status wf_profile_read(wf_op* op, int32_t kernel_id, int64_t* launches, double* total_ms);

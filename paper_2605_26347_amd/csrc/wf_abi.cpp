@@ -99,7 +99,9 @@ void destroy_op(wf_op* op) {
     dfree(c.htiles);
     dfree(c.hvals);
     dfree(c.flagged);
+    for (DevBuf* b : {&c.uvw, &c.wts, &c.uperm, &c.row_wi, &c.mids, &c.cents}) dfree(*b);
   }
+  dfree(op->otf_mis);
   for (size_t b = 0; b < op->br.size(); ++b) release_branch(op->br[b], b > 0);
   if (op->fork) (void)hipEventDestroy(op->fork);
   dfree(op->stamps);
@@ -163,12 +165,15 @@ struct ProfScope {
 // registers), then order them by (bin, patch class) -- one launch per class -- with the
 // largest items of a launch first so that the hardware's in-order dispatch starts the
 // longest work first.  trow: patch side of each sorted row.  Writes each row's value
-// offset inside its item (voff) and, if row_wi is given, its item index.
+// offset inside its item (voff) and, if row_wi is given, its item index.  An
+// on-the-fly channel (ch.gchunk set) orders by (chunk, class, size) instead and records
+// each chunk's item range per class.
 void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t maxrows,
                  std::vector<WorkItem>& wis, uint32_t* voff, int32_t* row_wi) {
   const int64_t maxtaps = 1 << 20;
+  const bool chunked = !ch.gchunk.empty();
   std::vector<WorkItem> w0;
-  std::vector<int> wcls;
+  std::vector<int> wcls, wck;
   std::vector<int64_t> wtaps;
   int bb[4] = {255, 255, 0, 0};   // running box of the last item: u0, v0, u1, v1
   auto close_box = [&]() {
@@ -177,7 +182,8 @@ void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t 
                               ((uint32_t)(bb[2] - bb[0]) << 16) |
                               ((uint32_t)(bb[3] - bb[1]) << 24));
   };
-  for (const RowGroup& g : ch.groups) {
+  for (size_t gi = 0; gi < ch.groups.size(); ++gi) {
+    const RowGroup& g = ch.groups[gi];
     int64_t abs = g.voff, taps_in = 0;
     for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) {
       const int64_t t2 = (int64_t)trow[r] * trow[r];
@@ -194,6 +200,7 @@ void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t 
         wi.bin = g.bin;
         w0.push_back(wi);
         wcls.push_back(g.cls);
+        wck.push_back(chunked ? ch.gchunk[gi] : 0);
         wtaps.push_back(0);
         taps_in = 0;
       }
@@ -219,6 +226,7 @@ void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t 
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
     if (w0[x].bin != w0[y].bin) return w0[x].bin < w0[y].bin;
+    if (wck[x] != wck[y]) return wck[x] < wck[y];   // chunks ascend with the bins
     if (wcls[x] != wcls[y]) return wcls[x] < wcls[y];
     return wtaps[x] > wtaps[y];
   });
@@ -228,6 +236,9 @@ void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t 
   ch.bin_nwi.assign(ch.P, 0);
   ch.cls_wi0.assign((size_t)ch.P * NCLS, 0);
   ch.cls_nwi.assign((size_t)ch.P * NCLS, 0);
+  const size_t nck = chunked ? ch.ck_s0.size() : 0;
+  ch.ck_wi0.assign(nck * NCLS, 0);
+  ch.ck_nwi.assign(nck * NCLS, 0);
   for (size_t i = 0; i < order.size(); ++i) {
     const WorkItem& w = w0[order[i]];
     wis[i] = w;
@@ -236,7 +247,12 @@ void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t 
     if (ch.bin_nwi[b] == 0) ch.bin_wi0[b] = (int32_t)i;
     ch.bin_nwi[b]++;
     if (ch.cls_nwi[b * NCLS + c] == 0) ch.cls_wi0[b * NCLS + c] = (int32_t)i;
-    ch.cls_nwi[b * NCLS + c]++;
+    ch.cls_nwi[b * NCLS + c]++;   // (class ranges of a chunked bin are not contiguous)
+    if (chunked) {
+      const size_t k = (size_t)wck[order[i]] * NCLS + c;
+      if (ch.ck_nwi[k] == 0) ch.ck_wi0[k] = (int32_t)i;
+      ch.ck_nwi[k]++;
+    }
   }
   if (row_wi)
     for (int64_t r = 0; r < ch.nrows; ++r) row_wi[r] = newidx[row_wi[r]];
@@ -253,6 +269,113 @@ struct RowSel {
   int64_t nvis = 0;                  // caller rows of the channel
 };
 
+// Stencil tiles of a holographic operator (one per active 32 x 32 grid tile and bin,
+// side 2 Tmax - 1), the transient G chunk its build needs, and its device bytes.
+struct HoloTiles {
+  std::vector<HTile> ht;
+  std::vector<int32_t> slot;      // [bin][tile] -> index among the bin's tiles, or -1
+  std::vector<int64_t> t0, nt;    // per bin: first tile, tile count
+  std::vector<int32_t> dmax;      // per bin: largest stencil side
+  std::vector<int64_t> gtaps;     // values of each row group
+  int64_t hv = 0;                 // stencil values
+  int64_t cht = 0;                // values of the largest transient G chunk
+  double need = 0;                // device bytes of the stencils and the chunk
+};
+
+HoloTiles holo_tiles(const ChanOp& ch, const uint8_t* trow, int64_t taps_total, int tile,
+                     int halo, int Kx, int Ky, const wf_options& opt, uint64_t budget) {
+  HoloTiles H;
+  const int tx = Kx / tile, ty = Ky / tile;
+  H.slot.assign((size_t)ch.P * tx * ty, -1);
+  H.t0.assign(ch.P, 0);
+  H.nt.assign(ch.P, 0);
+  H.dmax.assign(ch.P, 0);
+  std::vector<int> tmax((size_t)tx * ty);
+  int64_t maxbin = 0;
+  size_t gi = 0;
+  for (int p = 0; p < ch.P; ++p) {
+    std::fill(tmax.begin(), tmax.end(), 0);
+    for (; gi < ch.groups.size() && ch.groups[gi].bin == p; ++gi) {
+      const RowGroup& g = ch.groups[gi];
+      int Tg = 0;
+      for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) Tg = std::max<int>(Tg, trow[r]);
+      const int tu = (g.u0 + halo) / tile, tv = (g.v0 + halo) / tile;
+      const int dil = (halo + tile - 1) / tile;   // patches stay within the LDS window
+      for (int dv = -dil; dv <= dil; ++dv)
+        for (int du = -dil; du <= dil; ++du) {
+          const size_t t = (size_t)(((tv + dv) % ty + ty) % ty) * tx + ((tu + du) % tx + tx) % tx;
+          tmax[t] = std::max(tmax[t], Tg);
+        }
+    }
+    H.t0[p] = (int64_t)H.ht.size();
+    for (size_t t = 0; t < tmax.size(); ++t) {
+      if (!tmax[t]) continue;
+      HTile h;
+      h.tile = (int32_t)t;
+      h.D = 2 * tmax[t] - 1;
+      h.voff = H.hv;
+      H.slot[(size_t)p * tx * ty + t] = (int32_t)(H.ht.size() - H.t0[p]);
+      H.ht.push_back(h);
+      H.hv += (int64_t)h.D * h.D * tile * tile;
+      H.dmax[p] = std::max(H.dmax[p], h.D);
+    }
+    H.nt[p] = (int64_t)H.ht.size() - H.t0[p];
+    maxbin = std::max(maxbin, ch.bin_taps[p]);
+  }
+  // G is built for runs of whole row groups of one bin at a time, at most cht values
+  H.gtaps.resize(ch.groups.size());
+  int64_t maxgroup = 0;
+  for (size_t i = 0; i < ch.groups.size(); ++i) {
+    const int64_t end = i + 1 < ch.groups.size() ? ch.groups[i + 1].voff : taps_total;
+    H.gtaps[i] = end - ch.groups[i].voff;
+    maxgroup = std::max(maxgroup, H.gtaps[i]);
+  }
+  const int64_t cap = std::max<int64_t>(1 << 16, (int64_t)(0.1 * opt.budget_fraction *
+                                                            (double)budget / 8.0));
+  H.cht = std::max<int64_t>(maxgroup, std::min<int64_t>(maxbin, cap));
+  const int b_v = opt.store == WF_STORE_F32 ? 8 : 4;
+  H.need = (double)b_v * H.hv + (opt.store == WF_STORE_F32 ? 0.0 : 8.0 * H.hv) + 8.0 * H.cht;
+  return H;
+}
+
+// Strategy (c): cut every bin into runs of whole row groups of at most ck values (the
+// transient buffer of one branch: 2.5% of the budget share, so that four branches hold
+// a tenth of it) and record each chunk's sorted rows and values.
+void chunk_groups(ChanOp& ch, int64_t taps_total, int b_v, double share) {
+  const size_t ng = ch.groups.size();
+  std::vector<int64_t> gt(ng);
+  int64_t maxgroup = 0;
+  for (size_t i = 0; i < ng; ++i) {
+    gt[i] = (i + 1 < ng ? ch.groups[i + 1].voff : taps_total) - ch.groups[i].voff;
+    maxgroup = std::max(maxgroup, gt[i]);
+  }
+  const int64_t ck = std::max<int64_t>(maxgroup, std::max<int64_t>(1 << 16,
+                                                                  (int64_t)(0.025 * share / b_v)));
+  ch.gchunk.assign(ng, 0);
+  ch.ck_s0.clear();
+  ch.ck_s1.clear();
+  ch.ck_vbase.clear();
+  ch.ck_taps.clear();
+  ch.ck_first.assign(ch.P, 0);
+  ch.ck_count.assign(ch.P, 0);
+  ch.ck_max = 0;
+  for (size_t i = 0; i < ng; ++i) {
+    const RowGroup& g = ch.groups[i];
+    if (ch.ck_s0.empty() || ch.groups[i - 1].bin != g.bin || ch.ck_taps.back() + gt[i] > ck) {
+      if (ch.ck_count[g.bin] == 0) ch.ck_first[g.bin] = (int32_t)ch.ck_s0.size();
+      ch.ck_count[g.bin]++;
+      ch.ck_s0.push_back(g.row0);
+      ch.ck_s1.push_back(g.row0);
+      ch.ck_vbase.push_back(g.voff);
+      ch.ck_taps.push_back(0);
+    }
+    ch.gchunk[i] = (int32_t)(ch.ck_s0.size() - 1);
+    ch.ck_s1.back() = (int64_t)g.row0 + g.nrows;
+    ch.ck_taps.back() += gt[i];
+    ch.ck_max = std::max(ch.ck_max, ch.ck_taps.back());
+  }
+}
+
 wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double freq,
                         int64_t vis_off, uint64_t budget, const RowSel& sel, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
@@ -268,8 +391,6 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   for (int64_t k = 0; k < M; ++k) w[k] = uvw[3 * k + 2] * ch.scale;
   PlanResult pr;
   std::string perr;
-  if (opt.strategy == WF_ONTHEFLY)
-    return fail(WF_ENOTSUP, "the on-the-fly strategy (c) is not built");
   if (M > 0) {
     if (plan_channel(w.data(), M, op->shape, opt, budget, &pr, &perr) != 0)
       return fail(WF_ENOTSUP, "channel " + std::to_string(c) + ": " + perr);
@@ -277,7 +398,6 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     pr.P = 1;
     pr.centroids = {0.0};
   }
-  const bool holo = opt.strategy == WF_PRECOMP_H || pr.strategy == WF_PRECOMP_H;
   ch.P = pr.P;
   ch.centroids = pr.centroids;
   std::vector<double> mids(ch.P > 1 ? ch.P - 1 : 1, 0.0);
@@ -423,6 +543,29 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     ch.bin_nrows[bin]++;
     ch.bin_taps[bin] += (int64_t)T * T;
   }
+  // Fig. 2: (a) G when it fits; (b) H when the tree reaches it and the stencils fit;
+  // else (c), G rebuilt at every apply
+  const int b_v = opt.store == WF_STORE_F32 ? 8 : 4;
+  const double share = opt.budget_fraction * (double)budget;
+  bool holo = opt.strategy == WF_PRECOMP_H ||
+              (opt.strategy == WF_AUTO && pr.strategy == WF_PRECOMP_H);
+  bool otf = opt.strategy == WF_ONTHEFLY;
+  if (holo && opt.strategy == WF_AUTO &&
+      (tile != 32 ||
+       holo_tiles(ch, trow.data(), taps_total, tile, halo, Kx, Ky, opt, budget).need > share)) {
+    holo = false;
+    otf = true;
+  }
+  if (otf && mlp)
+    return fail(WF_ENOTSUP, "the on-the-fly strategy builds exact kernels only (no kernel network)");
+  ch.gchunk.clear();
+  if (otf) chunk_groups(ch, taps_total, b_v, share);
+  if (otf) {
+    const double meta_bytes = (24.0 + 16.0 + (sel.w ? 4.0 : 0.0) + (sel.keep ? 4.0 : 0.0)) * M;
+    if (meta_bytes + 4.0 * b_v * (double)ch.ck_max > share)
+      return fail(WF_EBUDGET, "no strategy fits the memory budget: the on-the-fly row data "
+                              "alone needs " + std::to_string(meta_bytes / 1e9) + " GB");
+  }
   std::vector<WorkItem> wis;
   ch.max_rows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
   split_items(ch, trow.data(), meta.data(), ch.max_rows, wis, voff.data(), row_wi.data());
@@ -497,7 +640,6 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   std::vector<uint64_t>().swap(keys);
   ch.ntaps = taps_total;
   ch.nwork = (int64_t)wis.size();
-  const int b_v = opt.store == WF_STORE_F32 ? 8 : 4;
   DevBuf drowwi, dmis;
   tmp.b.push_back(&drowwi);
   tmp.b.push_back(&dmis);
@@ -522,60 +664,18 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     const int tx = Kx / tile, ty = Ky / tile;
     int tsh = 0;
     while ((1 << tsh) < tile) ++tsh;
-    std::vector<HTile> ht;
-    std::vector<int32_t> slot((size_t)ch.P * tx * ty, -1);
-    std::vector<int> tmax((size_t)tx * ty);
-    ch.h_t0.assign(ch.P, 0);
-    ch.h_nt.assign(ch.P, 0);
-    ch.h_dmax.assign(ch.P, 0);
-    int64_t hv = 0, maxbin = 0;
-    size_t gi = 0;
-    for (int p = 0; p < ch.P; ++p) {
-      std::fill(tmax.begin(), tmax.end(), 0);
-      for (; gi < ch.groups.size() && ch.groups[gi].bin == p; ++gi) {
-        const RowGroup& g = ch.groups[gi];
-        int Tg = 0;
-        for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) Tg = std::max<int>(Tg, trow[r]);
-        const int tu = (g.u0 + halo) / tile, tv = (g.v0 + halo) / tile;
-        const int dil = (halo + tile - 1) / tile;   // patches stay within the LDS window
-        for (int dv = -dil; dv <= dil; ++dv)
-          for (int du = -dil; du <= dil; ++du) {
-            const size_t t = (size_t)(((tv + dv) % ty + ty) % ty) * tx + ((tu + du) % tx + tx) % tx;
-            tmax[t] = std::max(tmax[t], Tg);
-          }
-      }
-      ch.h_t0[p] = (int64_t)ht.size();
-      for (size_t t = 0; t < tmax.size(); ++t) {
-        if (!tmax[t]) continue;
-        HTile h;
-        h.tile = (int32_t)t;
-        h.D = 2 * tmax[t] - 1;
-        h.voff = hv;
-        slot[(size_t)p * tx * ty + t] = (int32_t)(ht.size() - ch.h_t0[p]);
-        ht.push_back(h);
-        hv += (int64_t)h.D * h.D * tile * tile;
-        ch.h_dmax[p] = std::max(ch.h_dmax[p], h.D);
-      }
-      ch.h_nt[p] = (int64_t)ht.size() - ch.h_t0[p];
-      maxbin = std::max(maxbin, ch.bin_taps[p]);
-    }
+    HoloTiles H = holo_tiles(ch, trow.data(), taps_total, tile, halo, Kx, Ky, opt, budget);
+    if (H.need > share)
+      return fail(WF_EBUDGET, "holographic matrix needs " + std::to_string(H.need / 1e9) +
+                                  " GB");
+    const std::vector<HTile>& ht = H.ht;
+    const std::vector<int32_t>& slot = H.slot;
+    const std::vector<int64_t>& gtaps = H.gtaps;
+    ch.h_t0 = H.t0;
+    ch.h_nt = H.nt;
+    ch.h_dmax = H.dmax;
+    const int64_t hv = H.hv, CHT = H.cht;
     ch.h_values = hv;
-    // G is built for runs of whole row groups of one bin at a time, at most CHT values
-    std::vector<int64_t> gtaps(ch.groups.size());
-    int64_t maxgroup = 0;
-    for (size_t i = 0; i < ch.groups.size(); ++i) {
-      const int64_t end = i + 1 < ch.groups.size() ? ch.groups[i + 1].voff : taps_total;
-      gtaps[i] = end - ch.groups[i].voff;
-      maxgroup = std::max(maxgroup, gtaps[i]);
-    }
-    const int64_t cap = std::max<int64_t>(1 << 16, (int64_t)(0.1 * opt.budget_fraction *
-                                                              (double)budget / 8.0));
-    const int64_t CHT = std::max<int64_t>(maxgroup, std::min<int64_t>(maxbin, cap));
-    const double need = (double)b_v * hv + (opt.store == WF_STORE_F32 ? 0.0 : 8.0 * hv) +
-                        8.0 * CHT;
-    if (need > opt.budget_fraction * (double)budget)
-      return fail(WF_EBUDGET, "holographic matrix needs " + std::to_string(need / 1e9) +
-                                  " GB (on-the-fly strategy (c) is not built)");
     DevBuf hacc, gtmp, dslot;
     tmp.b.push_back(&gtmp);
     tmp.b.push_back(&dslot);
@@ -645,7 +745,28 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     WF_HIP(hipStreamSynchronize(s));
     ch.holo = true;
   }
-  if (!holo) {
+  if (otf) {
+    // the value pass's inputs stay on the device; every chunk is built once into a
+    // transient buffer so that patch sides and the FP16 range are checked as for (a)
+    DevBuf gtmp;
+    tmp.b.push_back(&gtmp);
+    if ((st = dalloc(gtmp, (size_t)b_v * std::max<int64_t>(ch.ck_max, 1))) != WF_OK) return st;
+    for (size_t k = 0; k < ch.ck_s0.size(); ++k)
+      WF_HIP(launch_gbuild((const double*)duvw.p, ch.ck_s0[k], ch.ck_s1[k],
+                           (const int32_t*)ch.perm.p, (const uint32_t*)ch.meta.p,
+                           (const uint32_t*)ch.voff.p, (const int32_t*)drowwi.p,
+                           (const WorkItem*)ch.work.p, ch.scale, gsx, gsy,
+                           (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
+                           gtmp.p, ch.ck_vbase[k], opt.store, (int*)dmis.p, Surrogate{},
+                           (const float*)dwts.p, s));
+    std::swap(ch.uvw, duvw);
+    std::swap(ch.mids, dmids);
+    std::swap(ch.cents, dcents);
+    std::swap(ch.wts, dwts);
+    std::swap(ch.row_wi, drowwi);
+    ch.otf = true;
+  }
+  if (!holo && !otf) {
   if ((st = dalloc(ch.vals, (size_t)b_v * std::max<int64_t>(taps_total, 1))) != WF_OK)
     return st;
   st = surrogate_pass((const int32_t*)ch.perm.p,
@@ -674,6 +795,12 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     return fail(WF_EINVAL, "weighted values exceed the FP16 range: scale the weights down "
                            "or store FP32 / BF16");
   if (sel.keep && !holo) {
+    if (otf) {
+      // the value pass reads coordinates through the built-row permutation
+      if ((st = dalloc(ch.uperm, sizeof(int32_t) * M)) != WF_OK) return st;
+      WF_HIP(hipMemcpyAsync(ch.uperm.p, ch.perm.p, sizeof(int32_t) * M,
+                            hipMemcpyDeviceToDevice, s));
+    }
     // visibilities are read and written in caller order: sorted row -> caller row
     for (int64_t i = 0; i < M; ++i) idx[i] = sel.keep[idx[i]];
     WF_HIP(hipMemcpyAsync(ch.perm.p, idx.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
@@ -683,7 +810,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   wf_plan_info& in = ch.info;
   in.nchan = (int32_t)op->chans.size();
   in.nbins = ch.P;
-  in.strategy = holo ? WF_PRECOMP_H : WF_PRECOMP_G;
+  in.strategy = holo ? WF_PRECOMP_H : otf ? WF_ONTHEFLY : WF_PRECOMP_G;
   in.store = opt.store;
   in.Kx = Kx;
   in.Ky = Ky;
@@ -694,7 +821,10 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   in.ntaps = taps_total;
   in.nwork = ch.nwork;
   in.k_estimate = pr.k_est;
-  in.mem_g_bytes = (double)b_v * taps_total + 12.0 * M + sizeof(WorkItem) * wis.size();
+  in.mem_g_bytes = otf ? (double)(ch.uvw.bytes + ch.wts.bytes + ch.uperm.bytes +
+                                   ch.row_wi.bytes) + 12.0 * M + sizeof(WorkItem) * wis.size()
+                      : (double)b_v * taps_total + 12.0 * M + sizeof(WorkItem) * wis.size();
+  in.mem_transient_bytes = otf ? (double)b_v * ch.ck_max : 0.0;
   in.mem_model_bytes = pr.mem_model;
   in.cost_model = pr.cost_model;
   in.capped_fraction = M ? (double)ncapped / (double)M : 0.0;
@@ -741,12 +871,13 @@ struct Lane {
   float2* Y;
   float2* A;
   float* acc;
+  void* gbuf;   // transient G values (on-the-fly channels)
   hipStream_t s;
 };
 
 Lane lane_of(wf_op* op, int b, hipStream_t caller) {
   Branch& B = op->br[b];
-  return Lane{(float2*)B.X.p, (float2*)B.Y.p, (float2*)B.A.p, (float*)B.acc.p,
+  return Lane{(float2*)B.X.p, (float2*)B.Y.p, (float2*)B.A.p, (float*)B.acc.p, B.gbuf.p,
               b == 0 ? caller : B.s};
 }
 
@@ -805,10 +936,61 @@ float* chan_out(const wf_op* op, int kind, float* out, int c) {
   return out + c * out_floats(op, kind);
 }
 
+// Bin p of an on-the-fly channel (strategy (c)): each chunk of the bin's rows is built
+// into the lane's transient buffer by the FP64 value pass, then applied by the same row
+// kernels as a stored G (the buffer stands for the values [vbase, vbase + taps) of G).
+wf_status otf_bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
+                        const float* in, float* out, bool first) {
+  wf_status st;
+  const ColPrune pr = prune_of(op, ch, p);
+  const double wp = ch.centroids[p];
+  const WorkItem* wk = (const WorkItem*)ch.work.p;
+  const wf_store store = op->opt.store;
+  const size_t b_v = store == WF_STORE_F32 ? 8 : 4;
+  const double gsx = op->Kx * op->shape.cell_rad, gsy = op->Ky * op->shape.cell_rad;
+  const int32_t* uperm = (const int32_t*)(ch.uperm.p ? ch.uperm.p : ch.perm.p);
+  if (kind != WF_APPLY_ADJOINT && (st = layer_forward(op, L, in, wp, &pr)) != WF_OK) return st;
+  for (int k = ch.ck_first[p]; k < ch.ck_first[p] + ch.ck_count[p]; ++k) {
+    {
+      ProfScope ps(prof_of(op, 5), L.s);
+      WF_HIP(launch_gbuild((const double*)ch.uvw.p, ch.ck_s0[k], ch.ck_s1[k], uperm,
+                           (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
+                           (const int32_t*)ch.row_wi.p, wk, ch.scale, gsx, gsy,
+                           (const double*)ch.mids.p, ch.P, (const double*)ch.cents.p, op->kp,
+                           L.gbuf, ch.ck_vbase[k], store, (int*)op->otf_mis.p, Surrogate{},
+                           (const float*)ch.wts.p, L.s));
+    }
+    // item value offsets are absolute: shift the base so that they land in the buffer
+    const void* vals = (const char*)L.gbuf - (size_t)ch.ck_vbase[k] * b_v;
+    for (int c = 0; c < NCLS; ++c) {
+      const int n = ch.ck_nwi[(size_t)k * NCLS + c];
+      if (n == 0) continue;
+      const WorkItem* items = wk + ch.ck_wi0[(size_t)k * NCLS + c];
+      if (kind == WF_APPLY_FORWARD) {
+        WF_HIP(launch_degrid(c, items, n, (const uint32_t*)ch.meta.p,
+                             (const uint32_t*)ch.voff.p, (const int32_t*)ch.perm.p, vals, store,
+                             L.X, (float2*)out, op->Kx, op->Ky, L.s));
+      } else if (kind == WF_APPLY_ADJOINT) {
+        WF_HIP(launch_grid(c, items, n, (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
+                           (const int32_t*)ch.perm.p, vals, store, (const float2*)in, L.Y,
+                           op->Kx, op->Ky, op->win, L.s));
+      } else {
+        ProfScope ps(prof_of(op, 0), L.s);
+        WF_HIP(launch_gtg(c, items, n, (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
+                          vals, store, L.X, L.Y, op->Kx, op->Ky, op->win, L.s));
+      }
+    }
+  }
+  if (kind == WF_APPLY_FORWARD) return WF_OK;
+  const int mode = (kind == WF_APPLY_PSF_RE ? 2 : 0) + (first ? 0 : 1);
+  return layer_adjoint(op, L, out, wp, mode, &pr);
+}
+
 // Bin p of one channel: that w-layer's share of the apply.  first: the layer opens the
 // channel's image sum in out (overwrite) instead of adding to it.
 wf_status bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
                     const float* in, float* out, bool first) {
+  if (ch.otf) return otf_bin_apply(op, kind, L, ch, p, in, out, first);
   wf_status st;
   const ColPrune pr = prune_of(op, ch, p);
   const double wp = ch.centroids[p];
@@ -1033,6 +1215,7 @@ void release_branch(Branch& B, bool own_stream) {
   dfree(B.Y);
   dfree(B.A);
   dfree(B.acc);
+  dfree(B.gbuf);
   if (own_stream && B.s) (void)hipStreamDestroy(B.s);
   if (B.done) (void)hipEventDestroy(B.done);
   B.s = nullptr;
@@ -1062,6 +1245,10 @@ wf_status ensure_branches(wf_op* op) {
       if ((st = dalloc(B.A, arow)) != WF_OK) return st;
       WF_HIP(hipMemset(B.Y.p, 0, grid));
       WF_HIP(hipMemset(B.X.p, 0, grid));
+    }
+    if (op->otf_bytes > B.gbuf.bytes) {
+      dfree(B.gbuf);
+      if ((st = dalloc(B.gbuf, op->otf_bytes)) != WF_OK) return st;
     }
     if (need_acc[b] && !B.acc.p) {
       if ((st = dalloc(B.acc, sizeof(float2) * (size_t)npix_of(op))) != WF_OK) return st;
@@ -1094,7 +1281,11 @@ wf_status retune_channel(wf_op* op, int c, int32_t maxrows) {
   std::vector<uint8_t> trow(M);
   for (int64_t r = 0; r < M; ++r) trow[r] = (uint8_t)((meta[r] >> 16) & 0xff);
   std::vector<WorkItem> wis;
-  split_items(ch, trow.data(), meta.data(), maxrows, wis, voff.data(), nullptr);
+  std::vector<int32_t> row_wi(ch.otf ? M : 0);
+  split_items(ch, trow.data(), meta.data(), maxrows, wis, voff.data(),
+              ch.otf ? row_wi.data() : nullptr);
+  if (ch.otf)   // the on-the-fly value pass finds each row's item through row_wi
+    WF_HIP(hipMemcpy(ch.row_wi.p, row_wi.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
   if (ch.work.bytes < sizeof(WorkItem) * wis.size()) {
     dfree(ch.work);
     wf_status st = dalloc(ch.work, sizeof(WorkItem) * wis.size());
@@ -1321,7 +1512,15 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
       op->total_rows += Mc;
       if (chan_rows) off += Mc;
     }
-    for (auto& ch : op->chans) ch.info.nchan = nchan;
+    for (auto& ch : op->chans) {
+      ch.info.nchan = nchan;
+      if (ch.otf)
+        op->otf_bytes = std::max(op->otf_bytes, (size_t)ch.info.mem_transient_bytes);
+    }
+    if (op->otf_bytes > 0) {
+      if ((st = dalloc(op->otf_mis, 2 * sizeof(int))) != WF_OK) return st;
+      WF_HIP(hipMemsetAsync(op->otf_mis.p, 0, 2 * sizeof(int), s));
+    }
     WF_HIP(hipStreamSynchronize(s));
     if ((st = set_branches(op, opt.branches > 0 ? opt.branches
                                                 : (nchan > 1 ? std::min(nchan, 4) : 1))) !=
@@ -1390,6 +1589,7 @@ wf_status wf_get_row(const wf_op* op, int32_t chan, int64_t row, int32_t* T, int
     const ChanOp& ch = op->chans[chan];
     if (row < 0 || row >= ch.nvis) return fail(WF_EINVAL, "row out of range");
     if (ch.holo) return fail(WF_ENOTSUP, "a holographic operator keeps no rows of G");
+    if (ch.otf) return fail(WF_ENOTSUP, "an on-the-fly operator keeps no rows of G");
     WF_HIP(hipSetDevice(op->device));
     WF_HIP(hipDeviceSynchronize());
     // host index of the stored rows, built on first use (and after a re-split)

@@ -132,6 +132,15 @@ struct ChanOp {
   std::vector<int64_t> h_t0, h_nt;         // per bin: first tile, tile count
   std::vector<int32_t> h_dmax;             // per bin: largest stencil side
   int64_t h_values = 0;                    // stored stencil values (complex)
+  // strategy (c), G on the fly: no values are kept; each bin is cut into chunks of whole
+  // row groups whose values are rebuilt into a branch's transient buffer at every apply
+  bool otf = false;
+  DevBuf uvw, wts, uperm, row_wi, mids, cents;  // value-pass inputs kept on the device
+  std::vector<int32_t> gchunk;             // chunk of each row group
+  std::vector<int64_t> ck_s0, ck_s1, ck_vbase, ck_taps;  // sorted rows, first value, values
+  std::vector<int32_t> ck_first, ck_count; // per bin: first chunk, chunk count
+  std::vector<int32_t> ck_wi0, ck_nwi;     // [chunk * NCLS + class] work-item ranges
+  int64_t ck_max = 0;                      // values of the largest chunk
   DevBuf meta, voff, perm, vals, work;
   DevBuf prune;                            // per bin: strip bits, tile bits, groups
   std::vector<size_t> pr_strip, pr_tile, pr_groups;  // byte offsets into prune per bin
@@ -149,7 +158,7 @@ struct Profiler {
   double total_ms = 0;
 };
 
-constexpr int NPROF = 5;
+constexpr int NPROF = 6;
 
 // One concurrent branch of an apply: its own stream and work grids (branch 0 runs on the
 // caller's stream and owns the operator's first set of grids).  acc receives the partial
@@ -158,6 +167,7 @@ struct Branch {
   hipStream_t s = nullptr;
   hipEvent_t done = nullptr;
   DevBuf X, Y, A, acc;
+  DevBuf gbuf;   // transient G values of on-the-fly channels
 };
 
 // Work of one branch for one channel: a list of its non-empty bins.  A direct segment
@@ -192,6 +202,8 @@ struct wf_op {
   bool capturing = false;
   uint64_t generation = 0;           // bumped when work items or branches change
   wf::DevBuf fb_h, fb_x, fb_c, fb_red;  // forward-backward work images and reductions
+  size_t otf_bytes = 0;              // transient value buffer per branch (strategy (c))
+  wf::DevBuf otf_mis;                // counters the on-the-fly value pass writes
 };
 
 // Residual-kernel network: FP32 parameters with Adam state, per-batch activations, and
