@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Φ†Φ applies/s, Gvis/s (4096², 50M vis): mixed vs FP32 at ≤1e-3 rel err"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFS = 78.6
 
 
 def log(*a):
@@ -48,11 +49,14 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="precision",
-                    choices=["precision", "batched", "learned", "holographic", "counters"],
+                    choices=["precision", "batched", "learned", "holographic", "counters",
+                             "onthefly", "weighted"],
                     help="precision: one channel 4096^2 / 50M rows (default); batched: "
                          "16 channels 2048^2 / 48M rows, autotuned, one graph per sweep; "
                          "learned: G of 20M rows on 4096^2 / 16 bins built with the "
-                         "residual-kernel network vs the exact construction")
+                         "residual-kernel network vs the exact construction; onthefly: "
+                         "the precision form with G rebuilt at every apply (strategy (c)); "
+                         "weighted: the precision form with Briggs weights and 10%% flags")
     ap.add_argument("--train-examples", type=int, default=1_000_000)
     ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--store", default="f16", help="value storage of the batched form")
@@ -392,6 +396,148 @@ def bench_holographic(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def _timed_applies(op, x, out, n, torch):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(n):
+        op.psf_apply_re(x, out)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def bench_onthefly(args, torch):
+    """Strategy (c) on the precision form: no G is stored; every apply rebuilds each
+    w-bin's rows of G chunk by chunk with the FP64 value pass, then applies them with the
+    fused kernel.  Compared with the stored-G operator (same P) for time and result."""
+    import wfsynth as ws
+    from paper_2605_26347_amd import Operator
+    obs = ws.precision_form(n=args.n, nvis=args.nvis, fov_deg=args.fov)
+    M = obs.uvw_m.shape[0]
+    x = torch.from_numpy(obs.sky.astype(np.float32)[None]).to("cuda:0")
+    steps, warm = max(1, min(args.steps, 3)), max(1, min(args.warmup, 1))
+    t0 = time.time()
+    op = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad,
+                  memory_budget=args.budget, store=args.store, strategy="otf")
+    tb = time.time() - t0
+    info = op.plan(0)
+    log(f"on the fly: built in {tb:.1f} s, P={info['nbins']}, row data "
+        f"{info['mem_g_bytes'] / 1e9:.2f} GB, transient {info['mem_transient_bytes'] / 1e9:.2f} "
+        f"GB per branch, value pass {info['value_pass_flops'] / 1e12:.2f} TFLOP per apply")
+    out = torch.empty_like(x)
+    for _ in range(warm):
+        op.psf_apply_re(x, out)
+    ms = _timed_applies(op, x, out, steps, torch)
+    log(f"on the fly: {ms:.1f} ms/apply")
+    op.profile_enable(5, True)
+    op.profile_enable(0, True)
+    op.psf_apply_re(x, out)
+    n5, ms5 = op.profile_read(5)
+    n0, ms0 = op.profile_read(0)
+    op.profile_enable(5, False)
+    op.profile_enable(0, False)
+    log(f"on the fly: value pass {ms5:.1f} ms in {n5} launches, G^dag G {ms0:.1f} ms "
+        f"in {n0} launches")
+    otf_out = out.clone()
+    op.close()
+    del op
+    torch.cuda.empty_cache()
+    g = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad,
+                 memory_budget=args.budget, store=args.store, nbins=info["nbins"])
+    gout = torch.empty_like(x)
+    for _ in range(warm):
+        g.psf_apply_re(x, gout)
+    gms = _timed_applies(g, x, gout, steps, torch)
+    gbytes = g.plan(0)["mem_g_bytes"]
+    d = float((otf_out - gout).norm() / gout.norm())
+    log(f"stored G ({gbytes / 1e9:.1f} GB): {gms:.1f} ms/apply; on the fly vs stored {d:.2e}")
+    g.close()
+    flops = info["value_pass_flops"]
+    ach = flops / (ms5 * 1e-3) / 1e12 if ms5 > 0 else None
+    line = {
+        "metric": "Φ†Φ applies/s with G computed on the fly (strategy (c)), 4096², 50M vis",
+        "value": 1e3 / ms, "unit": "applies/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"Re{{Phi^dag Phi x}}, {obs.nx}^2 image, {M} visibilities, "
+                               f"3 deg field, G rebuilt at every apply",
+                   "store": args.store, "nbins": info["nbins"], "strategy": "on the fly"},
+        "build_s": tb, "row_data_bytes": info["mem_g_bytes"],
+        "transient_bytes_per_branch": info["mem_transient_bytes"],
+        "value_pass_ms": ms5, "value_pass_launches": n5, "gtg_ms": ms0,
+        "stored_G": {"ms": gms, "bytes": gbytes}, "otf_vs_stored_rel": d,
+        "roofline": {"bound": "alu", "kernel": "k_gbuild (value pass, FP64)",
+                     "achieved": ach, "peak": FP64_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": ach / FP64_VECTOR_PEAK_TFS if ach else None, "traffic": None,
+                     "flops_per_apply": flops,
+                     "flops": "16 nk^3 (two DFT sweeps of the nk x nk residual kernel) + "
+                              "4 J (n' T + T^2) (Kaiser-Bessel convolution) per row"},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_weighted(args, torch):
+    """Data weighting and flags in G (Sect. 2) on the precision form: Briggs robust
+    weights (R = 0) from log-normal noise levels, 10% of the rows flagged in runs, both
+    folded into the stored G; timed like the precision form."""
+    import wfsynth as ws
+    from paper_2605_26347_amd import Operator, briggs_weights
+    obs = ws.precision_form(n=args.n, nvis=args.nvis, fov_deg=args.fov)
+    M = obs.uvw_m.shape[0]
+    sigma = ws.noise_sigma(M)
+    flags = ws.flag_runs(M, 0.1)
+    nat = (1.0 / sigma.astype(np.float64) ** 2).astype(np.float32)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    w = briggs_weights(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad, 0.0,
+                       natural=nat, flags=flags)
+    tw = time.time() - t0
+    w = (w / w.max()).astype(np.float32)
+    log(f"Briggs weights of {M} rows in {tw:.2f} s (host arrays in and out)")
+    t0 = time.time()
+    op = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad,
+                  memory_budget=args.budget, store=args.store, weights=w, flags=flags)
+    tb = time.time() - t0
+    info = op.plan(0)
+    x = torch.from_numpy(obs.sky.astype(np.float32)[None]).to("cuda:0")
+    out = torch.empty_like(x)
+    tune = op.autotune(x, out, reps=2)
+    for _ in range(args.warmup):
+        op.psf_apply_re(x, out)
+    ms = _timed_applies(op, x, out, args.steps, torch)
+    op.set_branches(1)
+    for _ in range(args.warmup):
+        op.psf_apply_re(x, out)
+    op.profile_enable(0, True)
+    for _ in range(args.steps):
+        op.psf_apply_re(x, out)
+    nl, kms = op.profile_read(0)
+    op.profile_enable(0, False)
+    kl = kms / max(nl, 1)
+    P = info["nbins"]
+    per_launch = gtg_bytes(info, args.store) / max(P, 1)
+    ach = per_launch / (kl * 1e-3) / 1e9
+    log(f"weighted: built {tb:.1f} s, P={P}, {info['nrows']} rows kept, {ms:.3f} ms/apply, "
+        f"G^dag G {kl:.3f} ms/launch")
+    line = {
+        "metric": "Φ†Φ applies/s with Briggs weights and 10% flags in G (4096², 50M vis)",
+        "value": 1e3 / ms, "unit": "applies/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Re{{Phi^dag Phi x}}, {obs.nx}^2 image, {M} visibilities, "
+                               f"Briggs R=0, 10% flagged", "store": args.store, "nbins": P},
+        "briggs_s": tw, "build_s": tb, "rows_kept": info["nrows"],
+        "rows_flagged": info["nflagged"], "autotune": tune,
+        "roofline": {"bound": "hbm", "kernel": "fused G^dag G (k_gtg)", "achieved": ach,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": per_launch, "ms_per_launch": kl},
+    }
+    op.close()
+    print(json.dumps(line), flush=True)
+
+
 def bench_learned(args, torch):
     """Learned form: the residual-kernel network trained on 1M exact kernels (residual w
     of the 64-antenna array binned at 16 bins, fields of 1-4 degrees), then G of 20M rows
@@ -491,6 +637,12 @@ def main():
         return
     if args.workload == "counters":
         counters_run(args, torch)
+        return
+    if args.workload == "onthefly":
+        bench_onthefly(args, torch)
+        return
+    if args.workload == "weighted":
+        bench_weighted(args, torch)
         return
     t0 = time.time()
     obs = ws.precision_form(n=args.n, nvis=args.nvis, fov_deg=args.fov)

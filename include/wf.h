@@ -195,6 +195,9 @@ typedef struct {
   double mem_h_bytes;       /* device bytes of the holographic stencils (strategy (b))  */
   int64_t nflagged;         /* flagged rows of this channel (discarded)                 */
   double mem_transient_bytes;/* on-the-fly: value buffer of one branch (largest chunk)   */
+  double value_pass_flops;  /* on-the-fly: FP64 flops of one apply's value pass (two
+                               DFT sweeps of each residual kernel, 16 nk^3, and its
+                               Kaiser-Bessel convolution, 4 J (n' T + T^2)); else 0    */
 } wf_plan_info;
 
 /* Plan and matrix statistics of channel chan (Sect. 3.4 quantities). */

@@ -43,7 +43,8 @@ class WfPlanInfo(ctypes.Structure):
                 ("max_dropped_energy", ctypes.c_double), ("build_seconds", ctypes.c_double),
                 ("max_rows_per_item", ctypes.c_int32), ("branch", ctypes.c_int32),
                 ("surrogate_fraction", ctypes.c_double), ("mem_h_bytes", ctypes.c_double),
-                ("nflagged", ctypes.c_int64), ("mem_transient_bytes", ctypes.c_double)]
+                ("nflagged", ctypes.c_int64), ("mem_transient_bytes", ctypes.c_double),
+                ("value_pass_flops", ctypes.c_double)]
 
 
 class WfTuneInfo(ctypes.Structure):

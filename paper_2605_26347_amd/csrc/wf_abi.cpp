@@ -559,7 +559,18 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   if (otf && mlp)
     return fail(WF_ENOTSUP, "the on-the-fly strategy builds exact kernels only (no kernel network)");
   ch.gchunk.clear();
-  if (otf) chunk_groups(ch, taps_total, b_v, share);
+  double vp_flops = 0.0;
+  if (otf) {
+    chunk_groups(ch, taps_total, b_v, share);
+    // FP64 work of one value pass: two length-nk DFT sweeps of the nk x nk residual
+    // kernel (16 nk^3) and its Kaiser-Bessel convolution (4 J (n' T + T^2))
+    for (const RowGroup& g : ch.groups)
+      for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) {
+        const int nk = nk_rule(w[idx[r]] - ch.centroids[g.bin], op->kp, true);
+        const double T = trow[r], np = T - opt.J + 1;
+        vp_flops += (nk > 1 ? 16.0 * nk * nk * nk : 0.0) + 4.0 * opt.J * (np * T + T * T);
+      }
+  }
   if (otf) {
     const double meta_bytes = (24.0 + 16.0 + (sel.w ? 4.0 : 0.0) + (sel.keep ? 4.0 : 0.0)) * M;
     if (meta_bytes + 4.0 * b_v * (double)ch.ck_max > share)
@@ -825,6 +836,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
                                    ch.row_wi.bytes) + 12.0 * M + sizeof(WorkItem) * wis.size()
                       : (double)b_v * taps_total + 12.0 * M + sizeof(WorkItem) * wis.size();
   in.mem_transient_bytes = otf ? (double)b_v * ch.ck_max : 0.0;
+  in.value_pass_flops = vp_flops;
   in.mem_model_bytes = pr.mem_model;
   in.cost_model = pr.cost_model;
   in.capped_fraction = M ? (double)ncapped / (double)M : 0.0;

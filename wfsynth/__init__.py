@@ -114,11 +114,19 @@ def flag_runs(nrows: int, fraction: float, seed: int = SEED_DATA + 100,
     """Boolean flag mask with about `fraction` of the rows set, in contiguous runs of
     geometric length (mean mean_run rows), as time ranges or baselines are flagged."""
     rng = np.random.default_rng(seed)
-    m = np.zeros(nrows, dtype=bool)
     target = int(round(fraction * nrows))
-    while m.sum() < target:
-        a = int(rng.integers(0, nrows))
-        m[a:a + int(rng.geometric(1.0 / mean_run))] = True
+    cover = np.zeros(nrows + 1, dtype=np.int64)   # run starts +1, run ends -1
+    m = np.zeros(nrows, dtype=bool)
+    count = 0
+    while count < target:
+        # a batch of runs sized to the remaining deficit; overlaps leave some behind
+        k = max(1, (target - count) // mean_run)
+        a = rng.integers(0, nrows, k)
+        e = np.minimum(a + rng.geometric(1.0 / mean_run, k), nrows)
+        np.add.at(cover, a, 1)
+        np.add.at(cover, e, -1)
+        m = np.cumsum(cover[:nrows]) > 0
+        count = int(m.sum())
     return m
 
 
