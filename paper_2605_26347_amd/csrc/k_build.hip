@@ -1,6 +1,7 @@
 // Build of the de-gridding matrix G (workflow stages 2-3 of Sect. 3.5), FP64.
 //
-// Per visibility row k (one wavefront per row, one row at a time):
+// Per visibility row k (one wavefront per row; one launch per class of residual-kernel
+// side, whose LDS scratch is sized for that class):
 //   * u, v, w in wavelengths = uvw_m * f / c; bin p = nearest w-bin centroid with ties to
 //     the lower bin, i.e. the number of bin midpoints below w (Sect. 3.1 w-stacking);
 //     residual w_proj = w - w_p;
@@ -29,16 +30,39 @@ namespace wf {
 
 constexpr int MAXNK = 31;
 constexpr int MAXT = 37;      // J - 1 + smax <= 37
-constexpr int NSORT = 1024;   // power of two >= MAXNK^2
 
+constexpr int pow2_at_least(int v) {
+  int p = 16;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// LDS scratch of one row for residual-kernel sides up to NK.  A row needs, in turn, the
+// DFT intermediate t, the sort slots e and the convolution intermediate t2, never two
+// of them at once, so they share one region.  Rows are processed by kernel-side class
+// (sides in (nk_lo<NK>, NK]), so that small kernels get a small scratch and many rows
+// in flight per compute unit.
+template <int NK>
 struct KScratch {
-  double2 c[MAXNK * MAXNK];        // samples, then kernel
-  double2 t[MAXNK * MAXNK];        // DFT intermediate
-  double e[NSORT];                 // energies (sorted)
-  double2 roots[MAXNK];            // exp(-2 pi i m / nk)
-  double2 t2[MAXNK * MAXT];        // convolution intermediate
-  double ku[16], kv[16];           // Kaiser-Bessel taps (J <= 15)
+  static constexpr int NS = pow2_at_least(NK * NK);          // sort slots
+  static constexpr int TM = NK + 14 < MAXT ? NK + 14 : MAXT;  // patch side (J <= 15)
+  static constexpr int UW = (2 * NK * NK > NS ? (2 * NK * TM > 2 * NK * NK ? 2 * NK * TM
+                                                                           : 2 * NK * NK)
+                                              : (2 * NK * TM > NS ? 2 * NK * TM : NS));
+  double2 c[NK * NK];                     // samples, then kernel
+  alignas(16) double u[UW];               // t / e / t2
+  double2 roots[NK];                      // exp(-2 pi i m / nk)
+  double ku[16], kv[16];                  // Kaiser-Bessel taps (J <= 15)
+  __device__ double2* t() { return reinterpret_cast<double2*>(u); }
+  __device__ double* e() { return u; }
+  __device__ double2* t2() { return reinterpret_cast<double2*>(u); }
 };
+
+template <int NK>
+constexpr int nk_lo() {
+  return NK == 7 ? 0 : NK == 15 ? 7 : NK == 21 ? 15 : 21;
+}
+
 
 __device__ __forceinline__ double dev_i0(double x) {
 #pragma clang fp contract(off)
@@ -118,11 +142,13 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
-__device__ int wkernel_threshold(int nk, double eps, KScratch& S, double* dropped);
+template <int NK>
+__device__ int wkernel_threshold(int nk, double eps, KScratch<NK>& S, double* dropped);
 
 // Exact residual kernel of side nk with threshold; workgroup = one wavefront.
 // Leaves the masked kernel in S.c (nk x nk, [s_v][s_u]); returns h' (kept half-side).
-__device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratch& S,
+template <int NK>
+__device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratch<NK>& S,
                            double* dropped) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x;
@@ -164,7 +190,7 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
       re += x.x * r.x - x.y * r.y;
       im += x.x * r.y + x.y * r.x;
     }
-    S.t[idx] = make_double2(re, im);
+    S.t()[idx] = make_double2(re, im);
   }
   __syncthreads();
   const double inv = 1.0 / ((double)nk * (double)nk);
@@ -174,7 +200,7 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
     for (int b = 0; b < nk; ++b) {
       int m = ((sv - h) * (b - h)) % nk;
       if (m < 0) m += nk;
-      const double2 r = S.roots[m], x = S.t[b * nk + su];
+      const double2 r = S.roots[m], x = S.t()[b * nk + su];
       re += r.x * x.x - r.y * x.y;
       im += r.x * x.y + r.y * x.x;
     }
@@ -188,7 +214,8 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
 // most eps of the energy (ties within 1e-9 relative of the smallest kept energy are
 // kept), zero them in S.c, and return the half-side of the smallest centred square that
 // holds every kept entry.  Workgroup = one wavefront.
-__device__ int wkernel_threshold(int nk, double eps, KScratch& S, double* dropped) {
+template <int NK>
+__device__ int wkernel_threshold(int nk, double eps, KScratch<NK>& S, double* dropped) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x;
   const int nn2 = nk * nk;
@@ -200,9 +227,9 @@ __device__ int wkernel_threshold(int nk, double eps, KScratch& S, double* droppe
   for (int i = lane; i < NS; i += 64) {
     if (i < nn2) {
       const double2 v = S.c[i];
-      S.e[i] = v.x * v.x + v.y * v.y;
+      S.e()[i] = v.x * v.x + v.y * v.y;
     } else {
-      S.e[i] = DBL_MAX;
+      S.e()[i] = DBL_MAX;
     }
   }
   __syncthreads();
@@ -212,10 +239,10 @@ __device__ int wkernel_threshold(int nk, double eps, KScratch& S, double* droppe
         const int ixj = i ^ j;
         if (ixj > i) {
           const bool up = (i & k) == 0;
-          const double a = S.e[i], b = S.e[ixj];
+          const double a = S.e()[i], b = S.e()[ixj];
           if ((a > b) == up) {
-            S.e[i] = b;
-            S.e[ixj] = a;
+            S.e()[i] = b;
+            S.e()[ixj] = a;
           }
         }
       }
@@ -223,14 +250,14 @@ __device__ int wkernel_threshold(int nk, double eps, KScratch& S, double* droppe
     }
   }
   // inclusive prefix sums: lane holds slots pl*lane .. pl*lane + pl - 1
-  constexpr int PLMAX = NSORT / 64;
+  constexpr int PLMAX = KScratch<NK>::NS >= 64 ? KScratch<NK>::NS / 64 : 1;
   const int pl = NS >= 64 ? NS / 64 : 1;
   double loc[PLMAX];
   double run = 0.0;
 #pragma unroll
   for (int q = 0; q < PLMAX; ++q) {
     const int i = pl * lane + q;
-    const double v = (q < pl && i < nn2) ? S.e[i] : 0.0;
+    const double v = (q < pl && i < nn2) ? S.e()[i] : 0.0;
     run += v;
     loc[q] = run;
   }
@@ -251,7 +278,7 @@ __device__ int wkernel_threshold(int nk, double eps, KScratch& S, double* droppe
   }
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
   int jdrop = cnt < nn2 - 1 ? cnt : nn2 - 1;
-  const double tau = S.e[jdrop];
+  const double tau = S.e()[jdrop];
   const double cut = tau * (1.0 - 1e-9);
   int hp = 0;
   double dsum = 0.0;
@@ -288,7 +315,8 @@ __device__ __forceinline__ bool use_prediction(const float* pr, int nk_full,
 // window, cut to the smallest centred square whose outside holds at most eps of the
 // energy (whole square rings are dropped; no sort, unlike the exact kernel's per-entry
 // threshold, whose zeroed entries the network has learned as near-zero outputs).
-__device__ int predicted_kernel(const float* pr, int nk, const KernelParams& kp, KScratch& S,
+template <int NK>
+__device__ int predicted_kernel(const float* pr, int nk, const KernelParams& kp, KScratch<NK>& S,
                                 double* dropped) {
 #pragma clang fp contract(off)
   const int a = (MLP_SIDE - nk) / 2;
@@ -327,6 +355,7 @@ __device__ int predicted_kernel(const float* pr, int nk, const KernelParams& kp,
   return hp;
 }
 
+template <int NK>
 __global__ __launch_bounds__(64) void k_rowsym(const double* __restrict__ uvw, int64_t r0,
                                                int64_t r1, double scale, double gsx,
                                                double gsy, const double* __restrict__ mids,
@@ -335,11 +364,12 @@ __global__ __launch_bounds__(64) void k_rowsym(const double* __restrict__ uvw, i
                                                uint64_t* __restrict__ keys,
                                                float* __restrict__ dropped_out, Surrogate sg) {
 #pragma clang fp contract(off)
-  __shared__ KScratch S;
+  __shared__ KScratch<NK> S;
   for (int64_t k = r0 + blockIdx.x; k < r1; k += gridDim.x) {
     const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
     const int nk_full = dev_nk(g.wproj, kp, false);
     const int nk = nk_full > kp.smax ? kp.smax : nk_full;
+    if (nk > NK || nk <= nk_lo<NK>()) continue;   // another class's row (wave-uniform)
     double dropped;
     const float* pr = sg.pred ? sg.pred + (k - r0) * MLP_OUT : nullptr;
     const bool usep = use_prediction(pr, nk_full, kp, sg.logtol);
@@ -380,7 +410,7 @@ __device__ __forceinline__ void store_val(void* vals, int64_t i, double re, doub
   }
 }
 
-template <int STORE>
+template <int STORE, int NK>
 __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, int64_t s0,
                                                int64_t s1, const int32_t* __restrict__ perm,
                                                const uint32_t* __restrict__ meta,
@@ -394,7 +424,7 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
                                                int64_t vbase, int* __restrict__ mismatch,
                                                Surrogate sg, const float* __restrict__ wts) {
 #pragma clang fp contract(off)
-  __shared__ KScratch S;
+  __shared__ KScratch<NK> S;
   const int lane = threadIdx.x;
   const int half = (kp.J - 1) / 2;
   for (int64_t s = s0 + blockIdx.x; s < s1; s += gridDim.x) {
@@ -402,6 +432,7 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
     const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
     const int nk_full = dev_nk(g.wproj, kp, false);
     const int nk = nk_full > kp.smax ? kp.smax : nk_full;
+    if (nk > NK || nk <= nk_lo<NK>()) continue;   // another class's row (wave-uniform)
     double dropped;
     const float* pr = sg.pred ? sg.pred + (s - s0) * MLP_OUT : nullptr;
     const bool usep = use_prediction(pr, nk_full, kp, sg.logtol);
@@ -436,7 +467,7 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
           im += c.y * S.ku[dd];
         }
       }
-      S.t2[idx] = make_double2(re, im);
+      S.t2()[idx] = make_double2(re, im);
     }
     __syncthreads();
     const int64_t vb = wis[row_wi[s]].voff + voff[s] - vbase;
@@ -449,7 +480,7 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
         for (int m = 0; m < np; ++m) {
           const int dd = av - m;
           if (dd >= 0 && dd < kp.J) {
-            const double2 x = S.t2[m * T + au];
+            const double2 x = S.t2()[m * T + au];
             re += S.kv[dd] * x.x;
             im += S.kv[dd] * x.y;
           }
@@ -520,7 +551,7 @@ __global__ __launch_bounds__(64) void k_exact_targets(const double* __restrict__
                                                       const double* __restrict__ L, int64_t n,
                                                       KernelParams kp, float* __restrict__ t) {
 #pragma clang fp contract(off)
-  __shared__ KScratch S;
+  __shared__ KScratch<MLP_SIDE> S;
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
     const KernelParams q = with_field(kp, L[i]);
     const int nk = dev_nk(w[i], q, false);
@@ -547,9 +578,38 @@ hipError_t launch_rowsym(const double* uvw, int64_t r0, int64_t r1, double scale
   const int64_t n = r1 - r0;
   if (n <= 0) return hipSuccess;
   const int blocks = (int)(n < 262144 ? n : 262144);
-  hipLaunchKernelGGL(k_rowsym, dim3(blocks), dim3(64), 0, s, uvw, r0, r1, scale, gsx, gsy, mids,
-                     P, cents, Kx, Ky, tile, kp, keys, dropped, sg);
+  // one launch per kernel-side class over the whole range; each takes its own rows
+  hipLaunchKernelGGL(k_rowsym<7>, dim3(blocks), dim3(64), 0, s, uvw, r0, r1, scale, gsx, gsy,
+                     mids, P, cents, Kx, Ky, tile, kp, keys, dropped, sg);
+  hipLaunchKernelGGL(k_rowsym<15>, dim3(blocks), dim3(64), 0, s, uvw, r0, r1, scale, gsx, gsy,
+                     mids, P, cents, Kx, Ky, tile, kp, keys, dropped, sg);
+  hipLaunchKernelGGL(k_rowsym<21>, dim3(blocks), dim3(64), 0, s, uvw, r0, r1, scale, gsx, gsy,
+                     mids, P, cents, Kx, Ky, tile, kp, keys, dropped, sg);
+  hipLaunchKernelGGL(k_rowsym<31>, dim3(blocks), dim3(64), 0, s, uvw, r0, r1, scale, gsx, gsy,
+                     mids, P, cents, Kx, Ky, tile, kp, keys, dropped, sg);
   return hipGetLastError();
+}
+
+template <int STORE>
+void launch_gbuild_classes(int blocks, hipStream_t s, const double* uvw, int64_t s0, int64_t s1,
+                           const int32_t* perm, const uint32_t* meta, const uint32_t* voff,
+                           const int32_t* row_wi, const WorkItem* wi, double scale, double gsx,
+                           double gsy, const double* mids, int P, const double* cents,
+                           const KernelParams& kp, void* vals, int64_t vbase, int* mismatch,
+                           const Surrogate& sg, const float* wts) {
+  // one launch per kernel-side class over the whole range; each takes its own rows
+  hipLaunchKernelGGL((k_gbuild<STORE, 7>), dim3(blocks), dim3(64), 0, s, uvw, s0, s1, perm,
+                     meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
+                     mismatch, sg, wts);
+  hipLaunchKernelGGL((k_gbuild<STORE, 15>), dim3(blocks), dim3(64), 0, s, uvw, s0, s1, perm,
+                     meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
+                     mismatch, sg, wts);
+  hipLaunchKernelGGL((k_gbuild<STORE, 21>), dim3(blocks), dim3(64), 0, s, uvw, s0, s1, perm,
+                     meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
+                     mismatch, sg, wts);
+  hipLaunchKernelGGL((k_gbuild<STORE, 31>), dim3(blocks), dim3(64), 0, s, uvw, s0, s1, perm,
+                     meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
+                     mismatch, sg, wts);
 }
 
 hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_t* perm,
@@ -563,19 +623,19 @@ hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_
   const int blocks = (int)(n < 262144 ? n : 262144);
   switch (store) {
     case WF_STORE_F32:
-      hipLaunchKernelGGL(k_gbuild<WF_STORE_F32>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
-                         perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, vbase, mismatch, sg, wts);
+      launch_gbuild_classes<WF_STORE_F32>(blocks, s, uvw, s0, s1, perm, meta, voff, row_wi, wi,
+                                          scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
+                                          mismatch, sg, wts);
       break;
     case WF_STORE_F16:
-      hipLaunchKernelGGL(k_gbuild<WF_STORE_F16>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
-                         perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, vbase, mismatch, sg, wts);
+      launch_gbuild_classes<WF_STORE_F16>(blocks, s, uvw, s0, s1, perm, meta, voff, row_wi, wi,
+                                          scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
+                                          mismatch, sg, wts);
       break;
     default:
-      hipLaunchKernelGGL(k_gbuild<WF_STORE_BF16>, dim3(blocks), dim3(64), 0, s, uvw, s0, s1,
-                         perm, meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp,
-                         vals, vbase, mismatch, sg, wts);
+      launch_gbuild_classes<WF_STORE_BF16>(blocks, s, uvw, s0, s1, perm, meta, voff, row_wi,
+                                           wi, scale, gsx, gsy, mids, P, cents, kp, vals,
+                                           vbase, mismatch, sg, wts);
       break;
   }
   return hipGetLastError();
