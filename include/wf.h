@@ -61,7 +61,7 @@ typedef enum { WF_STORE_F32 = 0, WF_STORE_F16 = 1, WF_STORE_BF16 = 2 } wf_store;
  * Tmax the largest patch side reaching the tile) and applies Phi^dag Phi only:
  * wf_forward / wf_adjoint / wf_get_row return WF_ENOTSUP for it.  Needs tile 32.
  * An on-the-fly operator keeps per row only its coordinates, weight and patch word
- * (about 44 bytes) and rebuilds G chunk by chunk (runs of whole row groups of one bin,
+ * (about 48 bytes) and rebuilds G chunk by chunk (runs of whole row groups of one bin,
  * at most 2.5% of the budget share each) into a transient buffer of each branch at every
  * apply, with the same FP64 value pass as the build of (a): its results equal those of
  * (a) up to the order of FP32 atomic additions.  It uses exact kernels only (WF_ENOTSUP

@@ -9,9 +9,9 @@
 //   * residual-w kernel (Sect. 3.1 w-projection, Fig. 1): side n_k from the chirp's
 //     bandwidth over the padded field; the phase-tapered chirp is sampled on n_k x n_k
 //     points over o times the field; a small DFT gives the kernel; the smallest entries
-//     holding at most eps of the energy are dropped (a wave-wide bitonic sort and
-//     prefix sum find the cut; entries within 1e-9 relative of the smallest kept energy
-//     are kept with it) and the kernel is cut to the smallest centred square;
+//     holding at most eps of the energy are dropped (a binary search over the energies'
+//     bit patterns finds the cut; entries within 1e-9 relative of the smallest kept
+//     energy are kept with it) and the kernel is cut to the smallest centred square;
 //   * G row (Sect. 3.2): the kernel convolved with the 7 x 7 Kaiser-Bessel taps at the
 //     row's fractional grid offset, a dense T x T patch, T = n' + J - 1.
 // Decisions that turn floating point into integers (bin, nearest cell, n_k, threshold)
@@ -38,19 +38,17 @@ constexpr int pow2_at_least(int v) {
 }
 
 // LDS scratch of one row for residual-kernel sides up to NK.  A row needs, in turn, the
-// DFT intermediate t, the sort slots e and the convolution intermediate t2, never two
-// of them at once, so they share one region.  Rows are processed by kernel-side class
+// DFT intermediate t, the sort slots e (small classes) and the convolution intermediate
+// t2, never two at once, so they share one region.  Rows are processed by kernel-side class
 // (sides in (nk_lo<NK>, NK]), so that small kernels get a small scratch and many rows
 // in flight per compute unit.
 template <int NK>
 struct KScratch {
-  static constexpr int NS = pow2_at_least(NK * NK);          // sort slots
   static constexpr int TM = NK + 14 < MAXT ? NK + 14 : MAXT;  // patch side (J <= 15)
-  static constexpr int UW = (2 * NK * NK > NS ? (2 * NK * TM > 2 * NK * NK ? 2 * NK * TM
-                                                                           : 2 * NK * NK)
-                                              : (2 * NK * TM > NS ? 2 * NK * TM : NS));
+  static constexpr int NS = pow2_at_least(NK * NK);          // sort slots (NK <= 15)
+  static constexpr int UW = 2 * NK * TM > NS ? 2 * NK * TM : NS;  // TM >= NK: t2 >= t
   double2 c[NK * NK];                     // samples, then kernel
-  alignas(16) double u[UW];               // t / e / t2
+  alignas(16) double u[UW];               // t, then e, then t2
   double2 roots[NK];                      // exp(-2 pi i m / nk)
   double ku[16], kv[16];                  // Kaiser-Bessel taps (J <= 15)
   __device__ double2* t() { return reinterpret_cast<double2*>(u); }
@@ -62,6 +60,13 @@ template <int NK>
 constexpr int nk_lo() {
   return NK == 7 ? 0 : NK == 15 ? 7 : NK == 21 ? 15 : 21;
 }
+__host__ __device__ constexpr int class_of_nk(int nk) {
+  return nk <= 7 ? 0 : nk <= 15 ? 1 : nk <= 21 ? 2 : 3;
+}
+
+// Workgroups of a launch over n listed rows (grid-stride beyond 2^18).
+inline unsigned grid_for(int64_t n) { return (unsigned)(n < 262144 ? n : 262144); }
+
 
 
 __device__ __forceinline__ double dev_i0(double x) {
@@ -179,13 +184,16 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
     S.c[idx] = make_double2(c, -s);   // exp(-2 pi i ph)
   }
   __syncthreads();
-  // t[b][su] = sum_a c[b][a] exp(-2 pi i (su-h)(a-h)/nk)
+  // t[b][su] = sum_a c[b][a] exp(-2 pi i (su-h)(a-h)/nk); the root index
+  // (su-h)(a-h) mod nk advances by (su-h) mod nk per step of a
   for (int idx = lane; idx < nn2; idx += 64) {
     const int b = idx / nk, su = idx - b * nk;
     double re = 0.0, im = 0.0;
-    for (int a = 0; a < nk; ++a) {
-      int m = ((su - h) * (a - h)) % nk;
-      if (m < 0) m += nk;
+    const int step = (su - h + nk) % nk;
+    int m = ((su - h) * (-h)) % nk;
+    if (m < 0) m += nk;
+#pragma unroll 4
+    for (int a = 0; a < nk; ++a, m = (m + step >= nk ? m + step - nk : m + step)) {
       const double2 r = S.roots[m], x = S.c[b * nk + a];
       re += x.x * r.x - x.y * r.y;
       im += x.x * r.y + x.y * r.x;
@@ -197,9 +205,11 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
   for (int idx = lane; idx < nn2; idx += 64) {
     const int sv = idx / nk, su = idx - sv * nk;
     double re = 0.0, im = 0.0;
-    for (int b = 0; b < nk; ++b) {
-      int m = ((sv - h) * (b - h)) % nk;
-      if (m < 0) m += nk;
+    const int step = (sv - h + nk) % nk;
+    int m = ((sv - h) * (-h)) % nk;
+    if (m < 0) m += nk;
+#pragma unroll 4
+    for (int b = 0; b < nk; ++b, m = (m + step >= nk ? m + step - nk : m + step)) {
       const double2 r = S.roots[m], x = S.t()[b * nk + su];
       re += r.x * x.x - r.y * x.y;
       im += r.x * x.y + r.y * x.x;
@@ -214,71 +224,139 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
 // most eps of the energy (ties within 1e-9 relative of the smallest kept energy are
 // kept), zero them in S.c, and return the half-side of the smallest centred square that
 // holds every kept entry.  Workgroup = one wavefront.
+//
+// In ascending order the dropped entries are the longest prefix whose running sum stays
+// at most eps * total, and tau, the smallest kept energy, is the entry after it (the
+// largest entry when every prefix stays below).  Small kernels (n_k <= 15) sort their
+// energies (a bitonic sort over at most 256 slots in LDS) and scan the prefix sums.
+// Larger ones use the equivalent rule without sorting: with G(v) the sum of the energies
+// <= v, tau is the smallest energy with G(tau) > eps * total; non-negative doubles order
+// like their bit patterns, so a binary search over those patterns finds tau, with the
+// energies in registers (lane l holds entries l + 64 q).
+__device__ __forceinline__ double wave_min_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
 template <int NK>
 __device__ int wkernel_threshold(int nk, double eps, KScratch<NK>& S, double* dropped) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x;
   const int nn2 = nk * nk;
   const int h = (nk - 1) / 2;
-  // energies, ascending bitonic sort over NS slots (NS = next power of two >= nk^2,
-  // +inf padding)
-  int NS = 16;
-  while (NS < nn2) NS <<= 1;
-  for (int i = lane; i < NS; i += 64) {
-    if (i < nn2) {
-      const double2 v = S.c[i];
-      S.e()[i] = v.x * v.x + v.y * v.y;
-    } else {
-      S.e()[i] = DBL_MAX;
+  double tau, tot;
+  if constexpr (NK <= 15) {
+    // energies, ascending bitonic sort over NS slots (NS = next power of two >= nk^2,
+    // +inf padding)
+    int NS = 16;
+    while (NS < nn2) NS <<= 1;
+    for (int i = lane; i < NS; i += 64) {
+      if (i < nn2) {
+        const double2 v = S.c[i];
+        S.e()[i] = v.x * v.x + v.y * v.y;
+      } else {
+        S.e()[i] = DBL_MAX;
+      }
     }
-  }
-  __syncthreads();
-  for (int k = 2; k <= NS; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = lane; i < NS; i += 64) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const bool up = (i & k) == 0;
-          const double a = S.e()[i], b = S.e()[ixj];
-          if ((a > b) == up) {
-            S.e()[i] = b;
-            S.e()[ixj] = a;
+    __syncthreads();
+    for (int k = 2; k <= NS; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = lane; i < NS; i += 64) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const bool up = (i & k) == 0;
+            const double a = S.e()[i], b = S.e()[ixj];
+            if ((a > b) == up) {
+              S.e()[i] = b;
+              S.e()[ixj] = a;
+            }
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
-  }
-  // inclusive prefix sums: lane holds slots pl*lane .. pl*lane + pl - 1
-  constexpr int PLMAX = KScratch<NK>::NS >= 64 ? KScratch<NK>::NS / 64 : 1;
-  const int pl = NS >= 64 ? NS / 64 : 1;
-  double loc[PLMAX];
-  double run = 0.0;
+    // inclusive prefix sums: lane holds slots pl*lane .. pl*lane + pl - 1
+    constexpr int PLMAX = KScratch<NK>::NS >= 64 ? KScratch<NK>::NS / 64 : 1;
+    const int pl = NS >= 64 ? NS / 64 : 1;
+    double loc[PLMAX];
+    double run = 0.0;
 #pragma unroll
-  for (int q = 0; q < PLMAX; ++q) {
-    const int i = pl * lane + q;
-    const double v = (q < pl && i < nn2) ? S.e()[i] : 0.0;
-    run += v;
-    loc[q] = run;
-  }
-  double scan = run;
+    for (int q = 0; q < PLMAX; ++q) {
+      const int i = pl * lane + q;
+      const double v = (q < pl && i < nn2) ? S.e()[i] : 0.0;
+      run += v;
+      loc[q] = run;
+    }
+    double scan = run;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double y = __shfl_up(scan, o, 64);
-    if (lane >= o) scan += y;
-  }
-  const double offs = scan - run;
-  const double tot = __shfl(scan, 63, 64);
-  const double thr = eps * tot;
-  int cnt = 0;
+    for (int o = 1; o < 64; o <<= 1) {
+      const double y = __shfl_up(scan, o, 64);
+      if (lane >= o) scan += y;
+    }
+    const double offs = scan - run;
+    tot = __shfl(scan, 63, 64);
+    const double thr = eps * tot;
+    int cnt = 0;
 #pragma unroll
-  for (int q = 0; q < PLMAX; ++q) {
-    const int i = pl * lane + q;
-    if (q < pl && i < nn2 && offs + loc[q] <= thr) ++cnt;
+    for (int q = 0; q < PLMAX; ++q) {
+      const int i = pl * lane + q;
+      if (q < pl && i < nn2 && offs + loc[q] <= thr) ++cnt;
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    int jdrop = cnt < nn2 - 1 ? cnt : nn2 - 1;
+    tau = S.e()[jdrop];
+  } else {
+    constexpr int PL = (NK * NK + 63) / 64;
+    double en[PL];
+    double run = 0.0;
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int i = lane + 64 * q;
+      double v = 0.0;   // slots beyond nn2 hold no entry (0 adds nothing, is never tau)
+      if (i < nn2) {
+        const double2 c = S.c[i];
+        v = c.x * c.x + c.y * c.y;
+      }
+      en[q] = v;
+      run += v;
+    }
+    tot = wave_sum_d(run);
+    const double thr = eps * tot;
+    // largest bit pattern lo with G(lo) <= thr; G(0) = 0 <= thr always
+    uint64_t lo = 0, hi = 1ull << 63;
+    while (hi - lo > 1) {
+      const uint64_t mid = lo + ((hi - lo) >> 1);
+      double g = 0.0;
+#pragma unroll
+      for (int q = 0; q < PL; ++q)
+        if ((uint64_t)__double_as_longlong(en[q]) <= mid) g += en[q];
+      g = wave_sum_d(g);   // identical in every lane: the branch is wave-uniform
+      if (g <= thr) lo = mid;
+      else hi = mid;
+    }
+    double tmin = DBL_MAX, tmax = 0.0;
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      if (lane + 64 * q >= nn2) continue;
+      if ((uint64_t)__double_as_longlong(en[q]) >= hi) tmin = en[q] < tmin ? en[q] : tmin;
+      tmax = en[q] > tmax ? en[q] : tmax;
+    }
+    tmin = wave_min_d(tmin);
+    tmax = wave_max_d(tmax);
+    tau = tmin < DBL_MAX ? tmin : tmax;
   }
-  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-  int jdrop = cnt < nn2 - 1 ? cnt : nn2 - 1;
-  const double tau = S.e()[jdrop];
   const double cut = tau * (1.0 - 1e-9);
   int hp = 0;
   double dsum = 0.0;
@@ -357,7 +435,8 @@ __device__ int predicted_kernel(const float* pr, int nk, const KernelParams& kp,
 
 template <int NK>
 __global__ __launch_bounds__(64) void k_rowsym(const double* __restrict__ uvw, int64_t r0,
-                                               int64_t r1, double scale, double gsx,
+                                               const int32_t* __restrict__ rows, int64_t nl,
+                                               double scale, double gsx,
                                                double gsy, const double* __restrict__ mids,
                                                int P, const double* __restrict__ cents, int Kx,
                                                int Ky, int tile, KernelParams kp,
@@ -365,11 +444,15 @@ __global__ __launch_bounds__(64) void k_rowsym(const double* __restrict__ uvw, i
                                                float* __restrict__ dropped_out, Surrogate sg) {
 #pragma clang fp contract(off)
   __shared__ KScratch<NK> S;
-  for (int64_t k = r0 + blockIdx.x; k < r1; k += gridDim.x) {
+  for (int64_t i = blockIdx.x; i < nl; i += gridDim.x) {
+    const int64_t k = rows[i];
     const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
     const int nk_full = dev_nk(g.wproj, kp, false);
     const int nk = nk_full > kp.smax ? kp.smax : nk_full;
-    if (nk > NK || nk <= nk_lo<NK>()) continue;   // another class's row (wave-uniform)
+    if (nk > NK || nk <= nk_lo<NK>()) {   // class byte disagrees: mark the key invalid
+      if (threadIdx.x == 0) keys[k] = ~0ull;
+      continue;
+    }
     double dropped;
     const float* pr = sg.pred ? sg.pred + (k - r0) * MLP_OUT : nullptr;
     const bool usep = use_prediction(pr, nk_full, kp, sg.logtol);
@@ -412,7 +495,8 @@ __device__ __forceinline__ void store_val(void* vals, int64_t i, double re, doub
 
 template <int STORE, int NK>
 __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, int64_t s0,
-                                               int64_t s1, const int32_t* __restrict__ perm,
+                                               const int32_t* __restrict__ rows, int64_t nl,
+                                               const int32_t* __restrict__ perm,
                                                const uint32_t* __restrict__ meta,
                                                const uint32_t* __restrict__ voff,
                                                const int32_t* __restrict__ row_wi,
@@ -427,12 +511,16 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
   __shared__ KScratch<NK> S;
   const int lane = threadIdx.x;
   const int half = (kp.J - 1) / 2;
-  for (int64_t s = s0 + blockIdx.x; s < s1; s += gridDim.x) {
+  for (int64_t i = blockIdx.x; i < nl; i += gridDim.x) {
+    const int64_t s = rows[i];
     const int64_t k = perm[s];
     const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
     const int nk_full = dev_nk(g.wproj, kp, false);
     const int nk = nk_full > kp.smax ? kp.smax : nk_full;
-    if (nk > NK || nk <= nk_lo<NK>()) continue;   // another class's row (wave-uniform)
+    if (nk > NK || nk <= nk_lo<NK>()) {   // class byte disagrees: count it, build nothing
+      if (lane == 0) atomicAdd(mismatch, 1);
+      continue;
+    }
     double dropped;
     const float* pr = sg.pred ? sg.pred + (s - s0) * MLP_OUT : nullptr;
     const bool usep = use_prediction(pr, nk_full, kp, sg.logtol);
@@ -495,6 +583,22 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
     }
     if (over) atomicAdd(mismatch + 1, 1);
     __syncthreads();
+  }
+}
+
+// Kernel-side class (0: n_k <= 7, 1: <= 15, 2: <= 21, 3: <= 31) of rows [r0, r1) in
+// caller order; the same bin and side computation as the build kernels.
+__global__ __launch_bounds__(256) void k_row_class(const double* __restrict__ uvw, int64_t r0,
+                                                   int64_t r1, double scale, double gsx,
+                                                   double gsy, const double* __restrict__ mids,
+                                                   int P, const double* __restrict__ cents,
+                                                   KernelParams kp, uint8_t* __restrict__ cls) {
+#pragma clang fp contract(off)
+  for (int64_t k = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < r1;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
+    const int nk_full = dev_nk(g.wproj, kp, false);
+    cls[k] = (uint8_t)class_of_nk(nk_full > kp.smax ? kp.smax : nk_full);
   }
 }
 
@@ -571,75 +675,94 @@ __global__ __launch_bounds__(64) void k_exact_targets(const double* __restrict__
   }
 }
 
-hipError_t launch_rowsym(const double* uvw, int64_t r0, int64_t r1, double scale, double gsx,
-                         double gsy, const double* mids, int P, const double* cents, int Kx,
-                         int Ky, int tile, const KernelParams& kp, uint64_t* keys,
+hipError_t launch_rowsym(const double* uvw, int64_t r0, const ClassSlices& cs, double scale,
+                         double gsx, double gsy, const double* mids, int P, const double* cents,
+                         int Kx, int Ky, int tile, const KernelParams& kp, uint64_t* keys,
                          float* dropped, const Surrogate& sg, hipStream_t s) {
-  const int64_t n = r1 - r0;
-  if (n <= 0) return hipSuccess;
-  const int blocks = (int)(n < 262144 ? n : 262144);
-  // one launch per kernel-side class over the whole range; each takes its own rows
-  hipLaunchKernelGGL(k_rowsym<7>, dim3(blocks), dim3(64), 0, s, uvw, r0, r1, scale, gsx, gsy,
-                     mids, P, cents, Kx, Ky, tile, kp, keys, dropped, sg);
-  hipLaunchKernelGGL(k_rowsym<15>, dim3(blocks), dim3(64), 0, s, uvw, r0, r1, scale, gsx, gsy,
-                     mids, P, cents, Kx, Ky, tile, kp, keys, dropped, sg);
-  hipLaunchKernelGGL(k_rowsym<21>, dim3(blocks), dim3(64), 0, s, uvw, r0, r1, scale, gsx, gsy,
-                     mids, P, cents, Kx, Ky, tile, kp, keys, dropped, sg);
-  hipLaunchKernelGGL(k_rowsym<31>, dim3(blocks), dim3(64), 0, s, uvw, r0, r1, scale, gsx, gsy,
-                     mids, P, cents, Kx, Ky, tile, kp, keys, dropped, sg);
+  // one launch per kernel-side class over that class's rows of the range
+#define WF_ROWSYM(NKC, C)                                                                   \
+  if (cs.n[C] > 0)                                                                          \
+    hipLaunchKernelGGL(k_rowsym<NKC>, dim3(grid_for(cs.n[C])), dim3(64), 0, s, uvw, r0,   \
+                       cs.rows[C], cs.n[C], scale, gsx, gsy, mids, P, cents, Kx, Ky, tile,  \
+                       kp, keys, dropped, sg);
+  WF_ROWSYM(7, 0)
+  WF_ROWSYM(15, 1)
+  WF_ROWSYM(21, 2)
+  WF_ROWSYM(31, 3)
+#undef WF_ROWSYM
   return hipGetLastError();
 }
 
 template <int STORE>
-void launch_gbuild_classes(int blocks, hipStream_t s, const double* uvw, int64_t s0, int64_t s1,
+void launch_gbuild_classes(hipStream_t s, const double* uvw, int64_t s0, const ClassSlices& cs,
                            const int32_t* perm, const uint32_t* meta, const uint32_t* voff,
                            const int32_t* row_wi, const WorkItem* wi, double scale, double gsx,
                            double gsy, const double* mids, int P, const double* cents,
                            const KernelParams& kp, void* vals, int64_t vbase, int* mismatch,
                            const Surrogate& sg, const float* wts) {
-  // one launch per kernel-side class over the whole range; each takes its own rows
-  hipLaunchKernelGGL((k_gbuild<STORE, 7>), dim3(blocks), dim3(64), 0, s, uvw, s0, s1, perm,
-                     meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
-                     mismatch, sg, wts);
-  hipLaunchKernelGGL((k_gbuild<STORE, 15>), dim3(blocks), dim3(64), 0, s, uvw, s0, s1, perm,
-                     meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
-                     mismatch, sg, wts);
-  hipLaunchKernelGGL((k_gbuild<STORE, 21>), dim3(blocks), dim3(64), 0, s, uvw, s0, s1, perm,
-                     meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
-                     mismatch, sg, wts);
-  hipLaunchKernelGGL((k_gbuild<STORE, 31>), dim3(blocks), dim3(64), 0, s, uvw, s0, s1, perm,
-                     meta, voff, row_wi, wi, scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
-                     mismatch, sg, wts);
+  // one launch per kernel-side class over that class's rows of the range
+#define WF_GBUILD(NKC, C)                                                                     \
+  if (cs.n[C] > 0)                                                                            \
+    hipLaunchKernelGGL((k_gbuild<STORE, NKC>), dim3(grid_for(cs.n[C])), dim3(64), 0, s, uvw,  \
+                       s0, cs.rows[C], cs.n[C], perm, meta, voff, row_wi, wi, scale, gsx, gsy, \
+                       mids, P, cents, kp, vals, vbase, mismatch, sg, wts);
+  WF_GBUILD(7, 0)
+  WF_GBUILD(15, 1)
+  WF_GBUILD(21, 2)
+  WF_GBUILD(31, 3)
+#undef WF_GBUILD
 }
 
-hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_t* perm,
-                         const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
-                         const WorkItem* wi, double scale, double gsx, double gsy,
-                         const double* mids, int P, const double* cents,
+hipError_t launch_gbuild(const double* uvw, int64_t s0, const ClassSlices& cs,
+                         const int32_t* perm, const uint32_t* meta, const uint32_t* voff,
+                         const int32_t* row_wi, const WorkItem* wi, double scale, double gsx,
+                         double gsy, const double* mids, int P, const double* cents,
                          const KernelParams& kp, void* vals, int64_t vbase, wf_store store,
                          int* mismatch, const Surrogate& sg, const float* wts, hipStream_t s) {
-  const int64_t n = s1 - s0;
-  if (n <= 0) return hipSuccess;
-  const int blocks = (int)(n < 262144 ? n : 262144);
   switch (store) {
     case WF_STORE_F32:
-      launch_gbuild_classes<WF_STORE_F32>(blocks, s, uvw, s0, s1, perm, meta, voff, row_wi, wi,
-                                          scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
-                                          mismatch, sg, wts);
+      launch_gbuild_classes<WF_STORE_F32>(s, uvw, s0, cs, perm, meta, voff, row_wi, wi, scale,
+                                          gsx, gsy, mids, P, cents, kp, vals, vbase, mismatch,
+                                          sg, wts);
       break;
     case WF_STORE_F16:
-      launch_gbuild_classes<WF_STORE_F16>(blocks, s, uvw, s0, s1, perm, meta, voff, row_wi, wi,
-                                          scale, gsx, gsy, mids, P, cents, kp, vals, vbase,
-                                          mismatch, sg, wts);
+      launch_gbuild_classes<WF_STORE_F16>(s, uvw, s0, cs, perm, meta, voff, row_wi, wi, scale,
+                                          gsx, gsy, mids, P, cents, kp, vals, vbase, mismatch,
+                                          sg, wts);
       break;
     default:
-      launch_gbuild_classes<WF_STORE_BF16>(blocks, s, uvw, s0, s1, perm, meta, voff, row_wi,
-                                           wi, scale, gsx, gsy, mids, P, cents, kp, vals,
-                                           vbase, mismatch, sg, wts);
+      launch_gbuild_classes<WF_STORE_BF16>(s, uvw, s0, cs, perm, meta, voff, row_wi, wi, scale,
+                                           gsx, gsy, mids, P, cents, kp, vals, vbase, mismatch,
+                                           sg, wts);
       break;
   }
   return hipGetLastError();
 }
+
+ClassSlices slice_classes(const RowClasses& rc, int64_t lo, int64_t hi) {
+  ClassSlices cs{};
+  for (int c = 0; c < 4; ++c) {
+    const int32_t* b = rc.h.data() + rc.off[c];
+    const int32_t* e = rc.h.data() + rc.off[c + 1];
+    const int64_t i0 = std::lower_bound(b, e, (int32_t)lo) - b;
+    const int64_t i1 = std::lower_bound(b, e, (int32_t)std::min<int64_t>(hi, INT32_MAX)) - b;
+    cs.rows[c] = rc.d + rc.off[c] + i0;
+    cs.n[c] = i1 - i0;
+  }
+  return cs;
+}
+
+hipError_t launch_row_class(const double* uvw, int64_t r0, int64_t r1, double scale, double gsx,
+                            double gsy, const double* mids, int P, const double* cents,
+                            const KernelParams& kp, uint8_t* cls, hipStream_t s) {
+  const int64_t n = r1 - r0;
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_row_class, dim3((unsigned)nb), dim3(256), 0, s, uvw, r0, r1, scale, gsx,
+                     gsy, mids, P, cents, kp, cls);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_row_inputs(const double* uvw, const int32_t* perm, int64_t r0, int64_t nr,
                              double scale, double gsx, double gsy, const double* mids, int P,

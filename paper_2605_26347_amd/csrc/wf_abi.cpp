@@ -99,7 +99,7 @@ void destroy_op(wf_op* op) {
     dfree(c.htiles);
     dfree(c.hvals);
     dfree(c.flagged);
-    for (DevBuf* b : {&c.uvw, &c.wts, &c.uperm, &c.row_wi, &c.mids, &c.cents}) dfree(*b);
+    for (DevBuf* b : {&c.uvw, &c.wts, &c.uperm, &c.row_wi, &c.mids, &c.cents, &c.crow}) dfree(*b);
   }
   dfree(op->otf_mis);
   for (size_t b = 0; b < op->br.size(); ++b) release_branch(op->br[b], b > 0);
@@ -450,6 +450,38 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     if ((st = dalloc(dused, sizeof(int))) != WF_OK) return st;
     WF_HIP(hipMemsetAsync(dused.p, 0, sizeof(int), s));
   }
+  // kernel-side class of every row: the build kernels take one class per launch, each
+  // with an LDS scratch sized for it, from per-class row lists (caller order for the
+  // symbolic pass, sorted order for the value pass)
+  DevBuf dclsk, dlk, dls;
+  tmp.b.push_back(&dclsk);
+  tmp.b.push_back(&dlk);
+  tmp.b.push_back(&dls);
+  if ((st = dalloc(dclsk, std::max<int64_t>(M, 1))) != WF_OK) return st;
+  if ((st = dalloc(dlk, sizeof(int32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
+  if ((st = dalloc(dls, sizeof(int32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
+  WF_HIP(launch_row_class((const double*)duvw.p, 0, M, ch.scale, gsx, gsy,
+                          (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
+                          (uint8_t*)dclsk.p, s));
+  std::vector<uint8_t> clsk(M);
+  WF_HIP(hipMemcpyAsync(clsk.data(), dclsk.p, M, hipMemcpyDeviceToHost, s));
+  WF_HIP(hipStreamSynchronize(s));
+  dfree(dclsk);
+  // counting sort of rows by class; order_of(i) gives the i-th row of the order
+  auto class_lists = [&](auto&& order_of, DevBuf& dl, RowClasses& rc) -> wf_status {
+    int64_t cnt[4] = {0, 0, 0, 0};
+    for (int64_t i = 0; i < M; ++i) ++cnt[clsk[order_of(i)]];
+    rc.off[0] = 0;
+    for (int c = 0; c < 4; ++c) rc.off[c + 1] = rc.off[c] + cnt[c];
+    int64_t at[4] = {rc.off[0], rc.off[1], rc.off[2], rc.off[3]};
+    rc.h.assign(M, 0);
+    for (int64_t i = 0; i < M; ++i) rc.h[at[clsk[order_of(i)]]++] = (int32_t)i;
+    rc.d = (const int32_t*)dl.p;
+    WF_HIP(hipMemcpyAsync(dl.p, rc.h.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
+    return WF_OK;
+  };
+  RowClasses rck, rcs;
+  if ((st = class_lists([](int64_t i) { return i; }, dlk, rck)) != WF_OK) return st;
   auto surrogate_pass = [&](const int32_t* order, auto&& launch) -> wf_status {
     if (!mlp) return launch(0, M, Surrogate{});
     for (int64_t r0 = 0; r0 < M; r0 += CH) {
@@ -468,9 +500,9 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     return WF_OK;
   };
   st = surrogate_pass(nullptr, [&](int64_t r0, int64_t r1, const Surrogate& sg) -> wf_status {
-    WF_HIP(launch_rowsym((const double*)duvw.p, r0, r1, ch.scale, gsx, gsy,
-                         (const double*)dmids.p, ch.P, (const double*)dcents.p, Kx, Ky, tile,
-                         op->kp, (uint64_t*)dkeys.p, (float*)ddrop.p, sg, s));
+    WF_HIP(launch_rowsym((const double*)duvw.p, r0, slice_classes(rck, r0, r1), ch.scale,
+                         gsx, gsy, (const double*)dmids.p, ch.P, (const double*)dcents.p, Kx,
+                         Ky, tile, op->kp, (uint64_t*)dkeys.p, (float*)ddrop.p, sg, s));
     return WF_OK;
   });
   if (st != WF_OK) return st;
@@ -485,6 +517,8 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   WF_HIP(hipStreamSynchronize(s));
   dfree(dkeys);
   dfree(ddrop);
+  for (int64_t k = 0; k < M; ++k)
+    if (keys[k] == ~0ull) return fail(WF_EINVAL, "kernel-side class disagreement in the symbolic pass");
   int64_t ncapped = 0;
   double maxdrop = 0.0;
   for (int64_t k = 0; k < M; ++k) {
@@ -572,7 +606,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
       }
   }
   if (otf) {
-    const double meta_bytes = (24.0 + 16.0 + (sel.w ? 4.0 : 0.0) + (sel.keep ? 4.0 : 0.0)) * M;
+    const double meta_bytes = (24.0 + 20.0 + (sel.w ? 4.0 : 0.0) + (sel.keep ? 4.0 : 0.0)) * M;
     if (meta_bytes + 4.0 * b_v * (double)ch.ck_max > share)
       return fail(WF_EBUDGET, "no strategy fits the memory budget: the on-the-fly row data "
                               "alone needs " + std::to_string(meta_bytes / 1e9) + " GB");
@@ -665,6 +699,8 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   WF_HIP(hipMemcpyAsync(ch.meta.p, meta.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(ch.voff.p, voff.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(ch.perm.p, idx.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
+  if ((st = class_lists([&](int64_t i) { return (int64_t)idx[i]; }, dls, rcs)) != WF_OK)
+    return st;
   WF_HIP(hipMemcpyAsync(drowwi.p, row_wi.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(ch.work.p, wis.data(), sizeof(WorkItem) * wis.size(),
                         hipMemcpyHostToDevice, s));
@@ -729,10 +765,11 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
       const int64_t vbase = ch.groups[ga].voff;
       size_t wj = wi_at;
       while (wj < wrow.size() && wrow[wj].row0 < s1) ++wj;
-      WF_HIP(launch_gbuild((const double*)duvw.p, s0, s1, (const int32_t*)ch.perm.p,
-                           (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
-                           (const int32_t*)drowwi.p, (const WorkItem*)ch.work.p, ch.scale, gsx,
-                           gsy, (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
+      WF_HIP(launch_gbuild((const double*)duvw.p, s0, slice_classes(rcs, s0, s1),
+                           (const int32_t*)ch.perm.p, (const uint32_t*)ch.meta.p,
+                           (const uint32_t*)ch.voff.p, (const int32_t*)drowwi.p,
+                           (const WorkItem*)ch.work.p, ch.scale, gsx, gsy,
+                           (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
                            gtmp.p, vbase, WF_STORE_F32, (int*)dmis.p, Surrogate{},
                            (const float*)dwts.p, s));
       WF_HIP(launch_hbuild((const WorkItem*)dwrow.p + wi_at, (int)(wj - wi_at),
@@ -762,19 +799,23 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     DevBuf gtmp;
     tmp.b.push_back(&gtmp);
     if ((st = dalloc(gtmp, (size_t)b_v * std::max<int64_t>(ch.ck_max, 1))) != WF_OK) return st;
-    for (size_t k = 0; k < ch.ck_s0.size(); ++k)
-      WF_HIP(launch_gbuild((const double*)duvw.p, ch.ck_s0[k], ch.ck_s1[k],
+    ch.ck_cls.resize(ch.ck_s0.size());
+    for (size_t k = 0; k < ch.ck_s0.size(); ++k) {
+      ch.ck_cls[k] = slice_classes(rcs, ch.ck_s0[k], ch.ck_s1[k]);
+      WF_HIP(launch_gbuild((const double*)duvw.p, ch.ck_s0[k], ch.ck_cls[k],
                            (const int32_t*)ch.perm.p, (const uint32_t*)ch.meta.p,
                            (const uint32_t*)ch.voff.p, (const int32_t*)drowwi.p,
                            (const WorkItem*)ch.work.p, ch.scale, gsx, gsy,
                            (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
                            gtmp.p, ch.ck_vbase[k], opt.store, (int*)dmis.p, Surrogate{},
                            (const float*)dwts.p, s));
+    }
     std::swap(ch.uvw, duvw);
     std::swap(ch.mids, dmids);
     std::swap(ch.cents, dcents);
     std::swap(ch.wts, dwts);
     std::swap(ch.row_wi, drowwi);
+    std::swap(ch.crow, dls);   // the chunks' class slices point into this list
     ch.otf = true;
   }
   if (!holo && !otf) {
@@ -782,7 +823,8 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     return st;
   st = surrogate_pass((const int32_t*)ch.perm.p,
                       [&](int64_t s0, int64_t s1, const Surrogate& sg) -> wf_status {
-                        WF_HIP(launch_gbuild((const double*)duvw.p, s0, s1,
+                        WF_HIP(launch_gbuild((const double*)duvw.p, s0,
+                                             slice_classes(rcs, s0, s1),
                                              (const int32_t*)ch.perm.p,
                                              (const uint32_t*)ch.meta.p,
                                              (const uint32_t*)ch.voff.p,
@@ -833,7 +875,8 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   in.nwork = ch.nwork;
   in.k_estimate = pr.k_est;
   in.mem_g_bytes = otf ? (double)(ch.uvw.bytes + ch.wts.bytes + ch.uperm.bytes +
-                                   ch.row_wi.bytes) + 12.0 * M + sizeof(WorkItem) * wis.size()
+                                   ch.row_wi.bytes + ch.crow.bytes) + 12.0 * M +
+                             sizeof(WorkItem) * wis.size()
                       : (double)b_v * taps_total + 12.0 * M + sizeof(WorkItem) * wis.size();
   in.mem_transient_bytes = otf ? (double)b_v * ch.ck_max : 0.0;
   in.value_pass_flops = vp_flops;
@@ -965,7 +1008,7 @@ wf_status otf_bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, in
   for (int k = ch.ck_first[p]; k < ch.ck_first[p] + ch.ck_count[p]; ++k) {
     {
       ProfScope ps(prof_of(op, 5), L.s);
-      WF_HIP(launch_gbuild((const double*)ch.uvw.p, ch.ck_s0[k], ch.ck_s1[k], uperm,
+      WF_HIP(launch_gbuild((const double*)ch.uvw.p, ch.ck_s0[k], ch.ck_cls[k], uperm,
                            (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
                            (const int32_t*)ch.row_wi.p, wk, ch.scale, gsx, gsy,
                            (const double*)ch.mids.p, ch.P, (const double*)ch.cents.p, op->kp,

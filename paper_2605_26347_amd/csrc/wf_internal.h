@@ -102,6 +102,19 @@ struct HTile {
 static_assert(sizeof(HTile) == 16, "HTile layout");
 
 // Host index of the stored rows for the diagnostic row reader (built on first use).
+// Rows of one order (caller or sorted) grouped by kernel-side class, each class's rows
+// ascending: class c occupies [off[c], off[c + 1]) of the device list d and its host copy.
+struct RowClasses {
+  const int32_t* d = nullptr;
+  std::vector<int32_t> h;
+  int64_t off[5] = {0, 0, 0, 0, 0};
+};
+// One launch range's rows per class: device pointers into a RowClasses list and counts.
+struct ClassSlices {
+  const int32_t* rows[4];
+  int64_t n[4];
+};
+
 struct DebugIndex {
   uint64_t gen = 0;                        // operator generation + 1 when valid
   std::vector<int32_t> sorted_of;          // caller row -> sorted row
@@ -135,7 +148,8 @@ struct ChanOp {
   // strategy (c), G on the fly: no values are kept; each bin is cut into chunks of whole
   // row groups whose values are rebuilt into a branch's transient buffer at every apply
   bool otf = false;
-  DevBuf uvw, wts, uperm, row_wi, mids, cents;  // value-pass inputs kept on the device
+  DevBuf uvw, wts, uperm, row_wi, mids, cents, crow;  // value-pass inputs on the device
+  std::vector<ClassSlices> ck_cls;         // per chunk: its rows by kernel-side class
   std::vector<int32_t> gchunk;             // chunk of each row group
   std::vector<int64_t> ck_s0, ck_s1, ck_vbase, ck_taps;  // sorted rows, first value, values
   std::vector<int32_t> ck_first, ck_count; // per bin: first chunk, chunk count
@@ -301,20 +315,30 @@ struct Surrogate {
   int* used = nullptr;          // counts rows built from the prediction (may be null)
 };
 
-// Build kernels (FP64).  Symbolic pass over rows [r0, r1) in caller order: bin, grid
+// Build kernels (FP64).  Symbolic pass over the caller-order rows listed in cs
+// (predictions, when given, indexed by k - r0): bin, grid
 // position, residual kernel side after thresholding, sort key.
-hipError_t launch_rowsym(const double* uvw, int64_t r0, int64_t r1, double scale, double gsx,
-                         double gsy, const double* mids, int P, const double* cents, int Kx,
-                         int Ky, int tile, const KernelParams& kp, uint64_t* keys,
+hipError_t launch_rowsym(const double* uvw, int64_t r0, const ClassSlices& cs, double scale,
+                         double gsx, double gsy, const double* mids, int P, const double* cents,
+                         int Kx, int Ky, int tile, const KernelParams& kp, uint64_t* keys,
                          float* dropped, const Surrogate& sg, hipStream_t s);
-// Value pass over sorted rows [s0, s1): writes each row's T*T values at its value offset
-// minus vbase, scaled by the row's data weight wts[perm[s]] (wts may be null: ones).
-// mismatch[0] counts rows whose patch side differs from the symbolic pass, mismatch[1]
+// Kernel-side class (0: n_k <= 7, 1: <= 15, 2: <= 21, 3: <= 31) of rows [r0, r1) in
+// caller order.  The build kernels take the rows of one class per launch.
+hipError_t launch_row_class(const double* uvw, int64_t r0, int64_t r1, double scale, double gsx,
+                            double gsy, const double* mids, int P, const double* cents,
+                            const KernelParams& kp, uint8_t* cls, hipStream_t s);
+// The rows of [lo, hi) (in the lists' order) of each class.
+ClassSlices slice_classes(const RowClasses& rc, int64_t lo, int64_t hi);
+// Value pass over the sorted rows listed in cs (rows of [s0, s1) by kernel-side class;
+// predictions, when given, are indexed by s - s0): writes each row's T*T values at its
+// value offset minus vbase, scaled by the row's data weight wts[perm[s]] (wts may be
+// null: ones).
+// mismatch[0] counts rows whose patch side (or class) differs from the symbolic pass, mismatch[1]
 // rows with a value beyond the FP16 range (FP16 store only).
-hipError_t launch_gbuild(const double* uvw, int64_t s0, int64_t s1, const int32_t* perm,
-                         const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
-                         const WorkItem* wi, double scale, double gsx, double gsy,
-                         const double* mids, int P, const double* cents,
+hipError_t launch_gbuild(const double* uvw, int64_t s0, const ClassSlices& cs,
+                         const int32_t* perm, const uint32_t* meta, const uint32_t* voff,
+                         const int32_t* row_wi, const WorkItem* wi, double scale, double gsx,
+                         double gsy, const double* mids, int P, const double* cents,
                          const KernelParams& kp, void* vals, int64_t vbase, wf_store store,
                          int* mismatch, const Surrogate& sg, const float* wts, hipStream_t s);
 // Network inputs of rows [r0, r0 + nr) (caller order, or sorted order through perm).
