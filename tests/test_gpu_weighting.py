@@ -161,3 +161,37 @@ def test_briggs_weights_match_oracle(obs):
         uvw = obs.uvw_m[sl] * (freqs[c] / C_LIGHT)
         ref = owt.operator_weights(uvw[:, 0], uvw[:, 1], obs.nx, obs.ny, obs.cell_rad, 0.0)
         assert np.max(np.abs(got[sl] - ref)) <= 1e-6 * ref.max()
+
+
+@pytest.mark.parametrize("strategy", ["G", "otf"])
+def test_fully_flagged_channel(strategy):
+    """Channel 0 has every row flagged (no row is built: zero visibilities, zero image);
+    channel 1 is weighted and partly flagged and matches the oracle on its own rows."""
+    base = ws.widefield(n=64, nvis=30_000, fov_deg=3.0, sky=False)
+    counts = np.array([11_000, 19_000])
+    obs = ws.Observation("two", base.uvw_m, np.array([1.0e9, 1.4e9]), 64, 64,
+                         base.cell_rad, None, chan_rows=counts)
+    flags = np.concatenate([np.ones(counts[0], bool), ws.flag_runs(counts[1], 0.2)])
+    w = (1.0 / ws.noise_sigma(int(counts.sum()))).astype(np.float32)
+    op = gpu_operator(obs, 3, weights=w, flags=flags, strategy=strategy,
+                      memory_budget=50e6 if strategy == "otf" else 288e9)
+    assert op.plan(0)["nrows"] == 0 and op.plan(0)["nflagged"] == counts[0]
+    x = np.stack([ws.gauss_image(64, 1), ws.gauss_image(64, 2)]).astype(np.float32)
+    out = op.psf_apply(to_dev(x)).cpu().numpy()
+    vis = torch.full((int(counts.sum()),), float("nan"), dtype=torch.complex64, device="cuda:0")
+    y = op.forward(to_dev(x), out=vis).cpu().numpy()
+    assert np.all(out[0] == 0) and np.all(y[:counts[0]] == 0)
+    sl = slice(counts[0], None)
+    orc = oracle_for(obs, 3, chan=1, uvw=base.uvw_m[sl], weights=w[sl].astype(np.float64),
+                     flags=flags[sl])
+    assert rel(out[1], orc.psf(x[1].astype(np.float64))) <= TOL["f32"]
+    assert rel(y[sl], orc.forward(x[1].astype(np.float64))) <= TOL["f32"]
+    assert np.all(y[sl][flags[sl]] == 0)
+
+
+def test_onthefly_with_network_is_refused(obs):
+    from paper_2605_26347_amd import Network
+    from paper_2605_26347_amd._lib import WfError
+    net = Network(5)
+    with pytest.raises(WfError, match="exact kernels only"):
+        gpu_operator(obs, 4, strategy="otf", surrogate=net, memory_budget=50e6)
