@@ -37,18 +37,26 @@ constexpr int pow2_at_least(int v) {
   return p;
 }
 
-// LDS scratch of one row for residual-kernel sides up to NK.  A row needs, in turn, the
-// DFT intermediate t, the sort slots e (small classes) and the convolution intermediate
-// t2, never two at once, so they share one region.  Rows are processed by kernel-side class
+// Columns of a G patch convolved per step by the large classes (their convolution
+// intermediate holds n' x CB values).
+constexpr int CB = 6;
+
+// LDS scratch of one row for residual-kernel sides up to NK: the samples / kernel c and
+// one region whose users never overlap in time.  Small classes (NK <= 15) keep the DFT
+// intermediate t, the sort slots e and the full convolution intermediate t2 there.  The
+// large classes, whose scratch limits how many rows are in flight, run the DFT sweeps in
+// place (through registers) and convolve CB patch columns at a time, so the region only
+// holds t2 for CB columns.  Rows are processed by kernel-side class
 // (sides in (nk_lo<NK>, NK]), so that small kernels get a small scratch and many rows
 // in flight per compute unit.
 template <int NK>
 struct KScratch {
+  static constexpr bool BIG = NK > 15;
   static constexpr int TM = NK + 14 < MAXT ? NK + 14 : MAXT;  // patch side (J <= 15)
-  static constexpr int NS = pow2_at_least(NK * NK);          // sort slots (NK <= 15)
-  static constexpr int UW = 2 * NK * TM > NS ? 2 * NK * TM : NS;  // TM >= NK: t2 >= t
+  static constexpr int NS = BIG ? 0 : pow2_at_least(NK * NK);  // sort slots
+  static constexpr int UW = BIG ? 2 * NK * CB : (2 * NK * TM > NS ? 2 * NK * TM : NS);
   double2 c[NK * NK];                     // samples, then kernel
-  alignas(16) double u[UW];               // t, then e, then t2
+  alignas(16) double u[UW];               // small: t, e, t2; large: t2 of CB columns
   double2 roots[NK];                      // exp(-2 pi i m / nk)
   double ku[16], kv[16];                  // Kaiser-Bessel taps (J <= 15)
   __device__ double2* t() { return reinterpret_cast<double2*>(u); }
@@ -184,39 +192,92 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
     S.c[idx] = make_double2(c, -s);   // exp(-2 pi i ph)
   }
   __syncthreads();
-  // t[b][su] = sum_a c[b][a] exp(-2 pi i (su-h)(a-h)/nk); the root index
-  // (su-h)(a-h) mod nk advances by (su-h) mod nk per step of a
-  for (int idx = lane; idx < nn2; idx += 64) {
-    const int b = idx / nk, su = idx - b * nk;
-    double re = 0.0, im = 0.0;
-    const int step = (su - h + nk) % nk;
-    int m = ((su - h) * (-h)) % nk;
-    if (m < 0) m += nk;
+  if constexpr (KScratch<NK>::BIG) {
+    // t[b][su] = sum_a c[b][a] exp(-2 pi i (su-h)(a-h)/nk), in place: each lane holds its
+    // outputs (entries lane + 64 q) in registers until every lane has read its inputs.
+    // The root index (su-h)(a-h) mod nk advances by (su-h) mod nk per step of a.
+    constexpr int PL = (NK * NK + 63) / 64;
+    double2 acc[PL];
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int idx = lane + 64 * q;
+      if (idx >= nn2) continue;
+      const int b = idx / nk, su = idx - b * nk;
+      double re = 0.0, im = 0.0;
+      const int step = (su - h + nk) % nk;
+      int m = ((su - h) * (-h)) % nk;
+      if (m < 0) m += nk;
 #pragma unroll 4
-    for (int a = 0; a < nk; ++a, m = (m + step >= nk ? m + step - nk : m + step)) {
-      const double2 r = S.roots[m], x = S.c[b * nk + a];
-      re += x.x * r.x - x.y * r.y;
-      im += x.x * r.y + x.y * r.x;
+      for (int a = 0; a < nk; ++a, m = (m + step >= nk ? m + step - nk : m + step)) {
+        const double2 r = S.roots[m], x = S.c[b * nk + a];
+        re += x.x * r.x - x.y * r.y;
+        im += x.x * r.y + x.y * r.x;
+      }
+      acc[q] = make_double2(re, im);
     }
-    S.t()[idx] = make_double2(re, im);
-  }
-  __syncthreads();
-  const double inv = 1.0 / ((double)nk * (double)nk);
-  for (int idx = lane; idx < nn2; idx += 64) {
-    const int sv = idx / nk, su = idx - sv * nk;
-    double re = 0.0, im = 0.0;
-    const int step = (sv - h + nk) % nk;
-    int m = ((sv - h) * (-h)) % nk;
-    if (m < 0) m += nk;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PL; ++q)
+      if (lane + 64 * q < nn2) S.c[lane + 64 * q] = acc[q];
+    __syncthreads();
+    const double inv = 1.0 / ((double)nk * (double)nk);
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int idx = lane + 64 * q;
+      if (idx >= nn2) continue;
+      const int sv = idx / nk, su = idx - sv * nk;
+      double re = 0.0, im = 0.0;
+      const int step = (sv - h + nk) % nk;
+      int m = ((sv - h) * (-h)) % nk;
+      if (m < 0) m += nk;
 #pragma unroll 4
-    for (int b = 0; b < nk; ++b, m = (m + step >= nk ? m + step - nk : m + step)) {
-      const double2 r = S.roots[m], x = S.t()[b * nk + su];
-      re += r.x * x.x - r.y * x.y;
-      im += r.x * x.y + r.y * x.x;
+      for (int b = 0; b < nk; ++b, m = (m + step >= nk ? m + step - nk : m + step)) {
+        const double2 r = S.roots[m], x = S.c[b * nk + su];
+        re += r.x * x.x - r.y * x.y;
+        im += r.x * x.y + r.y * x.x;
+      }
+      acc[q] = make_double2(re * inv, im * inv);
     }
-    S.c[idx] = make_double2(re * inv, im * inv);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PL; ++q)
+      if (lane + 64 * q < nn2) S.c[lane + 64 * q] = acc[q];
+    __syncthreads();
+  } else {
+    // t[b][su] = sum_a c[b][a] exp(-2 pi i (su-h)(a-h)/nk); the root index
+    // (su-h)(a-h) mod nk advances by (su-h) mod nk per step of a
+    for (int idx = lane; idx < nn2; idx += 64) {
+      const int b = idx / nk, su = idx - b * nk;
+      double re = 0.0, im = 0.0;
+      const int step = (su - h + nk) % nk;
+      int m = ((su - h) * (-h)) % nk;
+      if (m < 0) m += nk;
+#pragma unroll 4
+      for (int a = 0; a < nk; ++a, m = (m + step >= nk ? m + step - nk : m + step)) {
+        const double2 r = S.roots[m], x = S.c[b * nk + a];
+        re += x.x * r.x - x.y * r.y;
+        im += x.x * r.y + x.y * r.x;
+      }
+      S.t()[idx] = make_double2(re, im);
+    }
+    __syncthreads();
+    const double inv = 1.0 / ((double)nk * (double)nk);
+    for (int idx = lane; idx < nn2; idx += 64) {
+      const int sv = idx / nk, su = idx - sv * nk;
+      double re = 0.0, im = 0.0;
+      const int step = (sv - h + nk) % nk;
+      int m = ((sv - h) * (-h)) % nk;
+      if (m < 0) m += nk;
+#pragma unroll 4
+      for (int b = 0; b < nk; ++b, m = (m + step >= nk ? m + step - nk : m + step)) {
+        const double2 r = S.roots[m], x = S.t()[b * nk + su];
+        re += r.x * x.x - r.y * x.y;
+        im += r.x * x.y + r.y * x.x;
+      }
+      S.c[idx] = make_double2(re * inv, im * inv);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   return wkernel_threshold(nk, kp.eps, S, dropped);
 }
 
@@ -543,43 +604,86 @@ __global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, i
       else S.kv[lane % kp.J] = val;
     }
     __syncthreads();
-    // t2[m][au] = sum_n kern[m][n] ku[au - n], kern = kept centre square of S.c
-    for (int idx = lane; idx < np * T; idx += 64) {
-      const int m = idx / T, au = idx - m * T;
-      double re = 0.0, im = 0.0;
-      for (int nn = 0; nn < np; ++nn) {
-        const int dd = au - nn;
-        if (dd >= 0 && dd < kp.J) {
-          const double2 c = S.c[(m + h - hp) * nk + (nn + h - hp)];
-          re += c.x * S.ku[dd];
-          im += c.y * S.ku[dd];
-        }
-      }
-      S.t2()[idx] = make_double2(re, im);
-    }
-    __syncthreads();
     const int64_t vb = wis[row_wi[s]].voff + voff[s] - vbase;
     const double wk = wts ? (double)wts[k] : 1.0;   // data weight of the row
     bool over = false;
-    if (T == Tm) {
-      for (int idx = lane; idx < T * T; idx += 64) {
-        const int av = idx / T, au = idx - av * T;
-        double re = 0.0, im = 0.0;
-        for (int m = 0; m < np; ++m) {
-          const int dd = av - m;
-          if (dd >= 0 && dd < kp.J) {
-            const double2 x = S.t2()[m * T + au];
-            re += S.kv[dd] * x.x;
-            im += S.kv[dd] * x.y;
+    if constexpr (KScratch<NK>::BIG) {
+      // CB patch columns at a time: t2[m][c] = sum_n kern[m][n] ku[au - n] (au = au0 + c,
+      // kern = kept centre square of S.c), then G[av][au] = sum_m kv[av - m] t2[m][c]
+      for (int au0 = 0; au0 < T; au0 += CB) {
+        const int cw = T - au0 < CB ? T - au0 : CB;
+        for (int idx = lane; idx < np * cw; idx += 64) {
+          const int m = idx / cw, cc = idx - m * cw, au = au0 + cc;
+          double re = 0.0, im = 0.0;
+          for (int nn = 0; nn < np; ++nn) {
+            const int dd = au - nn;
+            if (dd >= 0 && dd < kp.J) {
+              const double2 c = S.c[(m + h - hp) * nk + (nn + h - hp)];
+              re += c.x * S.ku[dd];
+              im += c.y * S.ku[dd];
+            }
+          }
+          S.t2()[m * CB + cc] = make_double2(re, im);
+        }
+        __syncthreads();
+        if (T == Tm) {
+          for (int idx = lane; idx < T * cw; idx += 64) {
+            const int av = idx / cw, cc = idx - av * cw, au = au0 + cc;
+            double re = 0.0, im = 0.0;
+            for (int m = 0; m < np; ++m) {
+              const int dd = av - m;
+              if (dd >= 0 && dd < kp.J) {
+                const double2 x = S.t2()[m * CB + cc];
+                re += S.kv[dd] * x.x;
+                im += S.kv[dd] * x.y;
+              }
+            }
+            re *= wk;
+            im *= wk;
+            if constexpr (STORE == WF_STORE_F16)
+              over = over || fabs(re) > 65504.0 || fabs(im) > 65504.0;
+            store_val<STORE>(vals, vb + av * T + au, re, im);
           }
         }
-        re *= wk;
-        im *= wk;
-        if constexpr (STORE == WF_STORE_F16) over = over || fabs(re) > 65504.0 || fabs(im) > 65504.0;
-        store_val<STORE>(vals, vb + idx, re, im);
+        __syncthreads();
       }
-    } else if (lane == 0) {
-      atomicAdd(mismatch, 1);
+      if (T != Tm && lane == 0) atomicAdd(mismatch, 1);
+    } else {
+      // t2[m][au] = sum_n kern[m][n] ku[au - n], kern = kept centre square of S.c
+      for (int idx = lane; idx < np * T; idx += 64) {
+        const int m = idx / T, au = idx - m * T;
+        double re = 0.0, im = 0.0;
+        for (int nn = 0; nn < np; ++nn) {
+          const int dd = au - nn;
+          if (dd >= 0 && dd < kp.J) {
+            const double2 c = S.c[(m + h - hp) * nk + (nn + h - hp)];
+            re += c.x * S.ku[dd];
+            im += c.y * S.ku[dd];
+          }
+        }
+        S.t2()[idx] = make_double2(re, im);
+      }
+      __syncthreads();
+      if (T == Tm) {
+        for (int idx = lane; idx < T * T; idx += 64) {
+          const int av = idx / T, au = idx - av * T;
+          double re = 0.0, im = 0.0;
+          for (int m = 0; m < np; ++m) {
+            const int dd = av - m;
+            if (dd >= 0 && dd < kp.J) {
+              const double2 x = S.t2()[m * T + au];
+              re += S.kv[dd] * x.x;
+              im += S.kv[dd] * x.y;
+            }
+          }
+          re *= wk;
+          im *= wk;
+          if constexpr (STORE == WF_STORE_F16) over = over || fabs(re) > 65504.0 || fabs(im) > 65504.0;
+          store_val<STORE>(vals, vb + idx, re, im);
+        }
+      } else if (lane == 0) {
+        atomicAdd(mismatch, 1);
+      }
     }
     if (over) atomicAdd(mismatch + 1, 1);
     __syncthreads();
