@@ -495,7 +495,7 @@ __device__ int predicted_kernel(const float* pr, int nk, const KernelParams& kp,
 }
 
 template <int NK>
-__global__ __launch_bounds__(64) void k_rowsym(const double* __restrict__ uvw, int64_t r0,
+__global__ __launch_bounds__(64, NK <= 15 ? 4 : 1) void k_rowsym(const double* __restrict__ uvw, int64_t r0,
                                                const int32_t* __restrict__ rows, int64_t nl,
                                                double scale, double gsx,
                                                double gsy, const double* __restrict__ mids,
@@ -555,7 +555,7 @@ __device__ __forceinline__ void store_val(void* vals, int64_t i, double re, doub
 }
 
 template <int STORE, int NK>
-__global__ __launch_bounds__(64) void k_gbuild(const double* __restrict__ uvw, int64_t s0,
+__global__ __launch_bounds__(64, NK <= 15 ? 4 : 1) void k_gbuild(const double* __restrict__ uvw, int64_t s0,
                                                const int32_t* __restrict__ rows, int64_t nl,
                                                const int32_t* __restrict__ perm,
                                                const uint32_t* __restrict__ meta,
