@@ -294,6 +294,27 @@ __device__ int wkernel_row(double wproj, int nk, const KernelParams& kp, KScratc
 // <= v, tau is the smallest energy with G(tau) > eps * total; non-negative doubles order
 // like their bit patterns, so a binary search over those patterns finds tau, with the
 // energies in registers (lane l holds entries l + 64 q).
+// Wave sum of a double, identical in every lane: DPP steps inside each row of 16 lanes
+// (quad xor 1, quad xor 2, half-row mirror, row mirror) on both 32-bit halves, then the
+// four row sums read back in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_d<0xb1>(v);
+  v += dpp_d<0x4e>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  auto row = [&](int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+  };
+  return (row(0) + row(16)) + (row(32) + row(48));
+}
+
 __device__ __forceinline__ double wave_min_d(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -403,7 +424,7 @@ __device__ int wkernel_threshold(int nk, double eps, KScratch<NK>& S, double* dr
 #pragma unroll
       for (int q = 0; q < PL; ++q)
         if ((uint64_t)__double_as_longlong(en[q]) <= mid) g += en[q];
-      g = wave_sum_d(g);   // identical in every lane: the branch is wave-uniform
+      g = wave_sum_dpp(g);   // identical in every lane: the branch is wave-uniform
       if (g <= thr) lo = mid;
       else hi = mid;
     }
