@@ -77,12 +77,28 @@ inline unsigned grid_for(int64_t n) { return (unsigned)(n < 262144 ? n : 262144)
 
 
 
+// 1 / k^2 for the I0 series (k < 128; the series has converged by k ~ 60 for the
+// arguments of the Kaiser-Bessel taps, beta <= 2.34 * 15).
+struct InvSquares {
+  double v[128];
+};
+constexpr InvSquares make_inv_squares() {
+  InvSquares t{};
+  t.v[0] = 0.0;
+  for (int k = 1; k < 128; ++k) t.v[k] = 1.0 / ((double)k * (double)k);
+  return t;
+}
+__constant__ InvSquares c_inv_k2 = make_inv_squares();
+
+// I0(x) = sum_k (x^2 / 4)^k / (k!)^2, the term ratio q / k^2 taken as q * (1 / k^2) so
+// that the loop carries no division (the taps only scale values of G; no integer
+// decision depends on them).
 __device__ __forceinline__ double dev_i0(double x) {
 #pragma clang fp contract(off)
   const double q = 0.25 * x * x;
   double term = 1.0, s = 1.0;
-  for (int k = 1; k < 200; ++k) {
-    term = term * q / ((double)k * (double)k);
+  for (int k = 1; k < 128; ++k) {
+    term = term * (q * c_inv_k2.v[k]);
     s += term;
     if (term < 1e-18 * s) break;
   }
