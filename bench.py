@@ -138,8 +138,29 @@ def time_form(obs, store, args, torch):
     log(f"{store}: {ms:.3f} ms/apply (wall {1e3 * wall / args.steps:.3f}) on "
         f"{tune['branches']} branches; G^dag G alone {kms / max(nl, 1):.3f} ms/launch over "
         f"{nl} launches")
+    # Phi (de-gridding) and Phi^dag (gridding) applies on their own, tuned branches
+    op.set_branches(tune["branches"])
+    y = op.forward(x)
+    img_c = op.adjoint(y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(args.steps):
+        op.forward(x, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / args.steps
+    e0.record(stream)
+    for i in range(args.steps):
+        op.adjoint(y, out=img_c)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / args.steps
+    log(f"{store}: Phi {fwd_ms:.3f} ms, Phi^dag {adj_ms:.3f} ms per apply")
+    del y, img_c
     res = dict(ms=ms, info=info, build_s=tb, gtg_launches=nl, gtg_ms_total=kms,
-               out=out.clone(), store=store, tune=tune)
+               out=out.clone(), store=store, tune=tune, fwd_ms=fwd_ms, adj_ms=adj_ms)
     if store == args.forms.split(",")[0]:
         # forward-backward iterations (eq. 4) on the same operator, tuned branches
         op.set_branches(tune["branches"])
@@ -688,7 +709,8 @@ def main():
         "forms": {f: {"ms": r["ms"], "applies_per_s": 1e3 / r["ms"],
                       "gvis_per_s": 1e3 / r["ms"] * M / 1e9, "nbins": r["info"]["nbins"],
                       "ntaps": r["info"]["ntaps"], "build_s": r["build_s"],
-                      "g_bytes": r["info"]["mem_g_bytes"]} for f, r in res.items()},
+                      "g_bytes": r["info"]["mem_g_bytes"], "forward_ms": r["fwd_ms"],
+                      "adjoint_ms": r["adj_ms"]} for f, r in res.items()},
         "accuracy": acc,
         "autotune": head["tune"],
         "fb_iteration_ms": head.get("fb_ms"),

@@ -228,6 +228,13 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
     const int i = r - r0;
     return (uint32_t)__builtin_amdgcn_readlane((int)(i < 64 ? mv0 : mv1), i & 63);
   };
+  // gridding: the segment's visibilities are fetched once, like its metadata (lane i
+  // holds rows r0 + i and r0 + 64 + i), so that no row waits on its own y
+  float2 yv0 = make_float2(0.f, 0.f), yv1 = make_float2(0.f, 0.f);
+  if constexpr (MODE == 2) {
+    yv0 = vis[perm[wi.row0 + r0 + min(lane, nseg - 1)]];
+    yv1 = vis[perm[wi.row0 + r0 + min(64 + lane, nseg - 1)]];
+  }
   Raw buf[D][MK];
   uint32_t mb[D];
   int rp = r0;                                        // next row to request
@@ -298,9 +305,10 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
           if (lane == 0) vis[perm[row]] = make_float2(yx, yy);
         }
       } else {
-        const float2 y = vis[perm[row]];
-        yx = y.x;
-        yy = y.y;
+        const int i = r - r0;
+        const float2 yv = i < 64 ? yv0 : yv1;
+        yx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv.x), i & 63));
+        yy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv.y), i & 63));
       }
       if constexpr (SCATTER) {
 #pragma unroll
