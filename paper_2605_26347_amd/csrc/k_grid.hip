@@ -4,11 +4,14 @@
 // Rows are sorted by (bin, grid tile, patch side, patch origin) and cut into work
 // items that hold one patch-size class; a workgroup owns one work item and each of its
 // wavefronts walks a contiguous segment of the item's rows, its 64 lanes spread over a
-// row's T x T patch (MK taps per lane).  Consecutive rows with the same patch origin
-// and side (a "run": visibilities falling in one grid cell) share their grid cells, so
-//   * the grid values X of the run's patch are gathered once per run,
-//   * conj(g_k) y_k is accumulated in registers over the run and added into the LDS
-//     window of the tile (plus halo) once per run,
+// register patch (MK slots per lane).  Consecutive rows with the same patch origin and
+// side form a "run" (visibilities falling in one grid cell); consecutive runs with the
+// same side and patch row whose origins lie a few columns apart form a merge group that
+// shares one register patch of T x (T + span) cells (the span fills the class's spare
+// slots), each row's taps mapped in at its column offset.  Per group
+//   * the grid values X of the group's patch are gathered once,
+//   * conj(g_k) y_k is accumulated in registers over the group and added into the LDS
+//     window of the tile (plus halo) once,
 // and the stored values of G are streamed from HBM exactly once.  A row's sum
 // y_k = sum_t g_k[t] X[t] is reduced across the wavefront with DPP within each
 // 16-lane row and four readlanes, which leaves y_k wave-uniform.  At the end the
@@ -76,18 +79,32 @@ __device__ __forceinline__ float wave_sum_uniform(float v) {
           __int_as_float(__builtin_amdgcn_readlane(b, 48)));
 }
 
+// A merge group: runs of patch side T in one patch row whose origins lie within `span`
+// columns of the first run's origin lu0 share a register patch of T x Wx cells,
+// Wx = T + span, slot t <-> (t / Wx, t % Wx).  A row's word carries lu0 | lv0 << 8 |
+// T << 16 | du << 24, du being its column offset from the group's origin.
 struct RunGeom {
-  int T, TT, lu0, lv0;
+  int T, Wx, TT, lu0, lv0;
 };
 
-__device__ __forceinline__ RunGeom decode(uint32_t m) {
+// Group key of a row word: its origin moved back by du (no borrow: lu0 >= du).  Without
+// merging (de-gridding, which has no scatter to save) every run is its own group.
+template <bool MERGE>
+__device__ __forceinline__ uint32_t group_key(uint32_t m) {
+  return MERGE ? (m & 0x00ffffffu) - (m >> 24) : (m & 0x00ffffffu);
+}
+
+template <int MK, bool MERGE>
+__device__ __forceinline__ RunGeom decode(uint32_t gkey) {
   RunGeom r;
-  r.lu0 = m & 0xff;
-  r.lv0 = (m >> 8) & 0xff;
-  r.T = (m >> 16) & 0xff;
-  r.TT = r.T * r.T;
+  r.lu0 = gkey & 0xff;
+  r.lv0 = (gkey >> 8) & 0xff;
+  r.T = (gkey >> 16) & 0xff;
+  r.Wx = r.T + (MERGE ? group_span(r.T, MK) : 0);
+  r.TT = r.T * r.Wx;
   return r;
 }
+
 
 // Patch coordinates (a = row, b = column) of tap t; exact for t < 2^13, T <= 64.
 __device__ __forceinline__ void tap_ab(int t, int T, float invT, int& a, int& b) {
@@ -95,19 +112,41 @@ __device__ __forceinline__ void tap_ab(int t, int T, float invT, int& a, int& b)
   b = t - a * T;
 }
 
-// Load the grid values of a run's patch (one per lane and tap slot).
+// Slots of a row with patch side T and column offset du in its group's register patch:
+// bit k set when slot lane + 64 k holds one of the row's taps; tap[k] its index in the
+// row's stored values (0 for the other slots, an in-bounds dummy).
+template <int MK, bool MERGE>
+__device__ __forceinline__ uint32_t row_slots(uint32_t m, int lane, int (&tap)[MK]) {
+  const int T = (int)((m >> 16) & 0xff), du = MERGE ? (int)(m >> 24) : 0;
+  const int Wx = T + (MERGE ? group_span(T, MK) : 0);
+  const float invW = 1.0f / (float)Wx;
+  uint32_t valid = 0;
+#pragma unroll
+  for (int k = 0; k < MK; ++k) {
+    const int t = lane + 64 * k;
+    int a, b;
+    tap_ab(t, Wx, invW, a, b);
+    const int bb = b - du;
+    const bool ok = t < T * Wx && bb >= 0 && bb < T;
+    tap[k] = ok ? a * T + bb : 0;
+    valid |= ok ? (1u << k) : 0u;
+  }
+  return valid;
+}
+
+// Load the grid values of a group's register patch (one per lane and slot).
 template <int MK>
 __device__ __forceinline__ void load_patch_x(const RunGeom& r, int u0, int v0, int Kx, int Ky,
                                              const float2* __restrict__ X, int lane,
                                              float2 (&xr)[MK]) {
-  const float invT = 1.0f / (float)r.T;
+  const float invW = 1.0f / (float)r.Wx;
   // branch-free: lanes past the patch read its last cell and zero the value
 #pragma unroll
   for (int k = 0; k < MK; ++k) {
     const int t = lane + 64 * k;
     const int tc = t < r.TT ? t : r.TT - 1;
     int a, b;
-    tap_ab(tc, r.T, invT, a, b);
+    tap_ab(tc, r.Wx, invW, a, b);
     const int gu = (u0 + r.lu0 + b) & (Kx - 1);
     const int gv = (v0 + r.lv0 + a) & (Ky - 1);
     xr[k] = X[strip_index(gv, gu, Ky)];
@@ -117,20 +156,21 @@ __device__ __forceinline__ void load_patch_x(const RunGeom& r, int u0, int v0, i
     if (lane + 64 * k >= r.TT) xr[k] = make_float2(0.f, 0.f);
 }
 
-// Add a run's register accumulator into the LDS window.  The window is stored as two
-// planes (real parts, then imaginary parts) so that the consecutive cells of a patch row
-// fall in consecutive banks.
+// Add a group's register accumulator into the LDS window: the columns its runs covered,
+// b < bend = T + largest offset (inside the window: that run's patch is).  The window is
+// stored as two planes (real parts, then imaginary parts) so that the consecutive cells
+// of a patch row fall in consecutive banks.
 template <int MK>
-__device__ __forceinline__ void scatter_run(const RunGeom& r, int W, int lane,
+__device__ __forceinline__ void scatter_run(const RunGeom& r, int bend, int W, int lane,
                                             const float2 (&ac)[MK], float* accf) {
-  const float invT = 1.0f / (float)r.T;
+  const float invW = 1.0f / (float)r.Wx;
   float* acci = accf + W * W;
 #pragma unroll
   for (int k = 0; k < MK; ++k) {
     const int t = lane + 64 * k;
-    if (t < r.TT) {
-      int a, b;
-      tap_ab(t, r.T, invT, a, b);
+    int a, b;
+    tap_ab(t < r.TT ? t : 0, r.Wx, invW, a, b);
+    if (t < r.TT && b < bend) {
       const int li = (r.lv0 + a) * W + (r.lu0 + b);
       atomicAdd(accf + li, ac[k].x);
       atomicAdd(acci + li, ac[k].y);
@@ -192,6 +232,7 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   const WorkItem wi = wis[blockIdx.x];
   constexpr bool GATHER = MODE != 2;
   constexpr bool SCATTER = MODE != 1;
+  constexpr bool MERGE = SCATTER;   // merge groups save scatter work only
   const Box bx = box_of(wi.box);
   if constexpr (SCATTER) {
     window_zero(accf, W, bx);
@@ -236,25 +277,27 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
     yv1 = vis[perm[wi.row0 + r0 + min(64 + lane, nseg - 1)]];
   }
   Raw buf[D][MK];
-  uint32_t mb[D];
+  uint32_t mb[D], vm[D];                              // row word, slots holding its taps
   int rp = r0;                                        // next row to request
   int64_t vbp = wi.voff + (int64_t)voff[wi.row0 + r0];  // its value offset
   uint32_t mp = meta_of(r0);                          // its metadata
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     mb[d] = 0u;
+    vm[d] = 0u;
     if (rp < r1) {
       const int Tn = (int)((mp >> 16) & 0xff);
-      const int lastt = Tn * Tn - 1;
+      int tap[MK];
+      vm[d] = row_slots<MK, MERGE>(mp, lane, tap);
 #pragma unroll
-      for (int k = 0; k < MK; ++k)
-        buf[d][k] = load_raw<STORE>(vals, vbp + min(lane + 64 * k, lastt));
+      for (int k = 0; k < MK; ++k) buf[d][k] = load_raw<STORE>(vals, vbp + tap[k]);
       mb[d] = mp;
       vbp += (int64_t)Tn * Tn;
       ++rp;
       mp = rp < r1 ? meta_of(rp) : 0u;
     }
   }
+  int dmax = 0;   // largest column offset of the current group's rows
   for (int rb = r0; rb < r1; rb += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -262,35 +305,42 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
       if (r >= r1) break;
       const int row = wi.row0 + r;
       const uint32_t m = mb[d];
+      const uint32_t valid = vm[d];
       Raw graw[MK];
 #pragma unroll
       for (int k = 0; k < MK; ++k) graw[k] = buf[d][k];
-      if (m != cur) {
+      const uint32_t gk = group_key<MERGE>(m);
+      const int du = MERGE ? (int)(m >> 24) : 0;
+      if (gk != cur) {
         if constexpr (SCATTER) {
-          if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
+          if (cur != 0xffffffffu) scatter_run<MK>(rg, rg.T + dmax, W, lane, ac, accf);
         }
-        cur = m;
-        rg = decode(m);
+        cur = gk;
+        rg = decode<MK, MERGE>(gk);
+        dmax = du;
         if constexpr (GATHER) load_patch_x<MK>(rg, wi.u0, wi.v0, Kx, Ky, X, lane, xr);
 #pragma unroll
         for (int k = 0; k < MK; ++k) ac[k] = make_float2(0.f, 0.f);
+      } else {
+        dmax = du > dmax ? du : dmax;
       }
-      if (rp < r1) {  // request row rp = r + D (branch-free, clamped in-bounds loads)
+      if (rp < r1) {  // request row rp = r + D (branch-free, in-bounds loads)
         const int Tn = (int)((mp >> 16) & 0xff);
-        const int lastt = Tn * Tn - 1;
+        int tap[MK];
+        vm[d] = row_slots<MK, MERGE>(mp, lane, tap);
 #pragma unroll
-        for (int k = 0; k < MK; ++k)
-          buf[d][k] = load_raw<STORE>(vals, vbp + min(lane + 64 * k, lastt));
+        for (int k = 0; k < MK; ++k) buf[d][k] = load_raw<STORE>(vals, vbp + tap[k]);
         mb[d] = mp;
         vbp += (int64_t)Tn * Tn;
         ++rp;
         mp = rp < r1 ? meta_of(rp) : 0u;
       }
-      // lanes past the patch hold a copy of its last value: their grid values are zero
-      // (gather) and their accumulators are never added into the window (scatter)
+      // slots outside the row's own patch read an in-bounds dummy and are zeroed: they add
+      // nothing to y and nothing to the group's accumulator
       float2 g[MK];
 #pragma unroll
-      for (int k = 0; k < MK; ++k) g[k] = widen<STORE>(graw[k]);
+      for (int k = 0; k < MK; ++k)
+        g[k] = ((valid >> k) & 1u) ? widen<STORE>(graw[k]) : make_float2(0.f, 0.f);
       float yx, yy;
       if constexpr (GATHER) {
         float sx = 0.f, sy = 0.f;
@@ -320,7 +370,7 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
     }
   }
   if constexpr (SCATTER) {
-    if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
+    if (cur != 0xffffffffu) scatter_run<MK>(rg, rg.T + dmax, W, lane, ac, accf);
     __syncthreads();
     window_flush(accf, W, bx, wi.u0, wi.v0, Kx, Ky, Y);
   }

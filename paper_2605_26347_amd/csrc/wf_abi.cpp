@@ -611,6 +611,24 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
       return fail(WF_EBUDGET, "no strategy fits the memory budget: the on-the-fly row data "
                               "alone needs " + std::to_string(meta_bytes / 1e9) + " GB");
   }
+  // consecutive runs of a row group with the same patch side and patch row whose origins
+  // lie within the class's spare columns form a merge group: the row kernels hold one
+  // register patch of T x (T + span) cells for it (one gather of X, one scatter).  Each
+  // row records its column offset from the group's first run in bits 24..31 of its word.
+  for (const RowGroup& g : ch.groups) {
+    const int mk = class_mk(g.cls);
+    int gT = -1, glv = -1, glu = 0;
+    for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) {
+      const uint32_t m = meta[r];
+      const int lu = (int)(m & 0xff), lv = (int)((m >> 8) & 0xff), T = (int)((m >> 16) & 0xff);
+      if (T != gT || lv != glv || lu < glu || lu - glu > group_span(T, mk)) {
+        gT = T;
+        glv = lv;
+        glu = lu;
+      }
+      meta[r] |= (uint32_t)(lu - glu) << 24;
+    }
+  }
   std::vector<WorkItem> wis;
   ch.max_rows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
   split_items(ch, trow.data(), meta.data(), ch.max_rows, wis, voff.data(), row_wi.data());
