@@ -26,6 +26,8 @@ of the widefield radio-interferometric measurement model"):
                     per-row weights and flags (``OracleOperator(weights=, flags=)``).
 * ``planner``    -- WSClean bin bound (eq. 5), memory model (eq. 9, GPU byte form),
                     cost model (eq. 10) and the decision tree (Sect. 3.4, Fig. 2).
+* ``fb``         -- forward-backward iteration (Sect. 2, eq. 4) with the positivity +
+                    l1 prox as denoiser, and the power iteration for its step bound.
 * ``mlp``        -- (not in the paper) FP64 forward, backward and Adam step of the
                     network that predicts residual-w kernels, its input definition and
                     its training targets (thresholded exact kernels).
@@ -36,7 +38,8 @@ residual-kernel convergence towards the true-w direct sum, closed forms (delta
 images, w = 0 PSF convolution), k-means against an exact dynamic programme, and
 hand-computed planner values; weighted rows against the weighted direct sum, flags
 against building on the kept rows, Briggs weights against a hand-computed example and
-their natural / uniform limits.
+their natural / uniform limits; the forward-backward iteration against a brute-force
+prox, a dense eigenvalue bound and its monotone objective.
 """
 from .kernels import (kb_phi, kb_phihat, grid_correction, chirp, nm1, i0_series)  # noqa: F401
 from .directsum import direct_forward, direct_adjoint, direct_matrix  # noqa: F401
