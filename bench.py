@@ -185,13 +185,14 @@ def time_form(obs, store, args, torch):
 
 
 def cpu_baseline(obs, P_gpu):
-    """FP64 oracle on a bounded sample: one full-size w-layer (two 8192^2 FFTs and the
-    layer's w-modulation) and the sparse products of up to 40k rows of that layer (the
-    most populated bin); scaled to a full apply as P * t_layer_fft + M * t_row."""
+    """FP64 oracle on a bounded sample (about 10 s of host work): one full-size w-layer
+    (two 8192^2 FFTs and the layer's w-modulation) and the sparse products of up to 240k
+    rows of that layer (the most populated bin); scaled to a full apply as
+    P * t_layer_fft + M * t_row."""
     import threadpoolctl
     from oracle import OracleOperator, OperatorParams, wbins
     from oracle.operator import C_LIGHT
-    nsamp = 40_000
+    nsamp = 240_000
     prm = OperatorParams(obs.nx, obs.ny, obs.cell_rad)
     w_all = obs.uvw_m[:, 2] * (obs.freqs_hz[0] / C_LIGHT)
     mask = wbins.plan_subset_mask(w_all.size, 0.01, 0)
