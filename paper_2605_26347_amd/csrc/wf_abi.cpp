@@ -1609,20 +1609,36 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
   }
 }
 
-wf_status wf_forward(wf_op* op, const float* d_img, float* d_vis, void* stream) {
+static wf_status wf_forward_body(wf_op* op, const float* d_img, float* d_vis, void* stream) {
   return apply_entry(op, WF_APPLY_FORWARD, d_img, d_vis, stream);
 }
 
-wf_status wf_adjoint(wf_op* op, const float* d_vis, float* d_img, void* stream) {
+wf_status wf_forward(wf_op* op, const float* d_img, float* d_vis, void* stream) {
+  return guarded([&] { return wf_forward_body(op, d_img, d_vis, stream); });
+}
+
+static wf_status wf_adjoint_body(wf_op* op, const float* d_vis, float* d_img, void* stream) {
   return apply_entry(op, WF_APPLY_ADJOINT, d_vis, d_img, stream);
 }
 
-wf_status wf_psf_apply(wf_op* op, const float* d_img, float* d_out, void* stream) {
+wf_status wf_adjoint(wf_op* op, const float* d_vis, float* d_img, void* stream) {
+  return guarded([&] { return wf_adjoint_body(op, d_vis, d_img, stream); });
+}
+
+static wf_status wf_psf_apply_body(wf_op* op, const float* d_img, float* d_out, void* stream) {
   return apply_entry(op, WF_APPLY_PSF, d_img, d_out, stream);
 }
 
-wf_status wf_psf_apply_re(wf_op* op, const float* d_img, float* d_out, void* stream) {
+wf_status wf_psf_apply(wf_op* op, const float* d_img, float* d_out, void* stream) {
+  return guarded([&] { return wf_psf_apply_body(op, d_img, d_out, stream); });
+}
+
+static wf_status wf_psf_apply_re_body(wf_op* op, const float* d_img, float* d_out, void* stream) {
   return apply_entry(op, WF_APPLY_PSF_RE, d_img, d_out, stream);
+}
+
+wf_status wf_psf_apply_re(wf_op* op, const float* d_img, float* d_out, void* stream) {
+  return guarded([&] { return wf_psf_apply_re_body(op, d_img, d_out, stream); });
 }
 
 wf_status wf_get_plan(const wf_op* op, int32_t chan, wf_plan_info* out) {
@@ -1719,8 +1735,8 @@ wf_status wf_get_row(const wf_op* op, int32_t chan, int64_t row, int32_t* T, int
   }
 }
 
-wf_status wf_layer_grid(wf_op* op, int32_t chan, int32_t bin, const float* d_img,
-                        float* d_grid, void* stream) {
+static wf_status wf_layer_grid_body(wf_op* op, int32_t chan, int32_t bin, const float* d_img,
+                                    float* d_grid, void* stream) {
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
   if (chan < 0 || chan >= (int)op->chans.size()) return fail(WF_EINVAL, "bad channel");
@@ -1736,7 +1752,12 @@ wf_status wf_layer_grid(wf_op* op, int32_t chan, int32_t bin, const float* d_img
   return WF_OK;
 }
 
-wf_status wf_profile_enable(wf_op* op, int32_t kernel_id, int32_t enable) {
+wf_status wf_layer_grid(wf_op* op, int32_t chan, int32_t bin, const float* d_img, float* d_grid,
+                        void* stream) {
+  return guarded([&] { return wf_layer_grid_body(op, chan, bin, d_img, d_grid, stream); });
+}
+
+static wf_status wf_profile_enable_body(wf_op* op, int32_t kernel_id, int32_t enable) {
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
   if (kernel_id < 0 || kernel_id >= NPROF) return fail(WF_EINVAL, "bad kernel id");
@@ -1748,7 +1769,12 @@ wf_status wf_profile_enable(wf_op* op, int32_t kernel_id, int32_t enable) {
   return WF_OK;
 }
 
-wf_status wf_profile_read(wf_op* op, int32_t kernel_id, int64_t* launches, double* total_ms) {
+wf_status wf_profile_enable(wf_op* op, int32_t kernel_id, int32_t enable) {
+  return guarded([&] { return wf_profile_enable_body(op, kernel_id, enable); });
+}
+
+static wf_status wf_profile_read_body(wf_op* op, int32_t kernel_id, int64_t* launches,
+                                      double* total_ms) {
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
   if (kernel_id < 0 || kernel_id >= NPROF) return fail(WF_EINVAL, "bad kernel id");
@@ -1767,7 +1793,11 @@ wf_status wf_profile_read(wf_op* op, int32_t kernel_id, int64_t* launches, doubl
   return WF_OK;
 }
 
-wf_status wf_set_branches(wf_op* op, int32_t branches) {
+wf_status wf_profile_read(wf_op* op, int32_t kernel_id, int64_t* launches, double* total_ms) {
+  return guarded([&] { return wf_profile_read_body(op, kernel_id, launches, total_ms); });
+}
+
+static wf_status wf_set_branches_body(wf_op* op, int32_t branches) {
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
   if (branches < 1 || branches > 16) return fail(WF_EINVAL, "branches must be in [1,16]");
@@ -1775,8 +1805,12 @@ wf_status wf_set_branches(wf_op* op, int32_t branches) {
   return set_branches(op, branches);
 }
 
-wf_status wf_graph_capture(wf_op* op, wf_apply_kind kind, const float* d_in, float* d_out,
-                           void* hip_stream, wf_graph** out) {
+wf_status wf_set_branches(wf_op* op, int32_t branches) {
+  return guarded([&] { return wf_set_branches_body(op, branches); });
+}
+
+static wf_status wf_graph_capture_body(wf_op* op, wf_apply_kind kind, const float* d_in,
+                                       float* d_out, void* hip_stream, wf_graph** out) {
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
   if (!out) return fail(WF_EINVAL, "out is null");
@@ -1816,7 +1850,12 @@ wf_status wf_graph_capture(wf_op* op, wf_apply_kind kind, const float* d_in, flo
   return WF_OK;
 }
 
-wf_status wf_graph_launch(wf_graph* g, void* hip_stream) {
+wf_status wf_graph_capture(wf_op* op, wf_apply_kind kind, const float* d_in, float* d_out,
+                           void* hip_stream, wf_graph** out) {
+  return guarded([&] { return wf_graph_capture_body(op, kind, d_in, d_out, hip_stream, out); });
+}
+
+static wf_status wf_graph_launch_body(wf_graph* g, void* hip_stream) {
   if (!g || !g->op) return fail(WF_EINVAL, "null graph");
   if (g->gen != g->op->generation)
     return fail(WF_EINVAL, "the operator's work items or branches changed since the capture");
@@ -1825,7 +1864,11 @@ wf_status wf_graph_launch(wf_graph* g, void* hip_stream) {
   return WF_OK;
 }
 
-wf_status wf_graph_destroy(wf_graph* g) {
+wf_status wf_graph_launch(wf_graph* g, void* hip_stream) {
+  return guarded([&] { return wf_graph_launch_body(g, hip_stream); });
+}
+
+static wf_status wf_graph_destroy_body(wf_graph* g) {
   if (!g) return fail(WF_EINVAL, "null graph");
   (void)hipSetDevice(g->device);
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -1834,7 +1877,11 @@ wf_status wf_graph_destroy(wf_graph* g) {
   return WF_OK;
 }
 
-wf_status wf_latency_enable(wf_op* op, int32_t enable) {
+wf_status wf_graph_destroy(wf_graph* g) {
+  return guarded([&] { return wf_graph_destroy_body(g); });
+}
+
+static wf_status wf_latency_enable_body(wf_op* op, int32_t enable) {
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
   WF_HIP(hipSetDevice(op->device));
@@ -1847,6 +1894,10 @@ wf_status wf_latency_enable(wf_op* op, int32_t enable) {
   // the stamp buffer stays allocated: graphs captured while enabled keep writing it
   op->stamping = enable != 0;
   return WF_OK;
+}
+
+wf_status wf_latency_enable(wf_op* op, int32_t enable) {
+  return guarded([&] { return wf_latency_enable_body(op, enable); });
 }
 
 wf_status wf_read_latency(wf_op* op, double* ms, int32_t cap) {
@@ -1872,8 +1923,8 @@ wf_status wf_read_latency(wf_op* op, double* ms, int32_t cap) {
   }
 }
 
-wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_stream,
-                      int32_t reps, wf_tune_info* info) {
+wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_stream, int32_t reps,
+                      wf_tune_info* info) {
   try {
     wf_status st = check_op(op);
     if (st != WF_OK) return st;
@@ -1957,7 +2008,7 @@ wf_status fb_buffers(wf_op* op, bool complex_too) {
 
 }  // namespace
 
-wf_status wf_dirty_image(wf_op* op, const float* d_vis, float* d_dirty, void* stream) {
+static wf_status wf_dirty_image_body(wf_op* op, const float* d_vis, float* d_dirty, void* stream) {
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
   if (!d_vis || !d_dirty) return fail(WF_EINVAL, "null pointer");
@@ -1972,7 +2023,11 @@ wf_status wf_dirty_image(wf_op* op, const float* d_vis, float* d_dirty, void* st
   return WF_OK;
 }
 
-wf_status wf_op_norm(wf_op* op, int32_t iters, double* norm, void* stream) {
+wf_status wf_dirty_image(wf_op* op, const float* d_vis, float* d_dirty, void* stream) {
+  return guarded([&] { return wf_dirty_image_body(op, d_vis, d_dirty, stream); });
+}
+
+static wf_status wf_op_norm_body(wf_op* op, int32_t iters, double* norm, void* stream) {
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
   if (iters < 1 || !norm) return fail(WF_EINVAL, "bad power-iteration arguments");
@@ -1997,8 +2052,12 @@ wf_status wf_op_norm(wf_op* op, int32_t iters, double* norm, void* stream) {
   return WF_OK;
 }
 
-wf_status wf_fb_iterate(wf_op* op, const float* d_dirty, float* d_x, int32_t iters,
-                        double gamma, double lambda, void* stream) {
+wf_status wf_op_norm(wf_op* op, int32_t iters, double* norm, void* stream) {
+  return guarded([&] { return wf_op_norm_body(op, iters, norm, stream); });
+}
+
+static wf_status wf_fb_iterate_body(wf_op* op, const float* d_dirty, float* d_x, int32_t iters,
+                                    double gamma, double lambda, void* stream) {
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
   if (!d_dirty || !d_x || iters < 0 || !(gamma > 0) || !(lambda >= 0))
@@ -2015,10 +2074,21 @@ wf_status wf_fb_iterate(wf_op* op, const float* d_dirty, float* d_x, int32_t ite
   return WF_OK;
 }
 
-wf_status wf_destroy(wf_op* op) {
+wf_status wf_fb_iterate(wf_op* op, const float* d_dirty, float* d_x, int32_t iters, double gamma,
+                        double lambda, void* stream) {
+  return guarded([&] {
+    return wf_fb_iterate_body(op, d_dirty, d_x, iters, gamma, lambda, stream);
+  });
+}
+
+static wf_status wf_destroy_body(wf_op* op) {
   if (!op) return fail(WF_EINVAL, "null operator handle");
   destroy_op(op);
   return WF_OK;
+}
+
+wf_status wf_destroy(wf_op* op) {
+  return guarded([&] { return wf_destroy_body(op); });
 }
 
 }  // extern "C"

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -383,6 +385,20 @@ hipError_t launch_mlp_infer_bf16(const float* x, int64_t n, const float* params,
 // ------------------------------------------------------------------ host helpers
 // Record the thread-local error message of the ABI and return the status.
 wf_status fail(wf_status s, const std::string& m);
+// Run an entry point's body with C++ exceptions turned into status codes, so that none
+// crosses the C ABI: host allocation failures give WF_ENOMEM, anything else WF_EINVAL.
+template <typename F>
+wf_status guarded(F&& body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(WF_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(WF_EINVAL, e.what());
+  } catch (...) {
+    return fail(WF_EINVAL, "unexpected exception");
+  }
+}
 wf_status dalloc(DevBuf& b, size_t bytes);
 void dfree(DevBuf& b);
 

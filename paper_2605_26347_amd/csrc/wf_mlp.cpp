@@ -209,16 +209,22 @@ wf_status wf_mlp_create(uint64_t seed, wf_mlp** out) {
     return WF_OK;
   } catch (const std::bad_alloc&) {
     return fail(WF_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(WF_EINVAL, e.what());
   }
 }
 
-wf_status wf_mlp_destroy(wf_mlp* m) {
+static wf_status wf_mlp_destroy_body(wf_mlp* m) {
   if (!m) return fail(WF_EINVAL, "null network handle");
   free_mlp(m);
   return WF_OK;
 }
 
-wf_status wf_mlp_get_params(const wf_mlp* m, float* host, int64_t n) {
+wf_status wf_mlp_destroy(wf_mlp* m) {
+  return guarded([&] { return wf_mlp_destroy_body(m); });
+}
+
+static wf_status wf_mlp_get_params_body(const wf_mlp* m, float* host, int64_t n) {
   if (!m || !host) return fail(WF_EINVAL, "null pointer");
   if (n != mlp_num_params()) return fail(WF_EINVAL, "parameter count mismatch");
   WF_HIP(hipSetDevice(m->device));
@@ -227,7 +233,11 @@ wf_status wf_mlp_get_params(const wf_mlp* m, float* host, int64_t n) {
   return WF_OK;
 }
 
-wf_status wf_mlp_set_params(wf_mlp* m, const float* host, int64_t n) {
+wf_status wf_mlp_get_params(const wf_mlp* m, float* host, int64_t n) {
+  return guarded([&] { return wf_mlp_get_params_body(m, host, n); });
+}
+
+static wf_status wf_mlp_set_params_body(wf_mlp* m, const float* host, int64_t n) {
   if (!m || !host) return fail(WF_EINVAL, "null pointer");
   if (n != mlp_num_params()) return fail(WF_EINVAL, "parameter count mismatch");
   WF_HIP(hipSetDevice(m->device));
@@ -241,9 +251,13 @@ wf_status wf_mlp_set_params(wf_mlp* m, const float* host, int64_t n) {
   return WF_OK;
 }
 
-wf_status wf_mlp_inputs(const double* d_w, const double* d_L, const double* d_fu,
-                        const double* d_fv, int64_t n, const wf_options* opt, float* d_x,
-                        int32_t* d_nk, void* stream) {
+wf_status wf_mlp_set_params(wf_mlp* m, const float* host, int64_t n) {
+  return guarded([&] { return wf_mlp_set_params_body(m, host, n); });
+}
+
+static wf_status wf_mlp_inputs_body(const double* d_w, const double* d_L, const double* d_fu,
+                                    const double* d_fv, int64_t n, const wf_options* opt,
+                                    float* d_x, int32_t* d_nk, void* stream) {
   if (n < 0 || (n > 0 && (!d_w || !d_L || !d_fu || !d_fv || !d_x)))
     return fail(WF_EINVAL, "bad network input arguments");
   WF_HIP(launch_train_inputs(d_w, d_L, d_fu, d_fv, n, params_of(opt), d_x, d_nk,
@@ -251,16 +265,29 @@ wf_status wf_mlp_inputs(const double* d_w, const double* d_L, const double* d_fu
   return WF_OK;
 }
 
-wf_status wf_mlp_targets(const double* d_w, const double* d_L, int64_t n, const wf_options* opt,
-                         float* d_t, void* stream) {
+wf_status wf_mlp_inputs(const double* d_w, const double* d_L, const double* d_fu,
+                        const double* d_fv, int64_t n, const wf_options* opt, float* d_x,
+                        int32_t* d_nk, void* stream) {
+  return guarded([&] {
+    return wf_mlp_inputs_body(d_w, d_L, d_fu, d_fv, n, opt, d_x, d_nk, stream);
+  });
+}
+
+static wf_status wf_mlp_targets_body(const double* d_w, const double* d_L, int64_t n,
+                                     const wf_options* opt, float* d_t, void* stream) {
   if (n < 0 || (n > 0 && (!d_w || !d_L || !d_t)))
     return fail(WF_EINVAL, "bad network target arguments");
   WF_HIP(launch_exact_targets(d_w, d_L, n, params_of(opt), d_t, (hipStream_t)stream));
   return WF_OK;
 }
 
-wf_status wf_mlp_loss_grad(wf_mlp* m, const float* d_x, const float* d_t, int32_t batch,
-                           float* d_grad, float* d_loss, void* stream) {
+wf_status wf_mlp_targets(const double* d_w, const double* d_L, int64_t n, const wf_options* opt,
+                         float* d_t, void* stream) {
+  return guarded([&] { return wf_mlp_targets_body(d_w, d_L, n, opt, d_t, stream); });
+}
+
+static wf_status wf_mlp_loss_grad_body(wf_mlp* m, const float* d_x, const float* d_t, int32_t batch,
+                                       float* d_grad, float* d_loss, void* stream) {
   if (!m || !d_x || !d_t || !d_loss) return fail(WF_EINVAL, "null pointer");
   if (batch < 1 || batch > MAX_BATCH) return fail(WF_EINVAL, "batch must be in [1,65536]");
   WF_HIP(hipSetDevice(m->device));
@@ -275,10 +302,19 @@ wf_status wf_mlp_loss_grad(wf_mlp* m, const float* d_x, const float* d_t, int32_
   return WF_OK;
 }
 
-wf_status wf_mlp_adam_step(wf_mlp* m, float lr, void* stream) {
+wf_status wf_mlp_loss_grad(wf_mlp* m, const float* d_x, const float* d_t, int32_t batch,
+                           float* d_grad, float* d_loss, void* stream) {
+  return guarded([&] { return wf_mlp_loss_grad_body(m, d_x, d_t, batch, d_grad, d_loss, stream); });
+}
+
+static wf_status wf_mlp_adam_step_body(wf_mlp* m, float lr, void* stream) {
   if (!m) return fail(WF_EINVAL, "null network handle");
   WF_HIP(hipSetDevice(m->device));
   return adam(m, lr, (hipStream_t)stream);
+}
+
+wf_status wf_mlp_adam_step(wf_mlp* m, float lr, void* stream) {
+  return guarded([&] { return wf_mlp_adam_step_body(m, lr, stream); });
 }
 
 wf_status wf_mlp_train(wf_mlp* m, const float* d_x, const float* d_t, int64_t n, int32_t batch,
@@ -329,11 +365,13 @@ wf_status wf_mlp_train(wf_mlp* m, const float* d_x, const float* d_t, int64_t n,
     return WF_OK;
   } catch (const std::bad_alloc&) {
     return fail(WF_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(WF_EINVAL, e.what());
   }
 }
 
-wf_status wf_mlp_infer(wf_mlp* m, const float* d_x, int64_t n, int32_t bf16, float* d_out,
-                       void* stream) {
+static wf_status wf_mlp_infer_body(wf_mlp* m, const float* d_x, int64_t n, int32_t bf16,
+                                   float* d_out, void* stream) {
   if (!m || (n > 0 && (!d_x || !d_out))) return fail(WF_EINVAL, "null pointer");
   if (n < 0) return fail(WF_EINVAL, "negative row count");
   WF_HIP(hipSetDevice(m->device));
@@ -348,6 +386,11 @@ wf_status wf_mlp_infer(wf_mlp* m, const float* d_x, int64_t n, int32_t bf16, flo
     if ((st = forward(m, d_x + r0 * MLP_IN, B, d_out + r0 * MLP_OUT, s)) != WF_OK) return st;
   }
   return WF_OK;
+}
+
+wf_status wf_mlp_infer(wf_mlp* m, const float* d_x, int64_t n, int32_t bf16, float* d_out,
+                       void* stream) {
+  return guarded([&] { return wf_mlp_infer_body(m, d_x, n, bf16, d_out, stream); });
 }
 
 }  // extern "C"

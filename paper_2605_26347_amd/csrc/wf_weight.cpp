@@ -122,5 +122,7 @@ extern "C" wf_status wf_briggs_weights(const double* uvw_m, int64_t nrows,
     return WF_OK;
   } catch (const std::bad_alloc&) {
     return fail(WF_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(WF_EINVAL, e.what());
   }
 }
