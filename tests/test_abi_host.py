@@ -145,3 +145,53 @@ def test_weight_and_briggs_host_checks():
     # no rows: nothing to do, no device work
     assert lib.wf_briggs_weights(None, 0, None, ptr(fr), 1, WfImageShape(64, 64, 1e-4), 0.0,
                                  None, None, ptr(out), None) == _lib.WF_OK
+
+
+def _declarations():
+    """name -> number of parameters of every function include/wf.h declares."""
+    src = open(os.path.join(ROOT, "include", "wf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(wf_[a-z_0-9]+)\s*\(([^;{]*?)\)\s*;", src, flags=re.S):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    decl = _declarations()
+    assert len(decl) >= 30
+    for name, (_, args) in _lib.SIGNATURES.items():
+        assert name in decl, name
+        assert len(args) == decl[name], (name, len(args), decl[name])
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the ABI's structs have the C compiler's size and offsets."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"wf_image_shape": _lib.WfImageShape, "wf_options": _lib.WfOptions,
+               "wf_plan_info": _lib.WfPlanInfo, "wf_tune_info": _lib.WfTuneInfo}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "wf.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True, capture_output=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True,
+                             text=True).stdout.splitlines():
+        cname, field, val = ln.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
