@@ -155,6 +155,11 @@ wf_status wf_briggs_weights(const double* uvw_m, int64_t nrows, const int64_t* c
                             double robust, const float* natural, const uint8_t* flags,
                             float* out, void* hip_stream);
 
+/* The four apply calls below return WF_EINVAL for a null handle or buffer, WF_ENOTSUP for
+ * wf_forward / wf_adjoint on a holographic operator (it holds H_p only), and WF_EHIP when
+ * a HIP call fails (work already queued on the stream may then be partial).  They
+ * allocate nothing. */
+
 /* y = Phi x (eq. 3, eq. 6).  d_img: real FP32 [nchan][ny][nx];
  * d_vis: complex FP32 [total rows] in [chan][row] caller order. */
 wf_status wf_forward(wf_op* op, const float* d_img, float* d_vis, void* hip_stream);
