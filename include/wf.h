@@ -158,7 +158,7 @@ wf_status wf_briggs_weights(const double* uvw_m, int64_t nrows, const int64_t* c
 /* The four apply calls below return WF_EINVAL for a null handle or buffer, WF_ENOTSUP for
  * wf_forward / wf_adjoint on a holographic operator (it holds H_p only), and WF_EHIP when
  * a HIP call fails (work already queued on the stream may then be partial).  They
- * allocate nothing. */
+ * allocate no device memory. */
 
 /* y = Phi x (eq. 3, eq. 6).  d_img: real FP32 [nchan][ny][nx];
  * d_vis: complex FP32 [total rows] in [chan][row] caller order. */
