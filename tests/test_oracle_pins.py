@@ -140,6 +140,32 @@ def test_zero_residual_gives_delta_and_kb_row():
     assert np.array_equal(qu0, ru - 3) and np.array_equal(qv0, rv - 3)
 
 
+def test_kernel_side_rule_hand_values():
+    """Kernel side n_k (Sect. 3.1 bandwidth, read as: the chirp's largest local frequency
+    over the padded field, in grid cells, two-sided, with a factor-2 margin), worked by
+    hand for o = 2, alpha = 2, so that l_p = o Lx / 2 = Lx, m_p = Ly,
+    n_p = sqrt(1 - Lx^2 - Ly^2), B = max(2 |w| l_p / n_p * 2 Lx, 2 |w| m_p / n_p * 2 Ly)
+    and n_k = 2 ceil(B) + 1.
+      3 deg square (Lx = Ly = 0.0523599 rad, Lx^2 = 0.00274156, n_p = 0.9972547):
+        w = 100:  B = 4 * 100 * 0.00274156 / 0.9972547 = 1.09964 -> n_k = 5
+        w = -400: B = 4.39857                                    -> n_k = 11
+      1 deg square (Lx^2 = 3.04617e-4, n_p = 0.9996953):
+        w = 2000: B = 4 * 2000 * 3.04617e-4 / 0.9996953 = 2.43768 -> n_k = 7
+      4 deg x 2 deg (Lx = 0.0698132, Ly = 0.0349066, n_p = sqrt(1 - 0.00487388 -
+      0.00121847) = 0.9969492): the wider axis sets the band,
+        w = 300:  B = 4 * 300 * 0.00487388 / 0.9969492 = 5.86655 -> n_k = 13
+    A slip of a factor 2 anywhere in B moves every one of these values."""
+    d = math.radians
+    cases = [(100.0, d(3), d(3), 5), (-400.0, d(3), d(3), 11), (2000.0, d(1), d(1), 7),
+             (300.0, d(4), d(2), 13)]
+    for w, Lx, Ly, want in cases:
+        assert int(nk_rule(np.array([w]), Lx, Ly, smax=None)[0]) == want, (w, want)
+    # the axes enter symmetrically
+    assert int(nk_rule(np.array([300.0]), d(2), d(4), smax=None)[0]) == 13
+    # the cap
+    assert int(nk_rule(np.array([-400.0]), d(3), d(3), smax=9)[0]) == 9
+
+
 def test_kernel_reproduces_chirp_at_samples():
     """The inverse of the kernel DFT gives back the (phase-tapered) samples exactly, and
     inside the field the samples are the residual w-term itself."""
@@ -174,9 +200,18 @@ def test_threshold_definition_and_batch_agree():
         k2, dr = threshold_shrink(ks[i], 1e-6)
         assert k2.shape == got[i].shape and np.array_equal(k2, got[i])
         assert dr <= 1e-6 and abs(dr - dropped[i]) < 1e-12
-        # kept energy >= 1 - eps, and dropping also the smallest kept entry breaks it
+        # kept energy >= 1 - eps ...
         E = np.abs(ks[i]) ** 2
-        assert (np.abs(k2) ** 2).sum() >= (1 - 1e-6) * E.sum() * (1 - 1e-12)
+        Ek = np.abs(k2) ** 2
+        assert Ek.sum() >= (1 - 1e-6) * E.sum() * (1 - 1e-12)
+        # ... and the kept set is the smallest one that does so (Sect. 3.1: the threshold
+        # preserves the requested fraction of the energy, no more): removing the
+        # smallest kept entry -- together with its equal-energy mirror images, which the
+        # tie rule keeps or drops as one -- leaves less than 1 - eps of the energy
+        kept = Ek[Ek > 0]
+        tau = kept.min()
+        rest = kept[kept > tau * (1.0 + 1e-9)].sum()
+        assert rest < (1 - 1e-6) * E.sum()
 
 
 def test_residual_kernels_converge_to_true_w():
@@ -269,10 +304,29 @@ def test_dense_psf_and_holographic_matrix():
     # the method reaches 1 up to interpolation error plus the thresholded kernel
     # energy: |sum of dropped c_hat| <= sqrt(n_k^2 eps) <= 31e-3 for n_k <= 31
     assert np.abs(yj - 1.0).max() < 31e-3
-    # rows whose residual kernel is a delta reach it to interpolation accuracy
+    # Per row, the phase-centre column is exactly y_k = S_k I_u(k) I_v(k): the image is
+    # s_c delta_0, its padded DFT the constant s_c, so y_k = s_c^2 sum_q g_k[q], and a G
+    # row (Kaiser-Bessel taps convolved with the kept kernel) sums to S_k = sum of the kept
+    # c_hat_k times the two tap sums; I = s_c sum_d phi(t - d) = sum_d phi(t - d) / phihat(0)
+    # is the interpolator's partition-of-unity ratio.  Sampled chirps have unit modulus
+    # and c(0, 0) = 1, so an untruncated kernel has sum_s c_hat = 1 and (Parseval)
+    # sum_s |c_hat|^2 = 1: |S_k - 1| is the modulus of the dropped entries' sum.
+    t = np.linspace(-0.5, 0.5, 2001)
+    d = np.arange(-3, 4)
+    part = kb_phi(t[:, None] - d[None, :], prm.J, prm.beta).sum(1) / kb_phihat(0.0, prm.J, prm.beta)
+    e_i = float(np.abs(part - 1.0).max())
+    assert e_i < 1e-6                                  # J = 7, beta = 2.34 J
     nk = op.nk(np.arange(op.M))
-    if (nk == 1).any():
-        assert np.abs(yj[nk == 1] - 1.0).max() < 1e-5
+    bound = np.empty(op.M)
+    for k in range(op.M):
+        ch = wkernel_exact(op.wproj[k:k + 1], int(nk[k]), op.Lx, op.Ly)[0]
+        assert abs(ch.sum() - 1.0) <= 1e-12
+        assert abs((np.abs(ch) ** 2).sum() - 1.0) <= 1e-12
+        k2, _ = threshold_shrink(ch, prm.eps)
+        S = k2.sum()
+        bound[k] = abs(S - 1.0) + abs(S) * (2.0 * e_i + e_i * e_i) + 1e-12
+    assert (nk > 1).mean() > 0.5                       # mostly true residual kernels
+    assert np.all(np.abs(yj - 1.0) <= bound)
 
 
 def test_delta_image_closed_form(tiny_obs):
