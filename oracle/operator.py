@@ -22,7 +22,10 @@ from __future__ import annotations
 import math
 from dataclasses import dataclass
 
+import os
+
 import numpy as np
+import scipy.fft
 import scipy.sparse as sp
 
 from . import wbins
@@ -128,12 +131,14 @@ class OracleOperator:
         return s * np.exp(-2j * np.pi * self.centroids[p] * self.d) / self.n
 
     def fwd_fft(self, img):
+        """F: unnormalised 2-D DFT of the zero-padded image (library FFT, all host cores)."""
         g = np.zeros((self.Ky, self.Kx), dtype=np.complex128)
         g[np.ix_(self.rows_j, self.cols_i)] = img
-        return np.fft.fft2(g)
+        return scipy.fft.fft2(g, workers=os.cpu_count())
 
     def inv_fft_crop(self, grid):
-        full = np.fft.ifft2(grid) * (self.Kx * self.Ky)
+        """F^dag: unnormalised inverse 2-D DFT, then the crop back to the image."""
+        full = scipy.fft.ifft2(grid, norm="forward", workers=os.cpu_count())
         return full[np.ix_(self.rows_j, self.cols_i)]
 
     def nk(self, idx):
