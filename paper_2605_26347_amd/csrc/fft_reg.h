@@ -1,0 +1,170 @@
+// Register-resident radix-16/32 FFT passes for CDNA (wave64), used by the row passes of
+// the oversampled 2-D DFT F (Sect. 3.2, eq. 6) at the long row lengths.
+//
+// A length-N transform runs as three Stockham passes of radices R1, R2, R3
+// (N = R1 R2 R3, each at most 32).  A thread holds E = N / NT elements and performs
+// E / R butterflies per pass entirely in registers; between passes the data crosses
+// LDS once.  The first pass reads its inputs straight from global memory (with the
+// image-domain modulation fused in) and the last pass writes its outputs, which come
+// out in natural order, straight to global memory.  Pass with radix R and sub-transform
+// length Ns: butterfly j in [0, N/R) reads x[j + r N/R], multiplies input r by
+// W_{Ns R}^{r (j mod Ns)}, does an R-point DFT and writes output r to
+// ((j / Ns) Ns R + j mod Ns) + r Ns.
+// R-point DFTs of 16 and 32 points are Cooley-Tukey products of the 2/4/8-point ones
+// with their inner twiddles as compile-time constants (cos and sin of k pi / 16 from
+// their Taylor series, evaluated in double precision by the compiler).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+
+namespace wf {
+
+namespace twc {
+constexpr double PI = 3.14159265358979323846264338327950288;
+// sin and cos of x in [-pi, pi] from their Taylor series (terms to x^49: below 1e-17)
+constexpr double tsin(double x) {
+  double term = x, sum = x;
+  for (int i = 1; i < 25; ++i) {
+    term *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double tcos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int i = 1; i < 25; ++i) {
+    term *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+    sum += term;
+  }
+  return sum;
+}
+// angle 2 pi m / n reduced to [-pi, pi]
+constexpr double ang(int m, int n) {
+  const int r = ((m % n) + n) % n;
+  const double a = 2.0 * PI * (double)r / (double)n;
+  return a > PI ? a - 2.0 * PI : a;
+}
+}  // namespace twc
+
+// exp(-2 pi i m / n) (forward) or its conjugate (inverse), rounded to FP32
+template <int M, int N, bool INV>
+struct Twiddle {
+  static constexpr float c = (float)twc::tcos(twc::ang(M, N));
+  static constexpr float s = (float)(INV ? twc::tsin(twc::ang(M, N)) : -twc::tsin(twc::ang(M, N)));
+};
+
+template <int M, int N, bool INV>
+__device__ __forceinline__ float2 twiddle_const(float2 a) {
+  if constexpr (((M % N) + N) % N == 0) {
+    return a;
+  } else if constexpr (4 * (((M % N) + N) % N) == N) {  // -i (forward) / +i (inverse)
+    return rot90<INV>(a);
+  } else if constexpr (2 * (((M % N) + N) % N) == N) {
+    return make_float2(-a.x, -a.y);
+  } else {
+    constexpr float c = Twiddle<M, N, INV>::c, s = Twiddle<M, N, INV>::s;
+    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft_reg(float2* v);
+
+// Cooley-Tukey R = A B: x[B n1 + n2] -> A-point DFTs over n1, twiddles W_R^{n2 k1},
+// B-point DFTs over n2 -> X[k1 + A k2].
+template <int A, int B, bool INV>
+struct CT {
+  template <int K1, int N2>
+  static __device__ __forceinline__ void tw(float2 (&t)[A * B]) {
+    t[K1 * B + N2] = twiddle_const<K1 * N2, A * B, INV>(t[K1 * B + N2]);
+    if constexpr (N2 + 1 < B) {
+      tw<K1, N2 + 1>(t);
+    } else if constexpr (K1 + 1 < A) {
+      tw<K1 + 1, 0>(t);
+    }
+  }
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 t[A * B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+      float2 s[A];
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) s[n1] = v[B * n1 + n2];
+      dft_reg<A, INV>(s);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) t[k1 * B + n2] = s[k1];
+    }
+    tw<0, 0>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      float2 s[B];
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) s[n2] = t[k1 * B + n2];
+      dft_reg<B, INV>(s);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = s[k2];
+    }
+  }
+};
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft_reg(float2* v) {
+  if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 4) dft4<INV>(v);
+  else if constexpr (R == 8) dft8<INV>(v);
+  else if constexpr (R == 16) CT<4, 4, INV>::run(v);
+  else CT<8, 4, INV>::run(v);
+}
+
+// The three radices of a length-N row transform and its thread count.
+template <int N>
+struct RowPlan {
+  static constexpr int R1 = N >= 8192 ? 32 : 16;
+  static constexpr int R2 = N >= 16384 ? 32 : 16;
+  static constexpr int R3 = N / (R1 * R2);
+  static constexpr int E = R1 > R2 ? (R1 > R3 ? R1 : R3) : (R2 > R3 ? R2 : R3);
+  static constexpr int NT = N / E;
+};
+
+// LDS slot of element idx: one float2 of padding after every 32, so that the strided
+// writes of the first pass (stride R1 elements) spread over the banks.
+__device__ __forceinline__ int lds_slot(int idx) { return idx + (idx >> 5); }
+template <int N>
+constexpr int lds_elems() {
+  return N + N / 32;
+}
+
+// One middle pass: inputs from LDS, outputs to LDS (all inputs are read before the
+// barrier, outputs written after it).  The butterflies of a thread are j = tid + b NT.
+template <int N, int R, int NS, int NT, bool INV>
+__device__ __forceinline__ void reg_pass_lds(float2* buf, const float2* __restrict__ tw) {
+  constexpr int B = (N / R) / NT;
+  float2 v[B][R];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = threadIdx.x + b * NT;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[b][r] = buf[lds_slot(j + r * (N / R))];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = threadIdx.x + b * NT;
+    const int kk = j & (NS - 1);
+    const int step = kk * (N / (NS * R));
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      const float2 t = tw[r * step];
+      v[b][r] = INV ? cmulc(v[b][r], t) : cmul(v[b][r], t);
+    }
+    dft_reg<R, INV>(v[b]);
+    const int d = (j - kk) * R + kk;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[lds_slot(d + r * NS)] = v[b][r];
+  }
+  __syncthreads();
+}
+
+}  // namespace wf

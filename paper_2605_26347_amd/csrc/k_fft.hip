@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "fft_lds.h"
+#include "fft_reg.h"
 #include "wf_internal.h"
 
 namespace wf {
@@ -125,6 +126,136 @@ __global__ __launch_bounds__(NT) void k_inv_rows(const float2* __restrict__ A,
   }
 }
 
+// Row passes at the long lengths (N = 2048 .. 16384): three register-resident passes
+// (fft_reg.h).  Since N = 2 nx, input r of a first-pass butterfly holds an image pixel
+// exactly when r < R1/4 (pixel q + nx/2) or r >= 3 R1/4 (pixel q - 3 nx/2), and output r
+// of a last-pass butterfly lands inside the crop under the same rule with R3: the zero
+// half of the padded row and the discarded half of the inverse are skipped at compile
+// time.
+template <int N>
+__global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
+    const float* __restrict__ img, float2* __restrict__ A, const float2* __restrict__ tw,
+    const float* __restrict__ sx, const float* __restrict__ sy, int nx, int ny, double cell,
+    double wp, const uint32_t* __restrict__ smask) {
+  using RP = RowPlan<N>;
+  constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3, NT = RP::NT;
+  extern __shared__ float2 buf[];
+  const int jr = blockIdx.x;
+  const float syj = sy[jr];
+  const float* __restrict__ row = img + (int64_t)jr * nx;
+  {
+    constexpr int B = (N / R1) / NT;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = threadIdx.x + b * NT;
+      float2 v[R1];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int q = j + r * (N / R1);
+        if (r < R1 / 4 || r >= 3 * R1 / 4) {
+          const int i = r < R1 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
+          const float x = row[i];
+          const float2 z = zvalue(i, jr, nx, ny, cell, wp, sx[i], syj);
+          v[r] = make_float2(x * z.x, x * z.y);
+        } else {
+          v[r] = make_float2(0.f, 0.f);
+        }
+      }
+      dft_reg<R1, false>(v);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) buf[lds_slot(j * R1 + r)] = v[r];
+    }
+  }
+  __syncthreads();
+  reg_pass_lds<N, R2, R1, NT, false>(buf, tw);
+  {
+    constexpr int NS = R1 * R2;
+    constexpr int B = (N / R3) / NT;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = threadIdx.x + b * NT;
+      float2 v[R3];
+#pragma unroll
+      for (int r = 0; r < R3; ++r) v[r] = buf[lds_slot(j + r * NS)];
+#pragma unroll
+      for (int r = 1; r < R3; ++r) v[r] = cmul(v[r], tw[r * j]);
+      dft_reg<R3, false>(v);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) {
+        const int q = j + r * NS;
+        if (!smask || bit_set(smask, q >> 4)) A[strip_index(jr, q, ny)] = v[r];
+      }
+    }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
+    const float2* __restrict__ A, void* __restrict__ out, const float2* __restrict__ tw,
+    const float* __restrict__ sx, const float* __restrict__ sy, int nx, int ny, double cell,
+    double wp, int mode, const uint32_t* __restrict__ smask) {
+  using RP = RowPlan<N>;
+  constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3, NT = RP::NT;
+  extern __shared__ float2 buf[];
+  const int jr = blockIdx.x;
+  {
+    constexpr int B = (N / R1) / NT;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = threadIdx.x + b * NT;
+      float2 v[R1];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int q = j + r * (N / R1);
+        v[r] = (!smask || bit_set(smask, q >> 4)) ? A[strip_index(jr, q, ny)]
+                                                  : make_float2(0.f, 0.f);
+      }
+      dft_reg<R1, true>(v);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) buf[lds_slot(j * R1 + r)] = v[r];
+    }
+  }
+  __syncthreads();
+  reg_pass_lds<N, R2, R1, NT, true>(buf, tw);
+  const float syj = sy[jr];
+  {
+    constexpr int NS = R1 * R2;
+    constexpr int B = (N / R3) / NT;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = threadIdx.x + b * NT;
+      float2 v[R3];
+#pragma unroll
+      for (int r = 0; r < R3; ++r) v[r] = buf[lds_slot(j + r * NS)];
+#pragma unroll
+      for (int r = 1; r < R3; ++r) v[r] = cmulc(v[r], tw[r * j]);
+      dft_reg<R3, true>(v);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) {
+        if (r < R3 / 4 || r >= 3 * R3 / 4) {
+          const int q = j + r * NS;
+          const int i = r < R3 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
+          const float2 z = zvalue(i, jr, nx, ny, cell, wp, sx[i], syj);
+          const float2 c = cmulc(v[r], z);
+          const int64_t o = (int64_t)jr * nx + i;
+          if (mode < 2) {
+            float2* po = reinterpret_cast<float2*>(out) + o;
+            if (mode == 1) {
+              const float2 p = *po;
+              *po = make_float2(p.x + c.x, p.y + c.y);
+            } else {
+              *po = c;
+            }
+          } else {
+            float* po = reinterpret_cast<float*>(out) + o;
+            *po = (mode == 3) ? (*po + c.x) : c.x;
+          }
+        }
+      }
+    }
+  }
+}
+
 // Column passes: CW adjacent columns of one strip per workgroup, lines padded by one
 // element in LDS so that the strip-order global accesses (column index fastest) hit
 // distinct banks.
@@ -228,9 +359,44 @@ static hipError_t set_lds(K kern, size_t bytes) {
 #define WF_FOR_SIZES(X) \
   X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
 
+template <int N>
+static hipError_t launch_fwd_rows_reg(const float* img, float2* A, const float2* tw,
+                                      const float* sx, const float* sy, int nx, int ny,
+                                      double cell, double wp, const uint32_t* smask,
+                                      hipStream_t s) {
+  const size_t lds = (size_t)lds_elems<N>() * sizeof(float2);
+  hipError_t e = set_lds(k_fwd_rows_reg<N>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fwd_rows_reg<N>), dim3(ny), dim3(RowPlan<N>::NT), lds, s, img, A, tw,
+                     sx, sy, nx, ny, cell, wp, smask);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_inv_rows_reg(const float2* A, void* out, const float2* tw,
+                                      const float* sx, const float* sy, int nx, int ny,
+                                      double cell, double wp, int mode, const uint32_t* smask,
+                                      hipStream_t s) {
+  const size_t lds = (size_t)lds_elems<N>() * sizeof(float2);
+  hipError_t e = set_lds(k_inv_rows_reg<N>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_inv_rows_reg<N>), dim3(ny), dim3(RowPlan<N>::NT), lds, s, A, out, tw,
+                     sx, sy, nx, ny, cell, wp, mode, smask);
+  return hipGetLastError();
+}
+
 hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const float* sx,
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
                            const uint32_t* smask, hipStream_t s) {
+  if (Kx == 2 * nx) {
+    switch (Kx) {
+      case 2048: return launch_fwd_rows_reg<2048>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, s);
+      case 4096: return launch_fwd_rows_reg<4096>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, s);
+      case 8192: return launch_fwd_rows_reg<8192>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, s);
+      case 16384: return launch_fwd_rows_reg<16384>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, s);
+      default: break;
+    }
+  }
   switch (Kx) {
 #define C(N)                                                                              \
   case N: {                                                                               \
@@ -252,6 +418,15 @@ hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const 
 hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const float* sx,
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
                            int mode, const uint32_t* smask, hipStream_t s) {
+  if (Kx == 2 * nx) {
+    switch (Kx) {
+      case 2048: return launch_inv_rows_reg<2048>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, s);
+      case 4096: return launch_inv_rows_reg<4096>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, s);
+      case 8192: return launch_inv_rows_reg<8192>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, s);
+      case 16384: return launch_inv_rows_reg<16384>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, s);
+      default: break;
+    }
+  }
   switch (Kx) {
 #define C(N)                                                                              \
   case N: {                                                                               \

@@ -3,14 +3,16 @@
 //
 // Rows are sorted by (bin, grid tile, patch side, patch origin) and cut into work
 // items that hold one patch-size class; a workgroup owns one work item and each of its
-// wavefronts walks a contiguous segment of the item's rows, its 64 lanes spread over a
-// register patch (MK slots per lane).  Consecutive rows with the same patch origin and
-// side form a "run" (visibilities falling in one grid cell); consecutive runs with the
-// same side and patch row whose origins lie a few columns apart form a merge group that
-// shares one register patch of T x (T + span) cells (the span fills the class's spare
-// slots), each row's taps mapped in at its column offset.  Per group
-//   * the grid values X of the group's patch are gathered once,
-//   * conj(g_k) y_k is accumulated in registers over the group and added into the LDS
+// wavefronts walks a contiguous segment of the item's rows.  The 64 lanes of a
+// wavefront hold a row's T x T patch in MK slots each, slot k of lane l being tap
+// t = l + 64 k of the row (patch row t / T, column t % T): a row's stored values are
+// read as they lie in memory, one coalesced pass, with no per-row index arithmetic.
+// The values are read through a buffer resource sized to the row, so that the slots
+// past its T^2 taps read zero from the hardware's range check instead of being masked.
+// Consecutive rows with the same patch origin and side form a "run" (visibilities
+// falling in one grid cell).  Per run
+//   * the grid values X of the run's patch are gathered once,
+//   * conj(g_k) y_k is accumulated in registers over the run and added into the LDS
 //     window of the tile (plus halo) once,
 // and the stored values of G are streamed from HBM exactly once.  A row's sum
 // y_k = sum_t g_k[t] X[t] is reduced across the wavefront with DPP within each
@@ -30,32 +32,42 @@ namespace wf {
 constexpr int GWAVES = 8;          // wavefronts per workgroup
 constexpr int GNT = GWAVES * 64;
 
-// Stored values are loaded in their raw form (float2, or one 32-bit word holding two
-// 16-bit halves) and widened to FP32 only where they are used, so that the loads of a
-// row can all be in flight together.
+// Word 3 of a raw (untyped, unswizzled) buffer resource on CDNA: 32-bit data format,
+// so that a load whose byte offset lies at or past the resource's size returns zero.
+constexpr int RSRC_WORD3 = 0x00020000;
+
+// Stored values are loaded in their raw form (two 32-bit words for FP32, one word
+// holding two 16-bit halves otherwise) and widened to FP32 only where they are used,
+// so that the loads of a row can all be in flight together.
 template <int STORE>
 struct RawT {
   using type = uint32_t;
 };
 template <>
 struct RawT<WF_STORE_F32> {
-  using type = float2;
+  using type = uint2;
 };
 
 template <int STORE>
-__device__ __forceinline__ typename RawT<STORE>::type load_raw(const void* __restrict__ vals,
-                                                               int64_t i) {
+constexpr int value_bytes() {
+  return STORE == WF_STORE_F32 ? 8 : 4;
+}
+
+template <int STORE>
+__device__ __forceinline__ typename RawT<STORE>::type load_tap(__amdgpu_buffer_rsrc_t r,
+                                                               int byte_off) {
   if constexpr (STORE == WF_STORE_F32) {
-    return reinterpret_cast<const float2*>(vals)[i];
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+    return make_uint2(v[0], v[1]);
   } else {
-    return reinterpret_cast<const uint32_t*>(vals)[i];
+    return __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
   }
 }
 
 template <int STORE>
 __device__ __forceinline__ float2 widen(typename RawT<STORE>::type r) {
   if constexpr (STORE == WF_STORE_F32) {
-    return r;
+    return make_float2(__uint_as_float(r.x), __uint_as_float(r.y));
   } else if constexpr (STORE == WF_STORE_F16) {
     __half2 h;
     __builtin_memcpy(&h, &r, 4);
@@ -66,111 +78,80 @@ __device__ __forceinline__ float2 widen(typename RawT<STORE>::type r) {
 }
 
 // Sum over the wavefront, returned wave-uniform: DPP butterflies inside each row of 16
-// lanes (quad xor 1, quad xor 2, half-row mirror, row mirror), then the four row sums.
+// lanes (quad xor 1, quad xor 2, half-row mirror, row mirror) leave every lane with its
+// row's sum; broadcasting lane 15 into row 1 (and 47 into row 3), then lane 31 into rows
+// 2 and 3, leaves the total in lane 63, which is read into a scalar register.
 __device__ __forceinline__ float wave_sum_uniform(float v) {
   v += __builtin_amdgcn_update_dpp(0.f, v, 0xb1, 0xf, 0xf, false);
   v += __builtin_amdgcn_update_dpp(0.f, v, 0x4e, 0xf, 0xf, false);
   v += __builtin_amdgcn_update_dpp(0.f, v, 0x141, 0xf, 0xf, false);
   v += __builtin_amdgcn_update_dpp(0.f, v, 0x140, 0xf, 0xf, false);
-  const int b = __float_as_int(v);
-  return (__int_as_float(__builtin_amdgcn_readlane(b, 0)) +
-          __int_as_float(__builtin_amdgcn_readlane(b, 16))) +
-         (__int_as_float(__builtin_amdgcn_readlane(b, 32)) +
-          __int_as_float(__builtin_amdgcn_readlane(b, 48)));
+  v += __builtin_amdgcn_update_dpp(0.f, v, 0x142, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0.f, v, 0x143, 0xc, 0xf, false);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// A merge group: runs of patch side T in one patch row whose origins lie within `span`
-// columns of the first run's origin lu0 share a register patch of T x Wx cells,
-// Wx = T + span, slot t <-> (t / Wx, t % Wx).  A row's word carries lu0 | lv0 << 8 |
-// T << 16 | du << 24, du being its column offset from the group's origin.
-struct RunGeom {
-  int T, Wx, TT, lu0, lv0;
+// A row's word: window-local patch origin lu0 | lv0 << 8 | patch side T << 16.
+struct Run {
+  int T, TT, lu0, lv0;
 };
-
-// Group key of a row word: its origin moved back by du (no borrow: lu0 >= du).  Without
-// merging (de-gridding, which has no scatter to save) every run is its own group.
-template <bool MERGE>
-__device__ __forceinline__ uint32_t group_key(uint32_t m) {
-  return MERGE ? (m & 0x00ffffffu) - (m >> 24) : (m & 0x00ffffffu);
-}
-
-template <int MK, bool MERGE>
-__device__ __forceinline__ RunGeom decode(uint32_t gkey) {
-  RunGeom r;
-  r.lu0 = gkey & 0xff;
-  r.lv0 = (gkey >> 8) & 0xff;
-  r.T = (gkey >> 16) & 0xff;
-  r.Wx = r.T + (MERGE ? group_span(r.T, MK) : 0);
-  r.TT = r.T * r.Wx;
+__device__ __forceinline__ Run decode(uint32_t m) {
+  Run r;
+  r.lu0 = m & 0xff;
+  r.lv0 = (m >> 8) & 0xff;
+  r.T = (m >> 16) & 0xff;
+  r.TT = r.T * r.T;
   return r;
 }
 
-
-// Patch coordinates (a = row, b = column) of tap t; exact for t < 2^13, T <= 64.
+// Patch coordinates (a = row, b = column) of tap t, invT ~ 1/T to within 2 ulp: exact for
+// t < 2^13, T <= 64, since (t + 1/2)/T stays at least 1/(2T) away from an integer.
 __device__ __forceinline__ void tap_ab(int t, int T, float invT, int& a, int& b) {
   a = (int)(((float)t + 0.5f) * invT);
   b = t - a * T;
 }
 
-// Slots of a row with patch side T and column offset du in its group's register patch:
-// bit k set when slot lane + 64 k holds one of the row's taps; tap[k] its index in the
-// row's stored values (0 for the other slots, an in-bounds dummy).
-template <int MK, bool MERGE>
-__device__ __forceinline__ uint32_t row_slots(uint32_t m, int lane, int (&tap)[MK]) {
-  const int T = (int)((m >> 16) & 0xff), du = MERGE ? (int)(m >> 24) : 0;
-  const int Wx = T + (MERGE ? group_span(T, MK) : 0);
-  const float invW = 1.0f / (float)Wx;
-  uint32_t valid = 0;
-#pragma unroll
-  for (int k = 0; k < MK; ++k) {
-    const int t = lane + 64 * k;
-    int a, b;
-    tap_ab(t, Wx, invW, a, b);
-    const int bb = b - du;
-    const bool ok = t < T * Wx && bb >= 0 && bb < T;
-    tap[k] = ok ? a * T + bb : 0;
-    valid |= ok ? (1u << k) : 0u;
-  }
-  return valid;
+// Buffer resource over the T^2 stored values of one row starting at value index vi.
+template <int STORE>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* vals, int64_t vi,
+                                                           int TT) {
+  const char* p = reinterpret_cast<const char*>(vals) + vi * value_bytes<STORE>();
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), (short)0,
+                                           TT * value_bytes<STORE>(), RSRC_WORD3);
 }
 
-// Load the grid values of a group's register patch (one per lane and slot).
+// Load the grid values of a run's patch (one per lane and slot).  Slots past the patch
+// read its first cell: their stored value is zero, so they add nothing.
 template <int MK>
-__device__ __forceinline__ void load_patch_x(const RunGeom& r, int u0, int v0, int Kx, int Ky,
+__device__ __forceinline__ void load_patch_x(const Run& r, int u0, int v0, int Kx, int Ky,
                                              const float2* __restrict__ X, int lane,
                                              float2 (&xr)[MK]) {
-  const float invW = 1.0f / (float)r.Wx;
-  // branch-free: lanes past the patch read its last cell and zero the value
+  const float invT = __builtin_amdgcn_rcpf((float)r.T);
 #pragma unroll
   for (int k = 0; k < MK; ++k) {
     const int t = lane + 64 * k;
-    const int tc = t < r.TT ? t : r.TT - 1;
     int a, b;
-    tap_ab(tc, r.Wx, invW, a, b);
+    tap_ab(t < r.TT ? t : 0, r.T, invT, a, b);
     const int gu = (u0 + r.lu0 + b) & (Kx - 1);
     const int gv = (v0 + r.lv0 + a) & (Ky - 1);
     xr[k] = X[strip_index(gv, gu, Ky)];
   }
-#pragma unroll
-  for (int k = 0; k < MK; ++k)
-    if (lane + 64 * k >= r.TT) xr[k] = make_float2(0.f, 0.f);
 }
 
-// Add a group's register accumulator into the LDS window: the columns its runs covered,
-// b < bend = T + largest offset (inside the window: that run's patch is).  The window is
-// stored as two planes (real parts, then imaginary parts) so that the consecutive cells
-// of a patch row fall in consecutive banks.
+// Add a run's register accumulator into the LDS window.  The window is stored as two
+// planes (real parts, then imaginary parts) so that the consecutive cells of a patch
+// row fall in consecutive banks.
 template <int MK>
-__device__ __forceinline__ void scatter_run(const RunGeom& r, int bend, int W, int lane,
+__device__ __forceinline__ void scatter_run(const Run& r, int W, int lane,
                                             const float2 (&ac)[MK], float* accf) {
-  const float invW = 1.0f / (float)r.Wx;
+  const float invT = __builtin_amdgcn_rcpf((float)r.T);
   float* acci = accf + W * W;
 #pragma unroll
   for (int k = 0; k < MK; ++k) {
     const int t = lane + 64 * k;
-    int a, b;
-    tap_ab(t < r.TT ? t : 0, r.Wx, invW, a, b);
-    if (t < r.TT && b < bend) {
+    if (t < r.TT) {
+      int a, b;
+      tap_ab(t, r.T, invT, a, b);
       const int li = (r.lv0 + a) * W + (r.lu0 + b);
       atomicAdd(accf + li, ac[k].x);
       atomicAdd(acci + li, ac[k].y);
@@ -232,7 +213,7 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   const WorkItem wi = wis[blockIdx.x];
   constexpr bool GATHER = MODE != 2;
   constexpr bool SCATTER = MODE != 1;
-  constexpr bool MERGE = SCATTER;   // merge groups save scatter work only
+  constexpr int VB = value_bytes<STORE>();
   const Box bx = box_of(wi.box);
   if constexpr (SCATTER) {
     window_zero(accf, W, bx);
@@ -244,7 +225,7 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   const int r0 = wave * seg;
   const int r1 = min(wi.nrows, r0 + seg);
   float2 xr[MK], ac[MK];
-  RunGeom rg{};
+  Run rg{};
   uint32_t cur = 0xffffffffu;
   using Raw = typename RawT<STORE>::type;
   if (r0 >= r1) {
@@ -277,27 +258,25 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
     yv1 = vis[perm[wi.row0 + r0 + min(64 + lane, nseg - 1)]];
   }
   Raw buf[D][MK];
-  uint32_t mb[D], vm[D];                              // row word, slots holding its taps
+  uint32_t mb[D];                                     // row words of the rows in flight
   int rp = r0;                                        // next row to request
-  int64_t vbp = wi.voff + (int64_t)voff[wi.row0 + r0];  // its value offset
-  uint32_t mp = meta_of(r0);                          // its metadata
+  int64_t vbp = wi.voff + (int64_t)voff[wi.row0 + r0];  // its first value
+  uint32_t mp = meta_of(r0);                          // its word
+  auto request = [&](int d) {
+    const int Tn = (int)((mp >> 16) & 0xff);
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc<STORE>(vals, vbp, Tn * Tn);
+#pragma unroll
+    for (int k = 0; k < MK; ++k) buf[d][k] = load_tap<STORE>(rs, (lane + 64 * k) * VB);
+    mb[d] = mp;
+    vbp += (int64_t)Tn * Tn;
+    ++rp;
+    mp = rp < r1 ? meta_of(rp) : 0u;
+  };
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     mb[d] = 0u;
-    vm[d] = 0u;
-    if (rp < r1) {
-      const int Tn = (int)((mp >> 16) & 0xff);
-      int tap[MK];
-      vm[d] = row_slots<MK, MERGE>(mp, lane, tap);
-#pragma unroll
-      for (int k = 0; k < MK; ++k) buf[d][k] = load_raw<STORE>(vals, vbp + tap[k]);
-      mb[d] = mp;
-      vbp += (int64_t)Tn * Tn;
-      ++rp;
-      mp = rp < r1 ? meta_of(rp) : 0u;
-    }
+    if (rp < r1) request(d);
   }
-  int dmax = 0;   // largest column offset of the current group's rows
   for (int rb = r0; rb < r1; rb += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -305,49 +284,32 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
       if (r >= r1) break;
       const int row = wi.row0 + r;
       const uint32_t m = mb[d];
-      const uint32_t valid = vm[d];
       Raw graw[MK];
 #pragma unroll
       for (int k = 0; k < MK; ++k) graw[k] = buf[d][k];
-      const uint32_t gk = group_key<MERGE>(m);
-      const int du = MERGE ? (int)(m >> 24) : 0;
-      if (gk != cur) {
+      if (m != cur) {
         if constexpr (SCATTER) {
-          if (cur != 0xffffffffu) scatter_run<MK>(rg, rg.T + dmax, W, lane, ac, accf);
+          if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
         }
-        cur = gk;
-        rg = decode<MK, MERGE>(gk);
-        dmax = du;
+        cur = m;
+        rg = decode(m);
         if constexpr (GATHER) load_patch_x<MK>(rg, wi.u0, wi.v0, Kx, Ky, X, lane, xr);
 #pragma unroll
         for (int k = 0; k < MK; ++k) ac[k] = make_float2(0.f, 0.f);
-      } else {
-        dmax = du > dmax ? du : dmax;
       }
-      if (rp < r1) {  // request row rp = r + D (branch-free, in-bounds loads)
-        const int Tn = (int)((mp >> 16) & 0xff);
-        int tap[MK];
-        vm[d] = row_slots<MK, MERGE>(mp, lane, tap);
-#pragma unroll
-        for (int k = 0; k < MK; ++k) buf[d][k] = load_raw<STORE>(vals, vbp + tap[k]);
-        mb[d] = mp;
-        vbp += (int64_t)Tn * Tn;
-        ++rp;
-        mp = rp < r1 ? meta_of(rp) : 0u;
-      }
-      // slots outside the row's own patch read an in-bounds dummy and are zeroed: they add
-      // nothing to y and nothing to the group's accumulator
+      if (rp < r1) request(d);   // row r + D (in-bounds: past a row's taps reads zero)
       float2 g[MK];
 #pragma unroll
-      for (int k = 0; k < MK; ++k)
-        g[k] = ((valid >> k) & 1u) ? widen<STORE>(graw[k]) : make_float2(0.f, 0.f);
+      for (int k = 0; k < MK; ++k) g[k] = widen<STORE>(graw[k]);
       float yx, yy;
       if constexpr (GATHER) {
         float sx = 0.f, sy = 0.f;
 #pragma unroll
-        for (int k = 0; k < MK; ++k) {
-          sx += g[k].x * xr[k].x - g[k].y * xr[k].y;
-          sy += g[k].x * xr[k].y + g[k].y * xr[k].x;
+        for (int k = 0; k < MK; ++k) {  // y += g X, one fused multiply-add per term
+          sx = fmaf(g[k].x, xr[k].x, sx);
+          sx = fmaf(-g[k].y, xr[k].y, sx);
+          sy = fmaf(g[k].x, xr[k].y, sy);
+          sy = fmaf(g[k].y, xr[k].x, sy);
         }
         yx = wave_sum_uniform(sx);
         yy = wave_sum_uniform(sy);
@@ -363,14 +325,16 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
       if constexpr (SCATTER) {
 #pragma unroll
         for (int k = 0; k < MK; ++k) {  // += conj(g) y
-          ac[k].x += g[k].x * yx + g[k].y * yy;
-          ac[k].y += g[k].x * yy - g[k].y * yx;
+          ac[k].x = fmaf(g[k].x, yx, ac[k].x);
+          ac[k].x = fmaf(g[k].y, yy, ac[k].x);
+          ac[k].y = fmaf(g[k].x, yy, ac[k].y);
+          ac[k].y = fmaf(-g[k].y, yx, ac[k].y);
         }
       }
     }
   }
   if constexpr (SCATTER) {
-    if (cur != 0xffffffffu) scatter_run<MK>(rg, rg.T + dmax, W, lane, ac, accf);
+    if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
     __syncthreads();
     window_flush(accf, W, bx, wi.u0, wi.v0, Kx, Ky, Y);
   }

@@ -54,13 +54,6 @@ __host__ __device__ inline uint32_t pack_meta(int lu0, int lv0, int T) {
 __host__ __device__ constexpr int class_mk(int c) {
   return c == 0 ? 2 : c == 1 ? 4 : c == 2 ? 7 : c == 3 ? 12 : c == 4 ? 16 : 22;
 }
-// Extra columns a merge group of runs of patch side T may span in a class of mk taps per
-// lane: the group's register patch is T x (T + span) cells, within 64 mk slots.
-__host__ __device__ inline int group_span(int T, int mk) {
-  const int s = (64 * mk) / T - T;
-  return s < 0 ? 0 : (s > 255 ? 255 : s);
-}
-
 // Active uv support of one bin for the column passes: tiles that hold rows, dilated by
 // one tile (the LDS windows reach into neighbours), the column strips under them, and the
 // column groups (col_width columns each) that cover those strips.
