@@ -164,7 +164,9 @@ wf_status wf_briggs_weights(const double* uvw_m, int64_t nrows, const int64_t* c
  * d_vis: complex FP32 [total rows] in [chan][row] caller order. */
 wf_status wf_forward(wf_op* op, const float* d_img, float* d_vis, void* hip_stream);
 
-/* x = Phi^dag y.  d_vis: complex FP32 [total rows]; d_img: complex FP32 [nchan][ny][nx]. */
+/* x = Phi^dag y = sum_p Z_p^dag F^dag G_p^dag y_p (the adjoint of eq. 6, the factors of
+ * eq. 8 applied to data; Sect. 3.3).  d_vis: complex FP32 [total rows] in [chan][row]
+ * caller order; d_img: complex FP32 [nchan][ny][nx]. */
 wf_status wf_adjoint(wf_op* op, const float* d_vis, float* d_img, void* hip_stream);
 
 /* Phi^dag Phi x (eq. 7-8): d_img real FP32 [nchan][ny][nx] -> d_out complex FP32
@@ -204,6 +206,21 @@ typedef struct {
                                DFT sweeps of each residual kernel, 16 nk^3, and its
                                Kaiser-Bessel convolution, 4 J (n' T + T^2)); else 0    */
 } wf_plan_info;
+
+/* The planner alone, on the host (the compute-resource planning of Sect. 3.4, run by the
+ * paper as a tool of its own before the build): for the rows uvw_m (host, [nrows][3]
+ * metres) of one channel at freq_hz it evaluates eq. 5 (the search range), K(P) on the
+ * planning subset, the GPU form of eq. 9 and eq. 10 for every P, and the decision tree
+ * of Fig. 2, exactly as wf_build_operator does.  Fills nbins, strategy (WF_PRECOMP_G,
+ * or WF_PRECOMP_H where no precomputed G fits: the build then settles (b) or (c) from
+ * the exact holographic size), store, Kx, Ky, p_wsclean, p_star, nrows, k_estimate,
+ * mem_model_bytes and cost_model of *out; other fields are zero.  centroids (may be
+ * NULL): the ascending w-bin centroids of the chosen P, cap >= nbins.  Touches no
+ * device.  WF_EINVAL on bad arguments (as wf_build_operator); WF_ENOTSUP when the
+ * strategy option forces precomputed G and none fits. */
+wf_status wf_plan(const double* uvw_m, int64_t nrows, double freq_hz, wf_image_shape shape,
+                  uint64_t memory_budget_bytes, const wf_options* opt, wf_plan_info* out,
+                  double* centroids, int32_t cap);
 
 /* Plan and matrix statistics of channel chan (Sect. 3.4 quantities). */
 wf_status wf_get_plan(const wf_op* op, int32_t chan, wf_plan_info* out);

@@ -18,7 +18,7 @@ from ._lib import (WfImageShape, WfOptions, WfPlanInfo, WfTuneInfo, check, APPLY
 
 _lib.load()
 
-__all__ = ["Operator", "Graph", "Network", "default_options", "briggs_weights"]
+__all__ = ["Operator", "Graph", "Network", "default_options", "briggs_weights", "plan"]
 
 
 def default_options(**kw) -> WfOptions:
@@ -61,6 +61,47 @@ def briggs_weights(uvw_m, freqs_hz, nx, ny, cell_rad, robust, chan_rows=None, na
                                 float(robust), ptr(nat), ptr(fl), ptr(out),
                                 _stream_handle(stream)), "wf_briggs_weights")
     return out
+
+
+def plan(uvw_m, freq_hz, nx, ny, cell_rad, memory_budget=288e9, **opts):
+    """The planner alone on the host (include/wf.h, wf_plan): (plan dict, centroids)."""
+    lib = _lib.load()
+    uvw = np.ascontiguousarray(uvw_m, dtype=np.float64)
+    o = default_options(**opts)
+    info = WfPlanInfo()
+    cent = np.zeros(256, dtype=np.float64)
+    check(lib.wf_plan(uvw.ctypes.data_as(ctypes.c_void_p), ctypes.c_int64(uvw.shape[0]),
+                      float(freq_hz), WfImageShape(int(nx), int(ny), float(cell_rad)),
+                      ctypes.c_uint64(int(memory_budget)), ctypes.byref(o), ctypes.byref(info),
+                      cent.ctypes.data_as(ctypes.c_void_p), cent.size), "wf_plan")
+    d = {k: getattr(info, k) for k, _ in WfPlanInfo._fields_}
+    return d, cent[:d["nbins"]].copy()
+
+
+def _layout(t, name, dtype, shape):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor is not contiguous")
+
+
+def _device_tensors(*specs):
+    """Check device buffers against what the C ABI will read or write through their
+    pointers (the ABI sees no sizes).  Each spec is (tensor, name, dtype, shape, device):
+    a torch tensor of that dtype and exact shape, contiguous, on the operator's device
+    (device None: any HIP device).  Layouts are checked first, then devices; anything
+    wrong raises before a call is made.  Returns the pointers."""
+    for t, name, dtype, shape, _ in specs:
+        _layout(t, name, dtype, shape)
+    for t, name, _, _, device in specs:
+        if t.device.type != "cuda" or (device is not None and t.device.index != device):
+            raise ValueError(f"{name}: tensor on {t.device}, expected cuda:{device}")
+    return [ctypes.c_void_p(t.data_ptr()) for t, *_ in specs]
 
 
 def _stream_handle(stream):
@@ -106,6 +147,8 @@ class Operator:
                 raise ValueError(f"flags must have shape ({self.nrows_total},)")
             self.opts.flags = fl.ctypes.data
         shape = WfImageShape(self.nx, self.ny, float(cell_rad))
+        import torch
+        self.device = torch.cuda.current_device()
         st = self._lib.wf_build_operator(
             uvw.ctypes.data_as(ctypes.c_void_p), ctypes.c_int64(uvw.shape[0]),
             cr.ctypes.data_as(ctypes.c_void_p) if cr is not None else None,
@@ -117,44 +160,50 @@ class Operator:
         check(st, "wf_build_operator")
 
     # ------------------------------------------------------------------ applies
-    def _call(self, name, a, b, stream):
-        check(getattr(self._lib, name)(self._h, ctypes.c_void_p(a.data_ptr()),
-                                       ctypes.c_void_p(b.data_ptr()), _stream_handle(stream)),
-              name)
+    def _img_shape(self):
+        return (self.nchan, self.ny, self.nx)
+
+    def _out(self, out, shape, dtype):
+        import torch
+        if out is None:
+            out = torch.empty(shape, dtype=dtype, device=f"cuda:{self.device}")
+        return out
+
+    def _call(self, name, a, a_spec, b, b_spec, stream):
+        pa, pb = _device_tensors((a, f"{name} input", *a_spec, self.device),
+                                 (b, f"{name} output", *b_spec, self.device))
+        check(getattr(self._lib, name)(self._h, pa, pb, _stream_handle(stream)), name)
 
     def forward(self, img, out=None, stream=None):
         """y = Phi x; img float32 [nchan, ny, nx] -> complex64 [total rows]."""
         import torch
-        if out is None:
-            out = torch.empty(self.nrows_total, dtype=torch.complex64, device=img.device)
-        self._call("wf_forward", img, out, stream)
+        out = self._out(out, (self.nrows_total,), torch.complex64)
+        self._call("wf_forward", img, (torch.float32, self._img_shape()), out,
+                   (torch.complex64, (self.nrows_total,)), stream)
         return out
 
     def adjoint(self, vis, out=None, stream=None):
         """Phi^dag y; vis complex64 [total rows] -> complex64 [nchan, ny, nx]."""
         import torch
-        if out is None:
-            out = torch.empty((self.nchan, self.ny, self.nx), dtype=torch.complex64,
-                              device=vis.device)
-        self._call("wf_adjoint", vis, out, stream)
+        out = self._out(out, self._img_shape(), torch.complex64)
+        self._call("wf_adjoint", vis, (torch.complex64, (self.nrows_total,)), out,
+                   (torch.complex64, self._img_shape()), stream)
         return out
 
     def psf_apply(self, img, out=None, stream=None):
         """Phi^dag Phi x; img float32 [nchan, ny, nx] -> complex64 [nchan, ny, nx]."""
         import torch
-        if out is None:
-            out = torch.empty((self.nchan, self.ny, self.nx), dtype=torch.complex64,
-                              device=img.device)
-        self._call("wf_psf_apply", img, out, stream)
+        out = self._out(out, self._img_shape(), torch.complex64)
+        self._call("wf_psf_apply", img, (torch.float32, self._img_shape()), out,
+                   (torch.complex64, self._img_shape()), stream)
         return out
 
     def psf_apply_re(self, img, out=None, stream=None):
         """Re{Phi^dag Phi x}; img float32 -> float32 [nchan, ny, nx]."""
         import torch
-        if out is None:
-            out = torch.empty((self.nchan, self.ny, self.nx), dtype=torch.float32,
-                              device=img.device)
-        self._call("wf_psf_apply_re", img, out, stream)
+        out = self._out(out, self._img_shape(), torch.float32)
+        self._call("wf_psf_apply_re", img, (torch.float32, self._img_shape()), out,
+                   (torch.float32, self._img_shape()), stream)
         return out
 
     # ------------------------------------------------------------------ introspection
@@ -191,11 +240,12 @@ class Operator:
     def layer_grid(self, chan, bin_, img, out=None, stream=None):
         """X_p = F Z_p x as complex64 [Ky, Kx] (rows = v)."""
         import torch
-        if out is None:
-            out = torch.empty((2 * self.ny, 2 * self.nx), dtype=torch.complex64,
-                              device=img.device)
-        check(self._lib.wf_layer_grid(self._h, chan, bin_, ctypes.c_void_p(img.data_ptr()),
-                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+        gshape = (2 * self.ny, 2 * self.nx)
+        out = self._out(out, gshape, torch.complex64)
+        pi, po = _device_tensors(
+            (img, "wf_layer_grid input", torch.float32, self._img_shape(), self.device),
+            (out, "wf_layer_grid output", torch.complex64, gshape, self.device))
+        check(self._lib.wf_layer_grid(self._h, chan, bin_, pi, po, _stream_handle(stream)),
               "wf_layer_grid")
         return out
 
@@ -213,10 +263,9 @@ class Operator:
     def dirty_image(self, vis, out=None, stream=None):
         """Re{Phi^dag y} as float32 [nchan, ny, nx]."""
         import torch
-        if out is None:
-            out = torch.empty((self.nchan, self.ny, self.nx), dtype=torch.float32,
-                              device=vis.device)
-        self._call("wf_dirty_image", vis, out, stream)
+        out = self._out(out, self._img_shape(), torch.float32)
+        self._call("wf_dirty_image", vis, (torch.complex64, (self.nrows_total,)), out,
+                   (torch.float32, self._img_shape()), stream)
         return out
 
     def op_norm(self, iters=50, stream=None):
@@ -228,9 +277,12 @@ class Operator:
 
     def fb_iterate(self, dirty, x, iters, gamma, lam, stream=None):
         """iters forward-backward iterations (eq. 4) on x in place."""
-        check(self._lib.wf_fb_iterate(self._h, ctypes.c_void_p(dirty.data_ptr()),
-                                      ctypes.c_void_p(x.data_ptr()), int(iters), float(gamma),
-                                      float(lam), _stream_handle(stream)), "wf_fb_iterate")
+        import torch
+        pd, px = _device_tensors(
+            (dirty, "wf_fb_iterate dirty", torch.float32, self._img_shape(), self.device),
+            (x, "wf_fb_iterate x", torch.float32, self._img_shape(), self.device))
+        check(self._lib.wf_fb_iterate(self._h, pd, px, int(iters), float(gamma), float(lam),
+                                      _stream_handle(stream)), "wf_fb_iterate")
         return x
 
     # ------------------------------------------------------------------ batched form
@@ -241,11 +293,17 @@ class Operator:
     def capture(self, kind, inp, out, stream):
         """Capture one apply ('forward', 'adjoint', 'psf', 'psf_re') with fixed buffers
         into a HIP graph; stream must be a created torch.cuda.Stream."""
+        import torch
+        img = (torch.float32, self._img_shape())
+        vis = (torch.complex64, (self.nrows_total,))
+        cimg = (torch.complex64, self._img_shape())
+        spec = {"forward": (img, vis), "adjoint": (vis, cimg), "psf": (img, cimg),
+                "psf_re": (img, img)}[kind]
+        pi, po = _device_tensors((inp, "wf_graph_capture input", *spec[0], self.device),
+                                 (out, "wf_graph_capture output", *spec[1], self.device))
         g = ctypes.c_void_p()
-        check(self._lib.wf_graph_capture(self._h, APPLY[kind], ctypes.c_void_p(inp.data_ptr()),
-                                         ctypes.c_void_p(out.data_ptr()),
-                                         _stream_handle(stream), ctypes.byref(g)),
-              "wf_graph_capture")
+        check(self._lib.wf_graph_capture(self._h, APPLY[kind], pi, po, _stream_handle(stream),
+                                         ctypes.byref(g)), "wf_graph_capture")
         return Graph(self, g)
 
     def latency_enable(self, enable=True):
@@ -259,10 +317,13 @@ class Operator:
         return out
 
     def autotune(self, img, out, reps=3, stream=None) -> dict:
+        import torch
+        pi, po = _device_tensors(
+            (img, "wf_autotune input", torch.float32, self._img_shape(), self.device),
+            (out, "wf_autotune output", torch.float32, self._img_shape(), self.device))
         info = WfTuneInfo()
-        check(self._lib.wf_autotune(self._h, ctypes.c_void_p(img.data_ptr()),
-                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream),
-                                    int(reps), ctypes.byref(info)), "wf_autotune")
+        check(self._lib.wf_autotune(self._h, pi, po, _stream_handle(stream), int(reps),
+                                    ctypes.byref(info)), "wf_autotune")
         return {k: getattr(info, k) for k, _ in WfTuneInfo._fields_}
 
     def close(self):
@@ -332,11 +393,13 @@ class Network:
         """Network inputs [n, 5] and uncapped kernel sides [n] from float64 tensors."""
         import torch
         n = w.numel()
+        dev = w.device.index
+        ptrs = _device_tensors(*((t, f"wf_mlp_inputs {nm}", torch.float64, (n,), dev)
+                                 for t, nm in ((w, "w"), (L, "L"), (fu, "fu"), (fv, "fv"))))
         x = torch.empty((n, 5), dtype=torch.float32, device=w.device)
         nk = torch.empty(n, dtype=torch.int32, device=w.device)
         o = default_options(**opts)
-        check(_lib.load().wf_mlp_inputs(*(ctypes.c_void_p(t.data_ptr()) for t in (w, L, fu, fv)),
-                                        n, ctypes.byref(o), ctypes.c_void_p(x.data_ptr()),
+        check(_lib.load().wf_mlp_inputs(*ptrs, n, ctypes.byref(o), ctypes.c_void_p(x.data_ptr()),
                                         ctypes.c_void_p(nk.data_ptr()), _stream_handle(stream)),
               "wf_mlp_inputs")
         return x, nk
@@ -346,20 +409,29 @@ class Network:
         """Exact thresholded kernels [n, 450] (zeros where the side exceeds 15)."""
         import torch
         n = w.numel()
+        dev = w.device.index
+        pw, pL = _device_tensors((w, "wf_mlp_targets w", torch.float64, (n,), dev),
+                                 (L, "wf_mlp_targets L", torch.float64, (n,), dev))
         t = torch.empty((n, 450), dtype=torch.float32, device=w.device)
         o = default_options(**opts)
-        check(_lib.load().wf_mlp_targets(ctypes.c_void_p(w.data_ptr()),
-                                         ctypes.c_void_p(L.data_ptr()), n, ctypes.byref(o),
-                                         ctypes.c_void_p(t.data_ptr()), _stream_handle(stream)),
-              "wf_mlp_targets")
+        check(_lib.load().wf_mlp_targets(pw, pL, n, ctypes.byref(o), ctypes.c_void_p(t.data_ptr()),
+                                         _stream_handle(stream)), "wf_mlp_targets")
         return t
+
+    @staticmethod
+    def _xt(x, t, name):
+        import torch
+        n = x.shape[0] if hasattr(x, "shape") and len(x.shape) else 0
+        dev = x.device.index if hasattr(x, "device") else None
+        return _device_tensors((x, f"{name} x", torch.float32, (n, Network.NIN), dev),
+                               (t, f"{name} t", torch.float32, (n, Network.NOUT - 1), dev))
 
     def loss_grad(self, x, t, stream=None):
         import torch
+        px, pt = self._xt(x, t, "wf_mlp_loss_grad")
         g = torch.empty(self.num_params(), dtype=torch.float32, device=x.device)
         loss = torch.empty(2, dtype=torch.float32, device=x.device)
-        check(self._lib.wf_mlp_loss_grad(self._h, ctypes.c_void_p(x.data_ptr()),
-                                         ctypes.c_void_p(t.data_ptr()), x.shape[0],
+        check(self._lib.wf_mlp_loss_grad(self._h, px, pt, x.shape[0],
                                          ctypes.c_void_p(g.data_ptr()),
                                          ctypes.c_void_p(loss.data_ptr()),
                                          _stream_handle(stream)), "wf_mlp_loss_grad")
@@ -372,9 +444,9 @@ class Network:
     def train(self, x, t, batch=4096, epochs=10, lr0=1e-3, lr_end=1e-5, seed=5, stream=None):
         """Returns the per-epoch mean (kernel loss, error-output loss)."""
         import torch
+        px, pt = self._xt(x, t, "wf_mlp_train")
         hist = torch.zeros((max(epochs, 1), 2), dtype=torch.float32, device=x.device)
-        check(self._lib.wf_mlp_train(self._h, ctypes.c_void_p(x.data_ptr()),
-                                     ctypes.c_void_p(t.data_ptr()), x.shape[0], batch, epochs,
+        check(self._lib.wf_mlp_train(self._h, px, pt, x.shape[0], batch, epochs,
                                      lr0, lr_end, ctypes.c_uint64(seed),
                                      ctypes.c_void_p(hist.data_ptr()), _stream_handle(stream)),
               "wf_mlp_train")
@@ -383,10 +455,14 @@ class Network:
     def infer(self, x, bf16=2, out=None, stream=None):
         """bf16: 0 FP32 kernels, 1 plain BF16, 2 split BF16 (the build's form)."""
         import torch
+        n = x.shape[0] if hasattr(x, "shape") and len(x.shape) else 0
+        dev = x.device.index if hasattr(x, "device") else None
+        _layout(x, "wf_mlp_infer x", torch.float32, (n, self.NIN))
         if out is None:
-            out = torch.empty((x.shape[0], self.NOUT), dtype=torch.float32, device=x.device)
-        check(self._lib.wf_mlp_infer(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
-                                     int(bf16), ctypes.c_void_p(out.data_ptr()),
+            out = torch.empty((n, self.NOUT), dtype=torch.float32, device=x.device)
+        px, po = _device_tensors((x, "wf_mlp_infer x", torch.float32, (n, self.NIN), dev),
+                                 (out, "wf_mlp_infer out", torch.float32, (n, self.NOUT), dev))
+        check(self._lib.wf_mlp_infer(self._h, px, n, int(bf16), po,
                                      _stream_handle(stream)), "wf_mlp_infer")
         return out
 

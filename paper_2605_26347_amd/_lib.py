@@ -68,6 +68,8 @@ SIGNATURES = {
     "wf_adjoint": (_I32, [_P, _P, _P, _P]),
     "wf_psf_apply": (_I32, [_P, _P, _P, _P]),
     "wf_psf_apply_re": (_I32, [_P, _P, _P, _P]),
+    "wf_plan": (_I32, [_P, _I64, _D, WfImageShape, ctypes.c_uint64,
+                       ctypes.POINTER(WfOptions), ctypes.POINTER(WfPlanInfo), _P, _I32]),
     "wf_get_plan": (_I32, [_P, _I32, ctypes.POINTER(WfPlanInfo)]),
     "wf_get_centroids": (_I32, [_P, _I32, _P, _I32]),
     "wf_get_bin_rows": (_I32, [_P, _I32, _P, _I32]),

@@ -611,24 +611,6 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
       return fail(WF_EBUDGET, "no strategy fits the memory budget: the on-the-fly row data "
                               "alone needs " + std::to_string(meta_bytes / 1e9) + " GB");
   }
-  // consecutive runs of a row group with the same patch side and patch row whose origins
-  // lie within the class's spare columns form a merge group: the row kernels hold one
-  // register patch of T x (T + span) cells for it (one gather of X, one scatter).  Each
-  // row records its column offset from the group's first run in bits 24..31 of its word.
-  for (const RowGroup& g : ch.groups) {
-    const int mk = class_mk(g.cls);
-    int gT = -1, glv = -1, glu = 0;
-    for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) {
-      const uint32_t m = meta[r];
-      const int lu = (int)(m & 0xff), lv = (int)((m >> 8) & 0xff), T = (int)((m >> 16) & 0xff);
-      if (T != gT || lv != glv || lu < glu || lu - glu > group_span(T, mk)) {
-        gT = T;
-        glv = lv;
-        glu = lu;
-      }
-      meta[r] |= (uint32_t)(lu - glu) << 24;
-    }
-  }
   std::vector<WorkItem> wis;
   ch.max_rows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
   split_items(ch, trow.data(), meta.data(), ch.max_rows, wis, voff.data(), row_wi.data());
@@ -1639,6 +1621,62 @@ static wf_status wf_psf_apply_re_body(wf_op* op, const float* d_img, float* d_ou
 
 wf_status wf_psf_apply_re(wf_op* op, const float* d_img, float* d_out, void* stream) {
   return guarded([&] { return wf_psf_apply_re_body(op, d_img, d_out, stream); });
+}
+
+wf_status wf_plan(const double* uvw_m, int64_t nrows, double freq_hz, wf_image_shape shape,
+                  uint64_t memory_budget_bytes, const wf_options* opt_in, wf_plan_info* out,
+                  double* centroids, int32_t cap) {
+  return guarded([&]() -> wf_status {
+    g_err.clear();
+    if (!out) return fail(WF_EINVAL, "out is null");
+    if (nrows <= 0 || !uvw_m) return fail(WF_EINVAL, "need at least one row");
+    if (!(freq_hz > 0) || !std::isfinite(freq_hz)) return fail(WF_EINVAL, "frequency must be positive");
+    if (!is_pow2(shape.nx) || !is_pow2(shape.ny) || shape.nx < 8 || shape.ny < 8 ||
+        shape.nx > 8192 || shape.ny > 8192)
+      return fail(WF_EINVAL, "nx, ny must be powers of two in [8, 8192]");
+    if (!(shape.cell_rad > 0.0) || !std::isfinite(shape.cell_rad))
+      return fail(WF_EINVAL, "cell must be positive");
+    wf_options opt;
+    if (opt_in) opt = *opt_in;
+    else wf_default_options(&opt);
+    if (opt.oversample != 2) return fail(WF_EINVAL, "oversample must be 2");
+    if (opt.J < 3 || opt.J > 15 || (opt.J % 2) == 0) return fail(WF_EINVAL, "J must be odd in [3,15]");
+    if (opt.smax < 1 || opt.smax > 31 || (opt.smax % 2) == 0)
+      return fail(WF_EINVAL, "smax must be odd in [1,31]");
+    if (opt.nbins < 0 || opt.nbins > 255) return fail(WF_EINVAL, "nbins must be in [0,255]");
+    if (!(opt.alpha > 0) || !(opt.plan_fraction > 0) || opt.plan_fraction > 1 ||
+        !(opt.budget_fraction > 0) || opt.budget_fraction > 1)
+      return fail(WF_EINVAL, "bad alpha / plan / budget fraction");
+    const double Lx = shape.nx * shape.cell_rad, Ly = shape.ny * shape.cell_rad;
+    if (Lx * Lx + Ly * Ly >= 1.0) return fail(WF_EINVAL, "field too wide: 2L^2 >= 1");
+    for (int64_t k = 0; k < 3 * nrows; ++k)
+      if (!std::isfinite(uvw_m[k])) return fail(WF_EINVAL, "non-finite uvw coordinate");
+    const double scale = freq_hz / C_LIGHT;
+    std::vector<double> w(nrows);
+    for (int64_t k = 0; k < nrows; ++k) w[k] = uvw_m[3 * k + 2] * scale;
+    PlanResult pr;
+    std::string perr;
+    if (plan_channel(w.data(), nrows, shape, opt, memory_budget_bytes, &pr, &perr) != 0)
+      return fail(WF_ENOTSUP, perr);
+    if (centroids && cap < (int32_t)pr.centroids.size())
+      return fail(WF_EINVAL, "centroid capacity too small");
+    wf_plan_info in{};
+    in.nchan = 1;
+    in.nbins = pr.P;
+    in.strategy = pr.strategy;
+    in.store = opt.store;
+    in.Kx = 2 * shape.nx;
+    in.Ky = 2 * shape.ny;
+    in.p_wsclean = pr.p_wsclean;
+    in.p_star = pr.p_star;
+    in.nrows = nrows;
+    in.k_estimate = pr.k_est;
+    in.mem_model_bytes = pr.mem_model;
+    in.cost_model = pr.cost_model;
+    *out = in;
+    if (centroids) std::copy(pr.centroids.begin(), pr.centroids.end(), centroids);
+    return WF_OK;
+  });
 }
 
 wf_status wf_get_plan(const wf_op* op, int32_t chan, wf_plan_info* out) {

@@ -1,0 +1,79 @@
+"""Parity of the library's planner (host C++, wf_plan) with the oracle planner (Sect.
+3.4: eq. 5 search range, K(P) on the planning subset, GPU form of eq. 9, eq. 10 and the
+decision tree of Fig. 2) on the same seeded inputs.  Budgets are chosen from the
+oracle's own table so that the tree lands on P* itself, on the feasible P nearest to
+P*, and on the branch where no precomputed G fits.  Runs on the CPU (no device)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import wfsynth as ws
+from oracle import planner
+from oracle.operator import C_LIGHT
+
+wf = pytest.importorskip("paper_2605_26347_amd")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def wide():
+    obs = ws.widefield(n=1024, nvis=200_000, fov_deg=2.0, sky=False)
+    w = obs.uvw_m[:, 2] * (obs.freqs_hz[0] / C_LIGHT)
+    return obs, w
+
+
+def compare(obs, w, budget, store):
+    ref = planner.plan(w, obs.nx, obs.ny, obs.cell_rad, budget, store=store)
+    got, cent = wf.plan(obs.uvw_m, obs.freqs_hz[0], obs.nx, obs.ny, obs.cell_rad,
+                        memory_budget=budget, store=store)
+    assert got["p_wsclean"] == int(math.ceil(ref["P_wsclean"]))
+    assert got["p_star"] == ref["P_star"]
+    assert got["nbins"] == ref["P"]
+    row = [r for r in ref["table"] if r[0] == ref["P"]][0]
+    assert got["k_estimate"] == pytest.approx(row[1], rel=1e-12)
+    assert got["mem_model_bytes"] == pytest.approx(row[3], rel=1e-12)
+    assert got["cost_model"] == pytest.approx(row[4], rel=1e-12)
+    strategy = {1: "G", 2: "H"}[got["strategy"]]
+    assert strategy == ("G" if ref["strategy"] == "G" else "H")
+    from oracle import wbins
+    mask = wbins.plan_subset_mask(w.size, 0.01, 0)
+    assert np.allclose(cent, wbins.kmeans_1d(w[mask], ref["P"]), rtol=1e-12, atol=1e-9)
+    return ref, got
+
+
+def test_branch_a_ample_budget(wide):
+    obs, w = wide
+    ref, got = compare(obs, w, 288e9, "f32")
+    assert ref["strategy"] == "G"
+    # here P* itself leaves more than 1% of the rows above the kernel-side cap, so the
+    # tree takes the feasible P nearest to it
+    assert got["nbins"] >= ref["P_star"]
+
+
+def test_branch_a_nearest_feasible_p(wide):
+    """Budget between the smallest feasible m_G and m_G of the ample-budget choice: the
+    tree moves to the feasible P nearest to P* under the smaller budget (Fig. 2 branch
+    (a), 'or the nearest P fitting m*')."""
+    obs, w = wide
+    ref = planner.plan(w, obs.nx, obs.ny, obs.cell_rad, 288e9, store="f16")
+    tab = {r[0]: r for r in ref["table"]}
+    p0 = ref["P"]
+    mems = sorted(r[3] for r in ref["table"] if r[2] >= planner.OK_FRACTION)
+    target = [m for m in mems if m < tab[p0][3]]
+    assert target, "the ample-budget choice already has the smallest m_G"
+    budget = target[len(target) // 2] / 0.65 * (1 + 1e-9)
+    r2, got = compare(obs, w, budget, "f16")
+    assert r2["strategy"] == "G" and got["nbins"] != p0
+
+
+def test_no_g_fits_goes_to_stabilised_p(wide):
+    """Budget below every m_G: branches (b)/(c) at the P where m_G stabilises."""
+    obs, w = wide
+    ref = planner.plan(w, obs.nx, obs.ny, obs.cell_rad, 288e9, store="bf16")
+    budget = min(r[3] for r in ref["table"]) / 0.65 * 0.5
+    r2, got = compare(obs, w, budget, "bf16")
+    assert r2["strategy"] != "G" and got["strategy"] == 2
