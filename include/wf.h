@@ -86,7 +86,9 @@ typedef struct {
   double plan_fraction;    /* planning / clustering subset fraction, default 0.01     */
   double budget_fraction;  /* share of memory_budget for the sparse matrix, 0.65      */
   uint64_t seed;           /* SplitMix64 state for the subset draw                    */
-  int32_t tile;            /* grid tile side of the fused G^dag G kernel (0 = auto)   */
+  int32_t tile;            /* grid tile side of the fused G^dag G kernel (0 = auto:
+                              32); a power of two with tile + J + smax - 2 <= 101, so
+                              that an item's FP64 accumulator fits one LDS (160 KiB)   */
   int32_t max_rows_per_item; /* rows per work item, <= 1024 (0 = auto: 1024)           */
   int32_t branches;        /* concurrent branches of an apply, <= 16 (0 = auto: one per
                               channel up to 4; a single channel runs on one branch)   */

@@ -138,30 +138,11 @@ __device__ __forceinline__ void load_patch_x(const Run& r, int u0, int v0, int K
   }
 }
 
-// Add a run's register accumulator into the LDS window.  The window is stored as two
-// planes (real parts, then imaginary parts) so that the consecutive cells of a patch
-// row fall in consecutive banks.
-template <int MK>
-__device__ __forceinline__ void scatter_run(const Run& r, int W, int lane,
-                                            const float2 (&ac)[MK], float* accf) {
-  const float invT = __builtin_amdgcn_rcpf((float)r.T);
-  float* acci = accf + W * W;
-#pragma unroll
-  for (int k = 0; k < MK; ++k) {
-    const int t = lane + 64 * k;
-    if (t < r.TT) {
-      int a, b;
-      tap_ab(t, r.T, invT, a, b);
-      const int li = (r.lv0 + a) * W + (r.lu0 + b);
-      atomicAdd(accf + li, ac[k].x);
-      atomicAdd(acci + li, ac[k].y);
-    }
-  }
-}
-
 // The work item's bounding box of patch cells in its window (packed by the host as
-// origin u, origin v, width, height, 8 bits each): only these cells are cleared and
-// flushed, which matters when an item holds few rows.
+// origin u, origin v, width, height, 8 bits each).  The LDS accumulator holds exactly
+// this box, as two planes of FP64 (real parts, then imaginary parts): LDS float atomics
+// in FP64 issue an order of magnitude faster than in FP32 on CDNA4, and the wider sums
+// cost no precision.  Only these cells are cleared and flushed.
 struct Box {
   int u0, v0, w, h;
 };
@@ -170,23 +151,37 @@ __device__ __forceinline__ Box box_of(int32_t packed) {
   return Box{(int)(b & 0xff), (int)((b >> 8) & 0xff), (int)((b >> 16) & 0xff), (int)(b >> 24)};
 }
 
-__device__ __forceinline__ void window_zero(float* accf, int W, const Box& bx) {
-  const int n = bx.w * bx.h;
-  for (int c = threadIdx.x; c < n; c += GNT) {
-    const int a = c / bx.w, b = c - a * bx.w;
-    const int o = (bx.v0 + a) * W + bx.u0 + b;
-    accf[o] = 0.f;
-    accf[W * W + o] = 0.f;
+// Add a run's register accumulator into the box accumulator.
+template <int MK>
+__device__ __forceinline__ void scatter_run(const Run& r, const Box& bx, int lane,
+                                            const float2 (&ac)[MK], double* acc) {
+  const float invT = __builtin_amdgcn_rcpf((float)r.T);
+  double* acci = acc + bx.w * bx.h;
+  const int base = (r.lv0 - bx.v0) * bx.w + (r.lu0 - bx.u0);
+#pragma unroll
+  for (int k = 0; k < MK; ++k) {
+    const int t = lane + 64 * k;
+    if (t < r.TT) {
+      int a, b;
+      tap_ab(t, r.T, invT, a, b);
+      const int li = base + a * bx.w + b;
+      atomicAdd(acc + li, (double)ac[k].x);
+      atomicAdd(acci + li, (double)ac[k].y);
+    }
   }
 }
-__device__ __forceinline__ void window_flush(const float* accf, int W, const Box& bx, int u0,
-                                             int v0, int Kx, int Ky, float2* __restrict__ Y) {
+
+__device__ __forceinline__ void window_zero(double* acc, const Box& bx) {
+  const int n = bx.w * bx.h;
+  for (int c = threadIdx.x; c < 2 * n; c += GNT) acc[c] = 0.0;
+}
+__device__ __forceinline__ void window_flush(const double* acc, const Box& bx, int u0, int v0,
+                                             int Kx, int Ky, float2* __restrict__ Y) {
   const int n = bx.w * bx.h;
   for (int c = threadIdx.x; c < n; c += GNT) {
-    const int a = c / bx.w, b = c - a * bx.w;
-    const int o = (bx.v0 + a) * W + bx.u0 + b;
-    const float2 v = make_float2(accf[o], accf[W * W + o]);
+    const float2 v = make_float2((float)acc[c], (float)acc[n + c]);
     if (v.x != 0.f || v.y != 0.f) {
+      const int a = c / bx.w, b = c - a * bx.w;
       const int gu = (u0 + bx.u0 + b) & (Kx - 1);
       const int gv = (v0 + bx.v0 + a) & (Ky - 1);
       float2* p = Y + strip_index(gv, gu, Ky);
@@ -205,9 +200,8 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
                                               const void* __restrict__ vals,
                                               const float2* __restrict__ X,
                                               float2* __restrict__ Y,
-                                              float2* __restrict__ vis, int Kx, int Ky,
-                                              int W) {
-  extern __shared__ float accf[];
+                                              float2* __restrict__ vis, int Kx, int Ky) {
+  extern __shared__ double acc[];
   // Items are ordered largest first and dealt round-robin over the XCDs by the hardware,
   // which spreads the dense uv core (many items) evenly and schedules longest first.
   const WorkItem wi = wis[blockIdx.x];
@@ -216,7 +210,7 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   constexpr int VB = value_bytes<STORE>();
   const Box bx = box_of(wi.box);
   if constexpr (SCATTER) {
-    window_zero(accf, W, bx);
+    window_zero(acc, bx);
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
@@ -231,7 +225,7 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   if (r0 >= r1) {
     if constexpr (SCATTER) {
       __syncthreads();
-      window_flush(accf, W, bx, wi.u0, wi.v0, Kx, Ky, Y);
+      window_flush(acc, bx, wi.u0, wi.v0, Kx, Ky, Y);
     }
     return;
   }
@@ -241,7 +235,10 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   // the LDS/scalar counter that the window atomics use.  Value offsets are the running
   // sum of T^2 inside the item; the values of row r + D are requested (after a new run's
   // grid values) before row r is reduced.
-  constexpr int D = MK <= 4 ? 4 : (MK <= 7 ? 2 : 1);
+  constexpr int D = MK <= 4 ? 4 : (MK <= 16 || STORE != WF_STORE_F32 ? 2 : 1);
+  // the next run's grid values are gathered while the current run is reduced (one run
+  // ahead), where registers allow
+  constexpr bool PREFETCH = GATHER && (MK <= 12 || (MK <= 16 && STORE != WF_STORE_F32));
   const int nseg = r1 - r0;
   const uint32_t* __restrict__ mrow = meta + wi.row0 + r0;
   const uint32_t mv0 = mrow[min(lane, nseg - 1)];
@@ -258,6 +255,8 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
     yv1 = vis[perm[wi.row0 + r0 + min(64 + lane, nseg - 1)]];
   }
   Raw buf[D][MK];
+  float2 xn[PREFETCH ? MK : 1];                       // grid values of the next run
+  uint32_t nm = 0xffffffffu;                          // ... and its row word
   uint32_t mb[D];                                     // row words of the rows in flight
   int rp = r0;                                        // next row to request
   int64_t vbp = wi.voff + (int64_t)voff[wi.row0 + r0];  // its first value
@@ -289,11 +288,24 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
       for (int k = 0; k < MK; ++k) graw[k] = buf[d][k];
       if (m != cur) {
         if constexpr (SCATTER) {
-          if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
+          if (cur != 0xffffffffu) scatter_run<MK>(rg, bx, lane, ac, acc);
         }
         cur = m;
         rg = decode(m);
-        if constexpr (GATHER) load_patch_x<MK>(rg, wi.u0, wi.v0, Kx, Ky, X, lane, xr);
+        if constexpr (PREFETCH) {
+          if (nm == m) {
+#pragma unroll
+            for (int k = 0; k < MK; ++k) xr[k] = xn[k];
+          } else {
+            load_patch_x<MK>(rg, wi.u0, wi.v0, Kx, Ky, X, lane, xr);
+          }
+          int q = r + 1;
+          while (q < r1 && meta_of(q) == m) ++q;
+          nm = q < r1 ? meta_of(q) : 0xffffffffu;
+          if (q < r1) load_patch_x<MK>(decode(nm), wi.u0, wi.v0, Kx, Ky, X, lane, xn);
+        } else if constexpr (GATHER) {
+          load_patch_x<MK>(rg, wi.u0, wi.v0, Kx, Ky, X, lane, xr);
+        }
 #pragma unroll
         for (int k = 0; k < MK; ++k) ac[k] = make_float2(0.f, 0.f);
       }
@@ -334,9 +346,9 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
     }
   }
   if constexpr (SCATTER) {
-    if (cur != 0xffffffffu) scatter_run<MK>(rg, W, lane, ac, accf);
+    if (cur != 0xffffffffu) scatter_run<MK>(rg, bx, lane, ac, acc);
     __syncthreads();
-    window_flush(accf, W, bx, wi.u0, wi.v0, Kx, Ky, Y);
+    window_flush(acc, bx, wi.u0, wi.v0, Kx, Ky, Y);
   }
 }
 
@@ -349,26 +361,36 @@ static hipError_t set_lds(K kern, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Largest (odd) patch side of a class of MK taps per lane.
+constexpr int class_tmax(int mk) {
+  int t = 1;
+  while ((t + 2) * (t + 2) <= 64 * mk) t += 2;
+  return t;
+}
+
 template <int STORE, int MK, int MODE>
 static hipError_t launch_one(const WorkItem* wi, int nwi, const uint32_t* meta,
                              const uint32_t* voff, const int32_t* perm, const void* vals,
-                             const float2* X, float2* Y, float2* vis, int Kx, int Ky, int win,
+                             const float2* X, float2* Y, float2* vis, int Kx, int Ky, int tile,
                              hipStream_t s) {
-  const size_t lds = MODE == 1 ? 0 : (size_t)win * win * sizeof(float2);
+  // the box accumulator of an item: rows' cells lie in one tile and their patches of
+  // side <= class_tmax reach tile + side - 1 cells per axis; two FP64 planes
+  const size_t side = (size_t)tile + class_tmax(MK) - 1;
+  const size_t lds = MODE == 1 ? 0 : side * side * 2 * sizeof(double);
   hipError_t e = set_lds(k_rows<STORE, MK, MODE>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_rows<STORE, MK, MODE>), dim3(nwi), dim3(GNT), lds, s, wi, meta, voff,
-                     perm, vals, X, Y, vis, Kx, Ky, win);
+                     perm, vals, X, Y, vis, Kx, Ky);
   return hipGetLastError();
 }
 
 template <int STORE, int MODE>
 static hipError_t launch_cls(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
                              const uint32_t* voff, const int32_t* perm, const void* vals,
-                             const float2* X, float2* Y, float2* vis, int Kx, int Ky, int win,
+                             const float2* X, float2* Y, float2* vis, int Kx, int Ky, int tile,
                              hipStream_t s) {
 #define WF_ONE(MK) \
-  launch_one<STORE, MK, MODE>(wi, nwi, meta, voff, perm, vals, X, Y, vis, Kx, Ky, win, s)
+  launch_one<STORE, MK, MODE>(wi, nwi, meta, voff, perm, vals, X, Y, vis, Kx, Ky, tile, s)
   switch (cls) {
     case 0: return WF_ONE(2);
     case 1: return WF_ONE(4);
@@ -384,26 +406,26 @@ template <int MODE>
 static hipError_t launch_mode(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
                               const uint32_t* voff, const int32_t* perm, const void* vals,
                               wf_store store, const float2* X, float2* Y, float2* vis, int Kx,
-                              int Ky, int win, hipStream_t s) {
+                              int Ky, int tile, hipStream_t s) {
   if (nwi <= 0) return hipSuccess;
   switch (store) {
     case WF_STORE_F32:
       return launch_cls<WF_STORE_F32, MODE>(cls, wi, nwi, meta, voff, perm, vals, X, Y, vis,
-                                            Kx, Ky, win, s);
+                                            Kx, Ky, tile, s);
     case WF_STORE_F16:
       return launch_cls<WF_STORE_F16, MODE>(cls, wi, nwi, meta, voff, perm, vals, X, Y, vis,
-                                            Kx, Ky, win, s);
+                                            Kx, Ky, tile, s);
     default:
       return launch_cls<WF_STORE_BF16, MODE>(cls, wi, nwi, meta, voff, perm, vals, X, Y, vis,
-                                             Kx, Ky, win, s);
+                                             Kx, Ky, tile, s);
   }
 }
 
 hipError_t launch_gtg(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
                       const uint32_t* voff, const void* vals, wf_store store, const float2* X,
-                      float2* Y, int Kx, int Ky, int win, hipStream_t s) {
+                      float2* Y, int Kx, int Ky, int tile, hipStream_t s) {
   return launch_mode<0>(cls, wi, nwi, meta, voff, nullptr, vals, store, X, Y, nullptr, Kx, Ky,
-                        win, s);
+                        tile, s);
 }
 
 hipError_t launch_degrid(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
@@ -416,10 +438,10 @@ hipError_t launch_degrid(int cls, const WorkItem* wi, int nwi, const uint32_t* m
 
 hipError_t launch_grid(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
                        const uint32_t* voff, const int32_t* perm, const void* vals,
-                       wf_store store, const float2* vis, float2* Y, int Kx, int Ky, int win,
+                       wf_store store, const float2* vis, float2* Y, int Kx, int Ky, int tile,
                        hipStream_t s) {
   return launch_mode<2>(cls, wi, nwi, meta, voff, perm, vals, store, nullptr, Y,
-                        const_cast<float2*>(vis), Kx, Ky, win, s);
+                        const_cast<float2*>(vis), Kx, Ky, tile, s);
 }
 
 }  // namespace wf

@@ -160,8 +160,8 @@ struct ProfScope {
   }
 };
 
-// Split the channel's row groups into work items of at most maxrows rows and 2^20
-// values (the row kernels keep a wavefront's metadata for at most 128 rows in
+// Split the channel's row groups into work items of at most maxrows rows and 2^17
+// values (so that the classes of wide patches, few rows each, still fill the device) (the row kernels keep a wavefront's metadata for at most 128 rows in
 // registers), then order them by (bin, patch class) -- one launch per class -- with the
 // largest items of a launch first so that the hardware's in-order dispatch starts the
 // longest work first.  trow: patch side of each sorted row.  Writes each row's value
@@ -170,7 +170,7 @@ struct ProfScope {
 // each chunk's item range per class.
 void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t maxrows,
                  std::vector<WorkItem>& wis, uint32_t* voff, int32_t* row_wi) {
-  const int64_t maxtaps = 1 << 20;
+  const int64_t maxtaps = 1 << 17;
   const bool chunked = !ch.gchunk.empty();
   std::vector<WorkItem> w0;
   std::vector<int> wcls, wck;
@@ -1028,11 +1028,11 @@ wf_status otf_bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, in
       } else if (kind == WF_APPLY_ADJOINT) {
         WF_HIP(launch_grid(c, items, n, (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
                            (const int32_t*)ch.perm.p, vals, store, (const float2*)in, L.Y,
-                           op->Kx, op->Ky, op->win, L.s));
+                           op->Kx, op->Ky, op->tile, L.s));
       } else {
         ProfScope ps(prof_of(op, 0), L.s);
         WF_HIP(launch_gtg(c, items, n, (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
-                          vals, store, L.X, L.Y, op->Kx, op->Ky, op->win, L.s));
+                          vals, store, L.X, L.Y, op->Kx, op->Ky, op->tile, L.s));
       }
     }
   }
@@ -1067,7 +1067,7 @@ wf_status bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
       if (n == 0) continue;
       WF_HIP(launch_grid(c, wk + ch.cls_wi0[p * NCLS + c], n, (const uint32_t*)ch.meta.p,
                          (const uint32_t*)ch.voff.p, (const int32_t*)ch.perm.p, ch.vals.p,
-                         op->opt.store, (const float2*)in, L.Y, op->Kx, op->Ky, op->win, L.s));
+                         op->opt.store, (const float2*)in, L.Y, op->Kx, op->Ky, op->tile, L.s));
     }
     return layer_adjoint(op, L, out, wp, first ? 0 : 1, &pr);
   }
@@ -1086,7 +1086,7 @@ wf_status bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
       if (n == 0) continue;
       WF_HIP(launch_gtg(c, wk + ch.cls_wi0[p * NCLS + c], n, (const uint32_t*)ch.meta.p,
                         (const uint32_t*)ch.voff.p, ch.vals.p, op->opt.store, L.X, L.Y,
-                        op->Kx, op->Ky, op->win, L.s));
+                        op->Kx, op->Ky, op->tile, L.s));
     }
   }
   const int mode = (kind == WF_APPLY_PSF_RE ? 2 : 0) + (first ? 0 : 1);
@@ -1492,6 +1492,10 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
     op->win = tile + 2 * op->halo;
     if (op->win > 255 || (op->Kx / tile) > 1024 || (op->Ky / tile) > 1024)
       return fail(WF_EINVAL, "tile/halo too large");
+    // an item's FP64 accumulator in LDS: (tile + largest patch side - 1)^2 cells x 16 B
+    if ((size_t)op->win * op->win * 16 > 160 * 1024)
+      return fail(WF_EINVAL, "tile too large for the LDS accumulator (tile + J + smax - 2 must "
+                             "not exceed 101)");
     KernelParams& kp = op->kp;
     kp.Lx = Lx;
     kp.Ly = Ly;

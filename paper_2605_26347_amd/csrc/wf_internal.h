@@ -258,17 +258,18 @@ hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const f
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
                            int mode, const uint32_t* smask, hipStream_t s);
 
-// Row kernels over the work items of one patch-size class `cls`.
+// Row kernels over the work items of one patch-size class `cls`; `tile` is the grid
+// tile side of the sort (it sizes each item's LDS accumulator).
 hipError_t launch_gtg(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
                       const uint32_t* voff, const void* vals, wf_store store, const float2* X,
-                      float2* Y, int Kx, int Ky, int win, hipStream_t s);
+                      float2* Y, int Kx, int Ky, int tile, hipStream_t s);
 hipError_t launch_degrid(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
                          const uint32_t* voff, const int32_t* perm, const void* vals,
                          wf_store store, const float2* X, float2* vis, int Kx, int Ky,
                          hipStream_t s);
 hipError_t launch_grid(int cls, const WorkItem* wi, int nwi, const uint32_t* meta,
                        const uint32_t* voff, const int32_t* perm, const void* vals,
-                       wf_store store, const float2* vis, float2* Y, int Kx, int Ky, int win,
+                       wf_store store, const float2* vis, float2* Y, int Kx, int Ky, int tile,
                        hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t nfloats, hipStream_t s);
 // out[idx[i]] = 0 for the n complex values listed (flagged visibilities).
