@@ -77,3 +77,17 @@ def test_no_g_fits_goes_to_stabilised_p(wide):
     budget = min(r[3] for r in ref["table"]) / 0.65 * 0.5
     r2, got = compare(obs, w, budget, "bf16")
     assert r2["strategy"] != "G" and got["strategy"] == 2
+
+
+def test_headline_plan_reproduced():
+    """The benchmark's plan (4096^2, 3 deg, 50M rows, 288 GB, FP16), against the oracle
+    planner's result stored by tests/golden/make_planner_headline.py."""
+    g = json.load(open(os.path.join(GOLDEN, "planner_headline.json")))
+    obs = ws.precision_form(sky=False)
+    got, _ = wf.plan(obs.uvw_m, obs.freqs_hz[0], obs.nx, obs.ny, obs.cell_rad,
+                     memory_budget=288e9, store="f16")
+    assert got["nbins"] == g["P"] and got["p_star"] == g["P_star"]
+    assert got["p_wsclean"] == g["P_wsclean_ceil"]
+    assert got["strategy"] == 1 and g["strategy"] == "G"
+    assert got["k_estimate"] == pytest.approx(g["K_at_P"], rel=1e-12)
+    assert got["cost_model"] == pytest.approx(g["cost_at_P"], rel=1e-12)

@@ -230,6 +230,32 @@ def precision_form(n: int = 4096, nvis: int = 50_000_000, fov_deg: float = 3.0,
                        n, n, cell, s)
 
 
+FULLSIZE_P = 22            # w-bins of the benchmark's plan, forced in the parity cases
+FULLSIZE_NPIX = 32768      # sampled output pixels of the full-size parity cases
+FULLSIZE_NROWS = 20000     # sampled visibilities of the full-size parity cases
+
+
+def fullsize_case(name: str):
+    """Inputs of the full-size parity cases of the precision form, (uvw_m, freq_hz, n,
+    cell_rad): 'crop512' = all 50M rows on the central 512^2 of the 4096^2 / 3 degree image
+    (same cell); 'sub4096' = the full 4096^2 image with a seeded 300k-row subset."""
+    obs = precision_form(sky=False)
+    if name == "crop512":
+        return obs.uvw_m, float(obs.freqs_hz[0]), 512, obs.cell_rad
+    if name != "sub4096":
+        raise ValueError(name)
+    rows = seeded_subset(obs.uvw_m.shape[0], 300_000, 7)
+    return np.ascontiguousarray(obs.uvw_m[rows]), float(obs.freqs_hz[0]), 4096, obs.cell_rad
+
+
+def fullsize_samples(n: int, nrows: int):
+    """Seeded sorted samples of output pixels (flat [ny*nx] indices) and of rows."""
+    rng = np.random.default_rng(11)
+    pix = np.sort(rng.choice(n * n, FULLSIZE_NPIX, replace=False))
+    rows = np.sort(rng.choice(nrows, FULLSIZE_NROWS, replace=False))
+    return pix, rows
+
+
 def learned_form(n: int = 4096, nvis: int = 20_000_000, fov_deg: float = 3.0,
                  sky: bool = True) -> Observation:
     """4096^2 over 3 degrees, 20M rows: a seeded subset of the 16 h sample set of the
