@@ -157,6 +157,27 @@ wf_status wf_briggs_weights(const double* uvw_m, int64_t nrows, const int64_t* c
                             double robust, const float* natural, const uint8_t* flags,
                             float* out, void* hip_stream);
 
+/* Allocation-free variant of wf_briggs_weights, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  One channel, every array already on the device:
+ *  d_uvw_m    device FP64 [nrows][3] metres; freq_hz the channel's frequency.
+ *  d_natural  device FP32 [nrows] natural weights (NULL = ones);
+ *  d_flags    device [nrows] (NULL = none): flagged samples get 0 and are left out.
+ *  d_out      device FP32 [nrows] operator weights sqrt(w'_k), as wf_briggs_weights.
+ * The density grid and the two sums live in a static device array of the library
+ * (WF_BRIGGS_NOALLOC_MAX_CELLS + 2 doubles, 32 MiB, one per device, held until the
+ * process ends); nx * ny beyond WF_BRIGGS_NOALLOC_MAX_CELLS is WF_EINVAL.  Nothing is
+ * allocated; the array is cleared by a kernel at every call.  Asynchronous on
+ * hip_stream: f^2 is formed on the device, nothing is read back.  Calls that overlap
+ * on one device share the array and race: order them on one stream.  Device data is
+ * not validated (non-finite coordinates give unspecified weights, never an access out
+ * of bounds).  Errors: WF_EINVAL (host-side arguments), WF_EHIP. */
+#define WF_BRIGGS_NOALLOC_MAX_CELLS 4194304
+wf_status wf_briggs_weights_noalloc(const double* d_uvw_m, int64_t nrows, double freq_hz,
+                                    wf_image_shape shape, double robust,
+                                    const float* d_natural, const uint8_t* d_flags,
+                                    float* d_out, void* hip_stream);
+
 /* The four apply calls below return WF_EINVAL for a null handle or buffer, WF_ENOTSUP for
  * wf_forward / wf_adjoint on a holographic operator (it holds H_p only), and WF_EHIP when
  * a HIP call fails (work already queued on the stream may then be partial).  They

@@ -62,6 +62,8 @@ SIGNATURES = {
     "wf_default_options": (None, [ctypes.POINTER(WfOptions)]),
     "wf_briggs_weights": (_I32, [_P, _I64, _P, _P, _I32, WfImageShape, ctypes.c_double, _P,
                                  _P, _P, _P]),
+    "wf_briggs_weights_noalloc": (_I32, [_P, _I64, _D, WfImageShape, ctypes.c_double, _P, _P,
+                                         _P, _P]),
     "wf_build_operator": (_I32, [_P, _I64, _P, _P, _I32, WfImageShape, ctypes.c_uint64,
                                  ctypes.POINTER(WfOptions), _P, ctypes.POINTER(_P)]),
     "wf_forward": (_I32, [_P, _P, _P, _P]),

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "wf_internal.h"
 
@@ -98,9 +99,72 @@ __global__ __launch_bounds__(256) void k_briggs_out(const double* __restrict__ u
   }
 }
 
+// As k_briggs_out with f^2 = a2 sums[1] / sums[0] formed on the device from the sums
+// k_briggs_sums wrote (same operations, in the same order, as the host form), so that
+// nothing waits on the host between the passes; all zero when either sum is not positive.
+__global__ __launch_bounds__(256) void k_briggs_out_dev(const double* __restrict__ uvw,
+                                                        int64_t n, double scale, double du,
+                                                        double dv, int nx, int ny,
+                                                        const float* __restrict__ w,
+                                                        const uint8_t* __restrict__ flags,
+                                                        const double* __restrict__ W,
+                                                        const double* __restrict__ sums,
+                                                        double a2, float* __restrict__ out) {
+#pragma clang fp contract(off)
+  const double s0 = sums[0], s1 = sums[1];
+  const bool ok = s0 > 0 && s1 > 0;
+  const double f2 = ok ? a2 * s1 / s0 : 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const double wk = nat_weight(w, flags, k);
+    if (!ok || wk == 0.0) {
+      out[k] = 0.f;
+      continue;
+    }
+    const double u = uvw[3 * k] * scale, v = uvw[3 * k + 1] * scale;
+    out[k] = (float)sqrt(wk / (1.0 + W[uv_cell(u, v, du, dv, nx, ny)] * f2));
+  }
+}
+
 unsigned blocks_for(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 8192); }
 
 }  // namespace
+
+// Device memory of the allocation-free entry point (wf_briggs_weights_noalloc): the
+// density over at most WF_BRIGGS_NOALLOC_MAX_CELLS Fourier cells, then the two sums.
+// Static device memory: every device the library runs on holds its own copy until the
+// process ends.  Host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (the symbol's name is a host-side stand-in).
+static __device__ __align__(256) double scratch[WF_BRIGGS_NOALLOC_MAX_CELLS + 2];
+
+hipError_t briggs_scratch(double** out) {
+  constexpr int MAXDEV = 64;
+  static std::mutex mu;
+  static double* ptr[MAXDEV] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[dev] = static_cast<double*>(p);
+  }
+  *out = ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_briggs_out_dev(const double* uvw, int64_t n, double scale, double du,
+                                 double dv, int nx, int ny, const float* w,
+                                 const uint8_t* flags, const double* W, const double* sums,
+                                 double a2, float* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_briggs_out_dev, dim3(blocks_for(n)), dim3(256), 0, s, uvw, n, scale,
+                     du, dv, nx, ny, w, flags, W, sums, a2, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_density(const double* uvw, int64_t n, double scale, double du, double dv,
                           int nx, int ny, const float* w, const uint8_t* flags, double* W,

@@ -287,6 +287,13 @@ hipError_t launch_briggs_sums(const double* uvw, int64_t n, double scale, double
 hipError_t launch_briggs_out(const double* uvw, int64_t n, double scale, double du, double dv,
                              int nx, int ny, const float* w, const uint8_t* flags,
                              const double* W, double f2, float* out, hipStream_t s);
+// Allocation-free Briggs weighting: the device address of this device's static scratch
+// (density then two sums), found once per device; f^2 = a2 sums[1] / sums[0] on the device.
+hipError_t briggs_scratch(double** out);
+hipError_t launch_briggs_out_dev(const double* uvw, int64_t n, double scale, double du,
+                                 double dv, int nx, int ny, const float* w,
+                                 const uint8_t* flags, const double* W, const double* sums,
+                                 double a2, float* out, hipStream_t s);
 hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
 hipError_t launch_add_into(float* out, const float* in, int64_t nfloats, hipStream_t s);
 // Forward-backward driver (eq. 4): x <- max(x + gamma (dirty - hx) - t, 0); *out = a.b;

@@ -126,3 +126,45 @@ extern "C" wf_status wf_briggs_weights(const double* uvw_m, int64_t nrows,
     return fail(WF_EINVAL, e.what());
   }
 }
+
+extern "C" wf_status wf_briggs_weights_noalloc(const double* d_uvw_m, int64_t nrows,
+                                               double freq_hz, wf_image_shape shape,
+                                               double robust, const float* d_natural,
+                                               const uint8_t* d_flags, float* d_out,
+                                               void* hip_stream) {
+  try {
+    if (nrows < 0) return fail(WF_EINVAL, "negative row count");
+    if (nrows > 0 && (!d_uvw_m || !d_out)) return fail(WF_EINVAL, "null uvw or output");
+    if (shape.nx < 1 || shape.ny < 1 ||
+        (int64_t)shape.nx * shape.ny > (int64_t)WF_BRIGGS_NOALLOC_MAX_CELLS)
+      return fail(WF_EINVAL, "nx * ny must be in [1, " +
+                                 std::to_string(WF_BRIGGS_NOALLOC_MAX_CELLS) + "]");
+    if (!(shape.cell_rad > 0.0) || !std::isfinite(shape.cell_rad))
+      return fail(WF_EINVAL, "cell must be positive");
+    if (!std::isfinite(robust)) return fail(WF_EINVAL, "robustness must be finite");
+    if (!(freq_hz > 0) || !std::isfinite(freq_hz)) return fail(WF_EINVAL, "frequency must be positive");
+    if (nrows == 0) return WF_OK;
+    double* W = nullptr;
+    WF_HIP(briggs_scratch(&W));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t ncell = (int64_t)shape.nx * shape.ny;
+    double* sums = W + ncell;
+    // density and sums start at zero (a fill kernel: the call may be captured in a graph)
+    WF_HIP(launch_fill_zero(W, 2 * (ncell + 2), s));
+    const double du = 1.0 / (shape.nx * shape.cell_rad);
+    const double dv = 1.0 / (shape.ny * shape.cell_rad);
+    const double scale = freq_hz / C_LIGHT_MS;
+    WF_HIP(launch_density(d_uvw_m, nrows, scale, du, dv, shape.nx, shape.ny, d_natural, d_flags,
+                          W, s));
+    WF_HIP(launch_briggs_sums(d_uvw_m, nrows, scale, du, dv, shape.nx, shape.ny, d_natural,
+                              d_flags, W, sums, s));
+    const double a = 5.0 * std::pow(10.0, -robust);
+    WF_HIP(launch_briggs_out_dev(d_uvw_m, nrows, scale, du, dv, shape.nx, shape.ny, d_natural,
+                                 d_flags, W, sums, a * a, d_out, s));
+    return WF_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(WF_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(WF_EINVAL, e.what());
+  }
+}
