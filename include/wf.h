@@ -288,6 +288,19 @@ wf_status wf_profile_read(wf_op* op, int32_t kernel_id, int64_t* launches, doubl
  * are added in the caller's stream.  Invalidates graphs captured earlier. */
 wf_status wf_set_branches(wf_op* op, int32_t branches);
 
+/* Layer-batched sweep (enable != 0): every later apply (and every graph captured
+ * afterwards) runs each stage as one launch over all (channel, bin) layers at once --
+ * forward row FFTs, forward column FFTs, the de-gridding / gridding / fused G^dag G row
+ * kernels as one persistent launch per patch class draining the items of every layer
+ * from a device queue, inverse column FFTs, and inverse row FFTs that sum each channel's
+ * layers in registers and write its image once.  Holds the grids of every layer
+ * (2 Kx Ky + ny Kx complex FP32 values each) while enabled; WF_ENOMEM when they do not
+ * fit.  Needs Kx = 2 nx and Ky = 2 ny in 2048 .. 16384 and a stored G for every channel
+ * (WF_ENOTSUP otherwise).  Latency stamps mark the completion of each channel's last
+ * image row.  Results equal the branch apply up to the order of FP32 additions.
+ * enable = 0 releases the sweep.  Synchronous; invalidates graphs captured earlier. */
+wf_status wf_set_sweep(wf_op* op, int32_t enable);
+
 typedef enum {
   WF_APPLY_FORWARD = 0,   /* wf_forward      */
   WF_APPLY_ADJOINT = 1,   /* wf_adjoint      */
@@ -308,6 +321,10 @@ wf_status wf_graph_capture(wf_op* op, wf_apply_kind kind, const float* d_in, flo
                            void* hip_stream, wf_graph** out);
 /* Launch a captured apply on hip_stream (any stream of the operator's device). */
 wf_status wf_graph_launch(wf_graph* g, void* hip_stream);
+/* Count the nodes of a captured apply: *kernels = kernel launches, *total = all nodes
+ * (kernels, event records and waits of the branch fork/join, copies).  Host-only query;
+ * WF_EINVAL for a null graph or output pointer. */
+wf_status wf_graph_nodes(const wf_graph* g, int64_t* kernels, int64_t* total);
 /* Release a graph; graphs of a handle are destroyed before the handle itself. */
 wf_status wf_graph_destroy(wf_graph* g);
 

@@ -290,6 +290,11 @@ class Operator:
         """Run applies on n concurrent branches (streams with their own work grids)."""
         check(self._lib.wf_set_branches(self._h, int(n)), "wf_set_branches")
 
+    def set_sweep(self, enable=True):
+        """Layer-batched applies: one launch per stage over every (channel, bin) layer
+        (include/wf.h, wf_set_sweep)."""
+        check(self._lib.wf_set_sweep(self._h, int(enable)), "wf_set_sweep")
+
     def capture(self, kind, inp, out, stream):
         """Capture one apply ('forward', 'adjoint', 'psf', 'psf_re') with fixed buffers
         into a HIP graph; stream must be a created torch.cuda.Stream."""
@@ -348,6 +353,13 @@ class Graph:
 
     def launch(self, stream=None):
         check(self._lib.wf_graph_launch(self._g, _stream_handle(stream)), "wf_graph_launch")
+
+    def nodes(self):
+        """(kernel launches, all nodes) of the captured apply."""
+        k, n = ctypes.c_int64(), ctypes.c_int64()
+        check(self._lib.wf_graph_nodes(self._g, ctypes.byref(k), ctypes.byref(n)),
+              "wf_graph_nodes")
+        return int(k.value), int(n.value)
 
     def close(self):
         if getattr(self, "_g", None) and self._g.value:

@@ -81,9 +81,11 @@ SIGNATURES = {
     "wf_profile_enable": (_I32, [_P, _I32, _I32]),
     "wf_profile_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "wf_set_branches": (_I32, [_P, _I32]),
+    "wf_set_sweep": (_I32, [_P, _I32]),
     "wf_graph_capture": (_I32, [_P, _I32, _P, _P, _P, ctypes.POINTER(_P)]),
     "wf_graph_launch": (_I32, [_P, _P]),
     "wf_graph_destroy": (_I32, [_P]),
+    "wf_graph_nodes": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "wf_latency_enable": (_I32, [_P, _I32]),
     "wf_read_latency": (_I32, [_P, _P, _I32]),
     "wf_autotune": (_I32, [_P, _P, _P, _P, _I32, ctypes.POINTER(WfTuneInfo)]),

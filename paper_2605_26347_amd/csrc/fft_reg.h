@@ -128,6 +128,23 @@ struct RowPlan {
   static constexpr int NT = N / E;
 };
 
+// Whether element q = j + r S (j < S) of a pass lies in a needed column strip of mask m
+// (strip q / 16).  When a step of S covers at most 32 strips, all lanes' strips of one r
+// share one mask word, so that word is one uniform load per r instead of a load per
+// element.
+template <int S>
+__device__ __forceinline__ bool strip_on(const uint32_t* __restrict__ m, int j, int r) {
+  constexpr int SS = S / 16;
+  if constexpr (SS <= 32) {
+    static_assert(32 % SS == 0, "strips per step must divide a mask word");
+    const uint32_t w = m[(r * SS) >> 5];
+    return (w >> (((r * SS) & 31) + (j >> 4))) & 1u;
+  } else {
+    const int st = (j >> 4) + r * SS;
+    return (m[st >> 5] >> (st & 31)) & 1u;
+  }
+}
+
 // LDS slot of element idx: one float2 of padding after every 32, so that the strided
 // writes of the first pass (stride R1 elements) spread over the banks.
 __device__ __forceinline__ int lds_slot(int idx) { return idx + (idx >> 5); }
@@ -136,22 +153,24 @@ constexpr int lds_elems() {
   return N + N / 32;
 }
 
-// One middle pass: inputs from LDS, outputs to LDS (all inputs are read before the
-// barrier, outputs written after it).  The butterflies of a thread are j = tid + b NT.
+// One middle pass over the line in buf: inputs from LDS, outputs to LDS (all inputs are
+// read before the barrier, outputs written after it).  The butterflies of a thread are
+// j = tid + b NT; several lines may share the block, each with its own NT threads.
 template <int N, int R, int NS, int NT, bool INV>
-__device__ __forceinline__ void reg_pass_lds(float2* buf, const float2* __restrict__ tw) {
+__device__ __forceinline__ void reg_pass_lds(float2* buf, const float2* __restrict__ tw,
+                                             int tid) {
   constexpr int B = (N / R) / NT;
   float2 v[B][R];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    const int j = threadIdx.x + b * NT;
+    const int j = tid + b * NT;
 #pragma unroll
     for (int r = 0; r < R; ++r) v[b][r] = buf[lds_slot(j + r * (N / R))];
   }
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    const int j = threadIdx.x + b * NT;
+    const int j = tid + b * NT;
     const int kk = j & (NS - 1);
     const int step = kk * (N / (NS * R));
 #pragma unroll

@@ -132,15 +132,24 @@ __global__ __launch_bounds__(NT) void k_inv_rows(const float2* __restrict__ A,
 // of a last-pass butterfly lands inside the crop under the same rule with R3: the zero
 // half of the padded row and the discarded half of the inverse are skipped at compile
 // time.
+// With a sweep's layer table sl, workgroup (row, layer) takes the layer's grid, mask and
+// centroid from sl[blockIdx.y] and its channel's image from img (all channels' images).
 template <int N>
 __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
     const float* __restrict__ img, float2* __restrict__ A, const float2* __restrict__ tw,
     const float* __restrict__ sx, const float* __restrict__ sy, int nx, int ny, double cell,
-    double wp, const uint32_t* __restrict__ smask) {
+    double wp, const uint32_t* __restrict__ smask, const SweepLayer* __restrict__ sl) {
   using RP = RowPlan<N>;
   constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3, NT = RP::NT;
   extern __shared__ float2 buf[];
   const int jr = blockIdx.x;
+  if (sl) {
+    const SweepLayer& L = sl[blockIdx.y];
+    img += (int64_t)L.chan * nx * ny;
+    A = L.A;
+    wp = L.wp;
+    smask = L.smask;
+  }
   const float syj = sy[jr];
   const float* __restrict__ row = img + (int64_t)jr * nx;
   {
@@ -167,7 +176,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
     }
   }
   __syncthreads();
-  reg_pass_lds<N, R2, R1, NT, false>(buf, tw);
+  reg_pass_lds<N, R2, R1, NT, false>(buf, tw, threadIdx.x);
   {
     constexpr int NS = R1 * R2;
     constexpr int B = (N / R3) / NT;
@@ -183,7 +192,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
 #pragma unroll
       for (int r = 0; r < R3; ++r) {
         const int q = j + r * NS;
-        if (!smask || bit_set(smask, q >> 4)) A[strip_index(jr, q, ny)] = v[r];
+        if (!smask || strip_on<NS>(smask, j, r)) A[strip_index(jr, q, ny)] = v[r];
       }
     }
   }
@@ -198,6 +207,26 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
   constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3, NT = RP::NT;
   extern __shared__ float2 buf[];
   const int jr = blockIdx.x;
+  constexpr int NS3 = R1 * R2;
+  constexpr int B3 = (N / R3) / NT;
+  // the previous image sum of the real-part accumulate mode is requested first, so that
+  // its latency hides behind the transform
+  float prev[B3][R3 / 2];
+  if (mode == 3) {
+#pragma unroll
+    for (int b = 0; b < B3; ++b) {
+      const int j = threadIdx.x + b * NT;
+#pragma unroll
+      for (int r = 0; r < R3; ++r) {
+        if (r < R3 / 4 || r >= 3 * R3 / 4) {
+          const int q = j + r * NS3;
+          const int i = r < R3 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
+          prev[b][r < R3 / 4 ? r : r - R3 / 2] =
+              reinterpret_cast<const float*>(out)[(int64_t)jr * nx + i];
+        }
+      }
+    }
+  }
   {
     constexpr int B = (N / R1) / NT;
 #pragma unroll
@@ -207,8 +236,8 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
         const int q = j + r * (N / R1);
-        v[r] = (!smask || bit_set(smask, q >> 4)) ? A[strip_index(jr, q, ny)]
-                                                  : make_float2(0.f, 0.f);
+        v[r] = (!smask || strip_on<N / R1>(smask, j, r)) ? A[strip_index(jr, q, ny)]
+                                                         : make_float2(0.f, 0.f);
       }
       dft_reg<R1, true>(v);
 #pragma unroll
@@ -216,7 +245,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
     }
   }
   __syncthreads();
-  reg_pass_lds<N, R2, R1, NT, true>(buf, tw);
+  reg_pass_lds<N, R2, R1, NT, true>(buf, tw, threadIdx.x);
   const float syj = sy[jr];
   {
     constexpr int NS = R1 * R2;
@@ -248,8 +277,287 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
             }
           } else {
             float* po = reinterpret_cast<float*>(out) + o;
-            *po = (mode == 3) ? (*po + c.x) : c.x;
+            *po = (mode == 3) ? (prev[b][r < R3 / 4 ? r : r - R3 / 2] + c.x) : c.x;
           }
+        }
+      }
+    }
+  }
+}
+
+// Inverse row pass of a sweep: workgroup (row jr, channel c) transforms row jr of every
+// layer of channel c in turn (chan_layers[c] = first layer, count) and accumulates
+// conj(Z_p) F^dag ... in registers, then writes the channel's image row once (complex, or
+// its real part): the sum over w-layers (eq. 7) needs no read-modify-write and no
+// atomics.  With stamps, the channel's last workgroup records the device clock.
+template <int N>
+__global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_sweep(
+    const SweepLayer* __restrict__ sl, const int2* __restrict__ chan_layers,
+    void* __restrict__ out, const float2* __restrict__ tw, const float* __restrict__ sx,
+    const float* __restrict__ sy, int nx, int ny, double cell, int real_out,
+    unsigned long long* __restrict__ stamps, int* __restrict__ done) {
+  using RP = RowPlan<N>;
+  constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3, NT = RP::NT;
+  constexpr int NS3 = R1 * R2;
+  constexpr int B3 = (N / R3) / NT;
+  extern __shared__ float2 buf[];
+  const int jr = blockIdx.x, c = blockIdx.y;
+  const int2 cl = chan_layers[c];
+  const float syj = sy[jr];
+  float2 acc[B3][R3 / 2];
+#pragma unroll
+  for (int b = 0; b < B3; ++b)
+#pragma unroll
+    for (int r = 0; r < R3 / 2; ++r) acc[b][r] = make_float2(0.f, 0.f);
+  for (int li = cl.x; li < cl.x + cl.y; ++li) {
+    const SweepLayer& L = sl[li];
+    const float2* __restrict__ A = L.A;
+    const uint32_t* __restrict__ smask = L.smask;
+    {
+      constexpr int B = (N / R1) / NT;
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int j = threadIdx.x + b * NT;
+        float2 v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          const int q = j + r * (N / R1);
+          v[r] = (!smask || strip_on<N / R1>(smask, j, r)) ? A[strip_index(jr, q, ny)]
+                                                           : make_float2(0.f, 0.f);
+        }
+        dft_reg<R1, true>(v);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) buf[lds_slot(j * R1 + r)] = v[r];
+      }
+    }
+    __syncthreads();
+    reg_pass_lds<N, R2, R1, NT, true>(buf, tw, threadIdx.x);
+#pragma unroll
+    for (int b = 0; b < B3; ++b) {
+      const int j = threadIdx.x + b * NT;
+      float2 v[R3];
+#pragma unroll
+      for (int r = 0; r < R3; ++r) v[r] = buf[lds_slot(j + r * NS3)];
+#pragma unroll
+      for (int r = 1; r < R3; ++r) v[r] = cmulc(v[r], tw[r * j]);
+      dft_reg<R3, true>(v);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) {
+        if (r < R3 / 4 || r >= 3 * R3 / 4) {
+          const int q = j + r * NS3;
+          const int i = r < R3 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
+          const float2 z = zvalue(i, jr, nx, ny, cell, L.wp, sx[i], syj);
+          const float2 t = cmulc(v[r], z);
+          float2& a = acc[b][r < R3 / 4 ? r : r - R3 / 2];
+          a = make_float2(a.x + t.x, a.y + t.y);
+        }
+      }
+    }
+    __syncthreads();   // every read of this layer's row is done before the next is written
+  }
+  const int64_t base = (int64_t)c * nx * ny + (int64_t)jr * nx;
+#pragma unroll
+  for (int b = 0; b < B3; ++b) {
+    const int j = threadIdx.x + b * NT;
+#pragma unroll
+    for (int r = 0; r < R3; ++r) {
+      if (r < R3 / 4 || r >= 3 * R3 / 4) {
+        const int q = j + r * NS3;
+        const int i = r < R3 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
+        const float2 a = acc[b][r < R3 / 4 ? r : r - R3 / 2];
+        if (real_out) reinterpret_cast<float*>(out)[base + i] = a.x;
+        else reinterpret_cast<float2*>(out)[base + i] = a;
+      }
+    }
+  }
+  if (stamps) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0 && atomicAdd(done + c, 1) == (int)gridDim.x - 1) {
+      stamps[c] = wall_clock64();
+      atomicExch(done + c, 0);
+    }
+  }
+}
+
+// Column passes at the long lengths (N = 2048 .. 16384), register-resident like the row
+// passes: CW columns of one strip per workgroup, NT threads per column, interleaved so
+// that the CW columns of one grid row are read and written by neighbouring lanes.  The
+// needed tiles of the group's column of tiles are copied into LDS flags once, so that no
+// element waits on a mask load.  Since N = 2 ny, the zero half of each forward column and
+// the discarded half of each inverse column follow the same compile-time rule as rows.
+template <int N>
+struct ColPlan {
+  static constexpr int CW = (16384 / N) > 16 ? 16 : (16384 / N);
+  static constexpr int NTC = RowPlan<N>::NT;   // threads per column
+  static constexpr int NT = CW * NTC;
+  // lines one element apart beyond their padded length, so that the CW columns of one
+  // grid row (neighbouring lanes) fall in different banks
+  static constexpr int LS = lds_elems<N>() + 1;
+  static constexpr size_t lds_bytes() { return (size_t)CW * LS * sizeof(float2) + N / 8; }
+};
+
+// Flags of the needed tiles of column-tile ct (one byte per row of tiles; all ones when
+// there is no mask).
+__device__ __forceinline__ void load_tile_flags(uint8_t* flags, const Masks& mk, int N, int ct,
+                                                int nthreads) {
+  const int nty = (N >> mk.tsh) > 0 ? (N >> mk.tsh) : 1;
+  for (int t = threadIdx.x; t < nty; t += nthreads)
+    flags[t] = mk.tile ? (uint8_t)bit_set(mk.tile, t * mk.tiles_x + ct) : (uint8_t)1;
+}
+
+// With a sweep's layer table sl, workgroup i takes (layer, column group) pairs[i].
+template <int N>
+__global__ __launch_bounds__(ColPlan<N>::NT) void k_fwd_cols_reg(const float2* __restrict__ A,
+                                                                 float2* __restrict__ X,
+                                                                 const float2* __restrict__ tw,
+                                                                 int ny, Masks mk,
+                                                                 const SweepLayer* __restrict__ sl,
+                                                                 const int2* __restrict__ pairs) {
+  using RP = RowPlan<N>;
+  constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3;
+  constexpr int CW = ColPlan<N>::CW, NTC = ColPlan<N>::NTC, NT = ColPlan<N>::NT;
+  constexpr int LS = ColPlan<N>::LS;
+  extern __shared__ float2 buf[];
+  uint8_t* tflag = reinterpret_cast<uint8_t*>(buf + CW * LS);
+  const int gi = xcd_remap(blockIdx.x, gridDim.x);
+  int g;
+  if (sl) {
+    const int2 pr = pairs[gi];
+    const SweepLayer& L = sl[pr.x];
+    A = L.A;
+    X = L.X;
+    mk.tile = L.tile;
+    g = pr.y;
+  } else {
+    g = mk.groups ? mk.groups[gi] : gi;
+  }
+  const int q0 = g * CW;
+  const int strip = q0 >> 4, c0 = q0 & (SW - 1);
+  const int c = threadIdx.x % CW, tj = threadIdx.x / CW;
+  float2* line = buf + c * LS;
+  load_tile_flags(tflag, mk, N, q0 >> mk.tsh, NT);
+  const float2* __restrict__ src = A + ((int64_t)strip * ny) * SW + c0 + c;
+  {
+    constexpr int B = (N / R1) / NTC;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = tj + b * NTC;
+      float2 v[R1];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int q = j + r * (N / R1);
+        if (r < R1 / 4 || r >= 3 * R1 / 4) {
+          const int jrow = r < R1 / 4 ? q + N / 4 : q - 3 * (N / 4);
+          v[r] = src[(int64_t)jrow * SW];
+        } else {
+          v[r] = make_float2(0.f, 0.f);
+        }
+      }
+      dft_reg<R1, false>(v);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) line[lds_slot(j * R1 + r)] = v[r];
+    }
+  }
+  __syncthreads();
+  reg_pass_lds<N, R2, R1, NTC, false>(line, tw, tj);
+  float2* __restrict__ dst = X + ((int64_t)strip * N) * SW + c0 + c;
+  {
+    constexpr int NS = R1 * R2;
+    constexpr int B = (N / R3) / NTC;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = tj + b * NTC;
+      float2 v[R3];
+#pragma unroll
+      for (int r = 0; r < R3; ++r) v[r] = line[lds_slot(j + r * NS)];
+#pragma unroll
+      for (int r = 1; r < R3; ++r) v[r] = cmul(v[r], tw[r * j]);
+      dft_reg<R3, false>(v);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) {
+        const int qv = j + r * NS;
+        if (tflag[qv >> mk.tsh]) dst[(int64_t)qv * SW] = v[r];
+      }
+    }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(ColPlan<N>::NT) void k_inv_cols_reg(float2* __restrict__ Y,
+                                                                 float2* __restrict__ A,
+                                                                 const float2* __restrict__ tw,
+                                                                 int ny, Masks mk,
+                                                                 const SweepLayer* __restrict__ sl,
+                                                                 const int2* __restrict__ pairs) {
+  using RP = RowPlan<N>;
+  constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3;
+  constexpr int CW = ColPlan<N>::CW, NTC = ColPlan<N>::NTC, NT = ColPlan<N>::NT;
+  constexpr int LS = ColPlan<N>::LS;
+  extern __shared__ float2 buf[];
+  uint8_t* tflag = reinterpret_cast<uint8_t*>(buf + CW * LS);
+  const int gi = xcd_remap(blockIdx.x, gridDim.x);
+  int g;
+  if (sl) {
+    const int2 pr = pairs[gi];
+    const SweepLayer& L = sl[pr.x];
+    Y = L.Y;
+    A = L.A;
+    mk.tile = L.tile;
+    g = pr.y;
+  } else {
+    g = mk.groups ? mk.groups[gi] : gi;
+  }
+  const int q0 = g * CW;
+  const int strip = q0 >> 4, c0 = q0 & (SW - 1);
+  const int c = threadIdx.x % CW, tj = threadIdx.x / CW;
+  float2* line = buf + c * LS;
+  load_tile_flags(tflag, mk, N, q0 >> mk.tsh, NT);
+  __syncthreads();
+  // Y is read only inside needed tiles and cleared behind the read, ready for the next
+  // gridding; elsewhere it is zero already
+  float2* __restrict__ src = Y + ((int64_t)strip * N) * SW + c0 + c;
+  {
+    constexpr int B = (N / R1) / NTC;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = tj + b * NTC;
+      float2 v[R1];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int q = j + r * (N / R1);
+        v[r] = make_float2(0.f, 0.f);
+        if (tflag[q >> mk.tsh]) {
+          v[r] = src[(int64_t)q * SW];
+          src[(int64_t)q * SW] = make_float2(0.f, 0.f);
+        }
+      }
+      dft_reg<R1, true>(v);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) line[lds_slot(j * R1 + r)] = v[r];
+    }
+  }
+  __syncthreads();
+  reg_pass_lds<N, R2, R1, NTC, true>(line, tw, tj);
+  float2* __restrict__ dst = A + ((int64_t)strip * ny) * SW + c0 + c;
+  {
+    constexpr int NS = R1 * R2;
+    constexpr int B = (N / R3) / NTC;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = tj + b * NTC;
+      float2 v[R3];
+#pragma unroll
+      for (int r = 0; r < R3; ++r) v[r] = line[lds_slot(j + r * NS)];
+#pragma unroll
+      for (int r = 1; r < R3; ++r) v[r] = cmulc(v[r], tw[r * j]);
+      dft_reg<R3, true>(v);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) {
+        if (r < R3 / 4 || r >= 3 * R3 / 4) {
+          const int q = j + r * NS;
+          const int jrow = r < R3 / 4 ? q + N / 4 : q - 3 * (N / 4);
+          dst[(int64_t)jrow * SW] = v[r];
         }
       }
     }
@@ -368,7 +676,7 @@ static hipError_t launch_fwd_rows_reg(const float* img, float2* A, const float2*
   hipError_t e = set_lds(k_fwd_rows_reg<N>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fwd_rows_reg<N>), dim3(ny), dim3(RowPlan<N>::NT), lds, s, img, A, tw,
-                     sx, sy, nx, ny, cell, wp, smask);
+                     sx, sy, nx, ny, cell, wp, smask, nullptr);
   return hipGetLastError();
 }
 
@@ -445,8 +753,49 @@ hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const f
   }
 }
 
+template <int N, bool INV>
+static hipError_t launch_cols_reg(float2* in, float2* out, const float2* tw, int ny, int Kx,
+                                  const ColPrune* pr, hipStream_t s) {
+  constexpr int CW = ColPlan<N>::CW;
+  if (Kx % CW != 0) return hipErrorInvalidValue;
+  const size_t lds = ColPlan<N>::lds_bytes();
+  Masks mk{nullptr, nullptr, nullptr, 1, 0};
+  int ng = Kx / CW;
+  if (pr) {
+    mk = Masks{pr->strip, pr->tile, pr->groups, pr->tiles_x, pr->tsh};
+    ng = pr->ngroups;
+  }
+  if (!pr || !pr->tile) {   // no mask: one row of tiles of any side
+    mk.tsh = 30;
+  }
+  if (ng == 0) return hipSuccess;
+  hipError_t e;
+  if constexpr (INV) {
+    e = set_lds(k_inv_cols_reg<N>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_inv_cols_reg<N>), dim3(ng), dim3(ColPlan<N>::NT), lds, s, in, out, tw,
+                       ny, mk, nullptr, nullptr);
+  } else {
+    e = set_lds(k_fwd_cols_reg<N>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fwd_cols_reg<N>), dim3(ng), dim3(ColPlan<N>::NT), lds, s,
+                       (const float2*)in, out, tw, ny, mk, nullptr, nullptr);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_fwd_cols(const float2* A, float2* X, const float2* tw, int ny, int Kx,
                            int Ky, const ColPrune* pr, hipStream_t s) {
+  if (Ky == 2 * ny) {
+    float2* a = const_cast<float2*>(A);
+    switch (Ky) {
+      case 2048: return launch_cols_reg<2048, false>(a, X, tw, ny, Kx, pr, s);
+      case 4096: return launch_cols_reg<4096, false>(a, X, tw, ny, Kx, pr, s);
+      case 8192: return launch_cols_reg<8192, false>(a, X, tw, ny, Kx, pr, s);
+      case 16384: return launch_cols_reg<16384, false>(a, X, tw, ny, Kx, pr, s);
+      default: break;
+    }
+  }
   switch (Ky) {
 #define C(N)                                                                              \
   case N: {                                                                               \
@@ -476,6 +825,15 @@ hipError_t launch_fwd_cols(const float2* A, float2* X, const float2* tw, int ny,
 
 hipError_t launch_inv_cols(float2* Y, float2* A, const float2* tw, int ny, int Kx, int Ky,
                            const ColPrune* pr, hipStream_t s) {
+  if (Ky == 2 * ny) {
+    switch (Ky) {
+      case 2048: return launch_cols_reg<2048, true>(Y, A, tw, ny, Kx, pr, s);
+      case 4096: return launch_cols_reg<4096, true>(Y, A, tw, ny, Kx, pr, s);
+      case 8192: return launch_cols_reg<8192, true>(Y, A, tw, ny, Kx, pr, s);
+      case 16384: return launch_cols_reg<16384, true>(Y, A, tw, ny, Kx, pr, s);
+      default: break;
+    }
+  }
   switch (Ky) {
 #define C(N)                                                                              \
   case N: {                                                                               \
@@ -509,6 +867,84 @@ hipError_t launch_strip_to_rowmajor(const float2* src, float2* dst, int R, int Q
   const int blocks = (int)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
   hipLaunchKernelGGL(k_strip_to_rowmajor, dim3(blocks), dim3(256), 0, s, src, dst, R, Q);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ sweep stages
+// One launch per stage over every layer of a sweep (grid sides 2048 .. 16384, Kx = 2 nx,
+// Ky = 2 ny).  Layer tables and pairs are device arrays built by the host.
+
+hipError_t launch_sweep_fwd_rows(const float* img, const SweepLayer* sl, int nlayers,
+                                 const float2* tw, const float* sx, const float* sy, int nx,
+                                 int ny, int Kx, double cell, hipStream_t s) {
+  if (nlayers <= 0) return hipSuccess;
+  switch (Kx) {
+#define C(NN)                                                                               \
+  case NN: {                                                                                \
+    const size_t lds = (size_t)lds_elems<NN>() * sizeof(float2);                            \
+    hipError_t e = set_lds(k_fwd_rows_reg<NN>, lds);                                        \
+    if (e != hipSuccess) return e;                                                          \
+    hipLaunchKernelGGL((k_fwd_rows_reg<NN>), dim3(ny, nlayers), dim3(RowPlan<NN>::NT), lds, \
+                       s, img, nullptr, tw, sx, sy, nx, ny, cell, 0.0, nullptr, sl);        \
+    return hipGetLastError();                                                               \
+  }
+    C(2048) C(4096) C(8192) C(16384)
+#undef C
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sweep_cols(bool inverse, const SweepLayer* sl, const int2* pairs, int npairs,
+                             const float2* tw, int ny, int Ky, int tsh, int tiles_x,
+                             hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  Masks mk{nullptr, nullptr, nullptr, tiles_x, tsh};
+  switch (Ky) {
+#define C(NN)                                                                                 \
+  case NN: {                                                                                  \
+    const size_t lds = ColPlan<NN>::lds_bytes();                                              \
+    hipError_t e;                                                                             \
+    if (inverse) {                                                                            \
+      e = set_lds(k_inv_cols_reg<NN>, lds);                                                   \
+      if (e != hipSuccess) return e;                                                          \
+      hipLaunchKernelGGL((k_inv_cols_reg<NN>), dim3(npairs), dim3(ColPlan<NN>::NT), lds, s,   \
+                         nullptr, nullptr, tw, ny, mk, sl, pairs);                            \
+    } else {                                                                                  \
+      e = set_lds(k_fwd_cols_reg<NN>, lds);                                                   \
+      if (e != hipSuccess) return e;                                                          \
+      hipLaunchKernelGGL((k_fwd_cols_reg<NN>), dim3(npairs), dim3(ColPlan<NN>::NT), lds, s,   \
+                         nullptr, nullptr, tw, ny, mk, sl, pairs);                            \
+    }                                                                                         \
+    return hipGetLastError();                                                                 \
+  }
+    C(2048) C(4096) C(8192) C(16384)
+#undef C
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sweep_inv_rows(const SweepLayer* sl, const int2* chan_layers, int nchan,
+                                 void* out, bool real_out, const float2* tw, const float* sx,
+                                 const float* sy, int nx, int ny, int Kx, double cell,
+                                 unsigned long long* stamps, int* done, hipStream_t s) {
+  if (nchan <= 0) return hipSuccess;
+  switch (Kx) {
+#define C(NN)                                                                                \
+  case NN: {                                                                                 \
+    const size_t lds = (size_t)lds_elems<NN>() * sizeof(float2);                             \
+    hipError_t e = set_lds(k_inv_rows_sweep<NN>, lds);                                       \
+    if (e != hipSuccess) return e;                                                           \
+    hipLaunchKernelGGL((k_inv_rows_sweep<NN>), dim3(ny, nchan), dim3(RowPlan<NN>::NT), lds,  \
+                       s, sl, chan_layers, out, tw, sx, sy, nx, ny, cell, real_out ? 1 : 0,  \
+                       stamps, done);                                                        \
+    return hipGetLastError();                                                                \
+  }
+    C(2048) C(4096) C(8192) C(16384)
+#undef C
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace wf

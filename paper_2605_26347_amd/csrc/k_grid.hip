@@ -24,6 +24,8 @@
 // Values are stored as complex FP32, FP16 or BF16; all arithmetic is FP32.
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
+
 #include "fft_lds.h"
 #include "wf_internal.h"
 
@@ -191,20 +193,16 @@ __device__ __forceinline__ void window_flush(const double* acc, const Box& bx, i
   }
 }
 
-// MODE 0: fused G^dag G; 1: de-gridding; 2: gridding.
+// One work item on one workgroup.  MODE 0: fused G^dag G; 1: de-gridding; 2: gridding.
+// Every thread passes the same two barriers (scattering modes), whatever its rows.
 template <int STORE, int MK, int MODE>
-__global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
-                                              const uint32_t* __restrict__ meta,
-                                              const uint32_t* __restrict__ voff,
-                                              const int32_t* __restrict__ perm,
-                                              const void* __restrict__ vals,
-                                              const float2* __restrict__ X,
-                                              float2* __restrict__ Y,
-                                              float2* __restrict__ vis, int Kx, int Ky) {
-  extern __shared__ double acc[];
-  // Items are ordered largest first and dealt round-robin over the XCDs by the hardware,
-  // which spreads the dense uv core (many items) evenly and schedules longest first.
-  const WorkItem wi = wis[blockIdx.x];
+__device__ __forceinline__ void row_item(const WorkItem& wi, const uint32_t* __restrict__ meta,
+                                         const uint32_t* __restrict__ voff,
+                                         const int32_t* __restrict__ perm,
+                                         const void* __restrict__ vals,
+                                         const float2* __restrict__ X, float2* __restrict__ Y,
+                                         float2* __restrict__ vis, int Kx, int Ky,
+                                         double* acc) {
   constexpr bool GATHER = MODE != 2;
   constexpr bool SCATTER = MODE != 1;
   constexpr int VB = value_bytes<STORE>();
@@ -352,6 +350,55 @@ __global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
   }
 }
 
+template <int STORE, int MK, int MODE>
+__global__ __launch_bounds__(GNT) void k_rows(const WorkItem* __restrict__ wis,
+                                              const uint32_t* __restrict__ meta,
+                                              const uint32_t* __restrict__ voff,
+                                              const int32_t* __restrict__ perm,
+                                              const void* __restrict__ vals,
+                                              const float2* __restrict__ X,
+                                              float2* __restrict__ Y,
+                                              float2* __restrict__ vis, int Kx, int Ky) {
+  extern __shared__ double acc[];
+  // Items are ordered largest first and dealt round-robin over the XCDs by the hardware,
+  // which spreads the dense uv core (many items) evenly and schedules longest first.
+  row_item<STORE, MK, MODE>(wis[blockIdx.x], meta, voff, perm, vals, X, Y, vis, Kx, Ky, acc);
+}
+
+// Persistent form over the items of every layer of a sweep (one patch class): resident
+// workgroups take items from a queue (queue[0]) until it is drained; each item's layer
+// (its bin field) selects its grids, its row data and its visibilities (vis_base plus
+// the layer's offset).  The last workgroup to leave clears the queue and the exit count
+// (queue[1]), so that the next launch, or the next replay of a captured graph, starts
+// from zero without a separate clearing step.
+template <int STORE, int MK, int MODE>
+__global__ __launch_bounds__(GNT) void k_rows_sweep(const WorkItem* __restrict__ wis,
+                                                    int nitems,
+                                                    const SweepLayer* __restrict__ layers,
+                                                    float2* __restrict__ vis_base,
+                                                    int* __restrict__ queue, int Kx, int Ky) {
+  extern __shared__ double acc[];
+  __shared__ int slot;
+  for (;;) {
+    if (threadIdx.x == 0) slot = atomicAdd(queue, 1);
+    __syncthreads();
+    const int i = slot;
+    __syncthreads();
+    if (i >= nitems) break;
+    const WorkItem wi = wis[i];
+    const SweepLayer& L = layers[wi.bin];
+    row_item<STORE, MK, MODE>(wi, L.meta, L.voff, L.perm, L.vals, L.X, L.Y,
+                              vis_base ? vis_base + L.vis_off : nullptr, Kx, Ky, acc);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
+      atomicExch(queue, 0);
+      atomicExch(queue + 1, 0);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <typename K>
@@ -418,6 +465,64 @@ static hipError_t launch_mode(int cls, const WorkItem* wi, int nwi, const uint32
     default:
       return launch_cls<WF_STORE_BF16, MODE>(cls, wi, nwi, meta, voff, perm, vals, X, Y, vis,
                                              Kx, Ky, tile, s);
+  }
+}
+
+template <int STORE, int MK, int MODE>
+static hipError_t launch_sweep_one(const WorkItem* wi, int nwi, const SweepLayer* layers,
+                                   float2* vis_base, int* queue, int Kx, int Ky, int tile,
+                                   int grid_cap, hipStream_t s) {
+  const size_t side = (size_t)tile + class_tmax(MK) - 1;
+  const size_t lds = MODE == 1 ? 0 : side * side * 2 * sizeof(double);
+  hipError_t e = set_lds(k_rows_sweep<STORE, MK, MODE>, lds);
+  if (e != hipSuccess) return e;
+  // resident workgroups only: as many as the device holds at once, capped by the items
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rows_sweep<STORE, MK, MODE>,
+                                                   GNT, lds);
+  if (e != hipSuccess) return e;
+  const int grid = std::max(1, std::min(nwi, std::max(1, per_cu) * grid_cap));
+  hipLaunchKernelGGL((k_rows_sweep<STORE, MK, MODE>), dim3(grid), dim3(GNT), lds, s, wi, nwi,
+                     layers, vis_base, queue, Kx, Ky);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_sweep_mode(int cls, const WorkItem* wi, int nwi,
+                                    const SweepLayer* layers, wf_store store, float2* vis_base,
+                                    int* queue, int Kx, int Ky, int tile, int ncu,
+                                    hipStream_t s) {
+  if (nwi <= 0) return hipSuccess;
+#define WF_SW(ST, MK) \
+  launch_sweep_one<ST, MK, MODE>(wi, nwi, layers, vis_base, queue, Kx, Ky, tile, ncu, s)
+#define WF_SWC(ST)                 \
+  switch (cls) {                   \
+    case 0: return WF_SW(ST, 2);   \
+    case 1: return WF_SW(ST, 4);   \
+    case 2: return WF_SW(ST, 7);   \
+    case 3: return WF_SW(ST, 12);  \
+    case 4: return WF_SW(ST, 16);  \
+    default: return WF_SW(ST, 22); \
+  }
+  switch (store) {
+    case WF_STORE_F32: WF_SWC(WF_STORE_F32)
+    case WF_STORE_F16: WF_SWC(WF_STORE_F16)
+    default: WF_SWC(WF_STORE_BF16)
+  }
+#undef WF_SWC
+#undef WF_SW
+}
+
+hipError_t launch_rows_sweep(int mode, int cls, const WorkItem* wi, int nwi,
+                             const SweepLayer* layers, wf_store store, float2* vis_base,
+                             int* queue, int Kx, int Ky, int tile, int ncu, hipStream_t s) {
+  switch (mode) {
+    case 0: return launch_sweep_mode<0>(cls, wi, nwi, layers, store, vis_base, queue, Kx, Ky,
+                                        tile, ncu, s);
+    case 1: return launch_sweep_mode<1>(cls, wi, nwi, layers, store, vis_base, queue, Kx, Ky,
+                                        tile, ncu, s);
+    default: return launch_sweep_mode<2>(cls, wi, nwi, layers, store, vis_base, queue, Kx, Ky,
+                                         tile, ncu, s);
   }
 }
 

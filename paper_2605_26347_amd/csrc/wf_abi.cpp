@@ -84,6 +84,7 @@ float half_bits_to_float(uint16_t h) {
 }
 
 void release_branch(Branch& B, bool own_stream);
+void release_sweep(wf_op* op);
 
 void destroy_op(wf_op* op) {
   if (!op) return;
@@ -102,6 +103,7 @@ void destroy_op(wf_op* op) {
     for (DevBuf* b : {&c.uvw, &c.wts, &c.uperm, &c.row_wi, &c.mids, &c.cents, &c.crow}) dfree(*b);
   }
   dfree(op->otf_mis);
+  release_sweep(op);
   for (size_t b = 0; b < op->br.size(); ++b) release_branch(op->br[b], b > 0);
   if (op->fork) (void)hipEventDestroy(op->fork);
   dfree(op->stamps);
@@ -1110,9 +1112,181 @@ wf_status run_channel(wf_op* op, int kind, int c, const Lane& L, const float* in
   return WF_OK;
 }
 
+// ------------------------------------------------------------------ sweep (layer-batched)
+
+void release_sweep(wf_op* op) {
+  Sweep& W = op->sweep;
+  for (DevBuf& b : W.grids) dfree(b);
+  W.grids.clear();
+  dfree(W.layers);
+  dfree(W.pairs);
+  dfree(W.chan_layers);
+  for (int c = 0; c < NCLS; ++c) {
+    dfree(W.items[c]);
+    W.nitems[c] = 0;
+  }
+  dfree(W.queues);
+  dfree(W.done);
+  W.nlayers = 0;
+  W.npairs = 0;
+  W.on = false;
+}
+
+bool sweep_size_ok(int K) { return K == 2048 || K == 4096 || K == 8192 || K == 16384; }
+
+// Lay out a sweep: the grids of every non-empty (channel, bin) layer, the layer table,
+// the column pairs of each layer's active column groups, each channel's layer range and,
+// per patch class, every layer's work items (bin field = layer), largest first.  The
+// caller has synchronised the device.
+wf_status sweep_build(wf_op* op) {
+  release_sweep(op);
+  Sweep& W = op->sweep;
+  wf_status st;
+  const int nchan = (int)op->chans.size();
+  const size_t grid = sizeof(float2) * (size_t)op->Kx * op->Ky;
+  const size_t arow = sizeof(float2) * (size_t)op->shape.ny * op->Kx;
+  std::vector<SweepLayer> tab;
+  std::vector<int2> pairs, cl(nchan, int2{0, 0});
+  std::vector<WorkItem> cls_items[NCLS];
+  for (int c = 0; c < nchan; ++c) {
+    const ChanOp& ch = op->chans[c];
+    cl[c].x = (int)tab.size();
+    if (ch.nrows == 0) continue;
+    std::vector<WorkItem> wk(ch.nwork);
+    WF_HIP(hipMemcpy(wk.data(), ch.work.p, sizeof(WorkItem) * wk.size(), hipMemcpyDeviceToHost));
+    std::vector<char> pr(ch.prune.bytes);
+    WF_HIP(hipMemcpy(pr.data(), ch.prune.p, pr.size(), hipMemcpyDeviceToHost));
+    for (int p = 0; p < ch.P; ++p) {
+      if (ch.bin_nrows[p] == 0) continue;
+      const int l = (int)tab.size();
+      const ColPrune cp = prune_of(op, ch, p);
+      SweepLayer L{};
+      DevBuf X, Y, A;
+      if ((st = dalloc(X, grid)) != WF_OK) return st;
+      W.grids.push_back(X);
+      if ((st = dalloc(Y, grid)) != WF_OK) return st;
+      W.grids.push_back(Y);
+      if ((st = dalloc(A, arow)) != WF_OK) return st;
+      W.grids.push_back(A);
+      WF_HIP(hipMemset(Y.p, 0, grid));
+      L.X = (float2*)X.p;
+      L.Y = (float2*)Y.p;
+      L.A = (float2*)A.p;
+      L.smask = cp.strip;
+      L.tile = cp.tile;
+      L.vals = ch.vals.p;
+      L.meta = (const uint32_t*)ch.meta.p;
+      L.voff = (const uint32_t*)ch.voff.p;
+      L.perm = (const int32_t*)ch.perm.p;
+      L.vis_off = ch.vis_off;
+      L.wp = ch.centroids[p];
+      L.chan = c;
+      tab.push_back(L);
+      const int32_t* grp = (const int32_t*)(pr.data() + ch.pr_groups[p]);
+      for (int g = 0; g < ch.pr_ngroups[p]; ++g) pairs.push_back(int2{l, grp[g]});
+      for (int k = 0; k < NCLS; ++k) {
+        const int n = ch.cls_nwi[p * NCLS + k];
+        for (int i = 0; i < n; ++i) {
+          WorkItem w = wk[ch.cls_wi0[p * NCLS + k] + i];
+          w.bin = l;
+          cls_items[k].push_back(w);
+        }
+      }
+    }
+    cl[c].y = (int)tab.size() - cl[c].x;
+  }
+  W.nlayers = (int)tab.size();
+  W.npairs = (int)pairs.size();
+  auto upload = [&](DevBuf& b, const void* src, size_t bytes) -> wf_status {
+    wf_status r = dalloc(b, std::max<size_t>(bytes, 16));
+    if (r != WF_OK) return r;
+    if (bytes) WF_HIP(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+    return WF_OK;
+  };
+  if ((st = upload(W.layers, tab.data(), sizeof(SweepLayer) * tab.size())) != WF_OK) return st;
+  if ((st = upload(W.pairs, pairs.data(), sizeof(int2) * pairs.size())) != WF_OK) return st;
+  if ((st = upload(W.chan_layers, cl.data(), sizeof(int2) * cl.size())) != WF_OK) return st;
+  for (int k = 0; k < NCLS; ++k) {
+    std::stable_sort(cls_items[k].begin(), cls_items[k].end(),
+                     [](const WorkItem& a, const WorkItem& b) { return a.nrows > b.nrows; });
+    W.nitems[k] = (int)cls_items[k].size();
+    if ((st = upload(W.items[k], cls_items[k].data(), sizeof(WorkItem) * cls_items[k].size())) !=
+        WF_OK)
+      return st;
+  }
+  if ((st = dalloc(W.queues, sizeof(int) * 2 * NCLS)) != WF_OK) return st;
+  WF_HIP(hipMemset(W.queues.p, 0, sizeof(int) * 2 * NCLS));
+  if ((st = dalloc(W.done, sizeof(int) * std::max(nchan, 1))) != WF_OK) return st;
+  WF_HIP(hipMemset(W.done.p, 0, sizeof(int) * std::max(nchan, 1)));
+  WF_HIP(hipDeviceGetAttribute(&W.ncu, hipDeviceAttributeMultiprocessorCount, op->device));
+  WF_HIP(hipDeviceSynchronize());
+  W.on = true;
+  return WF_OK;
+}
+
+// A whole apply as one launch per stage over every layer: forward rows, forward columns,
+// the row kernels per patch class (persistent), inverse columns, inverse rows summing
+// each channel's layers.  No stage waits on the host and nothing is allocated.
+wf_status run_sweep(wf_op* op, int kind, const float* in, float* out, hipStream_t s) {
+  const Sweep& W = op->sweep;
+  const int nchan = (int)op->chans.size();
+  const int nx = op->shape.nx, ny = op->shape.ny;
+  const SweepLayer* sl = (const SweepLayer*)W.layers.p;
+  const int2* pairs = (const int2*)W.pairs.p;
+  int* queues = (int*)W.queues.p;
+  unsigned long long* stamps = op->stamping ? (unsigned long long*)op->stamps.p : nullptr;
+  const int tsh = [&] { int t = 0; while ((1 << t) < op->tile) ++t; return t; }();
+  const int tiles_x = op->Kx / op->tile;
+  if (stamps) WF_HIP(launch_stamp(stamps + nchan, s));
+  const bool fwd = kind != WF_APPLY_ADJOINT;
+  const bool back = kind != WF_APPLY_FORWARD;
+  if (kind == WF_APPLY_FORWARD)
+    for (const ChanOp& ch : op->chans)
+      if (ch.nflag > 0)
+        WF_HIP(launch_scatter_zero((float2*)out + ch.vis_off, (const int32_t*)ch.flagged.p,
+                                   ch.nflag, s));
+  if (fwd) {
+    {
+      ProfScope ps(prof_of(op, 1), s);
+      WF_HIP(launch_sweep_fwd_rows(in, sl, W.nlayers, (const float2*)op->twx.p,
+                                   (const float*)op->sx.p, (const float*)op->sy.p, nx, ny,
+                                   op->Kx, op->shape.cell_rad, s));
+    }
+    ProfScope ps(prof_of(op, 2), s);
+    WF_HIP(launch_sweep_cols(false, sl, pairs, W.npairs, (const float2*)op->twy.p, ny, op->Ky,
+                             tsh, tiles_x, s));
+  }
+  {
+    const int mode = kind == WF_APPLY_FORWARD ? 1 : (kind == WF_APPLY_ADJOINT ? 2 : 0);
+    float2* vis = kind == WF_APPLY_FORWARD ? (float2*)out
+                  : (kind == WF_APPLY_ADJOINT ? (float2*)in : nullptr);
+    ProfScope ps(prof_of(op, 0), s);
+    for (int k = 0; k < NCLS; ++k)
+      WF_HIP(launch_rows_sweep(mode, k, (const WorkItem*)W.items[k].p, W.nitems[k], sl,
+                               op->opt.store, vis, queues + 2 * k, op->Kx, op->Ky, op->tile,
+                               W.ncu, s));
+  }
+  if (back) {
+    {
+      ProfScope ps(prof_of(op, 3), s);
+      WF_HIP(launch_sweep_cols(true, sl, pairs, W.npairs, (const float2*)op->twy.p, ny, op->Ky,
+                               tsh, tiles_x, s));
+    }
+    ProfScope ps(prof_of(op, 4), s);
+    WF_HIP(launch_sweep_inv_rows(sl, (const int2*)W.chan_layers.p, nchan, out,
+                                 kind == WF_APPLY_PSF_RE, (const float2*)op->twx.p,
+                                 (const float*)op->sx.p, (const float*)op->sy.p, nx, ny, op->Kx,
+                                 op->shape.cell_rad, stamps, (int*)W.done.p, s));
+  } else if (stamps) {
+    for (int c = 0; c < nchan; ++c) WF_HIP(launch_stamp(stamps + c, s));
+  }
+  return WF_OK;
+}
+
 // A whole apply: fork the branches off the caller's stream, issue every segment, join,
 // add the partial sums of split channels, and stamp each channel's completion.
 wf_status run_apply(wf_op* op, int kind, const float* in, float* out, hipStream_t s) {
+  if (op->sweep.on) return run_sweep(op, kind, in, out, s);
   wf_status st;
   const int nchan = (int)op->chans.size();
   unsigned long long* stamps = op->stamping ? (unsigned long long*)op->stamps.p : nullptr;
@@ -1839,6 +2013,35 @@ wf_status wf_profile_read(wf_op* op, int32_t kernel_id, int64_t* launches, doubl
   return guarded([&] { return wf_profile_read_body(op, kernel_id, launches, total_ms); });
 }
 
+static wf_status wf_set_sweep_body(wf_op* op, int32_t enable) {
+  wf_status st = check_op(op);
+  if (st != WF_OK) return st;
+  WF_HIP(hipSetDevice(op->device));
+  WF_HIP(hipDeviceSynchronize());
+  if (!enable) {
+    release_sweep(op);
+    op->generation++;
+    return WF_OK;
+  }
+  if (op->Kx != 2 * op->shape.nx || op->Ky != 2 * op->shape.ny || !sweep_size_ok(op->Kx) ||
+      !sweep_size_ok(op->Ky))
+    return fail(WF_ENOTSUP, "the sweep needs grid sides of 2048 .. 16384");
+  for (const ChanOp& ch : op->chans)
+    if (ch.otf || ch.holo)
+      return fail(WF_ENOTSUP, "the sweep needs every channel to store G (strategy (a))");
+  st = sweep_build(op);
+  op->generation++;
+  if (st != WF_OK) {
+    release_sweep(op);
+    return st;
+  }
+  return WF_OK;
+}
+
+wf_status wf_set_sweep(wf_op* op, int32_t enable) {
+  return guarded([&] { return wf_set_sweep_body(op, enable); });
+}
+
 static wf_status wf_set_branches_body(wf_op* op, int32_t branches) {
   wf_status st = check_op(op);
   if (st != WF_OK) return st;
@@ -1917,6 +2120,28 @@ static wf_status wf_graph_destroy_body(wf_graph* g) {
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
   return WF_OK;
+}
+
+static wf_status wf_graph_nodes_body(const wf_graph* g, int64_t* kernels, int64_t* total) {
+  if (!g || !g->graph) return fail(WF_EINVAL, "null graph");
+  if (!kernels || !total) return fail(WF_EINVAL, "null output");
+  size_t n = 0;
+  WF_HIP(hipGraphGetNodes(g->graph, nullptr, &n));
+  std::vector<hipGraphNode_t> nodes(n);
+  if (n > 0) WF_HIP(hipGraphGetNodes(g->graph, nodes.data(), &n));
+  int64_t k = 0;
+  for (size_t i = 0; i < n; ++i) {
+    hipGraphNodeType t;
+    WF_HIP(hipGraphNodeGetType(nodes[i], &t));
+    if (t == hipGraphNodeTypeKernel) ++k;
+  }
+  *kernels = k;
+  *total = (int64_t)n;
+  return WF_OK;
+}
+
+wf_status wf_graph_nodes(const wf_graph* g, int64_t* kernels, int64_t* total) {
+  return guarded([&] { return wf_graph_nodes_body(g, kernels, total); });
 }
 
 wf_status wf_graph_destroy(wf_graph* g) {
@@ -2001,22 +2226,29 @@ wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_str
       if (best != orig) ++retuned;
     }
     const int nchan = (int)op->chans.size();
-    std::vector<int> cands = {1, 2, 4};
-    if (nchan == 1) cands = {1, 2, 3, 4};
-    if (nchan >= 8) cands.push_back(8);
-    int best_nb = 1;
-    double best_ms = 1e300;
-    for (int nb : cands) {
-      if (nchan > 1 && nb > nchan) continue;
-      if ((st = set_branches(op, nb)) != WF_OK) return st;
-      double t = 0;
-      if ((st = time_runs(s, reps, sweep, &t)) != WF_OK) return st;
-      if (t < best_ms) {
-        best_ms = t;
-        best_nb = nb;
+    if (op->sweep.on) {
+      // a layer-batched sweep has no branches: only its item lists follow the new splits
+      WF_HIP(hipDeviceSynchronize());
+      if ((st = sweep_build(op)) != WF_OK) return st;
+      op->generation++;
+    } else {
+      std::vector<int> cands = {1, 2, 4};
+      if (nchan == 1) cands = {1, 2, 3, 4};
+      if (nchan >= 8) cands.push_back(8);
+      int best_nb = 1;
+      double best_ms = 1e300;
+      for (int nb : cands) {
+        if (nchan > 1 && nb > nchan) continue;
+        if ((st = set_branches(op, nb)) != WF_OK) return st;
+        double t = 0;
+        if ((st = time_runs(s, reps, sweep, &t)) != WF_OK) return st;
+        if (t < best_ms) {
+          best_ms = t;
+          best_nb = nb;
+        }
       }
+      if ((st = set_branches(op, best_nb)) != WF_OK) return st;
     }
-    if ((st = set_branches(op, best_nb)) != WF_OK) return st;
     double after = 0;
     if ((st = time_runs(s, reps, sweep, &after)) != WF_OK) return st;
     if (info) {

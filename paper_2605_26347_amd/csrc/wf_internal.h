@@ -54,6 +54,26 @@ __host__ __device__ inline uint32_t pack_meta(int lu0, int lv0, int T) {
 __host__ __device__ constexpr int class_mk(int c) {
   return c == 0 ? 2 : c == 1 ? 4 : c == 2 ? 7 : c == 3 ? 12 : c == 4 ? 16 : 22;
 }
+// One (channel, bin) layer of a sweep: its work grids, pruning masks, row data of G,
+// w-layer centroid, channel, and the offset of its channel's visibilities.  A sweep
+// holds the grids of every layer at once so that each stage of the apply runs as one
+// launch over all layers.
+struct SweepLayer {
+  float2* X;
+  float2* Y;
+  float2* A;
+  const uint32_t* smask;   // needed column strips (null: all)
+  const uint32_t* tile;    // needed tiles (null: all)
+  const void* vals;
+  const uint32_t* meta;
+  const uint32_t* voff;
+  const int32_t* perm;
+  int64_t vis_off;         // first visibility of the layer's channel in caller order
+  double wp;               // w-layer centroid
+  int32_t chan;
+  int32_t pad;
+};
+
 // Active uv support of one bin for the column passes: tiles that hold rows, dilated by
 // one tile (the LDS windows reach into neighbours), the column strips under them, and the
 // column groups (col_width columns each) that cover those strips.
@@ -199,6 +219,25 @@ struct Segment {
   std::vector<int> bins;
 };
 
+// Layer-batched applies (wf_set_sweep): the grids of every (channel, bin) layer at once,
+// the layer table, the (layer, column group) pairs of the column passes, each channel's
+// layer range, and per patch class the work items of all layers (bin = layer index),
+// largest first, drained by one persistent launch through a two-int queue.
+struct Sweep {
+  bool on = false;
+  int nlayers = 0;
+  std::vector<DevBuf> grids;         // per layer: X, Y, A
+  DevBuf layers;                     // SweepLayer [nlayers]
+  DevBuf pairs;                      // int2 [npairs]
+  int npairs = 0;
+  DevBuf chan_layers;                // int2 [nchan]: first layer, count
+  DevBuf items[NCLS];
+  int nitems[NCLS] = {0, 0, 0, 0, 0, 0};
+  DevBuf queues;                     // int [2 * NCLS]
+  DevBuf done;                       // int [nchan]: workgroups finished (completion stamps)
+  int ncu = 0;
+};
+
 }  // namespace wf
 
 struct wf_op {
@@ -223,6 +262,7 @@ struct wf_op {
   wf::DevBuf fb_h, fb_x, fb_c, fb_red;  // forward-backward work images and reductions
   size_t otf_bytes = 0;              // transient value buffer per branch (strategy (c))
   wf::DevBuf otf_mis;                // counters the on-the-fly value pass writes
+  wf::Sweep sweep;                   // layer-batched applies (wf_set_sweep)
 };
 
 // Residual-kernel network: FP32 parameters with Adam state, per-batch activations, and
@@ -318,6 +358,25 @@ hipError_t launch_happly(const HTile* ht, int ntiles, int Dmax, const void* hv, 
                          hipStream_t s);
 hipError_t launch_strip_to_rowmajor(const float2* src, float2* dst, int R, int Q,
                                     hipStream_t s);
+// Sweep stages (one launch over every layer; grid sides 2048 .. 16384 with K = 2 n).
+// Forward rows over all layers (images of all channels from img); forward or inverse
+// columns over the (layer, column group) pairs; inverse rows per (row, channel) summing
+// the channel's layers and writing its image once (stamps/done: completion clocks,
+// may be null); the row kernels in persistent form over one class's items of all layers
+// (queue: two ints, zero between launches; ncu: compute units).
+hipError_t launch_sweep_fwd_rows(const float* img, const SweepLayer* sl, int nlayers,
+                                 const float2* tw, const float* sx, const float* sy, int nx,
+                                 int ny, int Kx, double cell, hipStream_t s);
+hipError_t launch_sweep_cols(bool inverse, const SweepLayer* sl, const int2* pairs, int npairs,
+                             const float2* tw, int ny, int Ky, int tsh, int tiles_x,
+                             hipStream_t s);
+hipError_t launch_sweep_inv_rows(const SweepLayer* sl, const int2* chan_layers, int nchan,
+                                 void* out, bool real_out, const float2* tw, const float* sx,
+                                 const float* sy, int nx, int ny, int Kx, double cell,
+                                 unsigned long long* stamps, int* done, hipStream_t s);
+hipError_t launch_rows_sweep(int mode, int cls, const WorkItem* wi, int nwi,
+                             const SweepLayer* layers, wf_store store, float2* vis_base,
+                             int* queue, int Kx, int Ky, int tile, int ncu, hipStream_t s);
 
 // Kernels predicted by the residual-kernel network for a chunk of rows (null pred: every
 // row exact).  pred [rows of the chunk][451]; rows whose predicted log10 error exceeds

@@ -98,6 +98,9 @@ def test_null_handle_batched_calls():
     assert not g.value
     assert lib.wf_graph_launch(None, None) == _lib.WF_EINVAL
     assert lib.wf_graph_destroy(None) == _lib.WF_EINVAL
+    k, n = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    assert lib.wf_graph_nodes(None, ctypes.byref(k), ctypes.byref(n)) == _lib.WF_EINVAL
+    assert lib.wf_set_sweep(None, 1) == _lib.WF_EINVAL
     assert lib.wf_latency_enable(None, 1) == _lib.WF_EINVAL
     assert lib.wf_read_latency(None, None, 0) == _lib.WF_EINVAL
     assert lib.wf_autotune(None, None, None, None, 1, None) == _lib.WF_EINVAL
