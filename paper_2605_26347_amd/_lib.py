@@ -121,12 +121,16 @@ def load():
     # torch first: the library then binds to the HIP runtime torch has loaded (same
     # soname), so that one runtime owns the device, the tensors' memory and the streams
     import torch  # noqa: F401
-    lib = ctypes.CDLL(LIB_PATH)
+    _lib = bind(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def bind(lib):
+    """Declare the C signatures of every entry point on a loaded library."""
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    _lib = lib
     return lib
 
 

@@ -76,5 +76,56 @@ def build(verbose: bool = True) -> str:
     return OUT
 
 
+# Host-side AddressSanitizer build (CPU checks of the host C++: planner, partitioning,
+# argument paths).  Only host code is instrumented (each sanitizer flag is scoped to the
+# host pass); the device objects of the regular build are linked unchanged.
+HOST_SOURCES = [s for s in SOURCES if s.endswith(".cpp")]
+ASAN_DIR = os.path.join(BUILD, "asan")
+ASAN_OUT = os.path.join(ASAN_DIR, "libwf_asan.so")
+ASAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime() -> str:
+    """Path of the sanitizer runtime the instrumented library needs preloaded."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(_hipcc())), "..", "llvm", "bin",
+                         "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    r = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True, check=True)
+    return r.stdout.strip()
+
+
+def build_asan(verbose: bool = True) -> str:
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    dev = [os.path.join(BUILD, s + ".o") for s in SOURCES if s.endswith(".hip")]
+    if not all(os.path.exists(o) for o in dev):
+        build(verbose)
+
+    def host(src):
+        obj = os.path.join(ASAN_DIR, src + ".o")
+        cmd = ([_hipcc()] + _common() + SOURCES[src] + ASAN_HOST + ["-g", "-O1", "-c",
+               os.path.join(CSRC, src), "-o", obj])
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=len(HOST_SOURCES)) as ex:
+        objs = list(ex.map(host, HOST_SOURCES))
+    cmd = ([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host",
+            "-fsanitize=address", "-Xarch_host", "-shared-libasan", "-o", ASAN_OUT]
+           + objs + dev)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    if verbose:
+        print(f"built {ASAN_OUT}", file=sys.stderr)
+    return ASAN_OUT
+
+
 if __name__ == "__main__":
-    build()
+    if "--asan" in sys.argv:
+        build_asan()
+    else:
+        build()
