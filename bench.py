@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Φ†Φ applies/s, Gvis/s (4096², 50M vis): mixed vs FP32 at ≤1e-3 rel err"
 HBM_PEAK_GBS = 8000.0
+# arithmetic type of the path per value storage of G (phases and coordinates in FP64)
+DTYPE = {"f32": "f32", "f16": "f16-stored/f32-compute", "bf16": "bf16-stored/f32-compute"}
 FP64_VECTOR_PEAK_TFS = 78.6
 
 
@@ -50,13 +52,14 @@ def parse():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="precision",
                     choices=["precision", "batched", "learned", "holographic", "counters",
-                             "onthefly", "weighted"],
+                             "onthefly", "weighted", "cpu"],
                     help="precision: one channel 4096^2 / 50M rows (default); batched: "
                          "16 channels 2048^2 / 48M rows, autotuned, one graph per sweep; "
                          "learned: G of 20M rows on 4096^2 / 16 bins built with the "
                          "residual-kernel network vs the exact construction; onthefly: "
                          "the precision form with G rebuilt at every apply (strategy (c)); "
-                         "weighted: the precision form with Briggs weights and 10%% flags")
+                         "weighted: the precision form with Briggs weights and 10%% flags; "
+                         "cpu: the oracle's timing protocol on the host cores")
     ap.add_argument("--train-examples", type=int, default=1_000_000)
     ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--store", default="f16", help="value storage of the batched form")
@@ -184,49 +187,140 @@ def time_form(obs, store, args, torch):
     return res
 
 
-def cpu_baseline(obs, P_gpu):
-    """FP64 oracle on a bounded sample (about 10 s of host work): one full-size w-layer
-    (two 8192^2 FFTs and the layer's w-modulation) and the sparse products of up to 240k
-    rows of that layer (the most populated bin); scaled to a full apply as
-    P * t_layer_fft + M * t_row."""
+def accuracy_vs_oracle(forms, torch):
+    """Relative L2 error of Phi^dag Phi x against the FP64 oracle on the stored samples
+    (tests/golden/fullsize_*.npz, written by a script that calls only the oracle): all 50M
+    rows on the central 512^2 crop, and the 4096^2 image with a seeded 300k-row subset,
+    P = 22 w-bins as in the benchmark's plan, each value storage of G."""
+    import wfsynth as ws
+    from paper_2605_26347_amd import Operator
+    res = {}
+    for case in ("crop512", "sub4096"):
+        fx = np.load(os.path.join(ROOT, "tests", "golden", f"fullsize_{case}.npz"))
+        uvw, f, n, cell = ws.fullsize_case(case)
+        pix, _ = ws.fullsize_samples(n, uvw.shape[0])
+        x = torch.from_numpy(ws.gauss_image(n, 4).astype(np.float32)[None]).to("cuda:0")
+        pixd = torch.from_numpy(pix).to("cuda:0")
+        ref = fx["psf"]
+        for store in forms:
+            op = Operator(uvw, [f], n, n, cell, nbins=ws.FULLSIZE_P, store=store)
+            got = op.psf_apply(x)[0].flatten()[pixd].cpu().numpy()
+            op.close()
+            del op
+            torch.cuda.empty_cache()
+            e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            res[f"{store}_{case}"] = e
+            log(f"accuracy {case} {store}: Phi^dag Phi rel L2 vs FP64 oracle {e:.2e}")
+    return res
+
+
+def _warm_median(fn, reps=3):
+    """One untimed warm-up call, then the median wall time of `reps` calls (seconds)."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts))
+
+
+def _host_threads():
     import threadpoolctl
+    blas = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
+    return {"os_cpu_count": os.cpu_count(), "fft_workers": os.cpu_count(),
+            "blas_threads": int(blas), "sparse_products": "one thread (numpy)"}
+
+
+def oracle_full(obs, nbins, smax, cache_bytes=2 << 30):
+    """Seconds per oracle Phi^dag Phi apply of a whole configuration (G's patches cached
+    by the warm-up call when they fit `cache_bytes`, as G is stored on the GPU)."""
+    from oracle import OracleOperator, OperatorParams
+    prm = OperatorParams(obs.nx, obs.ny, obs.cell_rad, smax=smax)
+    orc = OracleOperator(obs.uvw_m, obs.freqs_hz[0], prm, nbins=nbins,
+                         cache_bytes=cache_bytes)
+    return _warm_median(lambda: orc.psf(obs.sky))
+
+
+def oracle_sampled(uvw, f, n, cell, centroids, nsamp, M_total, x):
+    """Seconds per oracle apply extrapolated from a bounded sample: every layer's FFT pair
+    and modulation at full size is timed on the most populated layer, the G^dag G products
+    on `nsamp` seeded rows of that layer; t = P t_layer + M t_row."""
     from oracle import OracleOperator, OperatorParams, wbins
     from oracle.operator import C_LIGHT
-    nsamp = 240_000
-    prm = OperatorParams(obs.nx, obs.ny, obs.cell_rad)
-    w_all = obs.uvw_m[:, 2] * (obs.freqs_hz[0] / C_LIGHT)
-    mask = wbins.plan_subset_mask(w_all.size, 0.01, 0)
-    cents = wbins.kmeans_1d(w_all[mask], P_gpu)
-    b = wbins.assign_bins(w_all, cents)
-    pbig = int(np.argmax(np.bincount(b, minlength=P_gpu)))
+    P = len(centroids)
+    b = wbins.assign_bins(uvw[:, 2] * (f / C_LIGHT), centroids)
+    pbig = int(np.argmax(np.bincount(b, minlength=P)))
     cand = np.nonzero(b == pbig)[0]
     rng = np.random.default_rng(11)
     rows = np.sort(rng.choice(cand, min(nsamp, cand.size), replace=False))
-    orc = OracleOperator(obs.uvw_m[rows], obs.freqs_hz[0], prm, centroids=cents)
-    x = obs.sky
-    info = threadpoolctl.threadpool_info()
-    cores = max([i.get("num_threads", 1) for i in info] + [1])
+    orc = OracleOperator(uvw[rows], f, OperatorParams(n, n, cell), centroids=centroids)
     p = int(np.argmax([r.size for r in orc.bin_rows]))
-    t0 = time.perf_counter()
     z = orc.zp(p)
     X = orc.fwd_fft(z * x)
-    t1 = time.perf_counter()
-    Y = orc.gtg(p, X)
-    t2 = time.perf_counter()
-    _ = np.conj(z) * orc.inv_fft_crop(Y)
-    t3 = time.perf_counter()
-    t_fft = (t1 - t0) + (t3 - t2)
-    t_row = (t2 - t1) / orc.bin_rows[p].size
+    t_fft = _warm_median(lambda: np.conj(z) * orc.inv_fft_crop(orc.fwd_fft(orc.zp(p) * x)))
+    t_rows = _warm_median(lambda: orc.gtg(p, X))
+    t_row = t_rows / orc.bin_rows[p].size
+    return P * t_fft + M_total * t_row, t_fft, t_row, int(orc.bin_rows[p].size)
+
+
+def cpu_baseline(obs, P_gpu):
+    """FP64 oracle on the host cores (1 warm-up, median of 3 for every timed part): the
+    headline apply extrapolated from a bounded sample, and the tiny configuration timed
+    in full.  The full protocol (the 1024^2 configuration in full, the 512^2 crop) is the
+    'cpu' workload, too long for the default run."""
+    import wfsynth as ws
+    from oracle import wbins
+    from oracle.operator import C_LIGHT
+    t0 = time.perf_counter()
+    f = float(obs.freqs_hz[0])
+    w_all = obs.uvw_m[:, 2] * (f / C_LIGHT)
+    mask = wbins.plan_subset_mask(w_all.size, 0.01, 0)
+    cents = wbins.kmeans_1d(w_all[mask], P_gpu)
     M = obs.uvw_m.shape[0]
-    t_apply = P_gpu * t_fft + M * t_row
-    log(f"cpu oracle: layer FFT+modulation {t_fft:.2f} s, {1e6 * t_row:.2f} us/row "
-        f"({orc.bin_rows[p].size} rows) -> {t_apply:.0f} s per full apply")
-    return {"value": 1.0 / t_apply, "unit": "applies/s", "cores": int(cores),
-            "kind": "oracle",
+    t_apply, t_fft, t_row, nrow = oracle_sampled(obs.uvw_m, f, obs.nx, obs.cell_rad, cents,
+                                                 80_000, M, obs.sky)
+    t_tiny = oracle_full(ws.tiny(), 1, 1)
+    log(f"cpu oracle: layer FFT pair + modulation {t_fft:.2f} s, {1e6 * t_row:.2f} us/row "
+        f"({nrow} rows) -> {t_apply:.0f} s per full apply (extrapolated); tiny "
+        f"configuration {1e3 * t_tiny:.1f} ms per apply")
+    return {"value": 1.0 / t_apply, "unit": "applies/s", "cores": os.cpu_count(),
+            "kind": "oracle", "extrapolated": True,
             "sample": (f"one full-size w-layer (4096^2 image, 8192^2 FFTs) plus the G^dag G "
-                       f"products of {orc.bin_rows[p].size} seeded rows of that (most populated) "
-                       f"layer, scaled to P={P_gpu} layers and {M} rows: P*t_layer + M*t_row"),
-            "seconds": t3 - t0}
+                       f"products of {nrow} seeded rows of that (most populated) layer, "
+                       f"scaled to P={P_gpu} layers and {M} rows: P*t_layer + M*t_row; "
+                       f"1 warm-up, median of 3"),
+            "threads": _host_threads(),
+            "tiny_full_apply_s": t_tiny,
+            "seconds": time.perf_counter() - t0}
+
+
+def bench_cpu(args):
+    """The oracle's timing protocol on the host cores, no GPU: the tiny configuration and
+    the 1024^2 / 2M-row configuration in full (8 bins, residual kernels up to 15), the
+    512^2 crop of the precision form (all 50M rows, P = 22) extrapolated from 1M seeded
+    rows, and the 4096^2 precision form extrapolated as in the bench line."""
+    import wfsynth as ws
+    res = {"threads": _host_threads()}
+    o = ws.tiny()
+    res["tiny_64sq_19200"] = {"s_per_apply": oracle_full(o, 1, 1), "kind": "full"}
+    log(f"tiny: {res['tiny_64sq_19200']}")
+    o = ws.widefield()
+    res["widefield_1024sq_2M_8bins"] = {"s_per_apply": oracle_full(o, 8, 15, 96 << 30),
+                                        "kind": "full"}
+    log(f"widefield: {res['widefield_1024sq_2M_8bins']}")
+    fx = np.load(os.path.join(ROOT, "tests", "golden", "fullsize_crop512.npz"))
+    uvw, f, n, cell = ws.fullsize_case("crop512")
+    x = ws.gauss_image(n, 4)
+    t, t_fft, t_row, nrow = oracle_sampled(uvw, f, n, cell, fx["centroids"], 1_000_000,
+                                           uvw.shape[0], x)
+    res["crop512_50M_22bins"] = {"s_per_apply": t, "kind": "extrapolated",
+                                 "t_layer_s": t_fft, "t_row_us": 1e6 * t_row, "rows": nrow}
+    log(f"crop512: {res['crop512_50M_22bins']}")
+    del uvw
+    obs = ws.precision_form()
+    res["precision_4096sq_50M_22bins"] = cpu_baseline(obs, ws.FULLSIZE_P)
+    print(json.dumps({"workload": "oracle timing protocol", "results": res}), flush=True)
 
 
 def fft_bytes_per_bin(nx, ny):
@@ -282,42 +376,67 @@ def bench_batched(args, torch):
     log(f"eager {eager_before:.2f} ms (default branches), {serial:.2f} ms (one branch); "
         f"autotune {tune}")
     op.latency_enable(True)
-    g = op.capture("psf_re", x, out, stream)
+
+    def graph_run(label):
+        g = op.capture("psf_re", x, out, stream)
+        kern, nodes = g.nodes()
+        for _ in range(args.warmup):
+            g.launch(stream)
+        ms = timed(lambda: g.launch(stream), args.steps)
+        d = float((out - ref).norm() / ref.norm())
+        lat = []
+        for _ in range(max(5, args.steps // 2)):
+            g.launch(stream)
+            stream.synchronize()
+            lat.append(op.read_latency())
+        lat = np.concatenate(lat)
+        g.close()
+        log(f"{label}: graph sweep {ms:.2f} ms ({1e3 / ms:.2f} sweeps/s), {kern} kernel "
+            f"nodes ({nodes} nodes), vs one-branch eager rel {d:.2e}, latency p50 "
+            f"{np.percentile(lat, 50):.2f} p99 {np.percentile(lat, 99):.2f}")
+        return dict(ms=ms, rel=d, kernels=kern, nodes=nodes,
+                    latency_ms={"p50": float(np.percentile(lat, 50)),
+                                "p99": float(np.percentile(lat, 99)),
+                                "max": float(lat.max())})
+
+    br = graph_run(f"branches ({tune['branches']})")
+    # the persistent form: every layer's grids resident, one launch per FFT stage over all
+    # layers and one persistent launch per patch class draining all (channel, bin) items
+    t0 = time.time()
+    op.set_sweep(True)
+    t_sw = time.time() - t0
     for _ in range(args.warmup):
-        g.launch(stream)
-    ms = timed(lambda: g.launch(stream), args.steps)
-    d = float((out - ref).norm() / ref.norm())
-    lat = []
-    for _ in range(max(5, args.steps // 2)):
-        g.launch(stream)
-        stream.synchronize()
-        lat.append(op.read_latency())
-    lat = np.concatenate(lat)
-    g.close()
+        op.psf_apply_re(x, out, stream=stream)
+    eager_sweep = timed(lambda: op.psf_apply_re(x, out, stream=stream), max(2, args.steps // 4))
+    sw = graph_run("persistent sweep")
+    ms = sw["ms"]
     plans = [op.plan(c) for c in range(nchan)]
     bv = 8 if args.store == "f32" else 4
     nbins_active = sum(int((op.bin_rows(c) > 0).sum()) for c in range(nchan))
     gbytes = sum(bv * p["ntaps"] + 8 * p["nrows"] + 32 * p["nwork"] for p in plans)
     fbytes = nbins_active * fft_bytes_per_bin(obs.nx, obs.ny)
     achieved = (gbytes + fbytes) / (ms * 1e-3) / 1e9
-    log(f"graph sweep {ms:.2f} ms ({1e3 / ms:.2f} sweeps/s), graph vs one-branch eager "
-        f"rel {d:.2e}, latency p50 {np.percentile(lat, 50):.2f} p99 {np.percentile(lat, 99):.2f}")
     line = {
-        "metric": "Φ†Φ sweeps/s and p50/p99 per-channel latency (16 × 2048², 48M vis)",
+        "metric": "\u03a6\u2020\u03a6 sweeps/s and p50/p99 per-channel latency "
+                  "(16 \u00d7 2048\u00b2, 48M vis)",
         "value": 1e3 / ms, "unit": "sweeps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.store],
+        "data": "synthetic",
         "config": {"workload": f"Re{{Phi^dag Phi x}} sweep over {nchan} channels "
                                f"0.9-1.67 GHz, {obs.nx}^2 image each, {M} visibilities "
                                f"(uneven per channel), 3 deg field",
                    "store": args.store, "nchan": nchan, "nvis": M,
                    "nbins": [p["nbins"] for p in plans]},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)),
-                       "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
+        "latency_ms": sw["latency_ms"],
+        "graph": {"kernel_nodes": sw["kernels"], "nodes": sw["nodes"]},
         "gvis_per_s": 1e3 / ms * M / 1e9,
+        "sweep_build_s": t_sw, "eager_ms_sweep": eager_sweep,
+        "branch_graph": {"ms": br["ms"], "kernel_nodes": br["kernels"], "nodes": br["nodes"],
+                         "latency_ms": br["latency_ms"], "branches": tune["branches"]},
         "eager_ms_default_branches": eager_before, "eager_ms_one_branch": serial,
-        "speedup_graph_vs_one_branch": serial / ms,
-        "autotune": tune, "graph_vs_eager_rel": d, "build_s": tb,
+        "speedup_vs_branch_graph": br["ms"] / ms,
+        "autotune": tune, "graph_vs_eager_rel": sw["rel"], "build_s": tb,
         "roofline": {"bound": "hbm", "kernel": "whole sweep (all kernels)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -648,6 +767,9 @@ def main():
         sys.exit(2)
     import torch
     import wfsynth as ws
+    if args.workload == "cpu":
+        bench_cpu(args)
+        return
     if args.workload == "batched":
         bench_batched(args, torch)
         return
@@ -684,13 +806,11 @@ def main():
     head = res[forms[0]]
     M = obs.uvw_m.shape[0]
     aps = 1e3 / head["ms"]
-    acc = {}
-    if "f32" in res:
-        ref = res["f32"]["out"]
-        for f in forms:
-            if f != "f32":
-                d = (res[f]["out"] - ref).norm() / ref.norm()
-                acc[f"{f}_vs_f32"] = float(d)
+    for r in res.values():
+        r.pop("out", None)
+    torch.cuda.empty_cache()
+    acc = {"vs_fp64_oracle": accuracy_vs_oracle(["f32", "f16", "bf16"], torch),
+           "samples": "32768 seeded pixels of Phi^dag Phi x per case"}
     nl = head["gtg_launches"]
     kms = head["gtg_ms_total"] / max(nl, 1)
     bytes_per_apply = gtg_bytes(head["info"], head["store"])
@@ -702,7 +822,7 @@ def main():
         "metric": METRIC, "value": aps, "unit": "applies/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": DTYPE[head["store"]], "data": "synthetic",
         "config": {"workload": f"Re{{Phi^dag Phi x}}, {obs.nx}^2 image, {M} visibilities, "
                                f"3 deg field, 64-antenna array 16 h, 1.28 GHz",
                    "store": head["store"], "nbins": P, "image": obs.nx, "nvis": M},
@@ -722,6 +842,12 @@ def main():
                      "timed": "one branch, HIP events around each launch on its stream",
                      "share_of_step": kms * P / head["ms"]},
     }
+    # whole apply: G's bytes plus the four FFT passes of every layer
+    e2e = (bytes_per_apply + P * fft_bytes_per_bin(obs.nx, obs.ny)) / (head["ms"] * 1e-3) / 1e9
+    line["end_to_end"] = {"achieved": e2e, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": e2e / HBM_PEAK_GBS,
+                          "bytes_per_apply": bytes_per_apply
+                          + P * fft_bytes_per_bin(obs.nx, obs.ny)}
     if "f32" in res and forms[0] != "f32":
         line["speedup_mixed_vs_f32"] = res["f32"]["ms"] / head["ms"]
     if not args.no_cpu:
