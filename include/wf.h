@@ -341,15 +341,30 @@ typedef struct {
   int32_t retuned_chans;   /* channels whose work-item size changed                   */
   double sweep_ms_before;  /* Re{Phi^dag Phi} sweep (all channels) before tuning      */
   double sweep_ms_after;   /* ... and after                                           */
+  int32_t wide_tile_bins;  /* bins whose work items now cover 2 x 2 base tiles        */
 } wf_tune_info;
 
 /* Autotuner: by timing Re{Phi^dag Phi} applies on d_img (real FP32 [nchan][ny][nx])
  * into the caller's scratch d_out (same shape), choose per channel the rows per work
- * item (256, 512 or 1024: only the work-item split of the stored rows changes, never
- * their values) and then the branch count (1, 2, 4, and 8 when nchan >= 8).  reps timed
- * applies per candidate (>= 1).  Synchronous; invalidates graphs captured earlier. */
+ * item (256, 512 or 1024) and per bin the work items' tile side (the base tile, or 2 x 2
+ * base tiles where the LDS accumulator of such an item fits), from the fused kernel's
+ * time on every bin under each combination; only the work-item split of the stored rows
+ * and their patch words change, never their values.  Then, unless the operator runs as
+ * a layer-batched sweep (wf_set_sweep, whose item lists are rebuilt instead), the branch
+ * count (1, 2, 4, and 8 when nchan >= 8).  reps timed runs per candidate (>= 1).
+ * Synchronous; invalidates graphs captured earlier. */
 wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_stream,
                       int32_t reps, wf_tune_info* info);
+
+/* Work-item tile side per bin of channel chan (tiles[P], cap >= P): the grid block that
+ * one work item of the fused, gridding and de-gridding kernels covers -- the operator's
+ * tile, or twice it (2 x 2 base tiles).  wf_set_bin_tiles sets them (each entry the
+ * tile or twice the tile; twice the tile only where the LDS accumulator fits, and for
+ * strategy (a) channels; n = P) and re-splits the channel's rows, keeping its rows per
+ * item; synchronous, invalidates graphs captured earlier.  Results equal the
+ * base-tile split up to the order of FP32 additions. */
+wf_status wf_get_bin_tiles(const wf_op* op, int32_t chan, int32_t* tiles, int32_t cap);
+wf_status wf_set_bin_tiles(wf_op* op, int32_t chan, const int32_t* tiles, int32_t n);
 
 /* ------------------------------------------------------------------ forward-backward
  * The operator's consumer (Sect. 2, eq. 4): x <- D(x + gamma (x_dirty - Re{Phi^dag Phi x}))

@@ -321,6 +321,19 @@ class Operator:
                                         self.nchan), "wf_read_latency")
         return out
 
+    def bin_tiles(self, chan=0):
+        """Work-item tile side of every bin of a channel (include/wf.h, wf_get_bin_tiles)."""
+        P = self.plan(chan)["nbins"]
+        out = np.zeros(P, dtype=np.int32)
+        check(self._lib.wf_get_bin_tiles(self._h, chan, out.ctypes.data_as(ctypes.c_void_p),
+                                         P), "wf_get_bin_tiles")
+        return out
+
+    def set_bin_tiles(self, tiles, chan=0):
+        t = np.ascontiguousarray(tiles, dtype=np.int32)
+        check(self._lib.wf_set_bin_tiles(self._h, chan, t.ctypes.data_as(ctypes.c_void_p),
+                                         t.size), "wf_set_bin_tiles")
+
     def autotune(self, img, out, reps=3, stream=None) -> dict:
         import torch
         pi, po = _device_tensors(

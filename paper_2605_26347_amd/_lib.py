@@ -49,7 +49,8 @@ class WfPlanInfo(ctypes.Structure):
 
 class WfTuneInfo(ctypes.Structure):
     _fields_ = [("branches", ctypes.c_int32), ("retuned_chans", ctypes.c_int32),
-                ("sweep_ms_before", ctypes.c_double), ("sweep_ms_after", ctypes.c_double)]
+                ("sweep_ms_before", ctypes.c_double), ("sweep_ms_after", ctypes.c_double),
+                ("wide_tile_bins", ctypes.c_int32)]
 
 
 APPLY = {"forward": 0, "adjoint": 1, "psf": 2, "psf_re": 3}
@@ -89,6 +90,8 @@ SIGNATURES = {
     "wf_latency_enable": (_I32, [_P, _I32]),
     "wf_read_latency": (_I32, [_P, _P, _I32]),
     "wf_autotune": (_I32, [_P, _P, _P, _P, _I32, ctypes.POINTER(WfTuneInfo)]),
+    "wf_get_bin_tiles": (_I32, [_P, _I32, _P, _I32]),
+    "wf_set_bin_tiles": (_I32, [_P, _I32, _P, _I32]),
     "wf_dirty_image": (_I32, [_P, _P, _P, _P]),
     "wf_op_norm": (_I32, [_P, _I32, ctypes.POINTER(_D), _P]),
     "wf_fb_iterate": (_I32, [_P, _P, _P, _I32, _D, _D, _P]),

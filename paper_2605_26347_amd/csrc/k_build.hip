@@ -565,9 +565,7 @@ __global__ __launch_bounds__(64, NK <= 15 ? 4 : 1) void k_rowsym(const double* _
       const int64_t rvm = ((rv % Ky) + Ky) % Ky;
       const uint64_t tu = (uint64_t)(rum / tile), lu = (uint64_t)(rum % tile);
       const uint64_t tv = (uint64_t)(rvm / tile), lv = (uint64_t)(rvm % tile);
-      // key: bin 8 | tile v 10 | tile u 10 | patch side 6 | local v 7 | local u 7 | 16 zero
-      keys[k] = ((uint64_t)g.p << 56) | (tv << 46) | (tu << 36) | ((uint64_t)T << 30) |
-                (lv << 23) | (lu << 16);
+      keys[k] = row_key(g.p, T, (uint32_t)tv, (uint32_t)tu, (uint32_t)lv, (uint32_t)lu);
       const float df = (float)dropped;
       dropped_out[k] = (nk_full > kp.smax) ? -df - 1e-30f : df;
     }

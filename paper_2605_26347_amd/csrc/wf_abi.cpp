@@ -163,15 +163,21 @@ struct ProfScope {
 };
 
 // Split the channel's row groups into work items of at most maxrows rows and 2^17
-// values (so that the classes of wide patches, few rows each, still fill the device) (the row kernels keep a wavefront's metadata for at most 128 rows in
-// registers), then order them by (bin, patch class) -- one launch per class -- with the
-// largest items of a launch first so that the hardware's in-order dispatch starts the
-// longest work first.  trow: patch side of each sorted row.  Writes each row's value
-// offset inside its item (voff) and, if row_wi is given, its item index.  An
+// values (so that the classes of wide patches, few rows each, still fill the device; the
+// row kernels keep a wavefront's metadata for at most 128 rows in registers), then order
+// them by (bin, patch class) -- one launch per class -- with the largest items of a
+// launch first so that the hardware's in-order dispatch starts the longest work first.
+// An item covers the rows of one patch class in one aligned block of 2^s x 2^s base
+// tiles (s = ch.bin_tsh of its bin, 0 when empty); the rows of such a block are
+// consecutive because the sort orders each class's tiles by interleaved index.
+// trow: patch side of each sorted row; meta_base: patch words relative to each row's
+// base-tile window.  Writes the words relative to the item's window (meta_out), each
+// row's value offset inside its item (voff) and, if row_wi is given, its item index.  An
 // on-the-fly channel (ch.gchunk set) orders by (chunk, class, size) instead and records
 // each chunk's item range per class.
-void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t maxrows,
-                 std::vector<WorkItem>& wis, uint32_t* voff, int32_t* row_wi) {
+void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta_base, int64_t maxrows,
+                 int tile, int halo, std::vector<WorkItem>& wis, uint32_t* voff,
+                 uint32_t* meta_out, int32_t* row_wi) {
   const int64_t maxtaps = 1 << 17;
   const bool chunked = !ch.gchunk.empty();
   std::vector<WorkItem> w0;
@@ -184,12 +190,23 @@ void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t 
                               ((uint32_t)(bb[2] - bb[0]) << 16) |
                               ((uint32_t)(bb[3] - bb[1]) << 24));
   };
+  int64_t prev_block = -1;
   for (size_t gi = 0; gi < ch.groups.size(); ++gi) {
     const RowGroup& g = ch.groups[gi];
-    int64_t abs = g.voff, taps_in = 0;
+    const int sh = ch.bin_tsh.empty() ? 0 : ch.bin_tsh[g.bin];
+    const int tu = (g.u0 + halo) / tile, tv = (g.v0 + halo) / tile;
+    const int su = (tu >> sh) << sh, sv = (tv >> sh) << sh;
+    // (bin, class, block, chunk) of this group; a new block opens a new item
+    const int64_t block = ((((int64_t)g.bin * NCLS + g.cls) * 1024 + sv) * 1024 + su) * 4096 +
+                          (chunked ? ch.gchunk[gi] : 0);
+    const bool open = block != prev_block;
+    prev_block = block;
+    const uint32_t shift = (uint32_t)((tu - su) * tile) | ((uint32_t)((tv - sv) * tile) << 8);
+    int64_t abs = g.voff;
+    int64_t taps_in = open || w0.empty() ? 0 : wtaps.back();
     for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) {
       const int64_t t2 = (int64_t)trow[r] * trow[r];
-      if (r == g.row0 || w0.back().nrows >= maxrows || taps_in + t2 > maxtaps) {
+      if ((open && r == g.row0) || w0.back().nrows >= maxrows || taps_in + t2 > maxtaps) {
         close_box();
         bb[0] = bb[1] = 255;
         bb[2] = bb[3] = 0;
@@ -197,8 +214,8 @@ void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t 
         wi.voff = abs;
         wi.row0 = (int32_t)r;
         wi.nrows = 0;
-        wi.u0 = g.u0;
-        wi.v0 = g.v0;
+        wi.u0 = su * tile - halo;
+        wi.v0 = sv * tile - halo;
         wi.bin = g.bin;
         w0.push_back(wi);
         wcls.push_back(g.cls);
@@ -207,7 +224,8 @@ void split_items(ChanOp& ch, const uint8_t* trow, const uint32_t* meta, int64_t 
         taps_in = 0;
       }
       {
-        const uint32_t m = meta[r];
+        const uint32_t m = meta_base[r] + shift;
+        meta_out[r] = m;
         const int lu0 = (int)(m & 0xff), lv0 = (int)((m >> 8) & 0xff);
         const int T = (int)((m >> 16) & 0xff);
         bb[0] = std::min(bb[0], lu0);
@@ -535,7 +553,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
 
   std::vector<int32_t> idx(M);
   std::iota(idx.begin(), idx.end(), 0);
-  radix_sort_pairs(keys, idx, 16);
+  radix_sort_pairs(keys, idx, KEY_LO_BIT);
 
   // rows grouped in runs of one (bin, tile, patch class); the work items split the
   // groups (split_items)
@@ -552,10 +570,11 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   for (int64_t sidx = 0; sidx < M; ++sidx) {
     const uint64_t k = keys[sidx];
     const int bin = (int)(k >> 56);
-    const int tv = (int)((k >> 46) & 1023), tu = (int)((k >> 36) & 1023);
-    const int T = (int)((k >> 30) & 63);
-    const int lv = (int)((k >> 23) & 127), lu = (int)((k >> 16) & 127);
-    const uint64_t grp = k >> 36;
+    int tv, tu;
+    tile_unmorton((uint32_t)((k >> 33) & 0xfffff), &tv, &tu);
+    const int T = (int)((k >> 27) & 63);
+    const int lv = (int)((k >> 20) & 127), lu = (int)((k >> 13) & 127);
+    const uint64_t grp = k >> 33;   // bin, class, base tile
     const int cls = tap_class(T);
     if (grp != cur || cls != curcls) {
       RowGroup g{};
@@ -615,7 +634,9 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   }
   std::vector<WorkItem> wis;
   ch.max_rows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
-  split_items(ch, trow.data(), meta.data(), ch.max_rows, wis, voff.data(), row_wi.data());
+  ch.bin_tsh.assign(ch.P, 0);
+  split_items(ch, trow.data(), meta.data(), ch.max_rows, tile, halo, wis, voff.data(),
+              meta.data(), row_wi.data());
 
   // active uv support per bin: tiles holding rows, dilated to cover the LDS windows'
   // halo, the column strips under them and the column groups of the column passes
@@ -940,6 +961,11 @@ Lane lane_of(wf_op* op, int b, hipStream_t caller) {
 
 Profiler* prof_of(wf_op* op, int k) { return op->capturing ? nullptr : &op->prof[k]; }
 
+// Side of the grid block that one work item of bin p covers.
+int bin_tile(const wf_op* op, const ChanOp& ch, int p) {
+  return op->tile << (ch.bin_tsh.empty() ? 0 : ch.bin_tsh[p]);
+}
+
 // One w-layer's forward half: X_p = F Z_p x (only inside the bin's support if pr).
 wf_status layer_forward(wf_op* op, const Lane& L, const float* x, double wp,
                         const ColPrune* pr) {
@@ -1069,7 +1095,8 @@ wf_status bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
       if (n == 0) continue;
       WF_HIP(launch_grid(c, wk + ch.cls_wi0[p * NCLS + c], n, (const uint32_t*)ch.meta.p,
                          (const uint32_t*)ch.voff.p, (const int32_t*)ch.perm.p, ch.vals.p,
-                         op->opt.store, (const float2*)in, L.Y, op->Kx, op->Ky, op->tile, L.s));
+                         op->opt.store, (const float2*)in, L.Y, op->Kx, op->Ky,
+                         bin_tile(op, ch, p), L.s));
     }
     return layer_adjoint(op, L, out, wp, first ? 0 : 1, &pr);
   }
@@ -1088,7 +1115,7 @@ wf_status bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
       if (n == 0) continue;
       WF_HIP(launch_gtg(c, wk + ch.cls_wi0[p * NCLS + c], n, (const uint32_t*)ch.meta.p,
                         (const uint32_t*)ch.voff.p, ch.vals.p, op->opt.store, L.X, L.Y,
-                        op->Kx, op->Ky, op->tile, L.s));
+                        op->Kx, op->Ky, bin_tile(op, ch, p), L.s));
     }
   }
   const int mode = (kind == WF_APPLY_PSF_RE ? 2 : 0) + (first ? 0 : 1);
@@ -1121,7 +1148,7 @@ void release_sweep(wf_op* op) {
   dfree(W.layers);
   dfree(W.pairs);
   dfree(W.chan_layers);
-  for (int c = 0; c < NCLS; ++c) {
+  for (int c = 0; c < Sweep::NLIST; ++c) {
     dfree(W.items[c]);
     W.nitems[c] = 0;
   }
@@ -1136,8 +1163,8 @@ bool sweep_size_ok(int K) { return K == 2048 || K == 4096 || K == 8192 || K == 1
 
 // Lay out a sweep: the grids of every non-empty (channel, bin) layer, the layer table,
 // the column pairs of each layer's active column groups, each channel's layer range and,
-// per patch class, every layer's work items (bin field = layer), largest first.  The
-// caller has synchronised the device.
+// per (patch class, item tile), every layer's work items (bin field = layer), largest
+// first.  The caller has synchronised the device.
 wf_status sweep_build(wf_op* op) {
   release_sweep(op);
   Sweep& W = op->sweep;
@@ -1147,7 +1174,7 @@ wf_status sweep_build(wf_op* op) {
   const size_t arow = sizeof(float2) * (size_t)op->shape.ny * op->Kx;
   std::vector<SweepLayer> tab;
   std::vector<int2> pairs, cl(nchan, int2{0, 0});
-  std::vector<WorkItem> cls_items[NCLS];
+  std::vector<WorkItem> cls_items[Sweep::NLIST];
   for (int c = 0; c < nchan; ++c) {
     const ChanOp& ch = op->chans[c];
     cl[c].x = (int)tab.size();
@@ -1189,7 +1216,7 @@ wf_status sweep_build(wf_op* op) {
         for (int i = 0; i < n; ++i) {
           WorkItem w = wk[ch.cls_wi0[p * NCLS + k] + i];
           w.bin = l;
-          cls_items[k].push_back(w);
+          cls_items[2 * k + (ch.bin_tsh.empty() ? 0 : ch.bin_tsh[p])].push_back(w);
         }
       }
     }
@@ -1206,7 +1233,7 @@ wf_status sweep_build(wf_op* op) {
   if ((st = upload(W.layers, tab.data(), sizeof(SweepLayer) * tab.size())) != WF_OK) return st;
   if ((st = upload(W.pairs, pairs.data(), sizeof(int2) * pairs.size())) != WF_OK) return st;
   if ((st = upload(W.chan_layers, cl.data(), sizeof(int2) * cl.size())) != WF_OK) return st;
-  for (int k = 0; k < NCLS; ++k) {
+  for (int k = 0; k < Sweep::NLIST; ++k) {
     std::stable_sort(cls_items[k].begin(), cls_items[k].end(),
                      [](const WorkItem& a, const WorkItem& b) { return a.nrows > b.nrows; });
     W.nitems[k] = (int)cls_items[k].size();
@@ -1214,8 +1241,8 @@ wf_status sweep_build(wf_op* op) {
         WF_OK)
       return st;
   }
-  if ((st = dalloc(W.queues, sizeof(int) * 2 * NCLS)) != WF_OK) return st;
-  WF_HIP(hipMemset(W.queues.p, 0, sizeof(int) * 2 * NCLS));
+  if ((st = dalloc(W.queues, sizeof(int) * 2 * Sweep::NLIST)) != WF_OK) return st;
+  WF_HIP(hipMemset(W.queues.p, 0, sizeof(int) * 2 * Sweep::NLIST));
   if ((st = dalloc(W.done, sizeof(int) * std::max(nchan, 1))) != WF_OK) return st;
   WF_HIP(hipMemset(W.done.p, 0, sizeof(int) * std::max(nchan, 1)));
   WF_HIP(hipDeviceGetAttribute(&W.ncu, hipDeviceAttributeMultiprocessorCount, op->device));
@@ -1261,10 +1288,10 @@ wf_status run_sweep(wf_op* op, int kind, const float* in, float* out, hipStream_
     float2* vis = kind == WF_APPLY_FORWARD ? (float2*)out
                   : (kind == WF_APPLY_ADJOINT ? (float2*)in : nullptr);
     ProfScope ps(prof_of(op, 0), s);
-    for (int k = 0; k < NCLS; ++k)
-      WF_HIP(launch_rows_sweep(mode, k, (const WorkItem*)W.items[k].p, W.nitems[k], sl,
-                               op->opt.store, vis, queues + 2 * k, op->Kx, op->Ky, op->tile,
-                               W.ncu, s));
+    for (int k = 0; k < Sweep::NLIST; ++k)
+      WF_HIP(launch_rows_sweep(mode, k / 2, (const WorkItem*)W.items[k].p, W.nitems[k], sl,
+                               op->opt.store, vis, queues + 2 * k, op->Kx, op->Ky,
+                               op->tile << (k & 1), W.ncu, s));
   }
   if (back) {
     {
@@ -1498,21 +1525,46 @@ wf_status set_branches(wf_op* op, int n) {
   return ensure_branches(op);
 }
 
-// Re-split channel c's stored rows into work items of at most maxrows rows.  Only the
-// item table and the rows' offsets inside their items change; the values stay put.
-wf_status retune_channel(wf_op* op, int c, int32_t maxrows) {
+// Patch words relative to each row's base-tile window, from words relative to the
+// windows of the current items (in place).
+void base_meta(const ChanOp& ch, int tile, int halo, uint32_t* meta) {
+  if (ch.bin_tsh.empty()) return;
+  for (const RowGroup& g : ch.groups) {
+    const int sh = ch.bin_tsh[g.bin];
+    if (!sh) continue;
+    const int mask = (1 << sh) - 1;
+    const int tu = (g.u0 + halo) / tile, tv = (g.v0 + halo) / tile;
+    const uint32_t d = (uint32_t)((tu & mask) * tile) | ((uint32_t)((tv & mask) * tile) << 8);
+    for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) meta[r] -= d;
+  }
+}
+
+// Re-split channel c's stored rows into work items of at most maxrows rows, each bin's
+// items covering blocks of 2^tsh[p] x 2^tsh[p] base tiles (tsh null: unchanged).  Only the
+// item table, the rows' patch words and their offsets inside their items change; the
+// values stay put.
+wf_status retune_channel(wf_op* op, int c, int32_t maxrows, const int8_t* tsh = nullptr) {
   ChanOp& ch = op->chans[c];
-  if (ch.nrows == 0 || ch.max_rows == maxrows || ch.holo) return WF_OK;
+  if (ch.nrows == 0 || ch.holo) return WF_OK;
+  std::vector<int8_t> ntsh = ch.bin_tsh;
+  if (ntsh.empty()) ntsh.assign(ch.P, 0);
+  if (tsh && !ch.otf)
+    for (int p = 0; p < ch.P; ++p) ntsh[p] = (int8_t)std::min<int>(tsh[p], op->max_tsh);
+  const bool same_tiles = ntsh == (ch.bin_tsh.empty() ? std::vector<int8_t>(ch.P, 0)
+                                                       : ch.bin_tsh);
+  if (ch.max_rows == maxrows && same_tiles) return WF_OK;
   const int64_t M = ch.nrows;
   WF_HIP(hipDeviceSynchronize());
   std::vector<uint32_t> meta(M), voff(M);
   WF_HIP(hipMemcpy(meta.data(), ch.meta.p, sizeof(uint32_t) * M, hipMemcpyDeviceToHost));
+  base_meta(ch, op->tile, op->halo, meta.data());
+  ch.bin_tsh = ntsh;
   std::vector<uint8_t> trow(M);
   for (int64_t r = 0; r < M; ++r) trow[r] = (uint8_t)((meta[r] >> 16) & 0xff);
   std::vector<WorkItem> wis;
   std::vector<int32_t> row_wi(ch.otf ? M : 0);
-  split_items(ch, trow.data(), meta.data(), maxrows, wis, voff.data(),
-              ch.otf ? row_wi.data() : nullptr);
+  split_items(ch, trow.data(), meta.data(), maxrows, op->tile, op->halo, wis, voff.data(),
+              meta.data(), ch.otf ? row_wi.data() : nullptr);
   if (ch.otf)   // the on-the-fly value pass finds each row's item through row_wi
     WF_HIP(hipMemcpy(ch.row_wi.p, row_wi.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
   if (ch.work.bytes < sizeof(WorkItem) * wis.size()) {
@@ -1520,12 +1572,27 @@ wf_status retune_channel(wf_op* op, int c, int32_t maxrows) {
     wf_status st = dalloc(ch.work, sizeof(WorkItem) * wis.size());
     if (st != WF_OK) return st;
   }
+  WF_HIP(hipMemcpy(ch.meta.p, meta.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice));
   WF_HIP(hipMemcpy(ch.voff.p, voff.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice));
   WF_HIP(hipMemcpy(ch.work.p, wis.data(), sizeof(WorkItem) * wis.size(),
                    hipMemcpyHostToDevice));
   ch.info.nwork = ch.nwork;
   ch.info.max_rows_per_item = ch.max_rows;
   op->generation++;
+  return WF_OK;
+}
+
+// The fused G^dag G launches of bin p alone on lane L (autotuning: X is read as it is,
+// Y is added into).
+wf_status bin_gtg(wf_op* op, const ChanOp& ch, int p, const Lane& L) {
+  const WorkItem* wk = (const WorkItem*)ch.work.p;
+  for (int c = 0; c < NCLS; ++c) {
+    const int n = ch.cls_nwi[p * NCLS + c];
+    if (n == 0) continue;
+    WF_HIP(launch_gtg(c, wk + ch.cls_wi0[p * NCLS + c], n, (const uint32_t*)ch.meta.p,
+                      (const uint32_t*)ch.voff.p, ch.vals.p, op->opt.store, L.X, L.Y,
+                      op->Kx, op->Ky, bin_tile(op, ch, p), L.s));
+  }
   return WF_OK;
 }
 
@@ -1664,6 +1731,10 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
     op->tile = tile;
     op->halo = (opt.J - 1) / 2 + (opt.smax - 1) / 2;
     op->win = tile + 2 * op->halo;
+    {   // items over 2 x 2 base tiles: their window and LDS accumulator must still fit
+      const int w2 = 2 * tile + 2 * op->halo;
+      op->max_tsh = (w2 <= 255 && 2 * tile <= 128 && (size_t)w2 * w2 * 16 <= 160 * 1024) ? 1 : 0;
+    }
     if (op->win > 255 || (op->Kx / tile) > 1024 || (op->Ky / tile) > 1024)
       return fail(WF_EINVAL, "tile/halo too large");
     // an item's FP64 accumulator in LDS: (tile + largest patch side - 1)^2 cells x 16 B
@@ -2190,6 +2261,47 @@ wf_status wf_read_latency(wf_op* op, double* ms, int32_t cap) {
   }
 }
 
+wf_status wf_get_bin_tiles(const wf_op* op, int32_t chan, int32_t* tiles, int32_t cap) {
+  wf_status st = check_op(op);
+  if (st != WF_OK) return st;
+  if (chan < 0 || chan >= (int)op->chans.size()) return fail(WF_EINVAL, "bad channel");
+  const ChanOp& ch = op->chans[chan];
+  if (!tiles || cap < ch.P) return fail(WF_EINVAL, "capacity too small");
+  for (int p = 0; p < ch.P; ++p) tiles[p] = bin_tile(op, ch, p);
+  return WF_OK;
+}
+
+static wf_status wf_set_bin_tiles_body(wf_op* op, int32_t chan, const int32_t* tiles,
+                                       int32_t n) {
+  wf_status st = check_op(op);
+  if (st != WF_OK) return st;
+  if (chan < 0 || chan >= (int)op->chans.size()) return fail(WF_EINVAL, "bad channel");
+  ChanOp& ch = op->chans[chan];
+  if (!tiles || n != ch.P) return fail(WF_EINVAL, "tiles must hold one entry per bin");
+  std::vector<int8_t> tsh(ch.P, 0);
+  for (int p = 0; p < ch.P; ++p) {
+    if (tiles[p] == op->tile) continue;
+    if (tiles[p] != 2 * op->tile)
+      return fail(WF_EINVAL, "a bin's tile must be the operator's tile or twice it");
+    if (op->max_tsh < 1) return fail(WF_EINVAL, "items of twice the tile do not fit in LDS");
+    if (ch.otf || ch.holo)
+      return fail(WF_ENOTSUP, "wider work items need stored G (strategy (a))");
+    tsh[p] = 1;
+  }
+  WF_HIP(hipSetDevice(op->device));
+  if ((st = retune_channel(op, chan, ch.max_rows, tsh.data())) != WF_OK) return st;
+  op->generation++;
+  if (op->sweep.on) {
+    WF_HIP(hipDeviceSynchronize());
+    if ((st = sweep_build(op)) != WF_OK) return st;
+  }
+  return WF_OK;
+}
+
+wf_status wf_set_bin_tiles(wf_op* op, int32_t chan, const int32_t* tiles, int32_t n) {
+  return guarded([&] { return wf_set_bin_tiles_body(op, chan, tiles, n); });
+}
+
 wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_stream, int32_t reps,
                       wf_tune_info* info) {
   try {
@@ -2203,28 +2315,85 @@ wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_str
     double before = 0;
     if ((st = time_runs(s, reps, sweep, &before)) != WF_OK) return st;
     int retuned = 0;
+    int64_t big_bins = 0;
     const int32_t cand_rows[3] = {256, 512, 1024};
+    const Lane L = lane_of(op, 0, s);
+    const int64_t grid_floats = 2 * (int64_t)op->Kx * op->Ky;
+    // the fused kernel alone reads X (any finite values) and adds into Y, which is
+    // cleared again afterwards
+    WF_HIP(launch_fill_zero(L.X, grid_floats, s));
     for (int c = 0; c < (int)op->chans.size(); ++c) {
       ChanOp& ch = op->chans[c];
       if (ch.nrows == 0) continue;
       const int32_t orig = ch.max_rows;
-      int32_t best = orig;
+      if (ch.otf || ch.holo) {
+        // no stored G to time alone: whole-channel applies choose the rows per item
+        int32_t best = orig;
+        double best_ms = 1e300;
+        for (int32_t mr : cand_rows) {
+          if ((st = retune_channel(op, c, mr)) != WF_OK) return st;
+          double tc = 0;
+          st = time_runs(s, reps, [&]() { return run_channel(op, kind, c, L, d_img, d_out); },
+                         &tc);
+          if (st != WF_OK) return st;
+          if (tc < best_ms) {
+            best_ms = tc;
+            best = mr;
+          }
+        }
+        if ((st = retune_channel(op, c, best)) != WF_OK) return st;
+        ch.measured_ms = best_ms;
+        if (best != orig) ++retuned;
+        continue;
+      }
+      const std::vector<int8_t> orig_tsh = ch.bin_tsh;
+      const int nsh = op->max_tsh + 1;
+      // fused-kernel time of every bin under each (rows per item, item tile)
+      std::vector<double> t((size_t)3 * nsh * ch.P, 0.0);
+      for (int i = 0; i < 3; ++i)
+        for (int sh = 0; sh < nsh; ++sh) {
+          const std::vector<int8_t> all(ch.P, (int8_t)sh);
+          if ((st = retune_channel(op, c, cand_rows[i], all.data())) != WF_OK) return st;
+          for (int p = 0; p < ch.P; ++p) {
+            if (ch.bin_nrows[p] == 0) continue;
+            double ms = 0;
+            st = time_runs(s, reps, [&]() { return bin_gtg(op, ch, p, L); }, &ms);
+            if (st != WF_OK) return st;
+            t[((size_t)i * nsh + sh) * ch.P + p] = ms;
+          }
+        }
+      int best = 0;
       double best_ms = 1e300;
-      for (int32_t mr : cand_rows) {
-        if ((st = retune_channel(op, c, mr)) != WF_OK) return st;
-        const Lane L = lane_of(op, 0, s);
-        double t = 0;
-        st = time_runs(s, reps, [&]() { return run_channel(op, kind, c, L, d_img, d_out); }, &t);
-        if (st != WF_OK) return st;
-        if (t < best_ms) {
-          best_ms = t;
-          best = mr;
+      std::vector<int8_t> best_tsh(ch.P, 0);
+      for (int i = 0; i < 3; ++i) {
+        double sum = 0;
+        std::vector<int8_t> pick(ch.P, 0);
+        for (int p = 0; p < ch.P; ++p) {
+          double m = 1e300;
+          for (int sh = 0; sh < nsh; ++sh) {
+            const double v = t[((size_t)i * nsh + sh) * ch.P + p];
+            if (v < m) {
+              m = v;
+              pick[p] = (int8_t)sh;
+            }
+          }
+          sum += m;
+        }
+        if (sum < best_ms) {
+          best_ms = sum;
+          best = i;
+          best_tsh = pick;
         }
       }
-      if ((st = retune_channel(op, c, best)) != WF_OK) return st;
-      ch.measured_ms = best_ms;
-      if (best != orig) ++retuned;
+      if ((st = retune_channel(op, c, cand_rows[best], best_tsh.data())) != WF_OK) return st;
+      for (int p = 0; p < ch.P; ++p) big_bins += best_tsh[p] > 0;
+      double tc = 0;
+      st = time_runs(s, reps, [&]() { return run_channel(op, kind, c, L, d_img, d_out); }, &tc);
+      if (st != WF_OK) return st;
+      ch.measured_ms = tc;
+      if (cand_rows[best] != orig || ch.bin_tsh != orig_tsh) ++retuned;
     }
+    WF_HIP(launch_fill_zero(L.Y, grid_floats, s));
     const int nchan = (int)op->chans.size();
     if (op->sweep.on) {
       // a layer-batched sweep has no branches: only its item lists follow the new splits
@@ -2254,6 +2423,7 @@ wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_str
     if (info) {
       info->branches = op->nbranch;
       info->retuned_chans = retuned;
+      info->wide_tile_bins = (int32_t)big_bins;
       info->sweep_ms_before = before;
       info->sweep_ms_after = after;
     }

@@ -46,6 +46,34 @@ __host__ __device__ inline int tap_class(int T) {
   return k <= 2 ? 0 : k <= 4 ? 1 : k <= 7 ? 2 : k <= 12 ? 3 : k <= 16 ? 4 : 5;
 }
 
+// Interleaved bits of a base tile's (v, u) indices (10 bits each): the tiles of every
+// aligned 2^s x 2^s block are consecutive in this order, so the rows of one patch class in
+// such a block form one contiguous range of the sorted rows.
+__host__ __device__ inline uint32_t tile_morton(uint32_t tv, uint32_t tu) {
+  uint32_t m = 0;
+  for (int b = 0; b < 10; ++b)
+    m |= (((tu >> b) & 1u) << (2 * b)) | (((tv >> b) & 1u) << (2 * b + 1));
+  return m;
+}
+inline void tile_unmorton(uint32_t m, int* tv, int* tu) {
+  int v = 0, u = 0;
+  for (int b = 0; b < 10; ++b) {
+    u |= (int)((m >> (2 * b)) & 1u) << b;
+    v |= (int)((m >> (2 * b + 1)) & 1u) << b;
+  }
+  *tv = v;
+  *tu = u;
+}
+// Sort key of a built row: bin 8 | patch class 3 | base tile (interleaved) 20 | patch
+// side 6 | cell v in the tile 7 | cell u 7 | 13 zero bits.
+constexpr int KEY_LO_BIT = 13;
+__host__ __device__ inline uint64_t row_key(int bin, int T, uint32_t tv, uint32_t tu,
+                                            uint32_t lv, uint32_t lu) {
+  return ((uint64_t)bin << 56) | ((uint64_t)tap_class(T) << 53) |
+         ((uint64_t)tile_morton(tv, tu) << 33) | ((uint64_t)T << 27) | ((uint64_t)lv << 20) |
+         ((uint64_t)lu << 13);
+}
+
 // Per-row metadata word: window-local patch origin and patch side.
 __host__ __device__ inline uint32_t pack_meta(int lu0, int lv0, int T) {
   return (uint32_t)lu0 | ((uint32_t)lv0 << 8) | ((uint32_t)T << 16);
@@ -162,6 +190,9 @@ struct ChanOp {
   std::vector<int64_t> bin_taps;           // stored values per bin
   std::vector<RowGroup> groups;            // in sorted-row order
   int32_t max_rows = 1024;                 // rows per work item of the current split
+  // per bin: work items cover aligned blocks of 2^s x 2^s base tiles (item tile side
+  // tile << s); the rows' patch words are relative to their item's window
+  std::vector<int8_t> bin_tsh;
   double measured_ms = 0;                  // last timed apply of this channel (0 = none)
   int64_t ntaps = 0;
   int64_t nwork = 0;
@@ -231,9 +262,11 @@ struct Sweep {
   DevBuf pairs;                      // int2 [npairs]
   int npairs = 0;
   DevBuf chan_layers;                // int2 [nchan]: first layer, count
-  DevBuf items[NCLS];
-  int nitems[NCLS] = {0, 0, 0, 0, 0, 0};
-  DevBuf queues;                     // int [2 * NCLS]
+  // work items per (patch class, item-tile shift): list k * 2 + s
+  static constexpr int NLIST = 2 * NCLS;
+  DevBuf items[NLIST];
+  int nitems[NLIST] = {};
+  DevBuf queues;                     // int [2 * NLIST]
   DevBuf done;                       // int [nchan]: workgroups finished (completion stamps)
   int ncu = 0;
 };
@@ -245,6 +278,7 @@ struct wf_op {
   wf_image_shape shape;
   int Kx = 0, Ky = 0;
   int tile = 64, halo = 10, win = 84;
+  int max_tsh = 0;   // largest item-tile shift whose LDS accumulator fits
   int device = 0;
   wf::KernelParams kp;
   std::vector<wf::ChanOp> chans;
