@@ -23,13 +23,37 @@
 
 namespace wf {
 
+// n - 1 = sqrt(1 - r2) - 1 for r2 = l^2 + m^2 in FP64.  Inside r2 < 1/20 (fields up to
+// about 25 degrees across) the binomial series of sqrt(1 - x) - 1 to x^12, whose
+// coefficients are exact dyadic fractions, in Horner form: the next term is below 1e-17
+// of the result, so it matches -r2 / (1 + sqrt(1 - r2)) to FP64 rounding, at a dozen
+// fused multiply-adds instead of a square root and a division.
+__device__ __forceinline__ double nm1_of(double r2) {
+  if (r2 < 0.05) {
+    double p = -29393.0 / 4194304.0;
+    p = fma(p, r2, -4199.0 / 524288.0);
+    p = fma(p, r2, -2431.0 / 262144.0);
+    p = fma(p, r2, -715.0 / 65536.0);
+    p = fma(p, r2, -429.0 / 32768.0);
+    p = fma(p, r2, -33.0 / 2048.0);
+    p = fma(p, r2, -21.0 / 1024.0);
+    p = fma(p, r2, -7.0 / 256.0);
+    p = fma(p, r2, -5.0 / 128.0);
+    p = fma(p, r2, -1.0 / 16.0);
+    p = fma(p, r2, -1.0 / 8.0);
+    p = fma(p, r2, -0.5);
+    return p * r2;
+  }
+  return -r2 / (1.0 + sqrt(1.0 - r2));
+}
+
 __device__ __forceinline__ float2 zvalue(int i, int j, int nx, int ny, double cell, double wp,
                                          float sxi, float syj) {
   const double l = (double)(i - nx / 2) * cell;
   const double m = (double)(j - ny / 2) * cell;
   const double r2 = l * l + m * m;
-  const double n = sqrt(1.0 - r2);
-  const double d = -r2 / (1.0 + n);
+  const double d = nm1_of(r2);
+  const double n = 1.0 + d;
   double cyc = -wp * d;
   cyc -= rint(cyc);
   float s, c;
@@ -391,9 +415,11 @@ struct ColPlan {
   static constexpr int CW = (16384 / N) > 16 ? 16 : (16384 / N);
   static constexpr int NTC = RowPlan<N>::NT;   // threads per column
   static constexpr int NT = CW * NTC;
-  // lines one element apart beyond their padded length, so that the CW columns of one
-  // grid row (neighbouring lanes) fall in different banks
-  static constexpr int LS = lds_elems<N>() + 1;
+  // The CW columns of one grid row sit on neighbouring lanes.  An LDS access of 64 lanes
+  // is served in halves of 32 lanes, i.e. 32 / CW consecutive elements of each of CW
+  // lines: lines 32 / CW elements apart beyond their padded length (which is a multiple
+  // of 32) put those CW runs on disjoint banks.
+  static constexpr int LS = lds_elems<N>() + 32 / CW;
   static constexpr size_t lds_bytes() { return (size_t)CW * LS * sizeof(float2) + N / 8; }
 };
 
