@@ -405,10 +405,14 @@ def bench_batched(args, torch):
     t0 = time.time()
     op.set_sweep(True)
     t_sw = time.time() - t0
+    # the autotuner in sweep mode: rows per item and item tiles again, then the lane count
+    # (channel ranges on streams of their own)
+    tune_sw = op.autotune(x, out, reps=2, stream=stream)
+    log(f"sweep autotune {tune_sw}")
     for _ in range(args.warmup):
         op.psf_apply_re(x, out, stream=stream)
     eager_sweep = timed(lambda: op.psf_apply_re(x, out, stream=stream), max(2, args.steps // 4))
-    sw = graph_run("persistent sweep")
+    sw = graph_run(f"persistent sweep ({tune_sw['branches']} lanes)")
     ms = sw["ms"]
     plans = [op.plan(c) for c in range(nchan)]
     bv = 8 if args.store == "f32" else 4
@@ -429,7 +433,9 @@ def bench_batched(args, torch):
                    "store": args.store, "nchan": nchan, "nvis": M,
                    "nbins": [p["nbins"] for p in plans]},
         "latency_ms": sw["latency_ms"],
-        "graph": {"kernel_nodes": sw["kernels"], "nodes": sw["nodes"]},
+        "graph": {"kernel_nodes": sw["kernels"], "nodes": sw["nodes"],
+                  "lanes": tune_sw["branches"]},
+        "sweep_autotune": tune_sw,
         "gvis_per_s": 1e3 / ms * M / 1e9,
         "sweep_build_s": t_sw, "eager_ms_sweep": eager_sweep,
         "branch_graph": {"ms": br["ms"], "kernel_nodes": br["kernels"], "nodes": br["nodes"],
@@ -735,6 +741,43 @@ def bench_learned(args, torch):
     ref = op_e.psf_apply(xs)
     got = op_s.psf_apply(xs)
     err = float((got - ref).norm() / ref.norm())
+    # against the FP64 oracle (exact kernels): its Phi^dag Phi of the N(0,1) probe at the
+    # stored pixel samples (tests/golden/learned_4096sq_20M.npz, written by a script that
+    # calls only the oracle; same rows, P = 16 and the oracle's centroids)
+    vs_oracle = None
+    fxp = os.path.join(ROOT, "tests", "golden", "learned_4096sq_20M.npz")
+    if os.path.exists(fxp):
+        fx = np.load(fxp)
+        if np.allclose(op_s.centroids(0), fx["centroids"], rtol=1e-12, atol=1e-9):
+            xg = torch.from_numpy(ws.gauss_image(obs.nx, 4).astype(np.float32)[None]).to("cuda:0")
+            pix = torch.from_numpy(fx["pix"]).to("cuda:0")
+            vs_oracle = {}
+            for name, o in (("network", op_s), ("exact", op_e)):
+                v = o.psf_apply(xg)[0].flatten()[pix].cpu().numpy()
+                vs_oracle[name] = float(np.linalg.norm(v - fx["psf"]) / np.linalg.norm(fx["psf"]))
+            log(f"Phi^dag Phi vs FP64 oracle (32768 pixels): {vs_oracle}")
+    # strategy (c): kernels rebuilt at every apply, with and without the network
+    otf = {}
+    for name, kw in (("exact", {}), ("network", {"surrogate": net})):
+        o = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad, strategy="otf",
+                     **{**mk, "store": "f16"}, **kw)
+        out = o.psf_apply_re(xs)
+        torch.cuda.synchronize()
+        o.profile_enable(5, True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            o.psf_apply_re(xs, out)
+        e1.record()
+        torch.cuda.synchronize()
+        _, vp = o.profile_read(5)
+        otf[name] = {"apply_ms": e0.elapsed_time(e1) / 3, "value_pass_ms": vp / 3,
+                     "network_rows": o.plan(0)["surrogate_fraction"]}
+        o.close()
+        del o
+        torch.cuda.empty_cache()
+    log(f"strategy (c): {otf}")
     log(f"build: exact {t_exact:.2f} s (channel {pe['build_seconds']:.2f} s), network "
         f"{t_sur:.2f} s (channel {ps['build_seconds']:.2f} s); network rows "
         f"{ps['surrogate_fraction']:.3f}; Phi^dag Phi rel vs exact {err:.2e}")
@@ -751,6 +794,9 @@ def bench_learned(args, torch):
         "network_rows": ps["surrogate_fraction"],
         "fallback_fraction": 1.0 - ps["surrogate_fraction"],
         "psf_rel_vs_exact": err,
+        "psf_rel_vs_fp64_oracle": vs_oracle,
+        "onthefly": otf,
+        "onthefly_value_pass_gain": otf["exact"]["value_pass_ms"] / otf["network"]["value_pass_ms"],
         "train": {"examples": int(x.shape[0]), "epochs": args.epochs, "seconds": t_train,
                   "kernel_loss_first": float(hist[0, 0]), "kernel_loss_last": float(hist[-1, 0])},
         "heldout_rel_err": {"p50": float(np.median(ev)), "p90": float(np.percentile(ev, 90)),

@@ -92,10 +92,14 @@ typedef struct {
   int32_t max_rows_per_item; /* rows per work item, <= 1024 (0 = auto: 1024)           */
   int32_t branches;        /* concurrent branches of an apply, <= 16 (0 = auto: one per
                               channel up to 4; a single channel runs on one branch)   */
-  const wf_mlp* surrogate; /* NULL: exact residual kernels.  Otherwise rows whose
-                              kernel the network predicts with log10 error at most
-                              log10(surrogate_tol) use the prediction (square fields;
-                              the network must outlive the build call only)          */
+  const wf_mlp* surrogate; /* NULL: exact residual kernels.  Otherwise the rows of
+                              residual-kernel side 9..15 (smaller kernels cost less to
+                              build exactly than an inference) whose kernel the network
+                              predicts with log10 error at most log10(surrogate_tol) use
+                              the prediction (square fields).  Under strategy (c) every
+                              apply re-infers them from a copy of the network's
+                              parameters taken at build, so the network must outlive
+                              the build call only.  Not with strategy (b).            */
   double surrogate_tol;    /* predicted relative L2 error bound, default 1e-3          */
   const float* weights;    /* NULL: unit weights.  Otherwise host FP32 [total rows] in
                               the [chan][row] order of the visibilities: row k of the
@@ -288,17 +292,22 @@ wf_status wf_profile_read(wf_op* op, int32_t kernel_id, int64_t* launches, doubl
  * are added in the caller's stream.  Invalidates graphs captured earlier. */
 wf_status wf_set_branches(wf_op* op, int32_t branches);
 
-/* Layer-batched sweep (enable != 0): every later apply (and every graph captured
+/* Layer-batched sweep (enable >= 1): every later apply (and every graph captured
  * afterwards) runs each stage as one launch over all (channel, bin) layers at once --
  * forward row FFTs, forward column FFTs, the de-gridding / gridding / fused G^dag G row
- * kernels as one persistent launch per patch class draining the items of every layer
- * from a device queue, inverse column FFTs, and inverse row FFTs that sum each channel's
- * layers in registers and write its image once.  Holds the grids of every layer
- * (2 Kx Ky + ny Kx complex FP32 values each) while enabled; WF_ENOMEM when they do not
- * fit.  Needs Kx = 2 nx and Ky = 2 ny in 2048 .. 16384 and a stored G for every channel
- * (WF_ENOTSUP otherwise).  Latency stamps mark the completion of each channel's last
- * image row.  Results equal the branch apply up to the order of FP32 additions.
- * enable = 0 releases the sweep.  Synchronous; invalidates graphs captured earlier. */
+ * kernels as one persistent launch per (patch class, work-item tile) draining the items
+ * of every layer from a device queue, inverse column FFTs, and inverse row FFTs that sum
+ * each channel's layers in registers and write its image once.  enable = lanes (at most
+ * 4, at most the channel count): the channels are cut into that many contiguous ranges
+ * of about equal work, each running the stages above on a stream of its own; lane k
+ * starts once lane k - 1 has issued its forward FFTs, so that one lane's row kernels run
+ * beside the next lane's FFTs (the Sect. 2 worker pools per frequency; wf_autotune
+ * times 1..3 lanes).  Holds the grids of every layer (2 Kx Ky + ny Kx complex FP32
+ * values each) while enabled; WF_ENOMEM when they do not fit.  Needs Kx = 2 nx and
+ * Ky = 2 ny in 2048 .. 16384 and a stored G for every channel (WF_ENOTSUP otherwise).
+ * Latency stamps mark the completion of each channel's last image row.  Results equal
+ * the branch apply up to the order of FP32 additions.  enable = 0 releases the sweep;
+ * WF_EINVAL for enable < 0.  Synchronous; invalidates graphs captured earlier. */
 wf_status wf_set_sweep(wf_op* op, int32_t enable);
 
 typedef enum {
@@ -337,7 +346,7 @@ wf_status wf_latency_enable(wf_op* op, int32_t enable);
 wf_status wf_read_latency(wf_op* op, double* ms, int32_t cap);
 
 typedef struct {
-  int32_t branches;        /* branch count chosen                                     */
+  int32_t branches;        /* branch count chosen (a sweep: its lane count)           */
   int32_t retuned_chans;   /* channels whose work-item size changed                   */
   double sweep_ms_before;  /* Re{Phi^dag Phi} sweep (all channels) before tuning      */
   double sweep_ms_after;   /* ... and after                                           */

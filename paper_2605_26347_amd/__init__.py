@@ -290,10 +290,11 @@ class Operator:
         """Run applies on n concurrent branches (streams with their own work grids)."""
         check(self._lib.wf_set_branches(self._h, int(n)), "wf_set_branches")
 
-    def set_sweep(self, enable=True):
-        """Layer-batched applies: one launch per stage over every (channel, bin) layer
-        (include/wf.h, wf_set_sweep)."""
-        check(self._lib.wf_set_sweep(self._h, int(enable)), "wf_set_sweep")
+    def set_sweep(self, enable=True, lanes=1):
+        """Layer-batched applies: one launch per stage over every (channel, bin) layer,
+        on `lanes` streams of contiguous channel ranges (include/wf.h, wf_set_sweep)."""
+        n = int(lanes) if enable else 0
+        check(self._lib.wf_set_sweep(self._h, n), "wf_set_sweep")
 
     def capture(self, kind, inp, out, stream):
         """Capture one apply ('forward', 'adjoint', 'psf', 'psf_re') with fixed buffers

@@ -552,7 +552,7 @@ __global__ __launch_bounds__(64, NK <= 15 ? 4 : 1) void k_rowsym(const double* _
       continue;
     }
     double dropped;
-    const float* pr = sg.pred ? sg.pred + (k - r0) * MLP_OUT : nullptr;
+    const float* pr = sg.pred ? sg.pred + (sg.by_slot ? i : k - r0) * MLP_OUT : nullptr;
     const bool usep = use_prediction(pr, nk_full, kp, sg.logtol);
     const int hp = usep ? predicted_kernel(pr, nk, kp, S, &dropped)
                         : wkernel_row(g.wproj, nk, kp, S, &dropped);
@@ -618,7 +618,7 @@ __global__ __launch_bounds__(64, NK <= 15 ? 4 : 1) void k_gbuild(const double* _
       continue;
     }
     double dropped;
-    const float* pr = sg.pred ? sg.pred + (s - s0) * MLP_OUT : nullptr;
+    const float* pr = sg.pred ? sg.pred + (sg.by_slot ? i : s - s0) * MLP_OUT : nullptr;
     const bool usep = use_prediction(pr, nk_full, kp, sg.logtol);
     const int hp = usep ? predicted_kernel(pr, nk, kp, S, &dropped)
                         : wkernel_row(g.wproj, nk, kp, S, &dropped);
@@ -744,6 +744,7 @@ __global__ __launch_bounds__(256) void k_row_class(const double* __restrict__ uv
 // Network inputs of rows [r0, r0 + nr) in caller order (perm null) or of sorted rows
 // perm[r0 ..] (field side L, square field).
 __global__ __launch_bounds__(256) void k_row_inputs(const double* __restrict__ uvw,
+                                                    const int32_t* __restrict__ list,
                                                     const int32_t* __restrict__ perm, int64_t r0,
                                                     int64_t nr, double scale, double gsx,
                                                     double gsy, const double* __restrict__ mids,
@@ -753,7 +754,7 @@ __global__ __launch_bounds__(256) void k_row_inputs(const double* __restrict__ u
 #pragma clang fp contract(off)
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nr;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = r0 + i;
+    const int64_t s = list ? (int64_t)list[r0 + i] : r0 + i;
     const int64_t k = perm ? (int64_t)perm[s] : s;
     const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
     const int nk_full = dev_nk(g.wproj, kp, false);
@@ -903,13 +904,14 @@ hipError_t launch_row_class(const double* uvw, int64_t r0, int64_t r1, double sc
 }
 
 
-hipError_t launch_row_inputs(const double* uvw, const int32_t* perm, int64_t r0, int64_t nr,
+hipError_t launch_row_inputs(const double* uvw, const int32_t* list, const int32_t* perm,
+                             int64_t r0, int64_t nr,
                              double scale, double gsx, double gsy, const double* mids, int P,
                              const double* cents, const KernelParams& kp, double L, float* x,
                              hipStream_t s) {
   if (nr <= 0) return hipSuccess;
   const int64_t nb = std::min<int64_t>((nr + 255) / 256, 16384);
-  hipLaunchKernelGGL(k_row_inputs, dim3((unsigned)nb), dim3(256), 0, s, uvw, perm, r0, nr,
+  hipLaunchKernelGGL(k_row_inputs, dim3((unsigned)nb), dim3(256), 0, s, uvw, list, perm, r0, nr,
                      scale, gsx, gsy, mids, P, cents, kp, L, x);
   return hipGetLastError();
 }

@@ -62,6 +62,71 @@ __device__ __forceinline__ float2 zvalue(int i, int j, int nx, int ny, double ce
   return make_float2(a * c, a * s);
 }
 
+// Z_p = s(l) s(m) / n exp(-2 i pi w_p (n - 1)) split by n - 1 = -(l^2 + m^2)/2 + D(r2),
+// r2 = l^2 + m^2, D = -r2^2/8 - r2^3/16 - 5 r2^4/128 - 7 r2^5/256 - ...:
+//   Z_p = C_p(l) R_p(m) exp(i theta) / n,  C_p(l) = s(l) exp(i pi w_p l^2) (a per-bin table
+//   of the image columns, FP64 phase at build), R_p(m) = s(m) exp(i pi w_p m^2) (FP64
+//   phase once per row), theta = -2 pi w_p D(r2).
+// Where r2 <= 1/100 over the image and |theta| <= 1/4 (the table exists only then), D and
+// 1/n = 1 + r2/2 + 3 r2^2/8 + ... are FP32 series truncated below 1e-9 relative, and
+// exp(i theta) its Taylor series to theta^7 (error below 1e-9): each factor carries an
+// FP32 rounding error, a few 1e-7 in all, like the FP32 sine and cosine of the direct form.
+struct ChirpRow {
+  float2 R;      // s(m) exp(i pi w_p m^2)
+  float m2;      // m^2
+  float kth;     // -2 pi w_p
+  float cellf;
+  int hx;        // nx / 2
+};
+
+__device__ __forceinline__ ChirpRow chirp_row(int j, int nx, int ny, double cell, double wp,
+                                              float syj) {
+  ChirpRow c;
+  const double m = (double)(j - ny / 2) * cell;
+  double cyc = 0.5 * wp * (m * m);
+  cyc -= rint(cyc);
+  float sn, cs;
+  sincospif((float)(2.0 * cyc), &sn, &cs);
+  c.R = make_float2(syj * cs, syj * sn);
+  c.m2 = (float)(m * m);
+  c.kth = (float)(-2.0 * M_PI * wp);
+  c.cellf = (float)cell;
+  c.hx = nx / 2;
+  return c;
+}
+
+__device__ __forceinline__ float2 zvalue_tab(const ChirpRow& c, int i, float2 ci) {
+  const float li = (float)(i - c.hx) * c.cellf;
+  const float r2 = fmaf(li, li, c.m2);
+  const float dl = -(r2 * r2) * fmaf(r2, fmaf(r2, fmaf(r2, 7.f / 256.f, 5.f / 128.f),
+                                               1.f / 16.f), 1.f / 8.f);
+  const float th = c.kth * dl;
+  const float t2 = th * th;
+  const float ct = fmaf(t2, fmaf(t2, fmaf(t2, -1.f / 720.f, 1.f / 24.f), -0.5f), 1.f);
+  const float st = th * fmaf(t2, fmaf(t2, fmaf(t2, -1.f / 5040.f, 1.f / 120.f), -1.f / 6.f),
+                             1.f);
+  const float inv_n =
+      fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, 35.f / 128.f, 5.f / 16.f), 3.f / 8.f), 0.5f), 1.f);
+  const float2 a = make_float2(ci.x * ct - ci.y * st, ci.x * st + ci.y * ct);
+  const float2 b = make_float2(a.x * c.R.x - a.y * c.R.y, a.x * c.R.y + a.y * c.R.x);
+  return make_float2(b.x * inv_n, b.y * inv_n);
+}
+
+// C_p(l_i) = s(l_i) exp(i pi w_p l_i^2), i < nx: FP64 phase reduced to one cycle, FP64 sine
+// and cosine.
+__global__ __launch_bounds__(256) void k_chirp_table(float2* __restrict__ ct, int nx,
+                                                     double cell, double wp,
+                                                     const float* __restrict__ sx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nx) return;
+  const double l = (double)(i - nx / 2) * cell;
+  double cyc = 0.5 * wp * (l * l);
+  cyc -= rint(cyc);
+  double sn, cs;
+  sincospi(2.0 * cyc, &sn, &cs);
+  ct[i] = make_float2((float)(sx[i] * cs), (float)(sx[i] * sn));
+}
+
 __device__ __forceinline__ bool bit_set(const uint32_t* __restrict__ m, int i) {
   return (m[i >> 5] >> (i & 31)) & 1u;
 }
@@ -162,7 +227,8 @@ template <int N>
 __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
     const float* __restrict__ img, float2* __restrict__ A, const float2* __restrict__ tw,
     const float* __restrict__ sx, const float* __restrict__ sy, int nx, int ny, double cell,
-    double wp, const uint32_t* __restrict__ smask, const SweepLayer* __restrict__ sl) {
+    double wp, const uint32_t* __restrict__ smask, const SweepLayer* __restrict__ sl,
+    const float2* __restrict__ ctab) {
   using RP = RowPlan<N>;
   constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3, NT = RP::NT;
   extern __shared__ float2 buf[];
@@ -173,22 +239,48 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
     A = L.A;
     wp = L.wp;
     smask = L.smask;
+    ctab = L.ctab;
   }
   const float syj = sy[jr];
   const float* __restrict__ row = img + (int64_t)jr * nx;
   {
     constexpr int B = (N / R1) / NT;
+    // the modulation of the lane's pixels, one uniform branch for the whole row (a
+    // branch per pixel would keep the loads of different pixels from overlapping)
+    auto pix = [&](int b, int r) {
+      const int q = threadIdx.x + b * NT + r * (N / R1);
+      return r < R1 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
+    };
+    float2 zr[B][R1 / 2];
+    if (ctab) {
+      const ChirpRow cr = chirp_row(jr, nx, ny, cell, wp, syj);
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+#pragma unroll
+        for (int r = 0; r < R1; ++r)
+          if (r < R1 / 4 || r >= 3 * R1 / 4) {
+            const int i = pix(b, r);
+            zr[b][r < R1 / 4 ? r : r - R1 / 2] = zvalue_tab(cr, i, ctab[i]);
+          }
+    } else {
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+#pragma unroll
+        for (int r = 0; r < R1; ++r)
+          if (r < R1 / 4 || r >= 3 * R1 / 4) {
+            const int i = pix(b, r);
+            zr[b][r < R1 / 4 ? r : r - R1 / 2] = zvalue(i, jr, nx, ny, cell, wp, sx[i], syj);
+          }
+    }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = threadIdx.x + b * NT;
       float2 v[R1];
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
-        const int q = j + r * (N / R1);
         if (r < R1 / 4 || r >= 3 * R1 / 4) {
-          const int i = r < R1 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
-          const float x = row[i];
-          const float2 z = zvalue(i, jr, nx, ny, cell, wp, sx[i], syj);
+          const float x = row[pix(b, r)];
+          const float2 z = zr[b][r < R1 / 4 ? r : r - R1 / 2];
           v[r] = make_float2(x * z.x, x * z.y);
         } else {
           v[r] = make_float2(0.f, 0.f);
@@ -226,7 +318,7 @@ template <int N>
 __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
     const float2* __restrict__ A, void* __restrict__ out, const float2* __restrict__ tw,
     const float* __restrict__ sx, const float* __restrict__ sy, int nx, int ny, double cell,
-    double wp, int mode, const uint32_t* __restrict__ smask) {
+    double wp, int mode, const uint32_t* __restrict__ smask, const float2* __restrict__ ctab) {
   using RP = RowPlan<N>;
   constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3, NT = RP::NT;
   extern __shared__ float2 buf[];
@@ -274,6 +366,32 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
   {
     constexpr int NS = R1 * R2;
     constexpr int B = (N / R3) / NT;
+    // the modulation of the lane's output pixels, one uniform branch for the row
+    auto pix = [&](int b, int r) {
+      const int q = threadIdx.x + b * NT + r * NS;
+      return r < R3 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
+    };
+    float2 zr[B][R3 / 2];
+    if (ctab) {
+      const ChirpRow cr = chirp_row(jr, nx, ny, cell, wp, syj);
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+#pragma unroll
+        for (int r = 0; r < R3; ++r)
+          if (r < R3 / 4 || r >= 3 * R3 / 4) {
+            const int i = pix(b, r);
+            zr[b][r < R3 / 4 ? r : r - R3 / 2] = zvalue_tab(cr, i, ctab[i]);
+          }
+    } else {
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+#pragma unroll
+        for (int r = 0; r < R3; ++r)
+          if (r < R3 / 4 || r >= 3 * R3 / 4) {
+            const int i = pix(b, r);
+            zr[b][r < R3 / 4 ? r : r - R3 / 2] = zvalue(i, jr, nx, ny, cell, wp, sx[i], syj);
+          }
+    }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = threadIdx.x + b * NT;
@@ -288,8 +406,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
         if (r < R3 / 4 || r >= 3 * R3 / 4) {
           const int q = j + r * NS;
           const int i = r < R3 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
-          const float2 z = zvalue(i, jr, nx, ny, cell, wp, sx[i], syj);
-          const float2 c = cmulc(v[r], z);
+          const float2 c = cmulc(v[r], zr[b][r < R3 / 4 ? r : r - R3 / 2]);
           const int64_t o = (int64_t)jr * nx + i;
           if (mode < 2) {
             float2* po = reinterpret_cast<float2*>(out) + o;
@@ -309,14 +426,14 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
   }
 }
 
-// Inverse row pass of a sweep: workgroup (row jr, channel c) transforms row jr of every
+// Inverse row pass of a sweep: workgroup (row jr, channel c = c0 + y) transforms row jr of every
 // layer of channel c in turn (chan_layers[c] = first layer, count) and accumulates
 // conj(Z_p) F^dag ... in registers, then writes the channel's image row once (complex, or
 // its real part): the sum over w-layers (eq. 7) needs no read-modify-write and no
 // atomics.  With stamps, the channel's last workgroup records the device clock.
 template <int N>
 __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_sweep(
-    const SweepLayer* __restrict__ sl, const int2* __restrict__ chan_layers,
+    const SweepLayer* __restrict__ sl, const int2* __restrict__ chan_layers, int c0,
     void* __restrict__ out, const float2* __restrict__ tw, const float* __restrict__ sx,
     const float* __restrict__ sy, int nx, int ny, double cell, int real_out,
     unsigned long long* __restrict__ stamps, int* __restrict__ done) {
@@ -325,7 +442,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_sweep(
   constexpr int NS3 = R1 * R2;
   constexpr int B3 = (N / R3) / NT;
   extern __shared__ float2 buf[];
-  const int jr = blockIdx.x, c = blockIdx.y;
+  const int jr = blockIdx.x, c = c0 + (int)blockIdx.y;
   const int2 cl = chan_layers[c];
   const float syj = sy[jr];
   float2 acc[B3][R3 / 2];
@@ -697,12 +814,12 @@ template <int N>
 static hipError_t launch_fwd_rows_reg(const float* img, float2* A, const float2* tw,
                                       const float* sx, const float* sy, int nx, int ny,
                                       double cell, double wp, const uint32_t* smask,
-                                      hipStream_t s) {
+                                      const float2* ctab, hipStream_t s) {
   const size_t lds = (size_t)lds_elems<N>() * sizeof(float2);
   hipError_t e = set_lds(k_fwd_rows_reg<N>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fwd_rows_reg<N>), dim3(ny), dim3(RowPlan<N>::NT), lds, s, img, A, tw,
-                     sx, sy, nx, ny, cell, wp, smask, nullptr);
+                     sx, sy, nx, ny, cell, wp, smask, nullptr, ctab);
   return hipGetLastError();
 }
 
@@ -710,24 +827,31 @@ template <int N>
 static hipError_t launch_inv_rows_reg(const float2* A, void* out, const float2* tw,
                                       const float* sx, const float* sy, int nx, int ny,
                                       double cell, double wp, int mode, const uint32_t* smask,
-                                      hipStream_t s) {
+                                      const float2* ctab, hipStream_t s) {
   const size_t lds = (size_t)lds_elems<N>() * sizeof(float2);
   hipError_t e = set_lds(k_inv_rows_reg<N>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_inv_rows_reg<N>), dim3(ny), dim3(RowPlan<N>::NT), lds, s, A, out, tw,
-                     sx, sy, nx, ny, cell, wp, mode, smask);
+                     sx, sy, nx, ny, cell, wp, mode, smask, ctab);
+  return hipGetLastError();
+}
+
+hipError_t launch_chirp_table(float2* ct, int nx, double cell, double wp, const float* sx,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_chirp_table, dim3((nx + 255) / 256), dim3(256), 0, s, ct, nx, cell, wp,
+                     sx);
   return hipGetLastError();
 }
 
 hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const float* sx,
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
-                           const uint32_t* smask, hipStream_t s) {
+                           const uint32_t* smask, const float2* ctab, hipStream_t s) {
   if (Kx == 2 * nx) {
     switch (Kx) {
-      case 2048: return launch_fwd_rows_reg<2048>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, s);
-      case 4096: return launch_fwd_rows_reg<4096>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, s);
-      case 8192: return launch_fwd_rows_reg<8192>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, s);
-      case 16384: return launch_fwd_rows_reg<16384>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, s);
+      case 2048: return launch_fwd_rows_reg<2048>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, ctab, s);
+      case 4096: return launch_fwd_rows_reg<4096>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, ctab, s);
+      case 8192: return launch_fwd_rows_reg<8192>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, ctab, s);
+      case 16384: return launch_fwd_rows_reg<16384>(img, A, tw, sx, sy, nx, ny, cell, wp, smask, ctab, s);
       default: break;
     }
   }
@@ -751,13 +875,14 @@ hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const 
 
 hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const float* sx,
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
-                           int mode, const uint32_t* smask, hipStream_t s) {
+                           int mode, const uint32_t* smask, const float2* ctab,
+                           hipStream_t s) {
   if (Kx == 2 * nx) {
     switch (Kx) {
-      case 2048: return launch_inv_rows_reg<2048>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, s);
-      case 4096: return launch_inv_rows_reg<4096>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, s);
-      case 8192: return launch_inv_rows_reg<8192>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, s);
-      case 16384: return launch_inv_rows_reg<16384>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, s);
+      case 2048: return launch_inv_rows_reg<2048>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, ctab, s);
+      case 4096: return launch_inv_rows_reg<4096>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, ctab, s);
+      case 8192: return launch_inv_rows_reg<8192>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, ctab, s);
+      case 16384: return launch_inv_rows_reg<16384>(A, out, tw, sx, sy, nx, ny, cell, wp, mode, smask, ctab, s);
       default: break;
     }
   }
@@ -910,7 +1035,8 @@ hipError_t launch_sweep_fwd_rows(const float* img, const SweepLayer* sl, int nla
     hipError_t e = set_lds(k_fwd_rows_reg<NN>, lds);                                        \
     if (e != hipSuccess) return e;                                                          \
     hipLaunchKernelGGL((k_fwd_rows_reg<NN>), dim3(ny, nlayers), dim3(RowPlan<NN>::NT), lds, \
-                       s, img, nullptr, tw, sx, sy, nx, ny, cell, 0.0, nullptr, sl);        \
+                       s, img, nullptr, tw, sx, sy, nx, ny, cell, 0.0, nullptr, sl,        \
+                       nullptr);                                                            \
     return hipGetLastError();                                                               \
   }
     C(2048) C(4096) C(8192) C(16384)
@@ -950,8 +1076,9 @@ hipError_t launch_sweep_cols(bool inverse, const SweepLayer* sl, const int2* pai
   }
 }
 
-hipError_t launch_sweep_inv_rows(const SweepLayer* sl, const int2* chan_layers, int nchan,
-                                 void* out, bool real_out, const float2* tw, const float* sx,
+hipError_t launch_sweep_inv_rows(const SweepLayer* sl, const int2* chan_layers, int c0,
+                                 int nchan, void* out, bool real_out, const float2* tw,
+                                 const float* sx,
                                  const float* sy, int nx, int ny, int Kx, double cell,
                                  unsigned long long* stamps, int* done, hipStream_t s) {
   if (nchan <= 0) return hipSuccess;
@@ -962,8 +1089,8 @@ hipError_t launch_sweep_inv_rows(const SweepLayer* sl, const int2* chan_layers, 
     hipError_t e = set_lds(k_inv_rows_sweep<NN>, lds);                                       \
     if (e != hipSuccess) return e;                                                           \
     hipLaunchKernelGGL((k_inv_rows_sweep<NN>), dim3(ny, nchan), dim3(RowPlan<NN>::NT), lds,  \
-                       s, sl, chan_layers, out, tw, sx, sy, nx, ny, cell, real_out ? 1 : 0,  \
-                       stamps, done);                                                        \
+                       s, sl, chan_layers, c0, out, tw, sx, sy, nx, ny, cell,              \
+                       real_out ? 1 : 0, stamps, done);                                      \
     return hipGetLastError();                                                                \
   }
     C(2048) C(4096) C(8192) C(16384)

@@ -243,8 +243,23 @@ constexpr int HS = MLP_HID + 8;      // LDS row stride (bf16 elements)
 // SPLIT: every operand is carried as a high BF16 part and a BF16 residual, and each
 // product as hi*hi + hi*lo + lo*hi (three BF16 matrix-core steps, FP32 accumulation):
 // about 16 significant bits instead of 8.
+// GELU for inference: z Phi(z) with erf from Abramowitz & Stegun 7.1.26 (absolute error
+// below 1.5e-7, far under the BF16 products' rounding), branch-free: one reciprocal and
+// one exponential instead of the library erf's two-range evaluation.
+__device__ __forceinline__ float gelu_infer(float z) {
+  const float x = fabsf(z) * 0.7071067811865475f;
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+  float p = 1.061405429f;
+  p = fmaf(p, t, -1.453152027f);
+  p = fmaf(p, t, 1.421413741f);
+  p = fmaf(p, t, -0.284496736f);
+  p = fmaf(p, t, 0.254829592f);
+  const float e = 1.0f - p * t * __expf(-x * x);   // erf(|z| / sqrt 2)
+  return 0.5f * z * (1.0f + copysignf(e, z));
+}
+
 template <bool SPLIT>
-__global__ __launch_bounds__(256) void k_infer_bf16(const float* __restrict__ x, int64_t n,
+__global__ __launch_bounds__(256, 2) void k_infer_bf16(const float* __restrict__ x, int64_t n,
                                                     const float* __restrict__ params,
                                                     const uint16_t* __restrict__ wt,
                                                     float* __restrict__ out) {
@@ -257,26 +272,32 @@ __global__ __launch_bounds__(256) void k_infer_bf16(const float* __restrict__ x,
     H[row * HS + col] = hi;
     if (SPLIT) Hl[row * HS + col] = to_bf16(v - from_bf16(hi));
   };
-  // layer 0 in FP32: thread tid owns hidden unit tid
+  // layer 0 in FP32: thread tid owns hidden unit tid; the tile's inputs are staged in
+  // LDS once (rows past n read as zero and are never written out)
   {
+    __shared__ float xs[IR * MLP_IN];
+    for (int i = tid; i < IR * MLP_IN; i += 256) {
+      const int64_t row = r0 + i / MLP_IN;
+      xs[i] = row < n ? x[r0 * MLP_IN + i] : 0.f;
+    }
     float w[MLP_IN];
 #pragma unroll
     for (int i = 0; i < MLP_IN; ++i) w[i] = params[(int64_t)i * MLP_HID + tid];
     const float b0 = params[mlp_b_offset(0) + tid];
+    __syncthreads();
+#pragma unroll 4
     for (int r = 0; r < IR; ++r) {
-      const int64_t row = r0 + r;
       float z = b0;
-      if (row < n) {
 #pragma unroll
-        for (int i = 0; i < MLP_IN; ++i) z += x[row * MLP_IN + i] * w[i];
-      }
-      put(r, tid, gelu(z));
+      for (int i = 0; i < MLP_IN; ++i) z += xs[r * MLP_IN + i] * w[i];
+      put(r, tid, gelu_infer(z));
     }
   }
   __syncthreads();
   const int am = lane & 31, ak = 8 * (lane >> 5);
   // layers 1..4: wave wv computes NB column tiles starting at column wv * 32 * NB
-  auto layer = [&](const uint16_t* W, auto nbt, f32x16 (&acc)[2][decltype(nbt)::value]) {
+  auto layer = [&](const uint16_t* W, int col0, auto nbt,
+                   f32x16 (&acc)[2][decltype(nbt)::value]) {
     constexpr int NB = decltype(nbt)::value;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -284,19 +305,27 @@ __global__ __launch_bounds__(256) void k_infer_bf16(const float* __restrict__ x,
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+    // the weights (L2-resident) of step k0 + 16 are requested before the products of
+    // step k0, so that their latency hides behind the matrix-core work
+    bf16x8 fb[NB], lb[NB];
+    auto load_b = [&](int k0, bf16x8 (&b0)[NB], bf16x8 (&b1)[NB]) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int64_t o = (int64_t)(col0 + wv * 32 * NB + b * 32 + am) * MLP_HID + k0 + ak;
+        b0[b] = *reinterpret_cast<const bf16x8*>(&W[o]);
+        if (SPLIT) b1[b] = *reinterpret_cast<const bf16x8*>(&W[WT_HALF + o]);
+      }
+    };
+    load_b(0, fb, lb);
+#pragma unroll 2
     for (int k0 = 0; k0 < MLP_HID; k0 += 16) {
-      bf16x8 fa[2], fb[NB], la[2], lb[NB];
+      bf16x8 fa[2], la[2], nfb[NB], nlb[NB];
+      if (k0 + 16 < MLP_HID) load_b(k0 + 16, nfb, nlb);
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int o = (a * 32 + am) * HS + k0 + ak;
         fa[a] = *reinterpret_cast<const bf16x8*>(&H[o]);
         if (SPLIT) la[a] = *reinterpret_cast<const bf16x8*>(&Hl[o]);
-      }
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int64_t o = (int64_t)(wv * 32 * NB + b * 32 + am) * MLP_HID + k0 + ak;
-        fb[b] = *reinterpret_cast<const bf16x8*>(&W[o]);
-        if (SPLIT) lb[b] = *reinterpret_cast<const bf16x8*>(&W[WT_HALF + o]);
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -310,11 +339,18 @@ __global__ __launch_bounds__(256) void k_infer_bf16(const float* __restrict__ x,
                 __builtin_amdgcn_mfma_f32_32x32x16_bf16(la[a], fb[b], acc[a][b], 0, 0, 0);
           }
         }
+      if (k0 + 16 < MLP_HID) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          fb[b] = nfb[b];
+          if (SPLIT) lb[b] = nlb[b];
+        }
+      }
     }
   };
   for (int l = 1; l < MLP_LAYERS; ++l) {
     f32x16 acc[2][2];
-    layer(wt + (int64_t)(l - 1) * MLP_HID * MLP_HID, std::integral_constant<int, 2>{}, acc);
+    layer(wt + (int64_t)(l - 1) * MLP_HID * MLP_HID, 0, std::integral_constant<int, 2>{}, acc);
     __syncthreads();
     const float* bias = params + mlp_b_offset(l);
 #pragma unroll
@@ -325,26 +361,31 @@ __global__ __launch_bounds__(256) void k_infer_bf16(const float* __restrict__ x,
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
-          put(a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3), col, gelu(acc[a][b][i] + bb));
+          put(a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3), col,
+              gelu_infer(acc[a][b][i] + bb));
     }
     __syncthreads();
   }
-  // output layer: wave wv computes columns [128 wv, 128 wv + 128) (451 real columns)
-  f32x16 acc[2][4];
-  layer(wt + 3LL * MLP_HID * MLP_HID, std::integral_constant<int, 4>{}, acc);
+  // output layer in two halves of 256 columns (451 real): in half h, wave wv computes
+  // columns [256 h + 64 wv, 256 h + 64 wv + 64), so that the accumulators of one half
+  // (64 registers) leave room for two waves per SIMD
   const float* bias = params + mlp_b_offset(MLP_LAYERS);
+  for (int h = 0; h < 2; ++h) {
+    f32x16 acc[2][2];
+    layer(wt + 3LL * MLP_HID * MLP_HID, 256 * h, std::integral_constant<int, 2>{}, acc);
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int col = wv * 128 + b * 32 + am;
-    if (col >= MLP_OUT) continue;
-    const float bb = bias[col];
+    for (int b = 0; b < 2; ++b) {
+      const int col = 256 * h + wv * 64 + b * 32 + am;
+      if (col >= MLP_OUT) continue;
+      const float bb = bias[col];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int64_t row = r0 + a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        if (row < n) out[row * MLP_OUT + col] = acc[a][b][i] + bb;
-      }
+        for (int i = 0; i < 16; ++i) {
+          const int64_t row = r0 + a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+          if (row < n) out[row * MLP_OUT + col] = acc[a][b][i] + bb;
+        }
+    }
   }
 }
 

@@ -100,9 +100,12 @@ void destroy_op(wf_op* op) {
     dfree(c.htiles);
     dfree(c.hvals);
     dfree(c.flagged);
+    dfree(c.ctab);
     for (DevBuf* b : {&c.uvw, &c.wts, &c.uperm, &c.row_wi, &c.mids, &c.cents, &c.crow}) dfree(*b);
   }
   dfree(op->otf_mis);
+  dfree(op->net_params);
+  dfree(op->net_wt);
   release_sweep(op);
   for (size_t b = 0; b < op->br.size(); ++b) release_branch(op->br[b], b > 0);
   if (op->fork) (void)hipEventDestroy(op->fork);
@@ -502,27 +505,41 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   };
   RowClasses rck, rcs;
   if ((st = class_lists([](int64_t i) { return i; }, dlk, rck)) != WF_OK) return st;
-  auto surrogate_pass = [&](const int32_t* order, auto&& launch) -> wf_status {
-    if (!mlp) return launch(0, M, Surrogate{});
-    for (int64_t r0 = 0; r0 < M; r0 += CH) {
-      const int64_t n = std::min<int64_t>(CH, M - r0);
-      WF_HIP(launch_row_inputs((const double*)duvw.p, order, r0, n, ch.scale, gsx, gsy,
-                               (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
-                               Lfield, (float*)dx.p, s));
-      wf_status e = mlp_infer_bf16(mlp, (const float*)dx.p, n, true, (float*)dpred.p, s);
-      if (e != WF_OK) return e;
+  // Residual kernels from the network where it pays: the rows of kernel-side class 1
+  // (sides 9..15).  Smaller kernels cost less to build exactly than one inference, and
+  // wider ones exceed the network's window.  That class's rows are inferred in chunks of
+  // its row list (predictions indexed by slot); the other classes launch once, exact.
+  auto surrogate_pass = [&](const RowClasses& rc, const int32_t* order,
+                            auto&& launch) -> wf_status {
+    const ClassSlices all = slice_classes(rc, 0, M);
+    if (!mlp) return launch(all, Surrogate{});
+    ClassSlices rest = all;
+    rest.n[NET_CLASS] = 0;
+    wf_status e = launch(rest, Surrogate{});
+    if (e != WF_OK) return e;
+    for (int64_t c0 = 0; c0 < all.n[NET_CLASS]; c0 += CH) {
+      const int64_t n = std::min<int64_t>(CH, all.n[NET_CLASS] - c0);
+      WF_HIP(launch_row_inputs((const double*)duvw.p, rc.d, order, rc.off[NET_CLASS] + c0, n,
+                               ch.scale, gsx, gsy, (const double*)dmids.p, ch.P,
+                               (const double*)dcents.p, op->kp, Lfield, (float*)dx.p, s));
+      if ((e = mlp_infer_bf16(mlp, (const float*)dx.p, n, true, (float*)dpred.p, s)) != WF_OK)
+        return e;
+      ClassSlices one{};
+      one.rows[NET_CLASS] = all.rows[NET_CLASS] + c0;
+      one.n[NET_CLASS] = n;
       Surrogate sg;
       sg.pred = (const float*)dpred.p;
       sg.logtol = logtol;
+      sg.by_slot = true;
       sg.used = order ? nullptr : (int*)dused.p;
-      if ((e = launch(r0, r0 + n, sg)) != WF_OK) return e;
+      if ((e = launch(one, sg)) != WF_OK) return e;
     }
     return WF_OK;
   };
-  st = surrogate_pass(nullptr, [&](int64_t r0, int64_t r1, const Surrogate& sg) -> wf_status {
-    WF_HIP(launch_rowsym((const double*)duvw.p, r0, slice_classes(rck, r0, r1), ch.scale,
-                         gsx, gsy, (const double*)dmids.p, ch.P, (const double*)dcents.p, Kx,
-                         Ky, tile, op->kp, (uint64_t*)dkeys.p, (float*)ddrop.p, sg, s));
+  st = surrogate_pass(rck, nullptr, [&](const ClassSlices& cs, const Surrogate& sg) -> wf_status {
+    WF_HIP(launch_rowsym((const double*)duvw.p, 0, cs, ch.scale, gsx, gsy,
+                         (const double*)dmids.p, ch.P, (const double*)dcents.p, Kx, Ky, tile,
+                         op->kp, (uint64_t*)dkeys.p, (float*)ddrop.p, sg, s));
     return WF_OK;
   });
   if (st != WF_OK) return st;
@@ -611,8 +628,15 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     holo = false;
     otf = true;
   }
-  if (otf && mlp)
-    return fail(WF_ENOTSUP, "the on-the-fly strategy builds exact kernels only (no kernel network)");
+  if (holo && mlp)
+    return fail(WF_ENOTSUP, "the holographic strategy builds exact kernels only (no kernel network)");
+  if (otf && mlp && !op->net_otf) {
+    // every apply re-infers the kernels of the network's rows: keep the parameters the
+    // build used, so that the predictions (and the patch sides they decide) never change
+    if ((st = mlp_snapshot(mlp, op->net_params, op->net_wt, s)) != WF_OK) return st;
+    op->net_otf = true;
+    op->net_logtol = logtol;
+  }
   ch.gchunk.clear();
   double vp_flops = 0.0;
   if (otf) {
@@ -844,10 +868,9 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   if (!holo && !otf) {
   if ((st = dalloc(ch.vals, (size_t)b_v * std::max<int64_t>(taps_total, 1))) != WF_OK)
     return st;
-  st = surrogate_pass((const int32_t*)ch.perm.p,
-                      [&](int64_t s0, int64_t s1, const Surrogate& sg) -> wf_status {
-                        WF_HIP(launch_gbuild((const double*)duvw.p, s0,
-                                             slice_classes(rcs, s0, s1),
+  st = surrogate_pass(rcs, (const int32_t*)ch.perm.p,
+                      [&](const ClassSlices& cs, const Surrogate& sg) -> wf_status {
+                        WF_HIP(launch_gbuild((const double*)duvw.p, 0, cs,
                                              (const int32_t*)ch.perm.p,
                                              (const uint32_t*)ch.meta.p,
                                              (const uint32_t*)ch.voff.p,
@@ -913,6 +936,29 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   in.surrogate_fraction = M ? (double)nused / (double)M : 0.0;
   in.mem_h_bytes = holo ? (double)b_v * ch.h_values + (double)ch.htiles.bytes : 0.0;
   in.nflagged = ch.nflag;
+  {
+    // column tables of the w-layer modulations (eq. 6): the series forms of the row FFT
+    // passes hold where r2 = l^2 + m^2 <= 1/100 over the image and the phase beyond the
+    // quadratic term, 2 pi |w_p| |n - 1 + r2/2|, stays within 1/4 radian
+    const int nx = op->shape.nx;
+    const double hl = 0.5 * nx * op->shape.cell_rad, hm = 0.5 * op->shape.ny * op->shape.cell_rad;
+    const double r2 = hl * hl + hm * hm;
+    const double dl = std::fabs(-r2 / (1.0 + std::sqrt(1.0 - r2)) + 0.5 * r2);
+    ch.cfast.assign(ch.P, 0);
+    bool any = false;
+    for (int p = 0; p < ch.P; ++p) {
+      ch.cfast[p] = r2 <= 0.01 && 2.0 * M_PI * std::fabs(ch.centroids[p]) * dl <= 0.25;
+      any = any || ch.cfast[p];
+    }
+    if (any) {
+      if ((st = dalloc(ch.ctab, sizeof(float2) * (size_t)ch.P * nx)) != WF_OK) return st;
+      for (int p = 0; p < ch.P; ++p)
+        if (ch.cfast[p])
+          WF_HIP(launch_chirp_table((float2*)ch.ctab.p + (size_t)p * nx, nx,
+                                    op->shape.cell_rad, ch.centroids[p],
+                                    (const float*)op->sx.p, s));
+    }
+  }
   if (holo) {
     // only the stencils serve the applies of a holographic operator
     dfree(ch.meta);
@@ -951,15 +997,23 @@ struct Lane {
   float* acc;
   void* gbuf;   // transient G values (on-the-fly channels)
   hipStream_t s;
+  float* net_x;      // network inputs / outputs (on-the-fly channels with the network)
+  float* net_pred;
 };
 
 Lane lane_of(wf_op* op, int b, hipStream_t caller) {
   Branch& B = op->br[b];
   return Lane{(float2*)B.X.p, (float2*)B.Y.p, (float2*)B.A.p, (float*)B.acc.p, B.gbuf.p,
-              b == 0 ? caller : B.s};
+              b == 0 ? caller : B.s, (float*)B.net_x.p, (float*)B.net_pred.p};
 }
 
 Profiler* prof_of(wf_op* op, int k) { return op->capturing ? nullptr : &op->prof[k]; }
+
+// Column table of bin p's w-layer modulation, or null where the direct form is used.
+const float2* ctab_of(const wf_op* op, const ChanOp& ch, int p) {
+  if (ch.cfast.empty() || !ch.cfast[p]) return nullptr;
+  return (const float2*)ch.ctab.p + (size_t)p * op->shape.nx;
+}
 
 // Side of the grid block that one work item of bin p covers.
 int bin_tile(const wf_op* op, const ChanOp& ch, int p) {
@@ -968,13 +1022,13 @@ int bin_tile(const wf_op* op, const ChanOp& ch, int p) {
 
 // One w-layer's forward half: X_p = F Z_p x (only inside the bin's support if pr).
 wf_status layer_forward(wf_op* op, const Lane& L, const float* x, double wp,
-                        const ColPrune* pr) {
+                        const ColPrune* pr, const float2* ctab = nullptr) {
   const int nx = op->shape.nx, ny = op->shape.ny;
   {
     ProfScope ps(prof_of(op, 1), L.s);
     WF_HIP(launch_fwd_rows(x, L.A, (const float2*)op->twx.p, (const float*)op->sx.p,
                            (const float*)op->sy.p, nx, ny, op->Kx, op->shape.cell_rad, wp,
-                           pr ? pr->strip : nullptr, L.s));
+                           pr ? pr->strip : nullptr, ctab, L.s));
   }
   {
     ProfScope ps(prof_of(op, 2), L.s);
@@ -986,7 +1040,7 @@ wf_status layer_forward(wf_op* op, const Lane& L, const float* x, double wp,
 // One w-layer's adjoint half from the gridded Y: out (+)= Z_p^dag F^dag Y (Y is cleared
 // where it was read; outside the bin's support it is zero already).
 wf_status layer_adjoint(wf_op* op, const Lane& L, void* out, double wp, int mode,
-                        const ColPrune* pr) {
+                        const ColPrune* pr, const float2* ctab = nullptr) {
   const int nx = op->shape.nx, ny = op->shape.ny;
   {
     ProfScope ps(prof_of(op, 3), L.s);
@@ -996,7 +1050,7 @@ wf_status layer_adjoint(wf_op* op, const Lane& L, void* out, double wp, int mode
     ProfScope ps(prof_of(op, 4), L.s);
     WF_HIP(launch_inv_rows(L.A, out, (const float2*)op->twx.p, (const float*)op->sx.p,
                            (const float*)op->sy.p, nx, ny, op->Kx, op->shape.cell_rad, wp,
-                           mode, pr ? pr->strip : nullptr, L.s));
+                           mode, pr ? pr->strip : nullptr, ctab, L.s));
   }
   return WF_OK;
 }
@@ -1032,16 +1086,47 @@ wf_status otf_bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, in
   const size_t b_v = store == WF_STORE_F32 ? 8 : 4;
   const double gsx = op->Kx * op->shape.cell_rad, gsy = op->Ky * op->shape.cell_rad;
   const int32_t* uperm = (const int32_t*)(ch.uperm.p ? ch.uperm.p : ch.perm.p);
-  if (kind != WF_APPLY_ADJOINT && (st = layer_forward(op, L, in, wp, &pr)) != WF_OK) return st;
+  const float2* ct = ctab_of(op, ch, p);
+  if (kind != WF_APPLY_ADJOINT && (st = layer_forward(op, L, in, wp, &pr, ct)) != WF_OK)
+    return st;
   for (int k = ch.ck_first[p]; k < ch.ck_first[p] + ch.ck_count[p]; ++k) {
     {
       ProfScope ps(prof_of(op, 5), L.s);
-      WF_HIP(launch_gbuild((const double*)ch.uvw.p, ch.ck_s0[k], ch.ck_cls[k], uperm,
-                           (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
-                           (const int32_t*)ch.row_wi.p, wk, ch.scale, gsx, gsy,
-                           (const double*)ch.mids.p, ch.P, (const double*)ch.cents.p, op->kp,
-                           L.gbuf, ch.ck_vbase[k], store, (int*)op->otf_mis.p, Surrogate{},
-                           (const float*)ch.wts.p, L.s));
+      auto gbuild = [&](const ClassSlices& cs, const Surrogate& sg) -> wf_status {
+        WF_HIP(launch_gbuild((const double*)ch.uvw.p, ch.ck_s0[k], cs, uperm,
+                             (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
+                             (const int32_t*)ch.row_wi.p, wk, ch.scale, gsx, gsy,
+                             (const double*)ch.mids.p, ch.P, (const double*)ch.cents.p,
+                             op->kp, L.gbuf, ch.ck_vbase[k], store, (int*)op->otf_mis.p, sg,
+                             (const float*)ch.wts.p, L.s));
+        return WF_OK;
+      };
+      if (!op->net_otf) {
+        if ((st = gbuild(ch.ck_cls[k], Surrogate{})) != WF_OK) return st;
+      } else {
+        // as at build: the network's class from its predictions, the others exact
+        const ClassSlices& all = ch.ck_cls[k];
+        ClassSlices rest = all;
+        rest.n[NET_CLASS] = 0;
+        if ((st = gbuild(rest, Surrogate{})) != WF_OK) return st;
+        const double Lfield = op->shape.nx * op->shape.cell_rad;
+        for (int64_t c0 = 0; c0 < all.n[NET_CLASS]; c0 += NET_CHUNK) {
+          const int64_t n = std::min<int64_t>(NET_CHUNK, all.n[NET_CLASS] - c0);
+          WF_HIP(launch_row_inputs((const double*)ch.uvw.p, all.rows[NET_CLASS], uperm, c0, n,
+                                   ch.scale, gsx, gsy, (const double*)ch.mids.p, ch.P,
+                                   (const double*)ch.cents.p, op->kp, Lfield, L.net_x, L.s));
+          WF_HIP(launch_mlp_infer_bf16(L.net_x, n, (const float*)op->net_params.p,
+                                       (const uint16_t*)op->net_wt.p, true, L.net_pred, L.s));
+          ClassSlices one{};
+          one.rows[NET_CLASS] = all.rows[NET_CLASS] + c0;
+          one.n[NET_CLASS] = n;
+          Surrogate sg;
+          sg.pred = L.net_pred;
+          sg.logtol = op->net_logtol;
+          sg.by_slot = true;
+          if ((st = gbuild(one, sg)) != WF_OK) return st;
+        }
+      }
     }
     // item value offsets are absolute: shift the base so that they land in the buffer
     const void* vals = (const char*)L.gbuf - (size_t)ch.ck_vbase[k] * b_v;
@@ -1066,7 +1151,7 @@ wf_status otf_bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, in
   }
   if (kind == WF_APPLY_FORWARD) return WF_OK;
   const int mode = (kind == WF_APPLY_PSF_RE ? 2 : 0) + (first ? 0 : 1);
-  return layer_adjoint(op, L, out, wp, mode, &pr);
+  return layer_adjoint(op, L, out, wp, mode, &pr, ct);
 }
 
 // Bin p of one channel: that w-layer's share of the apply.  first: the layer opens the
@@ -1078,8 +1163,9 @@ wf_status bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
   const ColPrune pr = prune_of(op, ch, p);
   const double wp = ch.centroids[p];
   const WorkItem* wk = (const WorkItem*)ch.work.p;
+  const float2* ct = ctab_of(op, ch, p);
   if (kind == WF_APPLY_FORWARD) {
-    if ((st = layer_forward(op, L, in, wp, &pr)) != WF_OK) return st;
+    if ((st = layer_forward(op, L, in, wp, &pr, ct)) != WF_OK) return st;
     for (int c = 0; c < NCLS; ++c) {
       const int n = ch.cls_nwi[p * NCLS + c];
       if (n == 0) continue;
@@ -1098,9 +1184,9 @@ wf_status bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
                          op->opt.store, (const float2*)in, L.Y, op->Kx, op->Ky,
                          bin_tile(op, ch, p), L.s));
     }
-    return layer_adjoint(op, L, out, wp, first ? 0 : 1, &pr);
+    return layer_adjoint(op, L, out, wp, first ? 0 : 1, &pr, ct);
   }
-  if ((st = layer_forward(op, L, in, wp, &pr)) != WF_OK) return st;
+  if ((st = layer_forward(op, L, in, wp, &pr, ct)) != WF_OK) return st;
   if (ch.holo) {
     ProfScope ps(prof_of(op, 0), L.s);
     int tsh = 0;
@@ -1119,7 +1205,7 @@ wf_status bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
     }
   }
   const int mode = (kind == WF_APPLY_PSF_RE ? 2 : 0) + (first ? 0 : 1);
-  return layer_adjoint(op, L, out, wp, mode, &pr);
+  return layer_adjoint(op, L, out, wp, mode, &pr, ct);
 }
 
 // All non-empty bins of channel c on one lane, written directly to the channel's output.
@@ -1141,19 +1227,28 @@ wf_status run_channel(wf_op* op, int kind, int c, const Lane& L, const float* in
 
 // ------------------------------------------------------------------ sweep (layer-batched)
 
+void release_sweep_lanes(Sweep& W) {
+  for (SweepLane& L : W.lanes) {
+    for (int c = 0; c < Sweep::NLIST; ++c) dfree(L.items[c]);
+    if (L.s) (void)hipStreamDestroy(L.s);
+    if (L.fwd) (void)hipEventDestroy(L.fwd);
+    if (L.end) (void)hipEventDestroy(L.end);
+  }
+  W.lanes.clear();
+  dfree(W.queues);
+}
+
 void release_sweep(wf_op* op) {
   Sweep& W = op->sweep;
+  release_sweep_lanes(W);
   for (DevBuf& b : W.grids) dfree(b);
   W.grids.clear();
   dfree(W.layers);
   dfree(W.pairs);
   dfree(W.chan_layers);
-  for (int c = 0; c < Sweep::NLIST; ++c) {
-    dfree(W.items[c]);
-    W.nitems[c] = 0;
-  }
-  dfree(W.queues);
   dfree(W.done);
+  if (W.fork) (void)hipEventDestroy(W.fork);
+  W.fork = nullptr;
   W.nlayers = 0;
   W.npairs = 0;
   W.on = false;
@@ -1161,11 +1256,109 @@ void release_sweep(wf_op* op) {
 
 bool sweep_size_ok(int K) { return K == 2048 || K == 4096 || K == 8192 || K == 16384; }
 
+// The lanes of a sweep: nlanes contiguous channel ranges of about equal cost (stored
+// values plus the FFT passes of their layers), each with its work items per (patch
+// class, item tile) -- bin field = layer, largest first -- its queues, and, beyond the
+// first, a stream and two events.  The caller has synchronised the device.
+wf_status sweep_lanes(wf_op* op, int nlanes) {
+  Sweep& W = op->sweep;
+  release_sweep_lanes(W);
+  wf_status st;
+  const int nchan = (int)op->chans.size();
+  // layer and pair ranges of every channel, and its cost
+  std::vector<int> lay0(nchan + 1, 0), pair0(nchan + 1, 0);
+  std::vector<double> cost(nchan, 0.0);
+  {
+    std::vector<int2> cl(nchan);
+    WF_HIP(hipMemcpy(cl.data(), W.chan_layers.p, sizeof(int2) * nchan, hipMemcpyDeviceToHost));
+    std::vector<int2> pr(W.npairs);
+    if (W.npairs)
+      WF_HIP(hipMemcpy(pr.data(), W.pairs.p, sizeof(int2) * W.npairs, hipMemcpyDeviceToHost));
+    const double b_v = op->opt.store == WF_STORE_F32 ? 8.0 : 4.0;
+    const double layer_bytes = 48.0 * (double)op->Kx * op->shape.ny;   // FFT passes, roughly
+    size_t pi = 0;
+    for (int c = 0; c < nchan; ++c) {
+      lay0[c] = cl[c].x;
+      pair0[c] = (int)pi;
+      while (pi < pr.size() && pr[pi].x < cl[c].x + cl[c].y) ++pi;
+      cost[c] = b_v * (double)op->chans[c].ntaps + layer_bytes * cl[c].y;
+    }
+    lay0[nchan] = W.nlayers;
+    pair0[nchan] = W.npairs;
+  }
+  nlanes = std::max(1, std::min({nlanes, nchan, Sweep::MAXLANES}));
+  double total = 0;
+  for (double c : cost) total += c;
+  std::vector<int> cut(nlanes + 1, nchan);
+  cut[0] = 0;
+  {
+    double acc = 0;
+    int k = 1;
+    for (int c = 0; c < nchan && k < nlanes; ++c) {
+      acc += cost[c];
+      if (acc >= total * k / nlanes && c + 1 < nchan) cut[k++] = c + 1;
+    }
+    for (; k < nlanes; ++k) cut[k] = nchan;
+  }
+  W.lanes.resize(nlanes);
+  for (int k = 0; k < nlanes; ++k) {
+    SweepLane& L = W.lanes[k];
+    L.c0 = cut[k];
+    L.nc = cut[k + 1] - cut[k];
+    L.l0 = lay0[L.c0];
+    L.nl = lay0[L.c0 + L.nc] - L.l0;
+    L.p0 = pair0[L.c0];
+    L.np = pair0[L.c0 + L.nc] - L.p0;
+    std::vector<WorkItem> lists[Sweep::NLIST];
+    int l = L.l0;
+    for (int c = L.c0; c < L.c0 + L.nc; ++c) {
+      const ChanOp& ch = op->chans[c];
+      if (ch.nrows == 0) continue;
+      std::vector<WorkItem> wk(ch.nwork);
+      WF_HIP(hipMemcpy(wk.data(), ch.work.p, sizeof(WorkItem) * wk.size(),
+                       hipMemcpyDeviceToHost));
+      for (int p = 0; p < ch.P; ++p) {
+        if (ch.bin_nrows[p] == 0) continue;
+        const int sh = ch.bin_tsh.empty() ? 0 : ch.bin_tsh[p];
+        for (int kc = 0; kc < NCLS; ++kc) {
+          const int n = ch.cls_nwi[p * NCLS + kc];
+          for (int i = 0; i < n; ++i) {
+            WorkItem w = wk[ch.cls_wi0[p * NCLS + kc] + i];
+            w.bin = l;
+            lists[2 * kc + sh].push_back(w);
+          }
+        }
+        ++l;
+      }
+    }
+    for (int j = 0; j < Sweep::NLIST; ++j) {
+      std::stable_sort(lists[j].begin(), lists[j].end(),
+                       [](const WorkItem& a, const WorkItem& b) { return a.nrows > b.nrows; });
+      L.nitems[j] = (int)lists[j].size();
+      if ((st = dalloc(L.items[j], std::max<size_t>(sizeof(WorkItem) * lists[j].size(), 16))) !=
+          WF_OK)
+        return st;
+      if (!lists[j].empty())
+        WF_HIP(hipMemcpy(L.items[j].p, lists[j].data(), sizeof(WorkItem) * lists[j].size(),
+                         hipMemcpyHostToDevice));
+    }
+    if (k > 0) {
+      WF_HIP(hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking));
+      WF_HIP(hipEventCreateWithFlags(&L.end, hipEventDisableTiming));
+    }
+    if (k + 1 < nlanes) WF_HIP(hipEventCreateWithFlags(&L.fwd, hipEventDisableTiming));
+  }
+  const size_t qb = sizeof(int) * 2 * Sweep::NLIST * nlanes;
+  if ((st = dalloc(W.queues, qb)) != WF_OK) return st;
+  WF_HIP(hipMemset(W.queues.p, 0, qb));
+  WF_HIP(hipDeviceSynchronize());
+  return WF_OK;
+}
+
 // Lay out a sweep: the grids of every non-empty (channel, bin) layer, the layer table,
-// the column pairs of each layer's active column groups, each channel's layer range and,
-// per (patch class, item tile), every layer's work items (bin field = layer), largest
-// first.  The caller has synchronised the device.
-wf_status sweep_build(wf_op* op) {
+// the column pairs of each layer's active column groups, each channel's layer range,
+// then the lanes (sweep_lanes).  The caller has synchronised the device.
+wf_status sweep_build(wf_op* op, int nlanes) {
   release_sweep(op);
   Sweep& W = op->sweep;
   wf_status st;
@@ -1174,13 +1367,10 @@ wf_status sweep_build(wf_op* op) {
   const size_t arow = sizeof(float2) * (size_t)op->shape.ny * op->Kx;
   std::vector<SweepLayer> tab;
   std::vector<int2> pairs, cl(nchan, int2{0, 0});
-  std::vector<WorkItem> cls_items[Sweep::NLIST];
   for (int c = 0; c < nchan; ++c) {
     const ChanOp& ch = op->chans[c];
     cl[c].x = (int)tab.size();
     if (ch.nrows == 0) continue;
-    std::vector<WorkItem> wk(ch.nwork);
-    WF_HIP(hipMemcpy(wk.data(), ch.work.p, sizeof(WorkItem) * wk.size(), hipMemcpyDeviceToHost));
     std::vector<char> pr(ch.prune.bytes);
     WF_HIP(hipMemcpy(pr.data(), ch.prune.p, pr.size(), hipMemcpyDeviceToHost));
     for (int p = 0; p < ch.P; ++p) {
@@ -1207,18 +1397,11 @@ wf_status sweep_build(wf_op* op) {
       L.perm = (const int32_t*)ch.perm.p;
       L.vis_off = ch.vis_off;
       L.wp = ch.centroids[p];
+      L.ctab = ctab_of(op, ch, p);
       L.chan = c;
       tab.push_back(L);
       const int32_t* grp = (const int32_t*)(pr.data() + ch.pr_groups[p]);
       for (int g = 0; g < ch.pr_ngroups[p]; ++g) pairs.push_back(int2{l, grp[g]});
-      for (int k = 0; k < NCLS; ++k) {
-        const int n = ch.cls_nwi[p * NCLS + k];
-        for (int i = 0; i < n; ++i) {
-          WorkItem w = wk[ch.cls_wi0[p * NCLS + k] + i];
-          w.bin = l;
-          cls_items[2 * k + (ch.bin_tsh.empty() ? 0 : ch.bin_tsh[p])].push_back(w);
-        }
-      }
     }
     cl[c].y = (int)tab.size() - cl[c].x;
   }
@@ -1233,34 +1416,26 @@ wf_status sweep_build(wf_op* op) {
   if ((st = upload(W.layers, tab.data(), sizeof(SweepLayer) * tab.size())) != WF_OK) return st;
   if ((st = upload(W.pairs, pairs.data(), sizeof(int2) * pairs.size())) != WF_OK) return st;
   if ((st = upload(W.chan_layers, cl.data(), sizeof(int2) * cl.size())) != WF_OK) return st;
-  for (int k = 0; k < Sweep::NLIST; ++k) {
-    std::stable_sort(cls_items[k].begin(), cls_items[k].end(),
-                     [](const WorkItem& a, const WorkItem& b) { return a.nrows > b.nrows; });
-    W.nitems[k] = (int)cls_items[k].size();
-    if ((st = upload(W.items[k], cls_items[k].data(), sizeof(WorkItem) * cls_items[k].size())) !=
-        WF_OK)
-      return st;
-  }
-  if ((st = dalloc(W.queues, sizeof(int) * 2 * Sweep::NLIST)) != WF_OK) return st;
-  WF_HIP(hipMemset(W.queues.p, 0, sizeof(int) * 2 * Sweep::NLIST));
   if ((st = dalloc(W.done, sizeof(int) * std::max(nchan, 1))) != WF_OK) return st;
   WF_HIP(hipMemset(W.done.p, 0, sizeof(int) * std::max(nchan, 1)));
+  WF_HIP(hipEventCreateWithFlags(&W.fork, hipEventDisableTiming));
   WF_HIP(hipDeviceGetAttribute(&W.ncu, hipDeviceAttributeMultiprocessorCount, op->device));
-  WF_HIP(hipDeviceSynchronize());
+  if ((st = sweep_lanes(op, nlanes)) != WF_OK) return st;
   W.on = true;
   return WF_OK;
 }
 
-// A whole apply as one launch per stage over every layer: forward rows, forward columns,
-// the row kernels per patch class (persistent), inverse columns, inverse rows summing
-// each channel's layers.  No stage waits on the host and nothing is allocated.
+// A whole apply as one launch per stage and lane: forward rows, forward columns, the row
+// kernels per (patch class, item tile) (persistent), inverse columns, inverse rows
+// summing each channel's layers.  Lane k > 0 runs on its own stream and starts when lane
+// k - 1 has issued its forward passes; the caller's stream joins every lane.  No stage
+// waits on the host and nothing is allocated.
 wf_status run_sweep(wf_op* op, int kind, const float* in, float* out, hipStream_t s) {
   const Sweep& W = op->sweep;
   const int nchan = (int)op->chans.size();
   const int nx = op->shape.nx, ny = op->shape.ny;
   const SweepLayer* sl = (const SweepLayer*)W.layers.p;
   const int2* pairs = (const int2*)W.pairs.p;
-  int* queues = (int*)W.queues.p;
   unsigned long long* stamps = op->stamping ? (unsigned long long*)op->stamps.p : nullptr;
   const int tsh = [&] { int t = 0; while ((1 << t) < op->tile) ++t; return t; }();
   const int tiles_x = op->Kx / op->tile;
@@ -1272,41 +1447,55 @@ wf_status run_sweep(wf_op* op, int kind, const float* in, float* out, hipStream_
       if (ch.nflag > 0)
         WF_HIP(launch_scatter_zero((float2*)out + ch.vis_off, (const int32_t*)ch.flagged.p,
                                    ch.nflag, s));
-  if (fwd) {
+  const int nl = (int)W.lanes.size();
+  if (nl > 1) WF_HIP(hipEventRecord(W.fork, s));
+  for (int k = 0; k < nl; ++k) {
+    const SweepLane& L = W.lanes[k];
+    const hipStream_t ls = k == 0 ? s : L.s;
+    if (k > 0) {
+      WF_HIP(hipStreamWaitEvent(ls, W.fork, 0));
+      WF_HIP(hipStreamWaitEvent(ls, W.lanes[k - 1].fwd, 0));
+    }
+    if (fwd) {
+      {
+        ProfScope ps(prof_of(op, 1), ls);
+        WF_HIP(launch_sweep_fwd_rows(in, sl + L.l0, L.nl, (const float2*)op->twx.p,
+                                     (const float*)op->sx.p, (const float*)op->sy.p, nx, ny,
+                                     op->Kx, op->shape.cell_rad, ls));
+      }
+      ProfScope ps(prof_of(op, 2), ls);
+      WF_HIP(launch_sweep_cols(false, sl, pairs + L.p0, L.np, (const float2*)op->twy.p, ny,
+                               op->Ky, tsh, tiles_x, ls));
+    }
+    if (k + 1 < nl) WF_HIP(hipEventRecord(L.fwd, ls));
     {
-      ProfScope ps(prof_of(op, 1), s);
-      WF_HIP(launch_sweep_fwd_rows(in, sl, W.nlayers, (const float2*)op->twx.p,
+      const int mode = kind == WF_APPLY_FORWARD ? 1 : (kind == WF_APPLY_ADJOINT ? 2 : 0);
+      float2* vis = kind == WF_APPLY_FORWARD ? (float2*)out
+                    : (kind == WF_APPLY_ADJOINT ? (float2*)in : nullptr);
+      int* queues = (int*)W.queues.p + 2 * Sweep::NLIST * k;
+      ProfScope ps(prof_of(op, 0), ls);
+      for (int j = 0; j < Sweep::NLIST; ++j)
+        WF_HIP(launch_rows_sweep(mode, j / 2, (const WorkItem*)L.items[j].p, L.nitems[j], sl,
+                                 op->opt.store, vis, queues + 2 * j, op->Kx, op->Ky,
+                                 op->tile << (j & 1), W.ncu, ls));
+    }
+    if (back) {
+      {
+        ProfScope ps(prof_of(op, 3), ls);
+        WF_HIP(launch_sweep_cols(true, sl, pairs + L.p0, L.np, (const float2*)op->twy.p, ny,
+                                 op->Ky, tsh, tiles_x, ls));
+      }
+      ProfScope ps(prof_of(op, 4), ls);
+      WF_HIP(launch_sweep_inv_rows(sl, (const int2*)W.chan_layers.p, L.c0, L.nc, out,
+                                   kind == WF_APPLY_PSF_RE, (const float2*)op->twx.p,
                                    (const float*)op->sx.p, (const float*)op->sy.p, nx, ny,
-                                   op->Kx, op->shape.cell_rad, s));
+                                   op->Kx, op->shape.cell_rad, stamps, (int*)W.done.p, ls));
+    } else if (stamps) {
+      for (int c = L.c0; c < L.c0 + L.nc; ++c) WF_HIP(launch_stamp(stamps + c, ls));
     }
-    ProfScope ps(prof_of(op, 2), s);
-    WF_HIP(launch_sweep_cols(false, sl, pairs, W.npairs, (const float2*)op->twy.p, ny, op->Ky,
-                             tsh, tiles_x, s));
+    if (k > 0) WF_HIP(hipEventRecord(L.end, ls));
   }
-  {
-    const int mode = kind == WF_APPLY_FORWARD ? 1 : (kind == WF_APPLY_ADJOINT ? 2 : 0);
-    float2* vis = kind == WF_APPLY_FORWARD ? (float2*)out
-                  : (kind == WF_APPLY_ADJOINT ? (float2*)in : nullptr);
-    ProfScope ps(prof_of(op, 0), s);
-    for (int k = 0; k < Sweep::NLIST; ++k)
-      WF_HIP(launch_rows_sweep(mode, k / 2, (const WorkItem*)W.items[k].p, W.nitems[k], sl,
-                               op->opt.store, vis, queues + 2 * k, op->Kx, op->Ky,
-                               op->tile << (k & 1), W.ncu, s));
-  }
-  if (back) {
-    {
-      ProfScope ps(prof_of(op, 3), s);
-      WF_HIP(launch_sweep_cols(true, sl, pairs, W.npairs, (const float2*)op->twy.p, ny, op->Ky,
-                               tsh, tiles_x, s));
-    }
-    ProfScope ps(prof_of(op, 4), s);
-    WF_HIP(launch_sweep_inv_rows(sl, (const int2*)W.chan_layers.p, nchan, out,
-                                 kind == WF_APPLY_PSF_RE, (const float2*)op->twx.p,
-                                 (const float*)op->sx.p, (const float*)op->sy.p, nx, ny, op->Kx,
-                                 op->shape.cell_rad, stamps, (int*)W.done.p, s));
-  } else if (stamps) {
-    for (int c = 0; c < nchan; ++c) WF_HIP(launch_stamp(stamps + c, s));
-  }
+  for (int k = 1; k < nl; ++k) WF_HIP(hipStreamWaitEvent(s, W.lanes[k].end, 0));
   return WF_OK;
 }
 
@@ -1472,6 +1661,8 @@ void release_branch(Branch& B, bool own_stream) {
   dfree(B.A);
   dfree(B.acc);
   dfree(B.gbuf);
+  dfree(B.net_x);
+  dfree(B.net_pred);
   if (own_stream && B.s) (void)hipStreamDestroy(B.s);
   if (B.done) (void)hipEventDestroy(B.done);
   B.s = nullptr;
@@ -1505,6 +1696,10 @@ wf_status ensure_branches(wf_op* op) {
     if (op->otf_bytes > B.gbuf.bytes) {
       dfree(B.gbuf);
       if ((st = dalloc(B.gbuf, op->otf_bytes)) != WF_OK) return st;
+    }
+    if (op->net_otf && !B.net_x.p) {
+      if ((st = dalloc(B.net_x, sizeof(float) * MLP_IN * NET_CHUNK)) != WF_OK) return st;
+      if ((st = dalloc(B.net_pred, sizeof(float) * MLP_OUT * NET_CHUNK)) != WF_OK) return st;
     }
     if (need_acc[b] && !B.acc.p) {
       if ((st = dalloc(B.acc, sizeof(float2) * (size_t)npix_of(op))) != WF_OK) return st;
@@ -2100,7 +2295,8 @@ static wf_status wf_set_sweep_body(wf_op* op, int32_t enable) {
   for (const ChanOp& ch : op->chans)
     if (ch.otf || ch.holo)
       return fail(WF_ENOTSUP, "the sweep needs every channel to store G (strategy (a))");
-  st = sweep_build(op);
+  if (enable < 0) return fail(WF_EINVAL, "enable must be 0 (off) or a lane count >= 1");
+  st = sweep_build(op, std::min<int>(enable, Sweep::MAXLANES));
   op->generation++;
   if (st != WF_OK) {
     release_sweep(op);
@@ -2293,7 +2489,7 @@ static wf_status wf_set_bin_tiles_body(wf_op* op, int32_t chan, const int32_t* t
   op->generation++;
   if (op->sweep.on) {
     WF_HIP(hipDeviceSynchronize());
-    if ((st = sweep_build(op)) != WF_OK) return st;
+    if ((st = sweep_lanes(op, (int)op->sweep.lanes.size())) != WF_OK) return st;
   }
   return WF_OK;
 }
@@ -2396,9 +2592,22 @@ wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_str
     WF_HIP(launch_fill_zero(L.Y, grid_floats, s));
     const int nchan = (int)op->chans.size();
     if (op->sweep.on) {
-      // a layer-batched sweep has no branches: only its item lists follow the new splits
+      // a layer-batched sweep has no branches: its item lists follow the new splits, and
+      // its lane count (channel ranges on streams of their own) is timed instead
+      int best_nl = 1;
+      double best_ms = 1e300;
+      for (int nl = 1; nl <= std::min(nchan, 3); ++nl) {
+        WF_HIP(hipDeviceSynchronize());
+        if ((st = sweep_lanes(op, nl)) != WF_OK) return st;
+        double t = 0;
+        if ((st = time_runs(s, reps, sweep, &t)) != WF_OK) return st;
+        if (t < best_ms) {
+          best_ms = t;
+          best_nl = nl;
+        }
+      }
       WF_HIP(hipDeviceSynchronize());
-      if ((st = sweep_build(op)) != WF_OK) return st;
+      if ((st = sweep_lanes(op, best_nl)) != WF_OK) return st;
       op->generation++;
     } else {
       std::vector<int> cands = {1, 2, 4};
@@ -2421,7 +2630,7 @@ wf_status wf_autotune(wf_op* op, const float* d_img, float* d_out, void* hip_str
     double after = 0;
     if ((st = time_runs(s, reps, sweep, &after)) != WF_OK) return st;
     if (info) {
-      info->branches = op->nbranch;
+      info->branches = op->sweep.on ? (int32_t)op->sweep.lanes.size() : op->nbranch;
       info->retuned_chans = retuned;
       info->wide_tile_bins = (int32_t)big_bins;
       info->sweep_ms_before = before;

@@ -96,6 +96,7 @@ struct SweepLayer {
   const uint32_t* meta;
   const uint32_t* voff;
   const int32_t* perm;
+  const float2* ctab;      // column table of the w-layer modulation (null: direct form)
   int64_t vis_off;         // first visibility of the layer's channel in caller order
   double wp;               // w-layer centroid
   int32_t chan;
@@ -193,6 +194,11 @@ struct ChanOp {
   // per bin: work items cover aligned blocks of 2^s x 2^s base tiles (item tile side
   // tile << s); the rows' patch words are relative to their item's window
   std::vector<int8_t> bin_tsh;
+  // per bin: the column table of its w-layer modulation ([P][nx] complex FP32, FP64
+  // phases), used by the row FFT passes where cfast[p] (field and w_p small enough for
+  // the series forms; otherwise the direct form)
+  DevBuf ctab;
+  std::vector<uint8_t> cfast;
   double measured_ms = 0;                  // last timed apply of this channel (0 = none)
   int64_t ntaps = 0;
   int64_t nwork = 0;
@@ -238,6 +244,7 @@ struct Branch {
   hipEvent_t done = nullptr;
   DevBuf X, Y, A, acc;
   DevBuf gbuf;   // transient G values of on-the-fly channels
+  DevBuf net_x, net_pred;   // network inputs and outputs (on-the-fly with the network)
 };
 
 // Work of one branch for one channel: a list of its non-empty bins.  A direct segment
@@ -252,8 +259,25 @@ struct Segment {
 
 // Layer-batched applies (wf_set_sweep): the grids of every (channel, bin) layer at once,
 // the layer table, the (layer, column group) pairs of the column passes, each channel's
-// layer range, and per patch class the work items of all layers (bin = layer index),
-// largest first, drained by one persistent launch through a two-int queue.
+// layer range, and the lanes.
+//
+// One lane of a sweep: a contiguous range of channels (and so of layers, column pairs
+// and work items) whose stages run in order on the lane's stream.  Lane k > 0 starts once
+// lane k - 1 has issued its forward passes, so that one lane's fused kernel runs beside
+// the next lane's FFT passes.
+struct SweepLane {
+  int l0 = 0, nl = 0;              // layers [l0, l0 + nl)
+  int p0 = 0, np = 0;              // column pairs [p0, p0 + np)
+  int c0 = 0, nc = 0;              // channels [c0, c0 + nc)
+  DevBuf items[2 * NCLS];          // work items per (patch class, item-tile shift) of all
+                                   // its layers (bin = layer index), largest first, drained
+                                   // by one persistent launch through a two-int queue
+  int nitems[2 * NCLS] = {};
+  hipStream_t s = nullptr;         // lanes > 0: a stream of their own (default priority)
+  hipEvent_t fwd = nullptr;        // the lane's forward passes are issued
+  hipEvent_t end = nullptr;        // all of the lane's stages are issued
+};
+
 struct Sweep {
   bool on = false;
   int nlayers = 0;
@@ -264,10 +288,11 @@ struct Sweep {
   DevBuf chan_layers;                // int2 [nchan]: first layer, count
   // work items per (patch class, item-tile shift): list k * 2 + s
   static constexpr int NLIST = 2 * NCLS;
-  DevBuf items[NLIST];
-  int nitems[NLIST] = {};
-  DevBuf queues;                     // int [2 * NLIST]
+  static constexpr int MAXLANES = 4;
+  std::vector<SweepLane> lanes;
+  DevBuf queues;                     // int [lanes][2 * NLIST]
   DevBuf done;                       // int [nchan]: workgroups finished (completion stamps)
+  hipEvent_t fork = nullptr;         // the caller's stream reached the sweep
   int ncu = 0;
 };
 
@@ -296,6 +321,11 @@ struct wf_op {
   wf::DevBuf fb_h, fb_x, fb_c, fb_red;  // forward-backward work images and reductions
   size_t otf_bytes = 0;              // transient value buffer per branch (strategy (c))
   wf::DevBuf otf_mis;                // counters the on-the-fly value pass writes
+  // strategy (c) with the kernel network: a copy of its parameters taken at build (FP32
+  // and the BF16 inference form), so that every apply infers exactly what the build did
+  bool net_otf = false;
+  float net_logtol = 0.f;
+  wf::DevBuf net_params, net_wt;
   wf::Sweep sweep;                   // layer-batched applies (wf_set_sweep)
 };
 
@@ -319,9 +349,12 @@ namespace wf {
 // (defined in the .hip translation units; all asynchronous on `s`)
 
 // Pruning arguments may be null (full grid).
+// Column table of the w-layer modulation of bin wp (see the FFT passes): ct[nx].
+hipError_t launch_chirp_table(float2* ct, int nx, double cell, double wp, const float* sx,
+                              hipStream_t s);
 hipError_t launch_fwd_rows(const float* img, float2* A, const float2* tw, const float* sx,
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
-                           const uint32_t* smask, hipStream_t s);
+                           const uint32_t* smask, const float2* ctab, hipStream_t s);
 hipError_t launch_fwd_cols(const float2* A, float2* X, const float2* tw, int ny, int Kx,
                            int Ky, const ColPrune* pr, hipStream_t s);
 hipError_t launch_inv_cols(float2* Y, float2* A, const float2* tw, int ny, int Kx, int Ky,
@@ -330,7 +363,8 @@ hipError_t launch_inv_cols(float2* Y, float2* A, const float2* tw, int ny, int K
 // 3: real part, accumulate
 hipError_t launch_inv_rows(const float2* A, void* out, const float2* tw, const float* sx,
                            const float* sy, int nx, int ny, int Kx, double cell, double wp,
-                           int mode, const uint32_t* smask, hipStream_t s);
+                           int mode, const uint32_t* smask, const float2* ctab,
+                           hipStream_t s);
 
 // Row kernels over the work items of one patch-size class `cls`; `tile` is the grid
 // tile side of the sort (it sizes each item's LDS accumulator).
@@ -404,8 +438,9 @@ hipError_t launch_sweep_fwd_rows(const float* img, const SweepLayer* sl, int nla
 hipError_t launch_sweep_cols(bool inverse, const SweepLayer* sl, const int2* pairs, int npairs,
                              const float2* tw, int ny, int Ky, int tsh, int tiles_x,
                              hipStream_t s);
-hipError_t launch_sweep_inv_rows(const SweepLayer* sl, const int2* chan_layers, int nchan,
-                                 void* out, bool real_out, const float2* tw, const float* sx,
+hipError_t launch_sweep_inv_rows(const SweepLayer* sl, const int2* chan_layers, int c0,
+                                 int nchan, void* out, bool real_out, const float2* tw,
+                                 const float* sx,
                                  const float* sy, int nx, int ny, int Kx, double cell,
                                  unsigned long long* stamps, int* done, hipStream_t s);
 hipError_t launch_rows_sweep(int mode, int cls, const WorkItem* wi, int nwi,
@@ -415,10 +450,18 @@ hipError_t launch_rows_sweep(int mode, int cls, const WorkItem* wi, int nwi,
 // Kernels predicted by the residual-kernel network for a chunk of rows (null pred: every
 // row exact).  pred [rows of the chunk][451]; rows whose predicted log10 error exceeds
 // logtol, or whose side is out of the network's range, use the exact construction.
+// Kernel-side class whose residual kernels the network predicts (sides 9..15): smaller
+// kernels cost less to build exactly than one inference, wider ones exceed its window.
+constexpr int NET_CLASS = 1;
+// Rows per network inference of an on-the-fly apply (per-branch input/output buffers).
+constexpr int64_t NET_CHUNK = 1 << 18;
+
 struct Surrogate {
   const float* pred = nullptr;
   float logtol = -3.f;
   int* used = nullptr;          // counts rows built from the prediction (may be null)
+  bool by_slot = false;         // predictions indexed by the row's slot in the launched
+                                // list (else by its index minus the range start)
 };
 
 // Build kernels (FP64).  Symbolic pass over the caller-order rows listed in cs
@@ -447,8 +490,10 @@ hipError_t launch_gbuild(const double* uvw, int64_t s0, const ClassSlices& cs,
                          double gsy, const double* mids, int P, const double* cents,
                          const KernelParams& kp, void* vals, int64_t vbase, wf_store store,
                          int* mismatch, const Surrogate& sg, const float* wts, hipStream_t s);
-// Network inputs of rows [r0, r0 + nr) (caller order, or sorted order through perm).
-hipError_t launch_row_inputs(const double* uvw, const int32_t* perm, int64_t r0, int64_t nr,
+// Network inputs of the rows at positions [r0, r0 + nr) of list (identity when null),
+// positions in caller order, or in sorted order through perm.
+hipError_t launch_row_inputs(const double* uvw, const int32_t* list, const int32_t* perm,
+                             int64_t r0, int64_t nr,
                              double scale, double gsx, double gsy, const double* mids, int P,
                              const double* cents, const KernelParams& kp, double L, float* x,
                              hipStream_t s);
@@ -473,6 +518,8 @@ hipError_t launch_mlp_adam(float* p, const float* g, float* m, float* v, int64_t
 hipError_t launch_mlp_gather(const float* X, int cx, const float* T, int ct,
                              const int32_t* idx, int B, float* xb, float* tb, hipStream_t s);
 hipError_t launch_mlp_prep_bf16(const float* params, uint16_t* wt, hipStream_t s);
+// Copy of a network's FP32 parameters and their BF16 inference form (allocated here).
+wf_status mlp_snapshot(const wf_mlp* m, DevBuf& params, DevBuf& wt, hipStream_t s);
 hipError_t launch_mlp_infer_bf16(const float* x, int64_t n, const float* params,
                                  const uint16_t* wt, bool split, float* out, hipStream_t s);
 

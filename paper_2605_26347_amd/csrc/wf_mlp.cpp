@@ -164,6 +164,17 @@ wf_status mlp_infer_bf16(const wf_mlp* m, const float* x, int64_t n, bool split,
   return WF_OK;
 }
 
+wf_status mlp_snapshot(const wf_mlp* m, DevBuf& params, DevBuf& wt, hipStream_t s) {
+  const size_t pb = sizeof(float) * (size_t)mlp_num_params();
+  const size_t wb = 2 * sizeof(uint16_t) * (3 * MLP_HID * MLP_HID + 512 * MLP_HID);
+  wf_status st;
+  if ((st = dalloc(params, pb)) != WF_OK) return st;
+  if ((st = dalloc(wt, wb)) != WF_OK) return st;
+  WF_HIP(hipMemcpyAsync(params.p, m->params.p, pb, hipMemcpyDeviceToDevice, s));
+  WF_HIP(launch_mlp_prep_bf16((const float*)params.p, (uint16_t*)wt.p, s));
+  return WF_OK;
+}
+
 }  // namespace wf
 
 extern "C" {

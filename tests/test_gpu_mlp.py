@@ -173,3 +173,59 @@ def test_surrogate_build_matches_exact_oracle(trained):
     # tolerance can only add rows
     op_l = gpu_operator(obs, 4, surrogate=net, surrogate_tol=0.5)
     assert op_l.plan()["surrogate_fraction"] >= frac
+
+
+def _value_pass_ms(op, x, reps):
+    """Milliseconds of the on-the-fly value pass per Re{Phi^dag Phi} apply."""
+    out = op.psf_apply_re(x)
+    torch.cuda.synchronize()
+    op.profile_enable(5, True)
+    n0, t0 = op.profile_read(5)
+    for _ in range(reps):
+        op.psf_apply_re(x, out)
+    n1, t1 = op.profile_read(5)
+    op.profile_enable(5, False)
+    return (t1 - t0) / reps
+
+
+def test_network_gain_under_strategy_c(trained):
+    """What the trained network gains over the method without it where the kernels are
+    built at every apply (strategy (c), Sect. 3.4 / Fig. 2): the residual kernels of the
+    side-9..15 rows it trusts come from one inference instead of the exact FP64
+    construction.  Phi^dag Phi stays within 1e-3 of the exact-kernel FP64 oracle, and on
+    2M rows of the 4096^2 / 3 degree configuration (16 bins) the per-apply value pass is
+    faster with the network than without it."""
+    from paper_2605_26347_amd import Operator
+    net, _ = trained
+    obs = ws.widefield(n=128, nvis=24_000, fov_deg=3.0, npoints=40, nblobs=3,
+                       blob_sigma=(1.0, 3.0))
+    op_c = gpu_operator(obs, 4, strategy="otf", surrogate=net)
+    assert op_c.plan()["strategy"] == 3
+    frac_small = op_c.plan()["surrogate_fraction"]
+    x = obs.sky.astype(np.float32)
+    e = rel(op_c.psf_apply(to_dev(x[None])).cpu().numpy()[0],
+            oracle_for(obs, 4).psf(x.astype(np.float64)))
+    say(f"[gpu] strategy (c) with the network: rows {frac_small:.3f}, psf rel vs oracle {e:.2e}")
+    assert e <= 1e-3 and frac_small > 0
+    op_c.close()
+    big = ws.learned_form(sky=False)
+    rows = ws.seeded_subset(big.uvw_m.shape[0], 2_000_000, 3)
+    uvw = np.ascontiguousarray(big.uvw_m[rows])
+    xb = to_dev(ws.gauss_image(big.nx, 4).astype(np.float32)[None])
+    mk = dict(nbins=16, store="f16", strategy="otf")
+    op_e = Operator(uvw, big.freqs_hz, big.nx, big.ny, big.cell_rad, **mk)
+    op_n = Operator(uvw, big.freqs_hz, big.nx, big.ny, big.cell_rad, surrogate=net, **mk)
+    frac = op_n.plan()["surrogate_fraction"]
+    te = _value_pass_ms(op_e, xb, 6)
+    tn = _value_pass_ms(op_n, xb, 6)
+    ye = op_e.psf_apply_re(xb)
+    yn = op_n.psf_apply_re(xb)
+    d = float((yn - ye).norm() / ye.norm())
+    say(f"[gpu] 4096^2 / 2M rows / 16 bins, strategy (c): value pass {te:.2f} ms exact, "
+        f"{tn:.2f} ms with the network ({frac:.3f} of the rows), gain {te / tn:.3f}x; "
+        f"Re psf rel to exact kernels {d:.2e}")
+    assert frac > 0.2
+    assert d <= 1e-3
+    assert tn < te
+    op_e.close()
+    op_n.close()

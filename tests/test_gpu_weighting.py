@@ -189,9 +189,11 @@ def test_fully_flagged_channel(strategy):
     assert np.all(y[sl][flags[sl]] == 0)
 
 
-def test_onthefly_with_network_is_refused(obs):
+def test_holographic_with_network_is_refused(obs):
+    """Branch (b) accumulates H from exact kernels only; a network is refused there
+    (branch (c) takes it: tests/test_gpu_mlp.py)."""
     from paper_2605_26347_amd import Network
     from paper_2605_26347_amd._lib import WfError
     net = Network(5)
     with pytest.raises(WfError, match="exact kernels only"):
-        gpu_operator(obs, 4, strategy="otf", surrogate=net, memory_budget=50e6)
+        gpu_operator(obs, 4, strategy="H", surrogate=net)
