@@ -556,41 +556,53 @@ def _timed_applies(op, x, out, n, torch):
 
 
 def bench_onthefly(args, torch):
-    """Strategy (c) on the precision form: no G is stored; every apply rebuilds each
-    w-bin's rows of G chunk by chunk with the FP64 value pass, then applies them with the
-    fused kernel.  Compared with the stored-G operator (same P) for time and result."""
+    """Strategy (c) on the precision form: no G is stored.  Factorised form (the value):
+    the build stores each row's thresholded residual kernel and every apply convolves it
+    with the row's Kaiser-Bessel taps, chunk by chunk, before the fused kernel applies
+    the chunk.  Rebuilt form: every apply repeats the FP64 value pass of the build.  Both
+    compared with the stored-G operator (same P) for time and result."""
     import wfsynth as ws
     from paper_2605_26347_amd import Operator
     obs = ws.precision_form(n=args.n, nvis=args.nvis, fov_deg=args.fov)
     M = obs.uvw_m.shape[0]
     x = torch.from_numpy(obs.sky.astype(np.float32)[None]).to("cuda:0")
-    steps, warm = max(1, min(args.steps, 3)), max(1, min(args.warmup, 1))
-    t0 = time.time()
-    op = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad,
-                  memory_budget=args.budget, store=args.store, strategy="otf")
-    tb = time.time() - t0
-    info = op.plan(0)
-    log(f"on the fly: built in {tb:.1f} s, P={info['nbins']}, row data "
-        f"{info['mem_g_bytes'] / 1e9:.2f} GB, transient {info['mem_transient_bytes'] / 1e9:.2f} "
-        f"GB per branch, value pass {info['value_pass_flops'] / 1e12:.2f} TFLOP per apply")
-    out = torch.empty_like(x)
-    for _ in range(warm):
+    steps, warm = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
+    b_v = 8 if args.store == "f32" else 4
+
+    def run(form, nsteps):
+        t0 = time.time()
+        op = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad,
+                      memory_budget=args.budget, store=args.store, strategy="otf",
+                      otf_form=form)
+        tb = time.time() - t0
+        info = op.plan(0)
+        log(f"on the fly, {form}: built in {tb:.1f} s, P={info['nbins']}, row data "
+            f"{info['mem_g_bytes'] / 1e9:.2f} GB (kernels {info['mem_khat_bytes'] / 1e9:.2f} "
+            f"GB), transient {info['mem_transient_bytes'] / 1e9:.2f} GB per branch, value "
+            f"pass {info['value_pass_flops'] / 1e12:.3f} TFLOP per apply")
+        out = torch.empty_like(x)
+        for _ in range(warm):
+            op.psf_apply_re(x, out)
+        ms = _timed_applies(op, x, out, nsteps, torch)
+        op.profile_enable(5, True)
+        op.profile_enable(0, True)
         op.psf_apply_re(x, out)
-    ms = _timed_applies(op, x, out, steps, torch)
-    log(f"on the fly: {ms:.1f} ms/apply")
-    op.profile_enable(5, True)
-    op.profile_enable(0, True)
-    op.psf_apply_re(x, out)
-    n5, ms5 = op.profile_read(5)
-    n0, ms0 = op.profile_read(0)
-    op.profile_enable(5, False)
-    op.profile_enable(0, False)
-    log(f"on the fly: value pass {ms5:.1f} ms in {n5} launches, G^dag G {ms0:.1f} ms "
-        f"in {n0} launches")
-    otf_out = out.clone()
-    op.close()
-    del op
-    torch.cuda.empty_cache()
+        n5, ms5 = op.profile_read(5)
+        n0, ms0 = op.profile_read(0)
+        op.profile_enable(5, False)
+        op.profile_enable(0, False)
+        log(f"on the fly, {form}: {ms:.1f} ms/apply; value pass {ms5:.1f} ms in {n5} "
+            f"launches, G^dag G {ms0:.1f} ms in {n0} launches")
+        res = out.clone()
+        op.close()
+        del op
+        torch.cuda.empty_cache()
+        return dict(build_s=tb, ms=ms, value_pass_ms=ms5, value_pass_launches=n5,
+                    gtg_ms=ms0, info=info), res
+
+    fac, fout = run("factorised", steps)
+    reb, rout = run("rebuilt", 1)
+    info = fac["info"]
     g = Operator(obs.uvw_m, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad,
                  memory_budget=args.budget, store=args.store, nbins=info["nbins"])
     gout = torch.empty_like(x)
@@ -598,29 +610,40 @@ def bench_onthefly(args, torch):
         g.psf_apply_re(x, gout)
     gms = _timed_applies(g, x, gout, steps, torch)
     gbytes = g.plan(0)["mem_g_bytes"]
-    d = float((otf_out - gout).norm() / gout.norm())
-    log(f"stored G ({gbytes / 1e9:.1f} GB): {gms:.1f} ms/apply; on the fly vs stored {d:.2e}")
+    df = float((fout - gout).norm() / gout.norm())
+    dr = float((rout - gout).norm() / gout.norm())
+    log(f"stored G ({gbytes / 1e9:.1f} GB): {gms:.1f} ms/apply; vs stored: factorised "
+        f"{df:.2e}, rebuilt {dr:.2e}; factorised {reb['ms'] / fac['ms']:.1f}x faster than "
+        f"rebuilt")
     g.close()
-    flops = info["value_pass_flops"]
-    ach = flops / (ms5 * 1e-3) / 1e12 if ms5 > 0 else None
+    # expansion traffic per apply: the kernels read (b_v n'^2 per row), G written
+    # (b_v T^2 per row), and per row its coordinates (16 B) and four 32-bit words
+    kvals = (info["mem_khat_bytes"] - 4.0 * M) / b_v
+    xbytes = b_v * (kvals + info["ntaps"]) + 32.0 * M
+    ach = xbytes / (fac["value_pass_ms"] * 1e-3) / 1e9 if fac["value_pass_ms"] > 0 else None
+    ms = fac["ms"]
+    strip = lambda d: {k: v for k, v in d.items() if k != "info"}
     line = {
         "metric": "Φ†Φ applies/s with G computed on the fly (strategy (c)), 4096², 50M vis",
         "value": 1e3 / ms, "unit": "applies/s", "n_gpus": 1, "steps": steps, "warmup": warm,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"Re{{Phi^dag Phi x}}, {obs.nx}^2 image, {M} visibilities, "
-                               f"3 deg field, G rebuilt at every apply",
-                   "store": args.store, "nbins": info["nbins"], "strategy": "on the fly"},
-        "build_s": tb, "row_data_bytes": info["mem_g_bytes"],
+                               f"3 deg field, G expanded from stored kernels at every apply",
+                   "store": args.store, "nbins": info["nbins"],
+                   "strategy": "on the fly, factorised"},
+        "factorised": strip(fac), "rebuilt": strip(reb),
+        "kernel_bytes": info["mem_khat_bytes"], "row_data_bytes": info["mem_g_bytes"],
         "transient_bytes_per_branch": info["mem_transient_bytes"],
-        "value_pass_ms": ms5, "value_pass_launches": n5, "gtg_ms": ms0,
-        "stored_G": {"ms": gms, "bytes": gbytes}, "otf_vs_stored_rel": d,
-        "roofline": {"bound": "alu", "kernel": "k_gbuild (value pass, FP64)",
-                     "achieved": ach, "peak": FP64_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
-                     "frac": ach / FP64_VECTOR_PEAK_TFS if ach else None, "traffic": None,
-                     "flops_per_apply": flops,
-                     "flops": "16 nk^3 (two DFT sweeps of the nk x nk residual kernel) + "
-                              "4 J (n' T + T^2) (Kaiser-Bessel convolution) per row"},
+        "stored_G": {"ms": gms, "bytes": gbytes},
+        "factorised_vs_stored_rel": df, "rebuilt_vs_stored_rel": dr,
+        "factorised_speedup_vs_rebuilt": reb["ms"] / ms,
+        "roofline": {"bound": "hbm", "kernel": "k_expand (all classes, per apply)",
+                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None,
+                     "bytes_per_apply": xbytes,
+                     "bytes": "b_v (n'^2 + T^2) + 32 per row: kernel read, G written, "
+                              "coordinates and row words"},
     }
     print(json.dumps(line), flush=True)
 
@@ -742,20 +765,29 @@ def bench_learned(args, torch):
     got = op_s.psf_apply(xs)
     err = float((got - ref).norm() / ref.norm())
     # against the FP64 oracle (exact kernels): its Phi^dag Phi of the N(0,1) probe at the
-    # stored pixel samples (tests/golden/learned_4096sq_20M.npz, written by a script that
-    # calls only the oracle; same rows, P = 16 and the oracle's centroids)
+    # stored pixel samples (tests/golden/learned_4096sq_2M.npz, written by a script that
+    # calls only the oracle) for a seeded 2M-row subset of these rows, P = 16 and the
+    # oracle's centroids
     vs_oracle = None
-    fxp = os.path.join(ROOT, "tests", "golden", "learned_4096sq_20M.npz")
+    fxp = os.path.join(ROOT, "tests", "golden", "learned_4096sq_2M.npz")
     if os.path.exists(fxp):
         fx = np.load(fxp)
-        if np.allclose(op_s.centroids(0), fx["centroids"], rtol=1e-12, atol=1e-9):
-            xg = torch.from_numpy(ws.gauss_image(obs.nx, 4).astype(np.float32)[None]).to("cuda:0")
-            pix = torch.from_numpy(fx["pix"]).to("cuda:0")
-            vs_oracle = {}
-            for name, o in (("network", op_s), ("exact", op_e)):
+        sub = np.ascontiguousarray(obs.uvw_m[ws.seeded_subset(M, 2_000_000, 3)])
+        xg = torch.from_numpy(ws.gauss_image(obs.nx, 4).astype(np.float32)[None]).to("cuda:0")
+        pix = torch.from_numpy(fx["pix"]).to("cuda:0")
+        vs_oracle = {}
+        for name, kw in (("network", {"surrogate": net}), ("exact", {})):
+            for strat in ("G", "otf"):
+                o = Operator(sub, obs.freqs_hz, obs.nx, obs.ny, obs.cell_rad, nbins=16,
+                             store="f32", strategy=strat, **kw)
+                assert np.allclose(o.centroids(0), fx["centroids"], rtol=1e-12, atol=1e-9)
                 v = o.psf_apply(xg)[0].flatten()[pix].cpu().numpy()
-                vs_oracle[name] = float(np.linalg.norm(v - fx["psf"]) / np.linalg.norm(fx["psf"]))
-            log(f"Phi^dag Phi vs FP64 oracle (32768 pixels): {vs_oracle}")
+                vs_oracle[f"{name}_{strat}"] = float(np.linalg.norm(v - fx["psf"]) /
+                                                      np.linalg.norm(fx["psf"]))
+                o.close()
+                del o
+                torch.cuda.empty_cache()
+        log(f"Phi^dag Phi vs FP64 oracle (2M-row subset, 32768 pixels): {vs_oracle}")
     # strategy (c): kernels rebuilt at every apply, with and without the network
     otf = {}
     for name, kw in (("exact", {}), ("network", {"surrogate": net})):

@@ -60,12 +60,17 @@ typedef enum { WF_STORE_F32 = 0, WF_STORE_F16 = 1, WF_STORE_BF16 = 2 } wf_store;
  * H_p = G_p^dag G_p as dense stencils per active 32 x 32 grid tile (side 2 Tmax - 1,
  * Tmax the largest patch side reaching the tile) and applies Phi^dag Phi only:
  * wf_forward / wf_adjoint / wf_get_row return WF_ENOTSUP for it.  Needs tile 32.
- * An on-the-fly operator keeps per row only its coordinates, weight and patch word
- * (about 48 bytes) and rebuilds G chunk by chunk (runs of whole row groups of one bin,
- * at most 2.5% of the budget share each) into a transient buffer of each branch at every
- * apply, with the same FP64 value pass as the build of (a): its results equal those of
- * (a) up to the order of FP32 atomic additions.  It uses exact kernels only (WF_ENOTSUP
- * with a kernel network); wf_get_row returns WF_ENOTSUP for it. */
+ * An on-the-fly operator keeps no values of G.  It writes G chunk by chunk (runs of
+ * whole row groups of one bin, at most 2.5% of the budget share each) into a transient
+ * buffer of each branch at every apply, in one of two forms (option otf_form):
+ *  - factorised: the build stores each row's thresholded residual kernel (n' x n'
+ *    values, times its weight, in the store format; about n'^2 / T^2 ~ 0.4 of G's
+ *    values); an apply only convolves it with the row's Kaiser-Bessel taps (FP64 taps,
+ *    FP32 convolution);
+ *  - rebuilt: only coordinates, weight and patch word are kept per row (about 48 bytes);
+ *    an apply repeats the FP64 value pass of the build of (a), so that its results equal
+ *    those of (a) up to the order of FP32 atomic additions.
+ * wf_get_row returns WF_ENOTSUP for it. */
 typedef enum { WF_AUTO = 0, WF_PRECOMP_G = 1, WF_PRECOMP_H = 2, WF_ONTHEFLY = 3 } wf_strategy;
 
 typedef struct {
@@ -96,10 +101,12 @@ typedef struct {
                               residual-kernel side 9..15 (smaller kernels cost less to
                               build exactly than an inference) whose kernel the network
                               predicts with log10 error at most log10(surrogate_tol) use
-                              the prediction (square fields).  Under strategy (c) every
-                              apply re-infers them from a copy of the network's
-                              parameters taken at build, so the network must outlive
-                              the build call only.  Not with strategy (b).            */
+                              the prediction (square fields).  Under strategy (c)
+                              the factorised form stores the predicted kernels; the
+                              rebuilt form re-infers them at every apply from a copy
+                              of the network's parameters taken at build.  Either way
+                              the network must outlive the build call only.  Not
+                              with strategy (b).                                      */
   double surrogate_tol;    /* predicted relative L2 error bound, default 1e-3          */
   const float* weights;    /* NULL: unit weights.  Otherwise host FP32 [total rows] in
                               the [chan][row] order of the visibilities: row k of the
@@ -113,6 +120,10 @@ typedef struct {
                               before planning: its row is never built, wf_forward
                               writes 0 there and wf_adjoint ignores it.  Read during the
                               build only.                                             */
+  int32_t otf_form;        /* form of strategy (c): 0 auto (factorised when its stored
+                              kernels fit the budget share, else rebuilt), 1 rebuilt at
+                              every apply, 2 factorised (WF_EBUDGET when its kernels do
+                              not fit)                                                */
 } wf_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -229,9 +240,13 @@ typedef struct {
   double mem_h_bytes;       /* device bytes of the holographic stencils (strategy (b))  */
   int64_t nflagged;         /* flagged rows of this channel (discarded)                 */
   double mem_transient_bytes;/* on-the-fly: value buffer of one branch (largest chunk)   */
-  double value_pass_flops;  /* on-the-fly: FP64 flops of one apply's value pass (two
-                               DFT sweeps of each residual kernel, 16 nk^3, and its
-                               Kaiser-Bessel convolution, 4 J (n' T + T^2)); else 0    */
+  double value_pass_flops;  /* on-the-fly, rebuilt: FP64 flops of one apply's value pass
+                               (two DFT sweeps of each residual kernel, 16 nk^3, and its
+                               Kaiser-Bessel convolution, 4 J (n' T + T^2)); factorised:
+                               FP32 flops of the convolution alone; else 0            */
+  double mem_khat_bytes;    /* factorised on-the-fly: device bytes of the stored kernels
+                               and their offsets (included in mem_g_bytes); else 0     */
+  int32_t otf_form;         /* on-the-fly: 1 rebuilt, 2 factorised; else 0             */
 } wf_plan_info;
 
 /* The planner alone, on the host (the compute-resource planning of Sect. 3.4, run by the

@@ -13,8 +13,8 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (WfImageShape, WfOptions, WfPlanInfo, WfTuneInfo, check, APPLY, STORE,
-                   STRATEGY)
+from ._lib import (WfImageShape, WfOptions, WfPlanInfo, WfTuneInfo, check, APPLY, OTF_FORM,
+                   STORE, STRATEGY)
 
 _lib.load()
 
@@ -29,6 +29,8 @@ def default_options(**kw) -> WfOptions:
             v = STORE[v] if isinstance(v, str) else int(v)
         elif k == "strategy":
             v = STRATEGY[v] if isinstance(v, str) else int(v)
+        elif k == "otf_form":
+            v = OTF_FORM[v] if isinstance(v, str) else int(v)
         elif k == "surrogate":
             v = None if v is None else (v._h.value if isinstance(v, Network) else int(v))
         elif k in ("weights", "flags"):

@@ -12,6 +12,7 @@ STATUS_NAMES = {0: "WF_OK", 1: "WF_EINVAL", 2: "WF_ENOMEM", 3: "WF_EBUDGET", 4: 
                 5: "WF_ENOTSUP"}
 STORE = {"f32": 0, "f16": 1, "bf16": 2}
 STRATEGY = {"auto": 0, "G": 1, "H": 2, "otf": 3}
+OTF_FORM = {"auto": 0, "rebuilt": 1, "factorised": 2}
 
 
 class WfImageShape(ctypes.Structure):
@@ -28,7 +29,7 @@ class WfOptions(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("max_rows_per_item", ctypes.c_int32),
                 ("branches", ctypes.c_int32), ("surrogate", ctypes.c_void_p),
                 ("surrogate_tol", ctypes.c_double), ("weights", ctypes.c_void_p),
-                ("flags", ctypes.c_void_p)]
+                ("flags", ctypes.c_void_p), ("otf_form", ctypes.c_int32)]
 
 
 class WfPlanInfo(ctypes.Structure):
@@ -44,7 +45,8 @@ class WfPlanInfo(ctypes.Structure):
                 ("max_rows_per_item", ctypes.c_int32), ("branch", ctypes.c_int32),
                 ("surrogate_fraction", ctypes.c_double), ("mem_h_bytes", ctypes.c_double),
                 ("nflagged", ctypes.c_int64), ("mem_transient_bytes", ctypes.c_double),
-                ("value_pass_flops", ctypes.c_double)]
+                ("value_pass_flops", ctypes.c_double), ("mem_khat_bytes", ctypes.c_double),
+                ("otf_form", ctypes.c_int32)]
 
 
 class WfTuneInfo(ctypes.Structure):

@@ -725,6 +725,345 @@ __global__ __launch_bounds__(64, NK <= 15 ? 4 : 1) void k_gbuild(const double* _
   }
 }
 
+// Factorised strategy (c), build side: the thresholded residual kernel of each listed
+// row (the kept n' x n' centre of c_hat_k, Sect. 3.1), times the row's data weight,
+// written in the value format at khat[kabs[s] ..] ([s_v][s_u], row-major).  The kernel
+// is built and checked exactly as by k_gbuild; the Kaiser-Bessel convolution is left
+// to every apply (k_expand).
+template <int STORE, int NK>
+__global__ __launch_bounds__(64, NK <= 15 ? 4 : 1) void k_khat(const double* __restrict__ uvw, int64_t s0,
+                                               const int32_t* __restrict__ rows, int64_t nl,
+                                               const int32_t* __restrict__ perm,
+                                               const uint32_t* __restrict__ meta,
+                                               const int64_t* __restrict__ kabs, double scale,
+                                               double gsx, double gsy,
+                                               const double* __restrict__ mids, int P,
+                                               const double* __restrict__ cents,
+                                               KernelParams kp, void* __restrict__ khat,
+                                               int* __restrict__ mismatch, Surrogate sg,
+                                               const float* __restrict__ wts) {
+#pragma clang fp contract(off)
+  __shared__ KScratch<NK> S;
+  const int lane = threadIdx.x;
+  for (int64_t i = blockIdx.x; i < nl; i += gridDim.x) {
+    const int64_t s = rows[i];
+    const int64_t k = perm[s];
+    const RowGeom g = dev_geom(uvw, k, scale, gsx, gsy, mids, P, cents);
+    const int nk_full = dev_nk(g.wproj, kp, false);
+    const int nk = nk_full > kp.smax ? kp.smax : nk_full;
+    if (nk > NK || nk <= nk_lo<NK>()) {
+      if (lane == 0) atomicAdd(mismatch, 1);
+      continue;
+    }
+    double dropped;
+    const float* pr = sg.pred ? sg.pred + (sg.by_slot ? i : s - s0) * MLP_OUT : nullptr;
+    const bool usep = use_prediction(pr, nk_full, kp, sg.logtol);
+    const int hp = usep ? predicted_kernel(pr, nk, kp, S, &dropped)
+                        : wkernel_row(g.wproj, nk, kp, S, &dropped);
+    const int h = (nk - 1) / 2;
+    const int np = 2 * hp + 1;
+    if (np + kp.J - 1 != (int)((meta[s] >> 16) & 0xff)) {
+      if (lane == 0) atomicAdd(mismatch, 1);
+    } else {
+      const double wk = wts ? (double)wts[k] : 1.0;
+      const int64_t kb = kabs[s];
+      for (int idx = lane; idx < np * np; idx += 64) {
+        const int m = idx / np, nn = idx - m * np;
+        const double2 c = S.c[(m + h - hp) * nk + (nn + h - hp)];
+        store_val<STORE>(khat, kb + idx, c.x * wk, c.y * wk);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int STORE>
+__device__ __forceinline__ float2 load_val(const void* __restrict__ v, int64_t i) {
+  if constexpr (STORE == WF_STORE_F32) {
+    return reinterpret_cast<const float2*>(v)[i];
+  } else if constexpr (STORE == WF_STORE_F16) {
+    return __half22float2(reinterpret_cast<const __half2*>(v)[i]);
+  } else {
+    const uint32_t b = reinterpret_cast<const uint32_t*>(v)[i];
+    return make_float2(__uint_as_float(b << 16), __uint_as_float(b & 0xffff0000u));
+  }
+}
+
+// Factorised strategy (c), apply side: rows of G from the stored kernels,
+// G = Kv c Ku^T (Sect. 3.2), Ku / Kv the banded matrices of the Kaiser-Bessel taps at the
+// row's fractional grid offset.  The taps are evaluated in FP64 (the uvw -> grid map),
+// the convolution in FP32; values are written in the store format where the value pass
+// would write them (item offset + row offset - vbase).
+//
+// A workgroup is one wavefront and takes rpw <= 64 listed rows at a time (fewer where a
+// launch has few rows, so that every SIMD still holds several wavefronts): lane i reads
+// the i-th row's words and evaluates its taps.  The rows are then expanded SL at a time,
+// one per slot of TM = NK + JT - 1 lanes (the largest patch side of the class), lane a_u
+// of a slot computing patch column a_u: first t[m] = sum_d ku[d] c[m][a_u - d] for the
+// kernel rows m (c staged in LDS), then G[a_v][a_u] = sum_d kv[d] t[a_v - d] in registers,
+// so that the lanes of a slot write each patch row with consecutive values.  Loops run
+// to the largest n' and T among the wavefront's slots.  The next rows' kernels are
+// loaded while the current ones are expanded.  JT >= J taps are carried (zero past J).
+// over counts values beyond the FP16 range (FP16 store only).
+template <int NK, int JT>
+struct EScratch {
+  static constexpr int NN = NK * NK;
+  static constexpr int TM = NK + JT - 1;
+  static constexpr int SL = 64 / TM;                   // rows expanded side by side
+  static constexpr int CK = (SL * NN + 63) / 64;       // kernel values per lane and step
+  float2 c[SL * NN];     // the step's kernels, [slot][s_v][s_u] (n' x n' each)
+};
+
+// Raw stored value: two 32-bit words (FP32) or one word of two 16-bit halves.
+template <int STORE>
+struct KRaw {
+  using type = uint32_t;
+};
+template <>
+struct KRaw<WF_STORE_F32> {
+  using type = uint2;
+};
+template <int STORE>
+__device__ __forceinline__ typename KRaw<STORE>::type kraw_load(const void* __restrict__ v,
+                                                                int64_t i) {
+  if constexpr (STORE == WF_STORE_F32) return reinterpret_cast<const uint2*>(v)[i];
+  else return reinterpret_cast<const uint32_t*>(v)[i];
+}
+template <int STORE>
+__device__ __forceinline__ float2 kraw_widen(typename KRaw<STORE>::type r) {
+  if constexpr (STORE == WF_STORE_F32) {
+    return make_float2(__uint_as_float(r.x), __uint_as_float(r.y));
+  } else if constexpr (STORE == WF_STORE_F16) {
+    __half2 h;
+    __builtin_memcpy(&h, &r, 4);
+    return __half22float2(h);
+  } else {
+    return make_float2(__uint_as_float(r << 16), __uint_as_float(r & 0xffff0000u));
+  }
+}
+
+// Orders one wavefront's LDS accesses: its LDS operations complete in order, so a
+// workgroup of one wavefront needs only that the compiler keep them in program order.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The JT Kaiser-Bessel taps phi(f - d + (J - 1)/2), d < JT, zero past J and outside the
+// support, rounded to FP32.  dev_i0's series is run for all taps at once until every tap
+// of the wavefront has added its last term (the first below 1e-18 of its sum): the
+// terms after that one are smaller still, below half an ulp of the sum, and leave it
+// unchanged, so each tap equals dev_i0's value bit for bit, with no divergent branch.
+template <int JT>
+__device__ __forceinline__ void kb_taps_f32(double f, const KernelParams& kp, float (&k)[JT]) {
+#pragma clang fp contract(off)
+  const int half = (kp.J - 1) / 2;
+  double q[JT], term[JT], s[JT];
+  bool live[JT];
+#pragma unroll
+  for (int d = 0; d < JT; ++d) {
+    const double t = f - (double)(d - half);
+    const double z = 1.0 - ((2.0 * t) / (double)kp.J) * ((2.0 * t) / (double)kp.J);
+    live[d] = d < kp.J && z >= 0.0;
+    const double x = kp.beta * sqrt(live[d] ? z : 0.0);
+    q[d] = 0.25 * x * x;
+    term[d] = 1.0;
+    s[d] = 1.0;
+  }
+  for (int i = 1; i < 128; ++i) {
+    bool more = false;
+#pragma unroll
+    for (int d = 0; d < JT; ++d) {
+      term[d] = term[d] * (q[d] * c_inv_k2.v[i]);
+      s[d] += term[d];
+      more = more || !(term[d] < 1e-18 * s[d]);
+    }
+    if (__builtin_amdgcn_ballot_w64(more) == 0) break;
+  }
+#pragma unroll
+  for (int d = 0; d < JT; ++d) k[d] = live[d] ? (float)(s[d] / kp.i0beta) : 0.f;
+}
+
+__device__ __forceinline__ int wave_max_u(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+template <int STORE, int NK, int JT>
+__global__ __launch_bounds__(64) void k_expand(const double* __restrict__ uvw,
+                                               const int32_t* __restrict__ rows, int64_t nl,
+                                               const int32_t* __restrict__ perm,
+                                               const uint32_t* __restrict__ meta,
+                                               const uint32_t* __restrict__ voff,
+                                               const int32_t* __restrict__ row_wi,
+                                               const WorkItem* __restrict__ wis, double scale,
+                                               double gsx, double gsy, KernelParams kp,
+                                               const void* __restrict__ khat,
+                                               const uint32_t* __restrict__ kof,
+                                               void* __restrict__ vals, int64_t vbase,
+                                               int rpw, int* __restrict__ over) {
+#pragma clang fp contract(off)
+  using ES = EScratch<NK, JT>;
+  using Raw = typename KRaw<STORE>::type;
+  constexpr int NN = ES::NN, TM = ES::TM, SL = ES::SL, CK = ES::CK;
+  __shared__ ES S;
+  const int lane = threadIdx.x;
+  const int slot = lane / TM, au = lane - slot * TM;   // slot == SL: spare lanes
+  bool ovf = false;
+  for (int64_t b0 = (int64_t)blockIdx.x * rpw; b0 < nl; b0 += (int64_t)gridDim.x * rpw) {
+    const int nb = (int)(nl - b0 < rpw ? nl - b0 : rpw);
+    // lane i: row b0 + i's patch side, kernel and value offsets, and taps
+    int myT = 0;
+    uint32_t mykof = 0;
+    int64_t myvb = 0;
+    float myku[JT], mykv[JT];
+#pragma unroll
+    for (int d = 0; d < JT; ++d) myku[d] = mykv[d] = 0.f;
+    if (lane < nb) {
+      const int64_t s = rows[b0 + lane];
+      const int64_t k = perm[s];
+      myT = (int)((meta[s] >> 16) & 0xff);
+      mykof = kof[s];
+      myvb = wis[row_wi[s]].voff + voff[s] - vbase;
+      const double ub = (uvw[3 * k] * scale) * gsx;
+      const double vb = (uvw[3 * k + 1] * scale) * gsy;
+      kb_taps_f32<JT>(ub - floor(ub + 0.5), kp, myku);
+      kb_taps_f32<JT>(vb - floor(vb + 0.5), kp, mykv);
+    }
+    const int vlo = (int)(uint32_t)(uint64_t)myvb, vhi = (int)(uint32_t)((uint64_t)myvb >> 32);
+    // the SL kernels of the step at rb, contiguous in LDS slot by slot: issued into
+    // registers (value i of the step on lane i % 64), then written to LDS.  Slot j's
+    // kernel side, offset and first value within the step are wave-uniform.
+    Raw cb[CK];
+    struct Step {
+      int np[SL], cum[SL + 1];
+      uint32_t ko[SL];
+    };
+    auto step_of = [&](int rb) {
+      Step st;
+      st.cum[0] = 0;
+#pragma unroll
+      for (int j = 0; j < SL; ++j) {
+        const int r = rb + j;
+        st.np[j] = r < nb ? __builtin_amdgcn_readlane(myT, r & 63) - kp.J + 1 : 0;
+        st.ko[j] = r < nb ? (uint32_t)__builtin_amdgcn_readlane((int)mykof, r & 63) : 0u;
+        st.cum[j + 1] = st.cum[j] + st.np[j] * st.np[j];
+      }
+      return st;
+    };
+    // slot of step value i (< st.cum[SL]) and its index within that slot's kernel
+    auto locate = [&](const Step& st, int i, int& j, int& idx, uint32_t& ko) {
+      j = 0;
+#pragma unroll
+      for (int q = 1; q < SL; ++q) j += i >= st.cum[q] ? 1 : 0;
+      idx = i;
+      ko = st.ko[0];
+#pragma unroll
+      for (int q = 1; q < SL; ++q)
+        if (j == q) {
+          idx = i - st.cum[q];
+          ko = st.ko[q];
+        }
+    };
+    auto issue = [&](int rb) {
+      const Step st = step_of(rb);
+#pragma unroll
+      for (int q = 0; q < CK; ++q) {
+        const int i = lane + 64 * q;
+        if (i < st.cum[SL]) {
+          int j, idx;
+          uint32_t ko;
+          locate(st, i, j, idx, ko);
+          cb[q] = kraw_load<STORE>(khat, (int64_t)ko + idx);
+        }
+      }
+    };
+    auto stage = [&](int rb) {
+      const Step st = step_of(rb);
+#pragma unroll
+      for (int q = 0; q < CK; ++q) {
+        const int i = lane + 64 * q;
+        if (i < st.cum[SL]) {
+          int j, idx;
+          uint32_t ko;
+          locate(st, i, j, idx, ko);
+          S.c[j * NN + idx] = kraw_widen<STORE>(cb[q]);
+        }
+      }
+    };
+    issue(0);
+    for (int rb = 0; rb < nb; rb += SL) {
+      stage(rb);
+      wave_lds_sync();
+      if (rb + SL < nb) issue(rb + SL);
+      // this lane's row (slot) and its words and taps.  Every lane takes part in the
+      // cross-lane reads (a lane left out would read nothing to its peers).
+      const int r = rb + slot;
+      const bool valid = slot < SL && r < nb;
+      const int src = valid ? r : 0;
+      const int Tsrc = __shfl(myT, src, 64);
+      const int T = valid ? Tsrc : 0;
+      const int np = valid ? T - kp.J + 1 : 0;
+      const int64_t vb = (int64_t)(((uint64_t)(uint32_t)__shfl(vhi, src, 64) << 32) |
+                                   (uint64_t)(uint32_t)__shfl(vlo, src, 64));
+      float ku[JT], kv[JT];
+#pragma unroll
+      for (int d = 0; d < JT; ++d) {
+        ku[d] = __shfl(myku[d], src, 64);
+        kv[d] = __shfl(mykv[d], src, 64);
+      }
+      const int npmax = wave_max_u(np), Tmax = wave_max_u(T);
+      const float2* c = S.c + (slot < SL ? slot : 0) * NN;
+      // t[m] = sum_d ku[d] c[m][a_u - d]
+      float2 t[NK];
+#pragma unroll
+      for (int m = 0; m < NK; ++m) {
+        t[m] = make_float2(0.f, 0.f);
+        if (m < npmax) {
+          if (m < np) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int d = 0; d < JT; ++d) {
+              const int n = au - d;
+              const float2 v = (n >= 0 && n < np) ? c[m * np + n] : make_float2(0.f, 0.f);
+              re = fmaf(ku[d], v.x, re);
+              im = fmaf(ku[d], v.y, im);
+            }
+            t[m] = make_float2(re, im);
+          }
+        }
+      }
+      // G[a_v][a_u] = sum_d kv[d] t[a_v - d]
+      const bool col = valid && au < T;
+#pragma unroll
+      for (int av = 0; av < TM; ++av) {
+        if (av < Tmax) {
+          float re = 0.f, im = 0.f;
+#pragma unroll
+          for (int d = 0; d < JT; ++d) {
+            if (av - d >= 0 && av - d < NK) {
+              re = fmaf(kv[d], t[av - d].x, re);
+              im = fmaf(kv[d], t[av - d].y, im);
+            }
+          }
+          if (col && av < T) {
+            if constexpr (STORE == WF_STORE_F16)
+              ovf = ovf || fabsf(re) > 65504.f || fabsf(im) > 65504.f;
+            store_val<STORE>(vals, vb + (int64_t)av * T + au, (double)re, (double)im);
+          }
+        }
+      }
+      wave_lds_sync();   // every read of the step's kernels is done before the next staging
+    }
+  }
+  if (ovf) atomicAdd(over, 1);
+}
+
 // Kernel-side class (0: n_k <= 7, 1: <= 15, 2: <= 21, 3: <= 31) of rows [r0, r1) in
 // caller order; the same bin and side computation as the build kernels.
 __global__ __launch_bounds__(256) void k_row_class(const double* __restrict__ uvw, int64_t r0,
@@ -874,6 +1213,106 @@ hipError_t launch_gbuild(const double* uvw, int64_t s0, const ClassSlices& cs,
       launch_gbuild_classes<WF_STORE_BF16>(s, uvw, s0, cs, perm, meta, voff, row_wi, wi, scale,
                                            gsx, gsy, mids, P, cents, kp, vals, vbase, mismatch,
                                            sg, wts);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <int STORE>
+void launch_khat_classes(hipStream_t s, const double* uvw, int64_t s0, const ClassSlices& cs,
+                         const int32_t* perm, const uint32_t* meta, const int64_t* kabs,
+                         double scale, double gsx, double gsy, const double* mids, int P,
+                         const double* cents, const KernelParams& kp, void* khat,
+                         int* mismatch, const Surrogate& sg, const float* wts) {
+#define WF_KHAT(NKC, C)                                                                      \
+  if (cs.n[C] > 0)                                                                           \
+    hipLaunchKernelGGL((k_khat<STORE, NKC>), dim3(grid_for(cs.n[C])), dim3(64), 0, s, uvw,   \
+                       s0, cs.rows[C], cs.n[C], perm, meta, kabs, scale, gsx, gsy, mids, P,  \
+                       cents, kp, khat, mismatch, sg, wts);
+  WF_KHAT(7, 0)
+  WF_KHAT(15, 1)
+  WF_KHAT(21, 2)
+  WF_KHAT(31, 3)
+#undef WF_KHAT
+}
+
+hipError_t launch_khat(const double* uvw, int64_t s0, const ClassSlices& cs, const int32_t* perm,
+                       const uint32_t* meta, const int64_t* kabs, double scale, double gsx,
+                       double gsy, const double* mids, int P, const double* cents,
+                       const KernelParams& kp, void* khat, wf_store store, int* mismatch,
+                       const Surrogate& sg, const float* wts, hipStream_t s) {
+  switch (store) {
+    case WF_STORE_F32:
+      launch_khat_classes<WF_STORE_F32>(s, uvw, s0, cs, perm, meta, kabs, scale, gsx, gsy, mids,
+                                        P, cents, kp, khat, mismatch, sg, wts);
+      break;
+    case WF_STORE_F16:
+      launch_khat_classes<WF_STORE_F16>(s, uvw, s0, cs, perm, meta, kabs, scale, gsx, gsy, mids,
+                                        P, cents, kp, khat, mismatch, sg, wts);
+      break;
+    default:
+      launch_khat_classes<WF_STORE_BF16>(s, uvw, s0, cs, perm, meta, kabs, scale, gsx, gsy,
+                                         mids, P, cents, kp, khat, mismatch, sg, wts);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <int STORE, int JT>
+void launch_expand_classes(hipStream_t s, const double* uvw, const ClassSlices& cs,
+                           const int32_t* perm, const uint32_t* meta, const uint32_t* voff,
+                           const int32_t* row_wi, const WorkItem* wi, double scale, double gsx,
+                           double gsy, const KernelParams& kp, const void* khat,
+                           const uint32_t* kof, void* vals, int64_t vbase, int* over) {
+  // one launch per kernel-side class; a workgroup expands rpw listed rows per step, rpw
+  // chosen for about 8192 wavefronts per launch (eight per SIMD) and at least one row
+  // per slot
+#define WF_EXPAND(NKC, C)                                                                     \
+  if (cs.n[C] > 0) {                                                                          \
+    const int rpw = (int)std::min<int64_t>(                                                   \
+        64, std::max<int64_t>(EScratch<NKC, JT>::SL, (cs.n[C] + 8191) / 8192));              \
+    hipLaunchKernelGGL((k_expand<STORE, NKC, JT>), dim3(grid_for((cs.n[C] + rpw - 1) / rpw)), \
+                       dim3(64), 0, s, uvw, cs.rows[C], cs.n[C], perm, meta, voff, row_wi, wi, \
+                       scale, gsx, gsy, kp, khat, kof, vals, vbase, rpw, over);               \
+  }
+  WF_EXPAND(7, 0)
+  WF_EXPAND(15, 1)
+  WF_EXPAND(21, 2)
+  WF_EXPAND(31, 3)
+#undef WF_EXPAND
+}
+
+template <int STORE>
+void launch_expand_store(hipStream_t s, const double* uvw, const ClassSlices& cs,
+                         const int32_t* perm, const uint32_t* meta, const uint32_t* voff,
+                         const int32_t* row_wi, const WorkItem* wi, double scale, double gsx,
+                         double gsy, const KernelParams& kp, const void* khat,
+                         const uint32_t* kof, void* vals, int64_t vbase, int* over) {
+  if (kp.J <= 7)
+    launch_expand_classes<STORE, 7>(s, uvw, cs, perm, meta, voff, row_wi, wi, scale, gsx, gsy,
+                                    kp, khat, kof, vals, vbase, over);
+  else
+    launch_expand_classes<STORE, 15>(s, uvw, cs, perm, meta, voff, row_wi, wi, scale, gsx, gsy,
+                                     kp, khat, kof, vals, vbase, over);
+}
+
+hipError_t launch_expand(const double* uvw, const ClassSlices& cs, const int32_t* perm,
+                         const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
+                         const WorkItem* wi, double scale, double gsx, double gsy,
+                         const KernelParams& kp, const void* khat, const uint32_t* kof,
+                         void* vals, int64_t vbase, wf_store store, int* over, hipStream_t s) {
+  switch (store) {
+    case WF_STORE_F32:
+      launch_expand_store<WF_STORE_F32>(s, uvw, cs, perm, meta, voff, row_wi, wi, scale, gsx, gsy,
+                                        kp, khat, kof, vals, vbase, over);
+      break;
+    case WF_STORE_F16:
+      launch_expand_store<WF_STORE_F16>(s, uvw, cs, perm, meta, voff, row_wi, wi, scale, gsx, gsy,
+                                        kp, khat, kof, vals, vbase, over);
+      break;
+    default:
+      launch_expand_store<WF_STORE_BF16>(s, uvw, cs, perm, meta, voff, row_wi, wi, scale, gsx,
+                                         gsy, kp, khat, kof, vals, vbase, over);
       break;
   }
   return hipGetLastError();

@@ -101,7 +101,9 @@ void destroy_op(wf_op* op) {
     dfree(c.hvals);
     dfree(c.flagged);
     dfree(c.ctab);
-    for (DevBuf* b : {&c.uvw, &c.wts, &c.uperm, &c.row_wi, &c.mids, &c.cents, &c.crow}) dfree(*b);
+    for (DevBuf* b : {&c.uvw, &c.wts, &c.uperm, &c.row_wi, &c.mids, &c.cents, &c.crow,
+                      &c.khat, &c.kof})
+      dfree(*b);
   }
   dfree(op->otf_mis);
   dfree(op->net_params);
@@ -630,31 +632,49 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   }
   if (holo && mlp)
     return fail(WF_ENOTSUP, "the holographic strategy builds exact kernels only (no kernel network)");
-  if (otf && mlp && !op->net_otf) {
+  ch.gchunk.clear();
+  double vp_flops = 0.0;
+  bool fact = false;
+  int64_t khat_values = 0;
+  if (otf) {
+    chunk_groups(ch, taps_total, b_v, share);
+    for (int64_t r = 0; r < M; ++r) {
+      const int64_t np = (int64_t)trow[r] - opt.J + 1;
+      khat_values += np * np;
+    }
+    const double meta_bytes = (24.0 + 20.0 + (sel.w ? 4.0 : 0.0) + (sel.keep ? 4.0 : 0.0)) * M;
+    const double transient = 4.0 * b_v * (double)ch.ck_max;
+    if (meta_bytes + transient > share)
+      return fail(WF_EBUDGET, "no strategy fits the memory budget: the on-the-fly row data "
+                              "alone needs " + std::to_string(meta_bytes / 1e9) + " GB");
+    // factorised form: the kernels (value format) and a 32-bit offset per row
+    const double khat_bytes = (double)b_v * khat_values + 4.0 * M;
+    const bool fits = meta_bytes + khat_bytes + transient <= share;
+    if (opt.otf_form == 2 && !fits)
+      return fail(WF_EBUDGET, "the factorised on-the-fly kernels need " +
+                                  std::to_string(khat_bytes / 1e9) + " GB");
+    fact = opt.otf_form == 2 || (opt.otf_form == 0 && fits);
+    // work of one apply's value pass.  Rebuilt: two length-nk DFT sweeps of the nk x nk
+    // residual kernel (16 nk^3) and its Kaiser-Bessel convolution (4 J (n' T + T^2)), in
+    // FP64; factorised: the convolution alone, in FP32
+    for (const RowGroup& g : ch.groups)
+      for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) {
+        const double T = trow[r], np = T - opt.J + 1;
+        const double conv = 4.0 * opt.J * (np * T + T * T);
+        if (fact) {
+          vp_flops += conv;
+        } else {
+          const int nk = nk_rule(w[idx[r]] - ch.centroids[g.bin], op->kp, true);
+          vp_flops += (nk > 1 ? 16.0 * nk * nk * nk : 0.0) + conv;
+        }
+      }
+  }
+  if (otf && !fact && mlp && !op->net_otf) {
     // every apply re-infers the kernels of the network's rows: keep the parameters the
     // build used, so that the predictions (and the patch sides they decide) never change
     if ((st = mlp_snapshot(mlp, op->net_params, op->net_wt, s)) != WF_OK) return st;
     op->net_otf = true;
     op->net_logtol = logtol;
-  }
-  ch.gchunk.clear();
-  double vp_flops = 0.0;
-  if (otf) {
-    chunk_groups(ch, taps_total, b_v, share);
-    // FP64 work of one value pass: two length-nk DFT sweeps of the nk x nk residual
-    // kernel (16 nk^3) and its Kaiser-Bessel convolution (4 J (n' T + T^2))
-    for (const RowGroup& g : ch.groups)
-      for (int64_t r = g.row0; r < (int64_t)g.row0 + g.nrows; ++r) {
-        const int nk = nk_rule(w[idx[r]] - ch.centroids[g.bin], op->kp, true);
-        const double T = trow[r], np = T - opt.J + 1;
-        vp_flops += (nk > 1 ? 16.0 * nk * nk * nk : 0.0) + 4.0 * opt.J * (np * T + T * T);
-      }
-  }
-  if (otf) {
-    const double meta_bytes = (24.0 + 20.0 + (sel.w ? 4.0 : 0.0) + (sel.keep ? 4.0 : 0.0)) * M;
-    if (meta_bytes + 4.0 * b_v * (double)ch.ck_max > share)
-      return fail(WF_EBUDGET, "no strategy fits the memory budget: the on-the-fly row data "
-                              "alone needs " + std::to_string(meta_bytes / 1e9) + " GB");
   }
   std::vector<WorkItem> wis;
   ch.max_rows = opt.max_rows_per_item > 0 ? opt.max_rows_per_item : 1024;
@@ -846,16 +866,67 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     DevBuf gtmp;
     tmp.b.push_back(&gtmp);
     if ((st = dalloc(gtmp, (size_t)b_v * std::max<int64_t>(ch.ck_max, 1))) != WF_OK) return st;
-    ch.ck_cls.resize(ch.ck_s0.size());
-    for (size_t k = 0; k < ch.ck_s0.size(); ++k) {
-      ch.ck_cls[k] = slice_classes(rcs, ch.ck_s0[k], ch.ck_s1[k]);
-      WF_HIP(launch_gbuild((const double*)duvw.p, ch.ck_s0[k], ch.ck_cls[k],
-                           (const int32_t*)ch.perm.p, (const uint32_t*)ch.meta.p,
-                           (const uint32_t*)ch.voff.p, (const int32_t*)drowwi.p,
-                           (const WorkItem*)ch.work.p, ch.scale, gsx, gsy,
-                           (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
-                           gtmp.p, ch.ck_vbase[k], opt.store, (int*)dmis.p, Surrogate{},
-                           (const float*)dwts.p, s));
+    const size_t nck = ch.ck_s0.size();
+    ch.ck_cls.resize(nck);
+    for (size_t k = 0; k < nck; ++k) ch.ck_cls[k] = slice_classes(rcs, ch.ck_s0[k], ch.ck_s1[k]);
+    if (fact) {
+      // kernel offsets: absolute for the build pass, relative to the chunk's first kernel
+      // (32 bits: a chunk holds fewer kernel values than G values) for the applies
+      std::vector<int64_t> kabs(M);
+      std::vector<uint32_t> kof(M);
+      int64_t at = 0;
+      for (int64_t r = 0; r < M; ++r) {
+        kabs[r] = at;
+        const int64_t np = (int64_t)trow[r] - opt.J + 1;
+        at += np * np;
+      }
+      ch.ck_kbase.assign(nck, 0);
+      for (size_t k = 0; k < nck; ++k) {
+        ch.ck_kbase[k] = ch.ck_s0[k] < M ? kabs[ch.ck_s0[k]] : at;
+        for (int64_t r = ch.ck_s0[k]; r < ch.ck_s1[k]; ++r) {
+          const int64_t d = kabs[r] - ch.ck_kbase[k];
+          if (d > (int64_t)UINT32_MAX) return fail(WF_EINVAL, "on-the-fly chunk too large");
+          kof[r] = (uint32_t)d;
+        }
+      }
+      DevBuf dkabs;
+      tmp.b.push_back(&dkabs);
+      if ((st = dalloc(dkabs, sizeof(int64_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
+      if ((st = dalloc(ch.kof, sizeof(uint32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
+      if ((st = dalloc(ch.khat, (size_t)b_v * std::max<int64_t>(at, 1))) != WF_OK) return st;
+      WF_HIP(hipMemcpyAsync(dkabs.p, kabs.data(), sizeof(int64_t) * M, hipMemcpyHostToDevice, s));
+      WF_HIP(hipMemcpyAsync(ch.kof.p, kof.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice, s));
+      st = surrogate_pass(rcs, (const int32_t*)ch.perm.p,
+                          [&](const ClassSlices& cs, const Surrogate& sg) -> wf_status {
+                            WF_HIP(launch_khat((const double*)duvw.p, 0, cs,
+                                               (const int32_t*)ch.perm.p,
+                                               (const uint32_t*)ch.meta.p,
+                                               (const int64_t*)dkabs.p, ch.scale, gsx, gsy,
+                                               (const double*)dmids.p, ch.P,
+                                               (const double*)dcents.p, op->kp, ch.khat.p,
+                                               opt.store, (int*)dmis.p, sg,
+                                               (const float*)dwts.p, s));
+                            return WF_OK;
+                          });
+      if (st != WF_OK) return st;
+      // every chunk expanded once, as an apply expands it, for the FP16 range check
+      for (size_t k = 0; k < nck; ++k)
+        WF_HIP(launch_expand((const double*)duvw.p, ch.ck_cls[k], (const int32_t*)ch.perm.p,
+                             (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
+                             (const int32_t*)drowwi.p, (const WorkItem*)ch.work.p, ch.scale,
+                             gsx, gsy, op->kp,
+                             (const char*)ch.khat.p + (size_t)ch.ck_kbase[k] * b_v,
+                             (const uint32_t*)ch.kof.p, gtmp.p, ch.ck_vbase[k], opt.store,
+                             (int*)dmis.p + 1, s));
+    } else {
+      for (size_t k = 0; k < nck; ++k)
+        WF_HIP(launch_gbuild((const double*)duvw.p, ch.ck_s0[k], ch.ck_cls[k],
+                             (const int32_t*)ch.perm.p, (const uint32_t*)ch.meta.p,
+                             (const uint32_t*)ch.voff.p, (const int32_t*)drowwi.p,
+                             (const WorkItem*)ch.work.p, ch.scale, gsx, gsy,
+                             (const double*)dmids.p, ch.P, (const double*)dcents.p, op->kp,
+                             gtmp.p, ch.ck_vbase[k], opt.store, (int*)dmis.p, Surrogate{},
+                             (const float*)dwts.p, s));
     }
     std::swap(ch.uvw, duvw);
     std::swap(ch.mids, dmids);
@@ -864,6 +935,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     std::swap(ch.row_wi, drowwi);
     std::swap(ch.crow, dls);   // the chunks' class slices point into this list
     ch.otf = true;
+    ch.fact = fact;
   }
   if (!holo && !otf) {
   if ((st = dalloc(ch.vals, (size_t)b_v * std::max<int64_t>(taps_total, 1))) != WF_OK)
@@ -921,11 +993,14 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   in.nwork = ch.nwork;
   in.k_estimate = pr.k_est;
   in.mem_g_bytes = otf ? (double)(ch.uvw.bytes + ch.wts.bytes + ch.uperm.bytes +
-                                   ch.row_wi.bytes + ch.crow.bytes) + 12.0 * M +
+                                   ch.row_wi.bytes + ch.crow.bytes + ch.khat.bytes +
+                                   ch.kof.bytes) + 12.0 * M +
                              sizeof(WorkItem) * wis.size()
                       : (double)b_v * taps_total + 12.0 * M + sizeof(WorkItem) * wis.size();
   in.mem_transient_bytes = otf ? (double)b_v * ch.ck_max : 0.0;
   in.value_pass_flops = vp_flops;
+  in.mem_khat_bytes = (double)(ch.khat.bytes + ch.kof.bytes);
+  in.otf_form = otf ? (fact ? 2 : 1) : 0;
   in.mem_model_bytes = pr.mem_model;
   in.cost_model = pr.cost_model;
   in.capped_fraction = M ? (double)ncapped / (double)M : 0.0;
@@ -1073,9 +1148,10 @@ float* chan_out(const wf_op* op, int kind, float* out, int c) {
   return out + c * out_floats(op, kind);
 }
 
-// Bin p of an on-the-fly channel (strategy (c)): each chunk of the bin's rows is built
-// into the lane's transient buffer by the FP64 value pass, then applied by the same row
-// kernels as a stored G (the buffer stands for the values [vbase, vbase + taps) of G).
+// Bin p of an on-the-fly channel (strategy (c)): each chunk of the bin's rows is written
+// into the lane's transient buffer (factorised: the stored kernels convolved with the
+// rows' taps; rebuilt: the FP64 value pass), then applied by the same row kernels as a
+// stored G (the buffer stands for the values [vbase, vbase + taps) of G).
 wf_status otf_bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, int p,
                         const float* in, float* out, bool first) {
   wf_status st;
@@ -1101,7 +1177,15 @@ wf_status otf_bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, in
                              (const float*)ch.wts.p, L.s));
         return WF_OK;
       };
-      if (!op->net_otf) {
+      if (ch.fact) {
+        // factorised: the stored kernels convolved with the rows' taps
+        WF_HIP(launch_expand((const double*)ch.uvw.p, ch.ck_cls[k], uperm,
+                             (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
+                             (const int32_t*)ch.row_wi.p, wk, ch.scale, gsx, gsy, op->kp,
+                             (const char*)ch.khat.p + (size_t)ch.ck_kbase[k] * b_v,
+                             (const uint32_t*)ch.kof.p, L.gbuf, ch.ck_vbase[k], store,
+                             (int*)op->otf_mis.p + 1, L.s));
+      } else if (!op->net_otf) {
         if ((st = gbuild(ch.ck_cls[k], Surrogate{})) != WF_OK) return st;
       } else {
         // as at build: the network's class from its predictions, the others exact
@@ -1877,6 +1961,7 @@ wf_status wf_build_operator(const double* uvw_m, int64_t nrows, const int64_t* c
       return fail(WF_EINVAL, "max_rows_per_item must be in [0,1024]");
     if (opt.branches < 0 || opt.branches > 16)
       return fail(WF_EINVAL, "branches must be in [0,16]");
+    if (opt.otf_form < 0 || opt.otf_form > 2) return fail(WF_EINVAL, "otf_form must be in [0,2]");
     if (opt.surrogate && !(opt.surrogate_tol > 0))
       return fail(WF_EINVAL, "surrogate_tol must be positive");
     if (opt.surrogate && shape.nx != shape.ny)

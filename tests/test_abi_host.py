@@ -33,7 +33,7 @@ def test_default_options():
     assert (o.J, o.oversample, o.smax, o.nbins, o.store) == (7, 2, 31, 0, 0)
     assert abs(o.beta - 2.34 * 7) < 1e-12 and o.eps_w == 1e-6
     assert o.plan_fraction == 0.01 and o.budget_fraction == 0.65
-    assert o.branches == 0 and o.max_rows_per_item == 0
+    assert o.branches == 0 and o.max_rows_per_item == 0 and o.otf_form == 0
 
 
 def _build(uvw, freqs, nx=64, ny=64, cell=1e-4, chan_rows=None, **kw):
@@ -66,6 +66,8 @@ UVW = np.random.default_rng(0).normal(0, 100, (50, 3))
     (dict(oversample=3), "oversample"),
     (dict(tile=48), "tile"),
     (dict(branches=17), "branches"),
+    (dict(otf_form=3), "otf_form"),
+    (dict(otf_form=-1), "otf_form"),
 ])
 def test_invalid_arguments(kw, frag):
     st, msg, h = _build(UVW, [1e9], **kw)

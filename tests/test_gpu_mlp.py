@@ -4,6 +4,7 @@ forward pass (1e-5), the BF16 inference kernel, per-tensor gradients (1e-4), an 
 step, training, and an operator whose G is built from the trained network (Phi^dag Phi
 within 1e-3 of the exact FP64 oracle)."""
 import math
+import os
 import sys
 import time
 
@@ -199,20 +200,24 @@ def test_network_gain_under_strategy_c(trained):
     net, _ = trained
     obs = ws.widefield(n=128, nvis=24_000, fov_deg=3.0, npoints=40, nblobs=3,
                        blob_sigma=(1.0, 3.0))
-    op_c = gpu_operator(obs, 4, strategy="otf", surrogate=net)
-    assert op_c.plan()["strategy"] == 3
-    frac_small = op_c.plan()["surrogate_fraction"]
     x = obs.sky.astype(np.float32)
-    e = rel(op_c.psf_apply(to_dev(x[None])).cpu().numpy()[0],
-            oracle_for(obs, 4).psf(x.astype(np.float64)))
-    say(f"[gpu] strategy (c) with the network: rows {frac_small:.3f}, psf rel vs oracle {e:.2e}")
-    assert e <= 1e-3 and frac_small > 0
-    op_c.close()
+    ref = oracle_for(obs, 4).psf(x.astype(np.float64))
+    for form in ("rebuilt", "factorised"):
+        # rebuilt: the network re-infers at every apply; factorised: its kernels are stored
+        op_c = gpu_operator(obs, 4, strategy="otf", surrogate=net, otf_form=form)
+        assert op_c.plan()["strategy"] == 3
+        assert op_c.plan()["otf_form"] == (1 if form == "rebuilt" else 2)
+        frac_small = op_c.plan()["surrogate_fraction"]
+        e = rel(op_c.psf_apply(to_dev(x[None])).cpu().numpy()[0], ref)
+        say(f"[gpu] strategy (c), {form}, with the network: rows {frac_small:.3f}, "
+            f"psf rel vs oracle {e:.2e}")
+        assert e <= 1e-3 and frac_small > 0
+        op_c.close()
     big = ws.learned_form(sky=False)
     rows = ws.seeded_subset(big.uvw_m.shape[0], 2_000_000, 3)
     uvw = np.ascontiguousarray(big.uvw_m[rows])
     xb = to_dev(ws.gauss_image(big.nx, 4).astype(np.float32)[None])
-    mk = dict(nbins=16, store="f16", strategy="otf")
+    mk = dict(nbins=16, store="f16", strategy="otf", otf_form="rebuilt")
     op_e = Operator(uvw, big.freqs_hz, big.nx, big.ny, big.cell_rad, **mk)
     op_n = Operator(uvw, big.freqs_hz, big.nx, big.ny, big.cell_rad, surrogate=net, **mk)
     frac = op_n.plan()["surrogate_fraction"]
@@ -227,5 +232,16 @@ def test_network_gain_under_strategy_c(trained):
     assert frac > 0.2
     assert d <= 1e-3
     assert tn < te
+    # the same rows against the FP64 oracle's stored samples (exact kernels; written by
+    # tests/golden/make_learned_parity.py, which calls only the oracle)
+    fx = np.load(os.path.join(os.path.dirname(__file__), "golden", "learned_4096sq_2M.npz"))
+    assert np.allclose(op_n.centroids(), fx["centroids"], rtol=1e-12, atol=1e-9)
+    pix = torch.from_numpy(fx["pix"]).to("cuda:0")
+    xg = to_dev(ws.gauss_image(big.nx, 4).astype(np.float32)[None])
+    for name, o in (("exact", op_e), ("network", op_n)):
+        v = o.psf_apply(xg)[0].flatten()[pix].cpu().numpy()
+        e = rel(v, fx["psf"])
+        say(f"[gpu]   strategy (c), {name} kernels: psf rel vs FP64 oracle {e:.2e}")
+        assert e <= 1e-3
     op_e.close()
     op_n.close()

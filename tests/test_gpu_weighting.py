@@ -163,8 +163,9 @@ def test_briggs_weights_match_oracle(obs):
         assert np.max(np.abs(got[sl] - ref)) <= 1e-6 * ref.max()
 
 
-@pytest.mark.parametrize("strategy", ["G", "otf"])
-def test_fully_flagged_channel(strategy):
+@pytest.mark.parametrize("strategy,form", [("G", "auto"), ("otf", "factorised"),
+                                           ("otf", "rebuilt")])
+def test_fully_flagged_channel(strategy, form):
     """Channel 0 has every row flagged (no row is built: zero visibilities, zero image);
     channel 1 is weighted and partly flagged and matches the oracle on its own rows."""
     base = ws.widefield(n=64, nvis=30_000, fov_deg=3.0, sky=False)
@@ -173,8 +174,8 @@ def test_fully_flagged_channel(strategy):
                          base.cell_rad, None, chan_rows=counts)
     flags = np.concatenate([np.ones(counts[0], bool), ws.flag_runs(counts[1], 0.2)])
     w = (1.0 / ws.noise_sigma(int(counts.sum()))).astype(np.float32)
-    op = gpu_operator(obs, 3, weights=w, flags=flags, strategy=strategy,
-                      memory_budget=50e6 if strategy == "otf" else 288e9)
+    op = gpu_operator(obs, 3, weights=w, flags=flags, strategy=strategy, otf_form=form,
+                      memory_budget=400e6 if strategy == "otf" else 288e9)
     assert op.plan(0)["nrows"] == 0 and op.plan(0)["nflagged"] == counts[0]
     x = np.stack([ws.gauss_image(64, 1), ws.gauss_image(64, 2)]).astype(np.float32)
     out = op.psf_apply(to_dev(x)).cpu().numpy()
