@@ -810,8 +810,13 @@ struct EScratch {
   static constexpr int NN = NK * NK;
   static constexpr int TM = NK + JT - 1;
   static constexpr int SL = 64 / TM;                   // rows expanded side by side
-  static constexpr int CK = (SL * NN + 63) / 64;       // kernel values per lane and step
-  float2 c[SL * NN];     // the step's kernels, [slot][s_v][s_u] (n' x n' each)
+  static constexpr int CK = (SL * NN + 63) / 64;       // kernel cells per lane and step
+  static constexpr int PW = NK + 2 * (JT - 1);         // padded kernel row
+  static constexpr int PS = NK * PW;                   // padded kernel of one slot
+  // the step's kernels, [slot][s_v][JT - 1 + s_u]: an NK x NK interior (the n' x n'
+  // kernel, zero beyond it) between zero margins of JT - 1 cells, so that the taps'
+  // reads need no bounds checks
+  float2 c[SL * PS];
 };
 
 // Raw stored value: two 32-bit words (FP32) or one word of two 16-bit halves.
@@ -910,7 +915,7 @@ __global__ __launch_bounds__(64) void k_expand(const double* __restrict__ uvw,
 #pragma clang fp contract(off)
   using ES = EScratch<NK, JT>;
   using Raw = typename KRaw<STORE>::type;
-  constexpr int NN = ES::NN, TM = ES::TM, SL = ES::SL, CK = ES::CK;
+  constexpr int NN = ES::NN, TM = ES::TM, SL = ES::SL, CK = ES::CK, PW = ES::PW, PS = ES::PS;
   __shared__ ES S;
   const int lane = threadIdx.x;
   const int slot = lane / TM, au = lane - slot * TM;   // slot == SL: spare lanes
@@ -936,37 +941,37 @@ __global__ __launch_bounds__(64) void k_expand(const double* __restrict__ uvw,
       kb_taps_f32<JT>(vb - floor(vb + 0.5), kp, mykv);
     }
     const int vlo = (int)(uint32_t)(uint64_t)myvb, vhi = (int)(uint32_t)((uint64_t)myvb >> 32);
-    // the SL kernels of the step at rb, contiguous in LDS slot by slot: issued into
-    // registers (value i of the step on lane i % 64), then written to LDS.  Slot j's
-    // kernel side, offset and first value within the step are wave-uniform.
+    // the SL kernels of the step at rb: every interior cell (slot j, row m, column n) of
+    // the step is handled by lane (cell % 64), which loads the kernel value there (zero
+    // outside the slot's n' x n' kernel) into registers; the cells are then written to
+    // LDS.  Slot j's kernel side and offset are wave-uniform.
     Raw cb[CK];
     struct Step {
-      int np[SL], cum[SL + 1];
+      int np[SL];
       uint32_t ko[SL];
     };
     auto step_of = [&](int rb) {
       Step st;
-      st.cum[0] = 0;
 #pragma unroll
       for (int j = 0; j < SL; ++j) {
         const int r = rb + j;
         st.np[j] = r < nb ? __builtin_amdgcn_readlane(myT, r & 63) - kp.J + 1 : 0;
         st.ko[j] = r < nb ? (uint32_t)__builtin_amdgcn_readlane((int)mykof, r & 63) : 0u;
-        st.cum[j + 1] = st.cum[j] + st.np[j] * st.np[j];
       }
       return st;
     };
-    // slot of step value i (< st.cum[SL]) and its index within that slot's kernel
-    auto locate = [&](const Step& st, int i, int& j, int& idx, uint32_t& ko) {
-      j = 0;
-#pragma unroll
-      for (int q = 1; q < SL; ++q) j += i >= st.cum[q] ? 1 : 0;
-      idx = i;
+    // cell i of the step: slot j, kernel row m, column n; its kernel index when inside
+    auto cell = [&](const Step& st, int i, int& j, int& m, int& n, int& np, uint32_t& ko) {
+      j = i / NN;
+      const int e = i - j * NN;
+      m = e / NK;
+      n = e - m * NK;
+      np = st.np[0];
       ko = st.ko[0];
 #pragma unroll
       for (int q = 1; q < SL; ++q)
         if (j == q) {
-          idx = i - st.cum[q];
+          np = st.np[q];
           ko = st.ko[q];
         }
     };
@@ -975,12 +980,10 @@ __global__ __launch_bounds__(64) void k_expand(const double* __restrict__ uvw,
 #pragma unroll
       for (int q = 0; q < CK; ++q) {
         const int i = lane + 64 * q;
-        if (i < st.cum[SL]) {
-          int j, idx;
-          uint32_t ko;
-          locate(st, i, j, idx, ko);
-          cb[q] = kraw_load<STORE>(khat, (int64_t)ko + idx);
-        }
+        int j, m, n, np;
+        uint32_t ko;
+        cell(st, i, j, m, n, np, ko);
+        if (i < SL * NN && m < np && n < np) cb[q] = kraw_load<STORE>(khat, (int64_t)ko + m * np + n);
       }
     };
     auto stage = [&](int rb) {
@@ -988,14 +991,19 @@ __global__ __launch_bounds__(64) void k_expand(const double* __restrict__ uvw,
 #pragma unroll
       for (int q = 0; q < CK; ++q) {
         const int i = lane + 64 * q;
-        if (i < st.cum[SL]) {
-          int j, idx;
-          uint32_t ko;
-          locate(st, i, j, idx, ko);
-          S.c[j * NN + idx] = kraw_widen<STORE>(cb[q]);
-        }
+        int j, m, n, np;
+        uint32_t ko;
+        cell(st, i, j, m, n, np, ko);
+        if (i < SL * NN)
+          S.c[j * PS + m * PW + (JT - 1) + n] =
+              (m < np && n < np) ? kraw_widen<STORE>(cb[q]) : make_float2(0.f, 0.f);
       }
     };
+    // the margins stay zero
+    for (int i = lane; i < SL * NK * 2 * (JT - 1); i += 64) {
+      const int row = i / (2 * (JT - 1)), e = i - row * (2 * (JT - 1));
+      S.c[row * PW + (e < JT - 1 ? e : NK + e)] = make_float2(0.f, 0.f);
+    }
     issue(0);
     for (int rb = 0; rb < nb; rb += SL) {
       stage(rb);
@@ -1018,24 +1026,21 @@ __global__ __launch_bounds__(64) void k_expand(const double* __restrict__ uvw,
         kv[d] = __shfl(mykv[d], src, 64);
       }
       const int npmax = wave_max_u(np), Tmax = wave_max_u(T);
-      const float2* c = S.c + (slot < SL ? slot : 0) * NN;
-      // t[m] = sum_d ku[d] c[m][a_u - d]
+      // t[m] = sum_d ku[d] c[m][a_u - d]: reads at a_u - d + JT - 1 in [0, PW) (a_u < TM)
+      const float2* c = S.c + (slot < SL ? slot : 0) * PS + au;
       float2 t[NK];
 #pragma unroll
       for (int m = 0; m < NK; ++m) {
         t[m] = make_float2(0.f, 0.f);
         if (m < npmax) {
-          if (m < np) {
-            float re = 0.f, im = 0.f;
+          float re = 0.f, im = 0.f;
 #pragma unroll
-            for (int d = 0; d < JT; ++d) {
-              const int n = au - d;
-              const float2 v = (n >= 0 && n < np) ? c[m * np + n] : make_float2(0.f, 0.f);
-              re = fmaf(ku[d], v.x, re);
-              im = fmaf(ku[d], v.y, im);
-            }
-            t[m] = make_float2(re, im);
+          for (int d = 0; d < JT; ++d) {
+            const float2 v = c[m * PW + (JT - 1 - d)];
+            re = fmaf(ku[d], v.x, re);
+            im = fmaf(ku[d], v.y, im);
           }
+          t[m] = make_float2(re, im);
         }
       }
       // G[a_v][a_u] = sum_d kv[d] t[a_v - d]
