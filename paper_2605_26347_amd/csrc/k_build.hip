@@ -864,30 +864,36 @@ template <int JT>
 __device__ __forceinline__ void kb_taps_f32(double f, const KernelParams& kp, float (&k)[JT]) {
 #pragma clang fp contract(off)
   const int half = (kp.J - 1) / 2;
-  double q[JT], term[JT], s[JT];
-  bool live[JT];
+  constexpr int G = 4;   // series run side by side (registers: three FP64 values each)
 #pragma unroll
-  for (int d = 0; d < JT; ++d) {
-    const double t = f - (double)(d - half);
-    const double z = 1.0 - ((2.0 * t) / (double)kp.J) * ((2.0 * t) / (double)kp.J);
-    live[d] = d < kp.J && z >= 0.0;
-    const double x = kp.beta * sqrt(live[d] ? z : 0.0);
-    q[d] = 0.25 * x * x;
-    term[d] = 1.0;
-    s[d] = 1.0;
-  }
-  for (int i = 1; i < 128; ++i) {
-    bool more = false;
+  for (int d0 = 0; d0 < JT; d0 += G) {
+    double q[G], term[G], s[G];
+    bool live[G];
 #pragma unroll
-    for (int d = 0; d < JT; ++d) {
-      term[d] = term[d] * (q[d] * c_inv_k2.v[i]);
-      s[d] += term[d];
-      more = more || !(term[d] < 1e-18 * s[d]);
+    for (int g = 0; g < G; ++g) {
+      const int d = d0 + g;
+      const double t = f - (double)(d - half);
+      const double z = 1.0 - ((2.0 * t) / (double)kp.J) * ((2.0 * t) / (double)kp.J);
+      live[g] = d < JT && d < kp.J && z >= 0.0;
+      const double x = kp.beta * sqrt(live[g] ? z : 0.0);
+      q[g] = 0.25 * x * x;
+      term[g] = 1.0;
+      s[g] = 1.0;
     }
-    if (__builtin_amdgcn_ballot_w64(more) == 0) break;
-  }
+    for (int i = 1; i < 128; ++i) {
+      bool more = false;
 #pragma unroll
-  for (int d = 0; d < JT; ++d) k[d] = live[d] ? (float)(s[d] / kp.i0beta) : 0.f;
+      for (int g = 0; g < G; ++g) {
+        term[g] = term[g] * (q[g] * c_inv_k2.v[i]);
+        s[g] += term[g];
+        more = more || !(term[g] < 1e-18 * s[g]);
+      }
+      if (__builtin_amdgcn_ballot_w64(more) == 0) break;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (d0 + g < JT) k[d0 + g] = live[g] ? (float)(s[g] / kp.i0beta) : 0.f;
+  }
 }
 
 __device__ __forceinline__ int wave_max_u(int v) {
@@ -1264,14 +1270,14 @@ hipError_t launch_khat(const double* uvw, int64_t s0, const ClassSlices& cs, con
 }
 
 template <int STORE, int JT>
-void launch_expand_classes(hipStream_t s, const double* uvw, const ClassSlices& cs,
+void launch_expand_classes(hipStream_t s, const double* uvw, const ExpSlices& cs,
                            const int32_t* perm, const uint32_t* meta, const uint32_t* voff,
                            const int32_t* row_wi, const WorkItem* wi, double scale, double gsx,
                            double gsy, const KernelParams& kp, const void* khat,
                            const uint32_t* kof, void* vals, int64_t vbase, int* over) {
-  // one launch per kernel-side class; a workgroup expands rpw listed rows per step, rpw
-  // chosen for about 8192 wavefronts per launch (eight per SIMD) and at least one row
-  // per slot
+  // one launch per kept-kernel side class; a workgroup expands rpw listed rows per step,
+  // rpw chosen for about 8192 wavefronts per launch (eight per SIMD) and at least one
+  // row per slot
 #define WF_EXPAND(NKC, C)                                                                     \
   if (cs.n[C] > 0) {                                                                          \
     const int rpw = (int)std::min<int64_t>(                                                   \
@@ -1280,15 +1286,17 @@ void launch_expand_classes(hipStream_t s, const double* uvw, const ClassSlices& 
                        dim3(64), 0, s, uvw, cs.rows[C], cs.n[C], perm, meta, voff, row_wi, wi, \
                        scale, gsx, gsy, kp, khat, kof, vals, vbase, rpw, over);               \
   }
-  WF_EXPAND(7, 0)
-  WF_EXPAND(15, 1)
-  WF_EXPAND(21, 2)
-  WF_EXPAND(31, 3)
+  WF_EXPAND(3, 0)
+  WF_EXPAND(7, 1)
+  WF_EXPAND(11, 2)
+  WF_EXPAND(15, 3)
+  WF_EXPAND(21, 4)
+  WF_EXPAND(31, 5)
 #undef WF_EXPAND
 }
 
 template <int STORE>
-void launch_expand_store(hipStream_t s, const double* uvw, const ClassSlices& cs,
+void launch_expand_store(hipStream_t s, const double* uvw, const ExpSlices& cs,
                          const int32_t* perm, const uint32_t* meta, const uint32_t* voff,
                          const int32_t* row_wi, const WorkItem* wi, double scale, double gsx,
                          double gsy, const KernelParams& kp, const void* khat,
@@ -1301,7 +1309,7 @@ void launch_expand_store(hipStream_t s, const double* uvw, const ClassSlices& cs
                                      kp, khat, kof, vals, vbase, over);
 }
 
-hipError_t launch_expand(const double* uvw, const ClassSlices& cs, const int32_t* perm,
+hipError_t launch_expand(const double* uvw, const ExpSlices& cs, const int32_t* perm,
                          const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
                          const WorkItem* wi, double scale, double gsx, double gsy,
                          const KernelParams& kp, const void* khat, const uint32_t* kof,

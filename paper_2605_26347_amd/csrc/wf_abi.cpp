@@ -102,7 +102,7 @@ void destroy_op(wf_op* op) {
     dfree(c.flagged);
     dfree(c.ctab);
     for (DevBuf* b : {&c.uvw, &c.wts, &c.uperm, &c.row_wi, &c.mids, &c.cents, &c.crow,
-                      &c.khat, &c.kof})
+                      &c.khat, &c.kof, &c.xrow})
       dfree(*b);
   }
   dfree(op->otf_mis);
@@ -881,6 +881,10 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
         at += np * np;
       }
       ch.ck_kbase.assign(nck, 0);
+      // the expansion takes each chunk's rows by kept-kernel side class
+      std::vector<int32_t> xrow;
+      xrow.reserve(M);
+      std::vector<int64_t> xoff((size_t)nck * NXC), xcnt((size_t)nck * NXC, 0);
       for (size_t k = 0; k < nck; ++k) {
         ch.ck_kbase[k] = ch.ck_s0[k] < M ? kabs[ch.ck_s0[k]] : at;
         for (int64_t r = ch.ck_s0[k]; r < ch.ck_s1[k]; ++r) {
@@ -888,7 +892,23 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
           if (d > (int64_t)UINT32_MAX) return fail(WF_EINVAL, "on-the-fly chunk too large");
           kof[r] = (uint32_t)d;
         }
+        for (int c = 0; c < NXC; ++c) {
+          xoff[(size_t)k * NXC + c] = (int64_t)xrow.size();
+          for (int64_t r = ch.ck_s0[k]; r < ch.ck_s1[k]; ++r)
+            if (xclass_of((int)trow[r] - opt.J + 1) == c) xrow.push_back((int32_t)r);
+          xcnt[(size_t)k * NXC + c] = (int64_t)xrow.size() - xoff[(size_t)k * NXC + c];
+        }
       }
+      if ((st = dalloc(ch.xrow, sizeof(int32_t) * std::max<size_t>(xrow.size(), 1))) != WF_OK)
+        return st;
+      WF_HIP(hipMemcpyAsync(ch.xrow.p, xrow.data(), sizeof(int32_t) * xrow.size(),
+                            hipMemcpyHostToDevice, s));
+      ch.ck_xcls.assign(nck, ExpSlices{});
+      for (size_t k = 0; k < nck; ++k)
+        for (int c = 0; c < NXC; ++c) {
+          ch.ck_xcls[k].rows[c] = (const int32_t*)ch.xrow.p + xoff[(size_t)k * NXC + c];
+          ch.ck_xcls[k].n[c] = xcnt[(size_t)k * NXC + c];
+        }
       DevBuf dkabs;
       tmp.b.push_back(&dkabs);
       if ((st = dalloc(dkabs, sizeof(int64_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
@@ -911,7 +931,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
       if (st != WF_OK) return st;
       // every chunk expanded once, as an apply expands it, for the FP16 range check
       for (size_t k = 0; k < nck; ++k)
-        WF_HIP(launch_expand((const double*)duvw.p, ch.ck_cls[k], (const int32_t*)ch.perm.p,
+        WF_HIP(launch_expand((const double*)duvw.p, ch.ck_xcls[k], (const int32_t*)ch.perm.p,
                              (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
                              (const int32_t*)drowwi.p, (const WorkItem*)ch.work.p, ch.scale,
                              gsx, gsy, op->kp,
@@ -994,7 +1014,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   in.k_estimate = pr.k_est;
   in.mem_g_bytes = otf ? (double)(ch.uvw.bytes + ch.wts.bytes + ch.uperm.bytes +
                                    ch.row_wi.bytes + ch.crow.bytes + ch.khat.bytes +
-                                   ch.kof.bytes) + 12.0 * M +
+                                   ch.kof.bytes + ch.xrow.bytes) + 12.0 * M +
                              sizeof(WorkItem) * wis.size()
                       : (double)b_v * taps_total + 12.0 * M + sizeof(WorkItem) * wis.size();
   in.mem_transient_bytes = otf ? (double)b_v * ch.ck_max : 0.0;
@@ -1179,7 +1199,7 @@ wf_status otf_bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, in
       };
       if (ch.fact) {
         // factorised: the stored kernels convolved with the rows' taps
-        WF_HIP(launch_expand((const double*)ch.uvw.p, ch.ck_cls[k], uperm,
+        WF_HIP(launch_expand((const double*)ch.uvw.p, ch.ck_xcls[k], uperm,
                              (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
                              (const int32_t*)ch.row_wi.p, wk, ch.scale, gsx, gsy, op->kp,
                              (const char*)ch.khat.p + (size_t)ch.ck_kbase[k] * b_v,

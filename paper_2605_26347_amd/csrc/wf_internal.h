@@ -169,6 +169,17 @@ struct ClassSlices {
   int64_t n[4];
 };
 
+// Rows of a factorised on-the-fly chunk by kept-kernel side class: n' <= 3, 7, 11, 15,
+// 21, 31 (the expansion's lane slots are sized for the class's largest n').
+constexpr int NXC = 6;
+__host__ __device__ constexpr int xclass_of(int np) {
+  return np <= 3 ? 0 : np <= 7 ? 1 : np <= 11 ? 2 : np <= 15 ? 3 : np <= 21 ? 4 : 5;
+}
+struct ExpSlices {
+  const int32_t* rows[NXC];
+  int64_t n[NXC];
+};
+
 struct DebugIndex {
   uint64_t gen = 0;                        // operator generation + 1 when valid
   std::vector<int32_t> sorted_of;          // caller row -> sorted row
@@ -217,6 +228,8 @@ struct ChanOp {
   bool fact = false;
   DevBuf khat, kof;                        // kernels (value format); offset per sorted row
   std::vector<int64_t> ck_kbase;           // per chunk: its first kernel value
+  DevBuf xrow;                             // sorted rows of every chunk by n' class
+  std::vector<ExpSlices> ck_xcls;          // per chunk: its slices of xrow
   std::vector<int32_t> gchunk;             // chunk of each row group
   std::vector<int64_t> ck_s0, ck_s1, ck_vbase, ck_taps;  // sorted rows, first value, values
   std::vector<int32_t> ck_first, ck_count; // per bin: first chunk, chunk count
@@ -503,10 +516,11 @@ hipError_t launch_khat(const double* uvw, int64_t s0, const ClassSlices& cs, con
                        double gsy, const double* mids, int P, const double* cents,
                        const KernelParams& kp, void* khat, wf_store store, int* mismatch,
                        const Surrogate& sg, const float* wts, hipStream_t s);
-// Apply: the G rows of the listed sorted rows from their kernels at khat[kof[s] ..]
+// Apply: the G rows of the listed sorted rows (by kept-kernel side class) from their
+// kernels at khat[kof[s] ..]
 // (khat points at the chunk's first kernel), written as launch_gbuild writes them;
 // over counts values beyond the FP16 range (FP16 store only).
-hipError_t launch_expand(const double* uvw, const ClassSlices& cs, const int32_t* perm,
+hipError_t launch_expand(const double* uvw, const ExpSlices& cs, const int32_t* perm,
                          const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
                          const WorkItem* wi, double scale, double gsx, double gsy,
                          const KernelParams& kp, const void* khat, const uint32_t* kof,
