@@ -186,4 +186,83 @@ __device__ __forceinline__ void reg_pass_lds(float2* buf, const float2* __restri
   __syncthreads();
 }
 
+// Cross-lane exchange through LDS in two halves, the real parts and then the imaginary
+// parts, so that a line occupies N floats of LDS instead of N complex values.  out[k]
+// goes to slot oslot(k) and in[k] comes from slot islot(k); the block's threads pass the
+// four barriers together (the last one lets the next exchange reuse the buffer).
+// The slots are functions of (k, tid); they are computed afresh for the second half
+// (the empty asm hides that tid is unchanged) instead of being held in registers across
+// it.
+template <int KO, int KI, typename OS, typename IS>
+__device__ __forceinline__ void xchg_split(float* buf, int tid, const float2 (&out)[KO],
+                                           OS&& oslot, float2 (&in)[KI], IS&& islot) {
+  int t = tid;
+#pragma unroll
+  for (int k = 0; k < KO; ++k) buf[oslot(k, t)] = out[k].x;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KI; ++k) in[k].x = buf[islot(k, t)];
+  __syncthreads();
+  asm volatile("" : "+v"(t));
+#pragma unroll
+  for (int k = 0; k < KO; ++k) buf[oslot(k, t)] = out[k].y;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KI; ++k) in[k].y = buf[islot(k, t)];
+  __syncthreads();
+}
+
+// The middle of a row transform with the line crossing LDS as floats (xchg_split), so
+// that twice as many lines fit a compute unit as with complex values.  v1 holds the
+// first pass's outputs of the thread's butterflies j = tid + b NT (output r of butterfly
+// j belongs at position j R1 + r); the second pass (radix R2, sub-transform length R1,
+// twiddles from tw) runs in registers between the two exchanges; v3 receives the third
+// pass's inputs x[j + r R1 R2].
+template <int N, bool INV>
+__device__ __forceinline__ void row_middle(float* buf, const float2 (&v1)[N / RowPlan<N>::NT],
+                                           float2 (&v3)[N / RowPlan<N>::NT],
+                                           const float2* __restrict__ tw, int tid) {
+  using RP = RowPlan<N>;
+  constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3, NT = RP::NT, E = N / NT;
+  constexpr int B2 = (N / R2) / NT;
+  static_assert(((N / R1) / NT) * R1 == E && B2 * R2 == E && ((N / R3) / NT) * R3 == E,
+                "every pass holds E elements per thread");
+  float2 v2[E];
+  xchg_split(
+      buf, tid, v1,
+      [](int k, int t) {
+        const int b = k / R1, r = k - b * R1;
+        return lds_slot((t + b * NT) * R1 + r);
+      },
+      v2,
+      [](int k, int t) {
+        const int b = k / R2, r = k - b * R2;
+        return lds_slot(t + b * NT + r * (N / R2));
+      });
+#pragma unroll
+  for (int b = 0; b < B2; ++b) {
+    const int j = tid + b * NT;
+    const int kk = j & (R1 - 1);
+    const int step = kk * (N / (R1 * R2));
+#pragma unroll
+    for (int r = 1; r < R2; ++r) {
+      const float2 t = tw[r * step];
+      v2[b * R2 + r] = INV ? cmulc(v2[b * R2 + r], t) : cmul(v2[b * R2 + r], t);
+    }
+    dft_reg<R2, INV>(v2 + b * R2);
+  }
+  xchg_split(
+      buf, tid, v2,
+      [](int k, int t) {
+        const int b = k / R2, r = k - b * R2;
+        const int j = t + b * NT, kk = j & (R1 - 1);
+        return lds_slot((j - kk) * R2 + kk + r * R1);
+      },
+      v3,
+      [](int k, int t) {
+        const int b = k / R3, r = k - b * R3;
+        return lds_slot(t + b * NT + r * (R1 * R2));
+      });
+}
+
 }  // namespace wf

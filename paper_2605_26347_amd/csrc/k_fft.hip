@@ -243,6 +243,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
   }
   const float syj = sy[jr];
   const float* __restrict__ row = img + (int64_t)jr * nx;
+  float2 v1[N / NT];
   {
     constexpr int B = (N / R1) / NT;
     // the modulation of the lane's pixels, one uniform branch for the whole row (a
@@ -274,8 +275,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
     }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      const int j = threadIdx.x + b * NT;
-      float2 v[R1];
+      float2* v = v1 + b * R1;
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
         if (r < R1 / 4 || r >= 3 * R1 / 4) {
@@ -287,21 +287,17 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
         }
       }
       dft_reg<R1, false>(v);
-#pragma unroll
-      for (int r = 0; r < R1; ++r) buf[lds_slot(j * R1 + r)] = v[r];
     }
   }
-  __syncthreads();
-  reg_pass_lds<N, R2, R1, NT, false>(buf, tw, threadIdx.x);
+  float2 v3[N / NT];
+  row_middle<N, false>(reinterpret_cast<float*>(buf), v1, v3, tw, threadIdx.x);
   {
     constexpr int NS = R1 * R2;
     constexpr int B = (N / R3) / NT;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = threadIdx.x + b * NT;
-      float2 v[R3];
-#pragma unroll
-      for (int r = 0; r < R3; ++r) v[r] = buf[lds_slot(j + r * NS)];
+      float2* v = v3 + b * R3;
 #pragma unroll
       for (int r = 1; r < R3; ++r) v[r] = cmul(v[r], tw[r * j]);
       dft_reg<R3, false>(v);
@@ -315,7 +311,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
 }
 
 template <int N>
-__global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
+__global__ __launch_bounds__(RowPlan<N>::NT) __attribute__((amdgpu_waves_per_eu(3))) void k_inv_rows_reg(
     const float2* __restrict__ A, void* __restrict__ out, const float2* __restrict__ tw,
     const float* __restrict__ sx, const float* __restrict__ sy, int nx, int ny, double cell,
     double wp, int mode, const uint32_t* __restrict__ smask, const float2* __restrict__ ctab) {
@@ -343,12 +339,13 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
       }
     }
   }
+  float2 v1[N / NT];
   {
     constexpr int B = (N / R1) / NT;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = threadIdx.x + b * NT;
-      float2 v[R1];
+      float2* v = v1 + b * R1;
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
         const int q = j + r * (N / R1);
@@ -356,12 +353,10 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
                                                          : make_float2(0.f, 0.f);
       }
       dft_reg<R1, true>(v);
-#pragma unroll
-      for (int r = 0; r < R1; ++r) buf[lds_slot(j * R1 + r)] = v[r];
     }
   }
-  __syncthreads();
-  reg_pass_lds<N, R2, R1, NT, true>(buf, tw, threadIdx.x);
+  float2 v3[N / NT];
+  row_middle<N, true>(reinterpret_cast<float*>(buf), v1, v3, tw, threadIdx.x);
   const float syj = sy[jr];
   {
     constexpr int NS = R1 * R2;
@@ -371,33 +366,28 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
       const int q = threadIdx.x + b * NT + r * NS;
       return r < R3 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
     };
-    float2 zr[B][R3 / 2];
-    if (ctab) {
-      const ChirpRow cr = chirp_row(jr, nx, ny, cell, wp, syj);
-#pragma unroll
-      for (int b = 0; b < B; ++b)
-#pragma unroll
-        for (int r = 0; r < R3; ++r)
-          if (r < R3 / 4 || r >= 3 * R3 / 4) {
-            const int i = pix(b, r);
-            zr[b][r < R3 / 4 ? r : r - R3 / 2] = zvalue_tab(cr, i, ctab[i]);
-          }
-    } else {
-#pragma unroll
-      for (int b = 0; b < B; ++b)
-#pragma unroll
-        for (int r = 0; r < R3; ++r)
-          if (r < R3 / 4 || r >= 3 * R3 / 4) {
-            const int i = pix(b, r);
-            zr[b][r < R3 / 4 ? r : r - R3 / 2] = zvalue(i, jr, nx, ny, cell, wp, sx[i], syj);
-          }
-    }
+    const ChirpRow cr = chirp_row(jr, nx, ny, cell, wp, syj);
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      const int j = threadIdx.x + b * NT;
-      float2 v[R3];
+      // one group's modulations at a time (registers), one uniform branch per group
+      float2 zr[R3 / 2];
+      if (ctab) {
 #pragma unroll
-      for (int r = 0; r < R3; ++r) v[r] = buf[lds_slot(j + r * NS)];
+        for (int r = 0; r < R3; ++r)
+          if (r < R3 / 4 || r >= 3 * R3 / 4) {
+            const int i = pix(b, r);
+            zr[r < R3 / 4 ? r : r - R3 / 2] = zvalue_tab(cr, i, ctab[i]);
+          }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R3; ++r)
+          if (r < R3 / 4 || r >= 3 * R3 / 4) {
+            const int i = pix(b, r);
+            zr[r < R3 / 4 ? r : r - R3 / 2] = zvalue(i, jr, nx, ny, cell, wp, sx[i], syj);
+          }
+      }
+      const int j = threadIdx.x + b * NT;
+      float2* v = v3 + b * R3;
 #pragma unroll
       for (int r = 1; r < R3; ++r) v[r] = cmulc(v[r], tw[r * j]);
       dft_reg<R3, true>(v);
@@ -406,7 +396,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_reg(
         if (r < R3 / 4 || r >= 3 * R3 / 4) {
           const int q = j + r * NS;
           const int i = r < R3 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
-          const float2 c = cmulc(v[r], zr[b][r < R3 / 4 ? r : r - R3 / 2]);
+          const float2 c = cmulc(v[r], zr[r < R3 / 4 ? r : r - R3 / 2]);
           const int64_t o = (int64_t)jr * nx + i;
           if (mode < 2) {
             float2* po = reinterpret_cast<float2*>(out) + o;
@@ -454,12 +444,13 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_sweep(
     const SweepLayer& L = sl[li];
     const float2* __restrict__ A = L.A;
     const uint32_t* __restrict__ smask = L.smask;
+    float2 v1[N / NT];
     {
       constexpr int B = (N / R1) / NT;
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         const int j = threadIdx.x + b * NT;
-        float2 v[R1];
+        float2* v = v1 + b * R1;
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
           const int q = j + r * (N / R1);
@@ -467,18 +458,14 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_sweep(
                                                            : make_float2(0.f, 0.f);
         }
         dft_reg<R1, true>(v);
-#pragma unroll
-        for (int r = 0; r < R1; ++r) buf[lds_slot(j * R1 + r)] = v[r];
       }
     }
-    __syncthreads();
-    reg_pass_lds<N, R2, R1, NT, true>(buf, tw, threadIdx.x);
+    float2 v3[N / NT];
+    row_middle<N, true>(reinterpret_cast<float*>(buf), v1, v3, tw, threadIdx.x);
 #pragma unroll
     for (int b = 0; b < B3; ++b) {
       const int j = threadIdx.x + b * NT;
-      float2 v[R3];
-#pragma unroll
-      for (int r = 0; r < R3; ++r) v[r] = buf[lds_slot(j + r * NS3)];
+      float2* v = v3 + b * R3;
 #pragma unroll
       for (int r = 1; r < R3; ++r) v[r] = cmulc(v[r], tw[r * j]);
       dft_reg<R3, true>(v);
@@ -494,7 +481,6 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_sweep(
         }
       }
     }
-    __syncthreads();   // every read of this layer's row is done before the next is written
   }
   const int64_t base = (int64_t)c * nx * ny + (int64_t)jr * nx;
 #pragma unroll
@@ -537,7 +523,11 @@ struct ColPlan {
   // lines: lines 32 / CW elements apart beyond their padded length (which is a multiple
   // of 32) put those CW runs on disjoint banks.
   static constexpr int LS = lds_elems<N>() + 32 / CW;
-  static constexpr size_t lds_bytes() { return (size_t)CW * LS * sizeof(float2) + N / 8; }
+  // CW lines of LS complex values (forward pass) or floats (inverse pass, whose lines
+  // cross LDS in halves: xchg_split), then the tile flags
+  static constexpr size_t lds_bytes(bool split) {
+    return (size_t)CW * LS * (split ? sizeof(float) : sizeof(float2)) + N / 8;
+  }
 };
 
 // Flags of the needed tiles of column-tile ct (one byte per row of tiles; all ones when
@@ -627,7 +617,7 @@ __global__ __launch_bounds__(ColPlan<N>::NT) void k_fwd_cols_reg(const float2* _
 }
 
 template <int N>
-__global__ __launch_bounds__(ColPlan<N>::NT) void k_inv_cols_reg(float2* __restrict__ Y,
+__global__ __launch_bounds__(ColPlan<N>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_inv_cols_reg(float2* __restrict__ Y,
                                                                  float2* __restrict__ A,
                                                                  const float2* __restrict__ tw,
                                                                  int ny, Masks mk,
@@ -637,7 +627,8 @@ __global__ __launch_bounds__(ColPlan<N>::NT) void k_inv_cols_reg(float2* __restr
   constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3;
   constexpr int CW = ColPlan<N>::CW, NTC = ColPlan<N>::NTC, NT = ColPlan<N>::NT;
   constexpr int LS = ColPlan<N>::LS;
-  extern __shared__ float2 buf[];
+  extern __shared__ float2 lds2[];
+  float* buf = reinterpret_cast<float*>(lds2);
   uint8_t* tflag = reinterpret_cast<uint8_t*>(buf + CW * LS);
   const int gi = xcd_remap(blockIdx.x, gridDim.x);
   int g;
@@ -654,18 +645,19 @@ __global__ __launch_bounds__(ColPlan<N>::NT) void k_inv_cols_reg(float2* __restr
   const int q0 = g * CW;
   const int strip = q0 >> 4, c0 = q0 & (SW - 1);
   const int c = threadIdx.x % CW, tj = threadIdx.x / CW;
-  float2* line = buf + c * LS;
+  float* line = buf + c * LS;
   load_tile_flags(tflag, mk, N, q0 >> mk.tsh, NT);
   __syncthreads();
   // Y is read only inside needed tiles and cleared behind the read, ready for the next
   // gridding; elsewhere it is zero already
   float2* __restrict__ src = Y + ((int64_t)strip * N) * SW + c0 + c;
+  float2 v1[N / NTC];
   {
     constexpr int B = (N / R1) / NTC;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = tj + b * NTC;
-      float2 v[R1];
+      float2* v = v1 + b * R1;
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
         const int q = j + r * (N / R1);
@@ -676,12 +668,10 @@ __global__ __launch_bounds__(ColPlan<N>::NT) void k_inv_cols_reg(float2* __restr
         }
       }
       dft_reg<R1, true>(v);
-#pragma unroll
-      for (int r = 0; r < R1; ++r) line[lds_slot(j * R1 + r)] = v[r];
     }
   }
-  __syncthreads();
-  reg_pass_lds<N, R2, R1, NTC, true>(line, tw, tj);
+  float2 v3[N / NTC];
+  row_middle<N, true>(line, v1, v3, tw, tj);
   float2* __restrict__ dst = A + ((int64_t)strip * ny) * SW + c0 + c;
   {
     constexpr int NS = R1 * R2;
@@ -689,9 +679,7 @@ __global__ __launch_bounds__(ColPlan<N>::NT) void k_inv_cols_reg(float2* __restr
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = tj + b * NTC;
-      float2 v[R3];
-#pragma unroll
-      for (int r = 0; r < R3; ++r) v[r] = line[lds_slot(j + r * NS)];
+      float2* v = v3 + b * R3;
 #pragma unroll
       for (int r = 1; r < R3; ++r) v[r] = cmulc(v[r], tw[r * j]);
       dft_reg<R3, true>(v);
@@ -815,7 +803,7 @@ static hipError_t launch_fwd_rows_reg(const float* img, float2* A, const float2*
                                       const float* sx, const float* sy, int nx, int ny,
                                       double cell, double wp, const uint32_t* smask,
                                       const float2* ctab, hipStream_t s) {
-  const size_t lds = (size_t)lds_elems<N>() * sizeof(float2);
+  const size_t lds = (size_t)lds_elems<N>() * sizeof(float);   // xchg_split
   hipError_t e = set_lds(k_fwd_rows_reg<N>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fwd_rows_reg<N>), dim3(ny), dim3(RowPlan<N>::NT), lds, s, img, A, tw,
@@ -828,7 +816,7 @@ static hipError_t launch_inv_rows_reg(const float2* A, void* out, const float2* 
                                       const float* sx, const float* sy, int nx, int ny,
                                       double cell, double wp, int mode, const uint32_t* smask,
                                       const float2* ctab, hipStream_t s) {
-  const size_t lds = (size_t)lds_elems<N>() * sizeof(float2);
+  const size_t lds = (size_t)lds_elems<N>() * sizeof(float);   // xchg_split
   hipError_t e = set_lds(k_inv_rows_reg<N>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_inv_rows_reg<N>), dim3(ny), dim3(RowPlan<N>::NT), lds, s, A, out, tw,
@@ -909,7 +897,7 @@ static hipError_t launch_cols_reg(float2* in, float2* out, const float2* tw, int
                                   const ColPrune* pr, hipStream_t s) {
   constexpr int CW = ColPlan<N>::CW;
   if (Kx % CW != 0) return hipErrorInvalidValue;
-  const size_t lds = ColPlan<N>::lds_bytes();
+  const size_t lds = ColPlan<N>::lds_bytes(INV);
   Masks mk{nullptr, nullptr, nullptr, 1, 0};
   int ng = Kx / CW;
   if (pr) {
@@ -1031,7 +1019,7 @@ hipError_t launch_sweep_fwd_rows(const float* img, const SweepLayer* sl, int nla
   switch (Kx) {
 #define C(NN)                                                                               \
   case NN: {                                                                                \
-    const size_t lds = (size_t)lds_elems<NN>() * sizeof(float2);                            \
+    const size_t lds = (size_t)lds_elems<NN>() * sizeof(float);                             \
     hipError_t e = set_lds(k_fwd_rows_reg<NN>, lds);                                        \
     if (e != hipSuccess) return e;                                                          \
     hipLaunchKernelGGL((k_fwd_rows_reg<NN>), dim3(ny, nlayers), dim3(RowPlan<NN>::NT), lds, \
@@ -1054,7 +1042,7 @@ hipError_t launch_sweep_cols(bool inverse, const SweepLayer* sl, const int2* pai
   switch (Ky) {
 #define C(NN)                                                                                 \
   case NN: {                                                                                  \
-    const size_t lds = ColPlan<NN>::lds_bytes();                                              \
+    const size_t lds = ColPlan<NN>::lds_bytes(inverse);                                       \
     hipError_t e;                                                                             \
     if (inverse) {                                                                            \
       e = set_lds(k_inv_cols_reg<NN>, lds);                                                   \
@@ -1085,7 +1073,7 @@ hipError_t launch_sweep_inv_rows(const SweepLayer* sl, const int2* chan_layers, 
   switch (Kx) {
 #define C(NN)                                                                                \
   case NN: {                                                                                 \
-    const size_t lds = (size_t)lds_elems<NN>() * sizeof(float2);                             \
+    const size_t lds = (size_t)lds_elems<NN>() * sizeof(float);                              \
     hipError_t e = set_lds(k_inv_rows_sweep<NN>, lds);                                       \
     if (e != hipSuccess) return e;                                                           \
     hipLaunchKernelGGL((k_inv_rows_sweep<NN>), dim3(ny, nchan), dim3(RowPlan<NN>::NT), lds,  \
