@@ -212,14 +212,39 @@ __device__ __forceinline__ void xchg_split(float* buf, int tid, const float2 (&o
   __syncthreads();
 }
 
-// The middle of a row transform with the line crossing LDS as floats (xchg_split), so
-// that twice as many lines fit a compute unit as with complex values.  v1 holds the
-// first pass's outputs of the thread's butterflies j = tid + b NT (output r of butterfly
-// j belongs at position j R1 + r); the second pass (radix R2, sub-transform length R1,
-// twiddles from tw) runs in registers between the two exchanges; v3 receives the third
-// pass's inputs x[j + r R1 R2].
+// The same exchange with complex values in one go (N complex values of LDS per line).
+template <int KO, int KI, typename OS, typename IS>
+__device__ __forceinline__ void xchg_full(float2* buf, int tid, const float2 (&out)[KO],
+                                          OS&& oslot, float2 (&in)[KI], IS&& islot) {
+#pragma unroll
+  for (int k = 0; k < KO; ++k) buf[oslot(k, tid)] = out[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KI; ++k) in[k] = buf[islot(k, tid)];
+  __syncthreads();
+}
+
+// Whether a transform of length N exchanges its lines as floats (xchg_split): from 8192
+// points on, where a complex line's LDS, not its registers, limits the lines per compute
+// unit; shorter lines fit by registers already and would only pay the extra barriers.
+template <int N>
+constexpr bool line_split() {
+  return N >= 8192;
+}
+// LDS of one line in bytes.
+template <int N>
+constexpr size_t line_lds_bytes() {
+  return (size_t)lds_elems<N>() * (line_split<N>() ? sizeof(float) : sizeof(float2));
+}
+
+// The middle of a row transform, the line crossing LDS twice (xchg_split or xchg_full as
+// line_split says; buf is the line, in floats or complex values accordingly).  v1 holds
+// the first pass's outputs of the thread's butterflies j = tid + b NT (output r of
+// butterfly j belongs at position j R1 + r); the second pass (radix R2, sub-transform
+// length R1, twiddles from tw) runs in registers between the two exchanges; v3 receives
+// the third pass's inputs x[j + r R1 R2].
 template <int N, bool INV>
-__device__ __forceinline__ void row_middle(float* buf, const float2 (&v1)[N / RowPlan<N>::NT],
+__device__ __forceinline__ void row_middle(void* buf, const float2 (&v1)[N / RowPlan<N>::NT],
                                            float2 (&v3)[N / RowPlan<N>::NT],
                                            const float2* __restrict__ tw, int tid) {
   using RP = RowPlan<N>;
@@ -228,8 +253,14 @@ __device__ __forceinline__ void row_middle(float* buf, const float2 (&v1)[N / Ro
   static_assert(((N / R1) / NT) * R1 == E && B2 * R2 == E && ((N / R3) / NT) * R3 == E,
                 "every pass holds E elements per thread");
   float2 v2[E];
-  xchg_split(
-      buf, tid, v1,
+  auto xchg = [&](const float2(&o)[E], auto&& os, float2(&in)[E], auto&& is) {
+    if constexpr (line_split<N>())
+      xchg_split(reinterpret_cast<float*>(buf), tid, o, os, in, is);
+    else
+      xchg_full(reinterpret_cast<float2*>(buf), tid, o, os, in, is);
+  };
+  xchg(
+      v1,
       [](int k, int t) {
         const int b = k / R1, r = k - b * R1;
         return lds_slot((t + b * NT) * R1 + r);
@@ -251,8 +282,8 @@ __device__ __forceinline__ void row_middle(float* buf, const float2 (&v1)[N / Ro
     }
     dft_reg<R2, INV>(v2 + b * R2);
   }
-  xchg_split(
-      buf, tid, v2,
+  xchg(
+      v2,
       [](int k, int t) {
         const int b = k / R2, r = k - b * R2;
         const int j = t + b * NT, kk = j & (R1 - 1);

@@ -290,7 +290,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
     }
   }
   float2 v3[N / NT];
-  row_middle<N, false>(reinterpret_cast<float*>(buf), v1, v3, tw, threadIdx.x);
+  row_middle<N, false>(buf, v1, v3, tw, threadIdx.x);
   {
     constexpr int NS = R1 * R2;
     constexpr int B = (N / R3) / NT;
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) __attribute__((amdgpu_waves_per_eu(
     }
   }
   float2 v3[N / NT];
-  row_middle<N, true>(reinterpret_cast<float*>(buf), v1, v3, tw, threadIdx.x);
+  row_middle<N, true>(buf, v1, v3, tw, threadIdx.x);
   const float syj = sy[jr];
   {
     constexpr int NS = R1 * R2;
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_inv_rows_sweep(
       }
     }
     float2 v3[N / NT];
-    row_middle<N, true>(reinterpret_cast<float*>(buf), v1, v3, tw, threadIdx.x);
+    row_middle<N, true>(buf, v1, v3, tw, threadIdx.x);
 #pragma unroll
     for (int b = 0; b < B3; ++b) {
       const int j = threadIdx.x + b * NT;
@@ -523,10 +523,10 @@ struct ColPlan {
   // lines: lines 32 / CW elements apart beyond their padded length (which is a multiple
   // of 32) put those CW runs on disjoint banks.
   static constexpr int LS = lds_elems<N>() + 32 / CW;
-  // CW lines of LS complex values (forward pass) or floats (inverse pass, whose lines
-  // cross LDS in halves: xchg_split), then the tile flags
-  static constexpr size_t lds_bytes(bool split) {
-    return (size_t)CW * LS * (split ? sizeof(float) : sizeof(float2)) + N / 8;
+  // CW lines of LS complex values, or of LS floats for an inverse pass whose lines cross
+  // LDS in halves (xchg_split, line_split), then the tile flags
+  static constexpr size_t lds_bytes(bool inverse) {
+    return (size_t)CW * LS * (inverse && line_split<N>() ? sizeof(float) : sizeof(float2)) + N / 8;
   }
 };
 
@@ -627,9 +627,11 @@ __global__ __launch_bounds__(ColPlan<N>::NT) __attribute__((amdgpu_waves_per_eu(
   constexpr int R1 = RP::R1, R2 = RP::R2, R3 = RP::R3;
   constexpr int CW = ColPlan<N>::CW, NTC = ColPlan<N>::NTC, NT = ColPlan<N>::NT;
   constexpr int LS = ColPlan<N>::LS;
-  extern __shared__ float2 lds2[];
-  float* buf = reinterpret_cast<float*>(lds2);
-  uint8_t* tflag = reinterpret_cast<uint8_t*>(buf + CW * LS);
+  extern __shared__ float2 buf[];
+  // CW lines of LS floats (split exchange) or complex values, then the tile flags
+  constexpr bool SPLIT = line_split<N>();
+  uint8_t* tflag = SPLIT ? reinterpret_cast<uint8_t*>(reinterpret_cast<float*>(buf) + CW * LS)
+                         : reinterpret_cast<uint8_t*>(buf + CW * LS);
   const int gi = xcd_remap(blockIdx.x, gridDim.x);
   int g;
   if (sl) {
@@ -645,7 +647,7 @@ __global__ __launch_bounds__(ColPlan<N>::NT) __attribute__((amdgpu_waves_per_eu(
   const int q0 = g * CW;
   const int strip = q0 >> 4, c0 = q0 & (SW - 1);
   const int c = threadIdx.x % CW, tj = threadIdx.x / CW;
-  float* line = buf + c * LS;
+  void* line = SPLIT ? (void*)(reinterpret_cast<float*>(buf) + c * LS) : (void*)(buf + c * LS);
   load_tile_flags(tflag, mk, N, q0 >> mk.tsh, NT);
   __syncthreads();
   // Y is read only inside needed tiles and cleared behind the read, ready for the next
@@ -803,7 +805,7 @@ static hipError_t launch_fwd_rows_reg(const float* img, float2* A, const float2*
                                       const float* sx, const float* sy, int nx, int ny,
                                       double cell, double wp, const uint32_t* smask,
                                       const float2* ctab, hipStream_t s) {
-  const size_t lds = (size_t)lds_elems<N>() * sizeof(float);   // xchg_split
+  const size_t lds = line_lds_bytes<N>();
   hipError_t e = set_lds(k_fwd_rows_reg<N>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fwd_rows_reg<N>), dim3(ny), dim3(RowPlan<N>::NT), lds, s, img, A, tw,
@@ -816,7 +818,7 @@ static hipError_t launch_inv_rows_reg(const float2* A, void* out, const float2* 
                                       const float* sx, const float* sy, int nx, int ny,
                                       double cell, double wp, int mode, const uint32_t* smask,
                                       const float2* ctab, hipStream_t s) {
-  const size_t lds = (size_t)lds_elems<N>() * sizeof(float);   // xchg_split
+  const size_t lds = line_lds_bytes<N>();
   hipError_t e = set_lds(k_inv_rows_reg<N>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_inv_rows_reg<N>), dim3(ny), dim3(RowPlan<N>::NT), lds, s, A, out, tw,
@@ -1019,7 +1021,7 @@ hipError_t launch_sweep_fwd_rows(const float* img, const SweepLayer* sl, int nla
   switch (Kx) {
 #define C(NN)                                                                               \
   case NN: {                                                                                \
-    const size_t lds = (size_t)lds_elems<NN>() * sizeof(float);                             \
+    const size_t lds = line_lds_bytes<NN>();                                            \
     hipError_t e = set_lds(k_fwd_rows_reg<NN>, lds);                                        \
     if (e != hipSuccess) return e;                                                          \
     hipLaunchKernelGGL((k_fwd_rows_reg<NN>), dim3(ny, nlayers), dim3(RowPlan<NN>::NT), lds, \
@@ -1073,7 +1075,7 @@ hipError_t launch_sweep_inv_rows(const SweepLayer* sl, const int2* chan_layers, 
   switch (Kx) {
 #define C(NN)                                                                                \
   case NN: {                                                                                 \
-    const size_t lds = (size_t)lds_elems<NN>() * sizeof(float);                              \
+    const size_t lds = line_lds_bytes<NN>();                                            \
     hipError_t e = set_lds(k_inv_rows_sweep<NN>, lds);                                       \
     if (e != hipSuccess) return e;                                                           \
     hipLaunchKernelGGL((k_inv_rows_sweep<NN>), dim3(ny, nchan), dim3(RowPlan<NN>::NT), lds,  \
