@@ -581,9 +581,14 @@ def bench_onthefly(args, torch):
             f"GB), transient {info['mem_transient_bytes'] / 1e9:.2f} GB per branch, value "
             f"pass {info['value_pass_flops'] / 1e12:.3f} TFLOP per apply")
         out = torch.empty_like(x)
+        # the autotuner picks rows per item and the branch count (each branch has its own
+        # transient buffer: one bin's expansion overlaps another's fused kernel and FFTs)
+        tune = op.autotune(x, out, reps=1)
+        log(f"on the fly, {form}: autotune {tune}")
         for _ in range(warm):
             op.psf_apply_re(x, out)
         ms = _timed_applies(op, x, out, nsteps, torch)
+        op.set_branches(1)
         op.profile_enable(5, True)
         op.profile_enable(0, True)
         op.psf_apply_re(x, out)
@@ -591,14 +596,14 @@ def bench_onthefly(args, torch):
         n0, ms0 = op.profile_read(0)
         op.profile_enable(5, False)
         op.profile_enable(0, False)
-        log(f"on the fly, {form}: {ms:.1f} ms/apply; value pass {ms5:.1f} ms in {n5} "
-            f"launches, G^dag G {ms0:.1f} ms in {n0} launches")
+        log(f"on the fly, {form}: {ms:.1f} ms/apply on {tune['branches']} branches; value pass "
+            f"{ms5:.1f} ms in {n5} launches, G^dag G {ms0:.1f} ms in {n0} launches (one branch)")
         res = out.clone()
         op.close()
         del op
         torch.cuda.empty_cache()
         return dict(build_s=tb, ms=ms, value_pass_ms=ms5, value_pass_launches=n5,
-                    gtg_ms=ms0, info=info), res
+                    gtg_ms=ms0, branches=tune["branches"], info=info), res
 
     fac, fout = run("factorised", steps)
     reb, rout = run("rebuilt", 1)
