@@ -264,3 +264,24 @@ def test_factorised_large_launches():
     ep = rel(f.psf_apply(x).cpu().numpy(), g.psf_apply(x).cpu().numpy())
     say(f"[gpu] factorised 256^2 / 200k rows vs stored G: forward {ef:.2e}, psf {ep:.2e}")
     assert ef <= FACT and ep <= FACT
+
+
+@pytest.mark.parametrize("J", [5, 9])
+def test_other_kaiser_bessel_supports(obs, J):
+    """Kaiser-Bessel supports other than 7 (J odd in [3, 15], beta = 2.34 J): the stored
+    G and the factorised form, whose expansion carries 7 taps for J <= 7 (the taps past J
+    zero) and 15 above, against the FP64 oracle."""
+    kw = dict(J=J, beta=2.34 * J, smax=21)
+    orc = oracle_for(obs, 3, **kw)
+    x = obs.sky.astype(np.float32)
+    ref = orc.psf(x.astype(np.float64))
+    xd = to_dev(x[None])
+    g = gpu_operator(obs, 3, **kw)
+    f = gpu_operator(obs, 3, strategy="otf", otf_form="factorised", memory_budget=400e6, **kw)
+    assert f.plan()["otf_form"] == FACTORISED
+    eg = rel(g.psf_apply(xd).cpu().numpy()[0], ref)
+    ef = rel(f.psf_apply(xd).cpu().numpy()[0], ref)
+    y = f.forward(xd).cpu().numpy()
+    ey = rel(y, orc.forward(x.astype(np.float64)))
+    say(f"[gpu] J={J}: psf rel stored G {eg:.2e}, factorised {ef:.2e}; forward {ey:.2e}")
+    assert max(eg, ef, ey) <= TOL["f32"]
