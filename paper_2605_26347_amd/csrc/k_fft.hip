@@ -321,24 +321,6 @@ __global__ __launch_bounds__(RowPlan<N>::NT) __attribute__((amdgpu_waves_per_eu(
   const int jr = blockIdx.x;
   constexpr int NS3 = R1 * R2;
   constexpr int B3 = (N / R3) / NT;
-  // the previous image sum of the real-part accumulate mode is requested first, so that
-  // its latency hides behind the transform
-  float prev[B3][R3 / 2];
-  if (mode == 3) {
-#pragma unroll
-    for (int b = 0; b < B3; ++b) {
-      const int j = threadIdx.x + b * NT;
-#pragma unroll
-      for (int r = 0; r < R3; ++r) {
-        if (r < R3 / 4 || r >= 3 * R3 / 4) {
-          const int q = j + r * NS3;
-          const int i = r < R3 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
-          prev[b][r < R3 / 4 ? r : r - R3 / 2] =
-              reinterpret_cast<const float*>(out)[(int64_t)jr * nx + i];
-        }
-      }
-    }
-  }
   float2 v1[N / NT];
   {
     constexpr int B = (N / R1) / NT;
@@ -387,6 +369,19 @@ __global__ __launch_bounds__(RowPlan<N>::NT) __attribute__((amdgpu_waves_per_eu(
           }
       }
       const int j = threadIdx.x + b * NT;
+      // the previous image sum of the real-part accumulate mode, requested before this
+      // group's transform so that its latency hides behind it (per group: registers)
+      float prev[R3 / 2];
+      if (mode == 3) {
+#pragma unroll
+        for (int r = 0; r < R3; ++r)
+          if (r < R3 / 4 || r >= 3 * R3 / 4) {
+            const int q = j + r * NS3;
+            const int i = r < R3 / 4 ? q + nx / 2 : q - 3 * (nx / 2);
+            prev[r < R3 / 4 ? r : r - R3 / 2] =
+                reinterpret_cast<const float*>(out)[(int64_t)jr * nx + i];
+          }
+      }
       float2* v = v3 + b * R3;
 #pragma unroll
       for (int r = 1; r < R3; ++r) v[r] = cmulc(v[r], tw[r * j]);
@@ -408,7 +403,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) __attribute__((amdgpu_waves_per_eu(
             }
           } else {
             float* po = reinterpret_cast<float*>(out) + o;
-            *po = (mode == 3) ? (prev[b][r < R3 / 4 ? r : r - R3 / 2] + c.x) : c.x;
+            *po = (mode == 3) ? (prev[r < R3 / 4 ? r : r - R3 / 2] + c.x) : c.x;
           }
         }
       }
