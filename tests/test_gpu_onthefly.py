@@ -226,6 +226,8 @@ def test_factorised_only_when_its_kernels_fit(obs):
 
 
 def test_factorised_branches_and_graph(obs):
+    """Two channels on two branches (a transient buffer each), graph replays against the
+    eager apply, and the autotuner's re-split of the work items, in the factorised form."""
     M = obs.uvw_m.shape[0]
     cr = np.array([M // 2, M - M // 2])
     from paper_2605_26347_amd import Operator
@@ -248,6 +250,12 @@ def test_factorised_branches_and_graph(obs):
         two.forward(x)            # eager work on the same transient buffers between replays
         torch.cuda.synchronize()
     g.close()
+    y0 = one.forward(x).cpu().numpy()
+    info = one.autotune(x, torch.empty_like(x), reps=1)
+    say(f"[gpu] factorised autotune {info}")
+    assert one.plan(0)["max_rows_per_item"] in (256, 512, 1024)
+    assert np.array_equal(one.forward(x).cpu().numpy(), y0)
+    assert rel(one.psf_apply_re(x).cpu().numpy(), ref) <= SAME
 
 
 def test_factorised_large_launches():
