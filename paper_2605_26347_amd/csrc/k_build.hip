@@ -989,7 +989,8 @@ __global__ __launch_bounds__(64) void k_expand(const double* __restrict__ uvw,
         int j, m, n, np;
         uint32_t ko;
         cell(st, i, j, m, n, np, ko);
-        if (i < SL * NN && m < np && n < np) cb[q] = kraw_load<STORE>(khat, (int64_t)ko + m * np + n);
+        if (i < SL * NN && m < np && n < np)
+          cb[q] = kraw_load<STORE>(khat, (int64_t)ko + m * np + n);
       }
     };
     auto stage = [&](int rb) {
