@@ -622,9 +622,11 @@ def bench_onthefly(args, torch):
         f"rebuilt")
     g.close()
     # expansion traffic per apply: the kernels read (b_v n'^2 per row), G written
-    # (b_v T^2 per row), and per row its coordinates (16 B) and four 32-bit words
-    kvals = (info["mem_khat_bytes"] - 4.0 * M) / b_v
-    xbytes = b_v * (kvals + info["ntaps"]) + 32.0 * M
+    # (b_v T^2 per row), and per row its 2J FP32 taps (56 B at J = 7) and five 32-bit
+    # words (list entry, patch word, kernel offset, item, value offset)
+    J = 7
+    kvals = (info["mem_khat_bytes"] - (4.0 + 8.0 * J) * M) / b_v
+    xbytes = b_v * (kvals + info["ntaps"]) + (8.0 * J + 20.0) * M
     ach = xbytes / (fac["value_pass_ms"] * 1e-3) / 1e9 if fac["value_pass_ms"] > 0 else None
     ms = fac["ms"]
     strip = lambda d: {k: v for k, v in d.items() if k != "info"}
@@ -647,8 +649,8 @@ def bench_onthefly(args, torch):
                      "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None,
                      "bytes_per_apply": xbytes,
-                     "bytes": "b_v (n'^2 + T^2) + 32 per row: kernel read, G written, "
-                              "coordinates and row words"},
+                     "bytes": "b_v (n'^2 + T^2) + 8 J + 20 per row: kernel read, G written, "
+                              "taps and row words"},
     }
     print(json.dumps(line), flush=True)
 

@@ -740,11 +740,13 @@ __global__ __launch_bounds__(64, NK <= 15 ? 4 : 1) void k_khat(const double* __r
                                                const double* __restrict__ mids, int P,
                                                const double* __restrict__ cents,
                                                KernelParams kp, void* __restrict__ khat,
+                                               float* __restrict__ taps,
                                                int* __restrict__ mismatch, Surrogate sg,
                                                const float* __restrict__ wts) {
 #pragma clang fp contract(off)
   __shared__ KScratch<NK> S;
   const int lane = threadIdx.x;
+  const int half = (kp.J - 1) / 2;
   for (int64_t i = blockIdx.x; i < nl; i += gridDim.x) {
     const int64_t s = rows[i];
     const int64_t k = perm[s];
@@ -772,6 +774,15 @@ __global__ __launch_bounds__(64, NK <= 15 ? 4 : 1) void k_khat(const double* __r
         const double2 c = S.c[(m + h - hp) * nk + (nn + h - hp)];
         store_val<STORE>(khat, kb + idx, c.x * wk, c.y * wk);
       }
+      // the row's Kaiser-Bessel taps phi(f - d), d = -half..half, as k_gbuild evaluates
+      // them (FP64), rounded to FP32: u taps then v taps
+      if (lane < 2 * kp.J) {
+        const int d = (lane % kp.J) - half;
+        const double f = lane < kp.J ? g.ub - floor(g.ub + 0.5) : g.vb - floor(g.vb + 0.5);
+        const double t = f - (double)d;
+        const double z = 1.0 - ((2.0 * t) / (double)kp.J) * ((2.0 * t) / (double)kp.J);
+        taps[s * 2 * kp.J + lane] = z >= 0.0 ? (float)(dev_i0(kp.beta * sqrt(z)) / kp.i0beta) : 0.f;
+      }
     }
     __syncthreads();
   }
@@ -791,13 +802,14 @@ __device__ __forceinline__ float2 load_val(const void* __restrict__ v, int64_t i
 
 // Factorised strategy (c), apply side: rows of G from the stored kernels,
 // G = Kv c Ku^T (Sect. 3.2), Ku / Kv the banded matrices of the Kaiser-Bessel taps at the
-// row's fractional grid offset.  The taps are evaluated in FP64 (the uvw -> grid map),
-// the convolution in FP32; values are written in the store format where the value pass
+// row's fractional grid offset.  The taps were evaluated by the build in FP64 (the
+// uvw -> grid map) and stored in FP32, 2J per row (u then v, taps[s 2J ..]); the
+// convolution is FP32; values are written in the store format where the value pass
 // would write them (item offset + row offset - vbase).
 //
 // A workgroup is one wavefront and takes rpw <= 64 listed rows at a time (fewer where a
 // launch has few rows, so that every SIMD still holds several wavefronts): lane i reads
-// the i-th row's words and evaluates its taps.  The rows are then expanded SL at a time,
+// the i-th row's words and taps.  The rows are then expanded SL at a time,
 // one per slot of TM = NK + JT - 1 lanes (the largest patch side of the class), lane a_u
 // of a slot computing patch column a_u: first t[m] = sum_d ku[d] c[m][a_u - d] for the
 // kernel rows m (c staged in LDS), then G[a_v][a_u] = sum_d kv[d] t[a_v - d] in registers,
@@ -855,47 +867,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The JT Kaiser-Bessel taps phi(f - d + (J - 1)/2), d < JT, zero past J and outside the
-// support, rounded to FP32.  dev_i0's series is run for all taps at once until every tap
-// of the wavefront has added its last term (the first below 1e-18 of its sum): the
-// terms after that one are smaller still, below half an ulp of the sum, and leave it
-// unchanged, so each tap equals dev_i0's value bit for bit, with no divergent branch.
-template <int JT>
-__device__ __forceinline__ void kb_taps_f32(double f, const KernelParams& kp, float (&k)[JT]) {
-#pragma clang fp contract(off)
-  const int half = (kp.J - 1) / 2;
-  constexpr int G = 4;   // series run side by side (registers: three FP64 values each)
-#pragma unroll
-  for (int d0 = 0; d0 < JT; d0 += G) {
-    double q[G], term[G], s[G];
-    bool live[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int d = d0 + g;
-      const double t = f - (double)(d - half);
-      const double z = 1.0 - ((2.0 * t) / (double)kp.J) * ((2.0 * t) / (double)kp.J);
-      live[g] = d < JT && d < kp.J && z >= 0.0;
-      const double x = kp.beta * sqrt(live[g] ? z : 0.0);
-      q[g] = 0.25 * x * x;
-      term[g] = 1.0;
-      s[g] = 1.0;
-    }
-    for (int i = 1; i < 128; ++i) {
-      bool more = false;
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        term[g] = term[g] * (q[g] * c_inv_k2.v[i]);
-        s[g] += term[g];
-        more = more || !(term[g] < 1e-18 * s[g]);
-      }
-      if (__builtin_amdgcn_ballot_w64(more) == 0) break;
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-      if (d0 + g < JT) k[d0 + g] = live[g] ? (float)(s[g] / kp.i0beta) : 0.f;
-  }
-}
-
 __device__ __forceinline__ int wave_max_u(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -906,16 +877,14 @@ __device__ __forceinline__ int wave_max_u(int v) {
 }
 
 template <int STORE, int NK, int JT>
-__global__ __launch_bounds__(64) void k_expand(const double* __restrict__ uvw,
-                                               const int32_t* __restrict__ rows, int64_t nl,
-                                               const int32_t* __restrict__ perm,
+__global__ __launch_bounds__(64) void k_expand(const int32_t* __restrict__ rows, int64_t nl,
                                                const uint32_t* __restrict__ meta,
                                                const uint32_t* __restrict__ voff,
                                                const int32_t* __restrict__ row_wi,
-                                               const WorkItem* __restrict__ wis, double scale,
-                                               double gsx, double gsy, KernelParams kp,
-                                               const void* __restrict__ khat,
+                                               const WorkItem* __restrict__ wis,
+                                               KernelParams kp, const void* __restrict__ khat,
                                                const uint32_t* __restrict__ kof,
+                                               const float* __restrict__ taps,
                                                void* __restrict__ vals, int64_t vbase,
                                                int rpw, int* __restrict__ over) {
 #pragma clang fp contract(off)
@@ -937,14 +906,17 @@ __global__ __launch_bounds__(64) void k_expand(const double* __restrict__ uvw,
     for (int d = 0; d < JT; ++d) myku[d] = mykv[d] = 0.f;
     if (lane < nb) {
       const int64_t s = rows[b0 + lane];
-      const int64_t k = perm[s];
       myT = (int)((meta[s] >> 16) & 0xff);
       mykof = kof[s];
       myvb = wis[row_wi[s]].voff + voff[s] - vbase;
-      const double ub = (uvw[3 * k] * scale) * gsx;
-      const double vb = (uvw[3 * k + 1] * scale) * gsy;
-      kb_taps_f32<JT>(ub - floor(ub + 0.5), kp, myku);
-      kb_taps_f32<JT>(vb - floor(vb + 0.5), kp, mykv);
+      const float* tp = taps + s * 2 * kp.J;
+#pragma unroll
+      for (int d = 0; d < JT; ++d) {
+        if (d < kp.J) {
+          myku[d] = tp[d];
+          mykv[d] = tp[kp.J + d];
+        }
+      }
     }
     const int vlo = (int)(uint32_t)(uint64_t)myvb, vhi = (int)(uint32_t)((uint64_t)myvb >> 32);
     // the SL kernels of the step at rb: every interior cell (slot j, row m, column n) of
@@ -1234,13 +1206,13 @@ template <int STORE>
 void launch_khat_classes(hipStream_t s, const double* uvw, int64_t s0, const ClassSlices& cs,
                          const int32_t* perm, const uint32_t* meta, const int64_t* kabs,
                          double scale, double gsx, double gsy, const double* mids, int P,
-                         const double* cents, const KernelParams& kp, void* khat,
+                         const double* cents, const KernelParams& kp, void* khat, float* taps,
                          int* mismatch, const Surrogate& sg, const float* wts) {
 #define WF_KHAT(NKC, C)                                                                      \
   if (cs.n[C] > 0)                                                                           \
     hipLaunchKernelGGL((k_khat<STORE, NKC>), dim3(grid_for(cs.n[C])), dim3(64), 0, s, uvw,   \
                        s0, cs.rows[C], cs.n[C], perm, meta, kabs, scale, gsx, gsy, mids, P,  \
-                       cents, kp, khat, mismatch, sg, wts);
+                       cents, kp, khat, taps, mismatch, sg, wts);
   WF_KHAT(7, 0)
   WF_KHAT(15, 1)
   WF_KHAT(21, 2)
@@ -1251,31 +1223,30 @@ void launch_khat_classes(hipStream_t s, const double* uvw, int64_t s0, const Cla
 hipError_t launch_khat(const double* uvw, int64_t s0, const ClassSlices& cs, const int32_t* perm,
                        const uint32_t* meta, const int64_t* kabs, double scale, double gsx,
                        double gsy, const double* mids, int P, const double* cents,
-                       const KernelParams& kp, void* khat, wf_store store, int* mismatch,
-                       const Surrogate& sg, const float* wts, hipStream_t s) {
+                       const KernelParams& kp, void* khat, float* taps, wf_store store,
+                       int* mismatch, const Surrogate& sg, const float* wts, hipStream_t s) {
   switch (store) {
     case WF_STORE_F32:
       launch_khat_classes<WF_STORE_F32>(s, uvw, s0, cs, perm, meta, kabs, scale, gsx, gsy, mids,
-                                        P, cents, kp, khat, mismatch, sg, wts);
+                                        P, cents, kp, khat, taps, mismatch, sg, wts);
       break;
     case WF_STORE_F16:
       launch_khat_classes<WF_STORE_F16>(s, uvw, s0, cs, perm, meta, kabs, scale, gsx, gsy, mids,
-                                        P, cents, kp, khat, mismatch, sg, wts);
+                                        P, cents, kp, khat, taps, mismatch, sg, wts);
       break;
     default:
       launch_khat_classes<WF_STORE_BF16>(s, uvw, s0, cs, perm, meta, kabs, scale, gsx, gsy,
-                                         mids, P, cents, kp, khat, mismatch, sg, wts);
+                                         mids, P, cents, kp, khat, taps, mismatch, sg, wts);
       break;
   }
   return hipGetLastError();
 }
 
 template <int STORE, int JT>
-void launch_expand_classes(hipStream_t s, const double* uvw, const ExpSlices& cs,
-                           const int32_t* perm, const uint32_t* meta, const uint32_t* voff,
-                           const int32_t* row_wi, const WorkItem* wi, double scale, double gsx,
-                           double gsy, const KernelParams& kp, const void* khat,
-                           const uint32_t* kof, void* vals, int64_t vbase, int* over) {
+void launch_expand_classes(hipStream_t s, const ExpSlices& cs, const uint32_t* meta,
+                           const uint32_t* voff, const int32_t* row_wi, const WorkItem* wi,
+                           const KernelParams& kp, const void* khat, const uint32_t* kof,
+                           const float* taps, void* vals, int64_t vbase, int* over) {
   // one launch per kept-kernel side class; a workgroup expands rpw listed rows per step,
   // rpw chosen for about 8192 wavefronts per launch (eight per SIMD) and at least one
   // row per slot
@@ -1284,8 +1255,8 @@ void launch_expand_classes(hipStream_t s, const double* uvw, const ExpSlices& cs
     const int rpw = (int)std::min<int64_t>(                                                   \
         64, std::max<int64_t>(EScratch<NKC, JT>::SL, (cs.n[C] + 8191) / 8192));              \
     hipLaunchKernelGGL((k_expand<STORE, NKC, JT>), dim3(grid_for((cs.n[C] + rpw - 1) / rpw)), \
-                       dim3(64), 0, s, uvw, cs.rows[C], cs.n[C], perm, meta, voff, row_wi, wi, \
-                       scale, gsx, gsy, kp, khat, kof, vals, vbase, rpw, over);               \
+                       dim3(64), 0, s, cs.rows[C], cs.n[C], meta, voff, row_wi, wi, kp, khat,   \
+                       kof, taps, vals, vbase, rpw, over);                                    \
   }
   WF_EXPAND(3, 0)
   WF_EXPAND(7, 1)
@@ -1297,36 +1268,34 @@ void launch_expand_classes(hipStream_t s, const double* uvw, const ExpSlices& cs
 }
 
 template <int STORE>
-void launch_expand_store(hipStream_t s, const double* uvw, const ExpSlices& cs,
-                         const int32_t* perm, const uint32_t* meta, const uint32_t* voff,
-                         const int32_t* row_wi, const WorkItem* wi, double scale, double gsx,
-                         double gsy, const KernelParams& kp, const void* khat,
-                         const uint32_t* kof, void* vals, int64_t vbase, int* over) {
+void launch_expand_store(hipStream_t s, const ExpSlices& cs, const uint32_t* meta,
+                         const uint32_t* voff, const int32_t* row_wi, const WorkItem* wi,
+                         const KernelParams& kp, const void* khat, const uint32_t* kof,
+                         const float* taps, void* vals, int64_t vbase, int* over) {
   if (kp.J <= 7)
-    launch_expand_classes<STORE, 7>(s, uvw, cs, perm, meta, voff, row_wi, wi, scale, gsx, gsy,
-                                    kp, khat, kof, vals, vbase, over);
+    launch_expand_classes<STORE, 7>(s, cs, meta, voff, row_wi, wi, kp, khat, kof, taps, vals,
+                                    vbase, over);
   else
-    launch_expand_classes<STORE, 15>(s, uvw, cs, perm, meta, voff, row_wi, wi, scale, gsx, gsy,
-                                     kp, khat, kof, vals, vbase, over);
+    launch_expand_classes<STORE, 15>(s, cs, meta, voff, row_wi, wi, kp, khat, kof, taps, vals,
+                                     vbase, over);
 }
 
-hipError_t launch_expand(const double* uvw, const ExpSlices& cs, const int32_t* perm,
-                         const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
-                         const WorkItem* wi, double scale, double gsx, double gsy,
-                         const KernelParams& kp, const void* khat, const uint32_t* kof,
-                         void* vals, int64_t vbase, wf_store store, int* over, hipStream_t s) {
+hipError_t launch_expand(const ExpSlices& cs, const uint32_t* meta, const uint32_t* voff,
+                         const int32_t* row_wi, const WorkItem* wi, const KernelParams& kp,
+                         const void* khat, const uint32_t* kof, const float* taps, void* vals,
+                         int64_t vbase, wf_store store, int* over, hipStream_t s) {
   switch (store) {
     case WF_STORE_F32:
-      launch_expand_store<WF_STORE_F32>(s, uvw, cs, perm, meta, voff, row_wi, wi, scale, gsx, gsy,
-                                        kp, khat, kof, vals, vbase, over);
+      launch_expand_store<WF_STORE_F32>(s, cs, meta, voff, row_wi, wi, kp, khat, kof, taps, vals,
+                                        vbase, over);
       break;
     case WF_STORE_F16:
-      launch_expand_store<WF_STORE_F16>(s, uvw, cs, perm, meta, voff, row_wi, wi, scale, gsx, gsy,
-                                        kp, khat, kof, vals, vbase, over);
+      launch_expand_store<WF_STORE_F16>(s, cs, meta, voff, row_wi, wi, kp, khat, kof, taps, vals,
+                                        vbase, over);
       break;
     default:
-      launch_expand_store<WF_STORE_BF16>(s, uvw, cs, perm, meta, voff, row_wi, wi, scale, gsx,
-                                         gsy, kp, khat, kof, vals, vbase, over);
+      launch_expand_store<WF_STORE_BF16>(s, cs, meta, voff, row_wi, wi, kp, khat, kof, taps,
+                                         vals, vbase, over);
       break;
   }
   return hipGetLastError();

@@ -102,7 +102,7 @@ void destroy_op(wf_op* op) {
     dfree(c.flagged);
     dfree(c.ctab);
     for (DevBuf* b : {&c.uvw, &c.wts, &c.uperm, &c.row_wi, &c.mids, &c.cents, &c.crow,
-                      &c.khat, &c.kof, &c.xrow})
+                      &c.khat, &c.kof, &c.ktap, &c.xrow})
       dfree(*b);
   }
   dfree(op->otf_mis);
@@ -647,8 +647,9 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     if (meta_bytes + transient > share)
       return fail(WF_EBUDGET, "no strategy fits the memory budget: the on-the-fly row data "
                               "alone needs " + std::to_string(meta_bytes / 1e9) + " GB");
-    // factorised form: the kernels (value format) and a 32-bit offset per row
-    const double khat_bytes = (double)b_v * khat_values + 4.0 * M;
+    // factorised form: the kernels (value format), and per row a 32-bit offset, its 2J
+    // taps (FP32) and its entry in the expansion's row lists
+    const double khat_bytes = (double)b_v * khat_values + (8.0 + 8.0 * opt.J) * M;
     const bool fits = meta_bytes + khat_bytes + transient <= share;
     if (opt.otf_form == 2 && !fits)
       return fail(WF_EBUDGET, "the factorised on-the-fly kernels need " +
@@ -914,6 +915,8 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
       if ((st = dalloc(dkabs, sizeof(int64_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
       if ((st = dalloc(ch.kof, sizeof(uint32_t) * std::max<int64_t>(M, 1))) != WF_OK) return st;
       if ((st = dalloc(ch.khat, (size_t)b_v * std::max<int64_t>(at, 1))) != WF_OK) return st;
+      if ((st = dalloc(ch.ktap, sizeof(float) * 2 * opt.J * std::max<int64_t>(M, 1))) != WF_OK)
+        return st;
       WF_HIP(hipMemcpyAsync(dkabs.p, kabs.data(), sizeof(int64_t) * M, hipMemcpyHostToDevice, s));
       WF_HIP(hipMemcpyAsync(ch.kof.p, kof.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice, s));
       st = surrogate_pass(rcs, (const int32_t*)ch.perm.p,
@@ -924,20 +927,19 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
                                                (const int64_t*)dkabs.p, ch.scale, gsx, gsy,
                                                (const double*)dmids.p, ch.P,
                                                (const double*)dcents.p, op->kp, ch.khat.p,
-                                               opt.store, (int*)dmis.p, sg,
+                                               (float*)ch.ktap.p, opt.store, (int*)dmis.p, sg,
                                                (const float*)dwts.p, s));
                             return WF_OK;
                           });
       if (st != WF_OK) return st;
       // every chunk expanded once, as an apply expands it, for the FP16 range check
       for (size_t k = 0; k < nck; ++k)
-        WF_HIP(launch_expand((const double*)duvw.p, ch.ck_xcls[k], (const int32_t*)ch.perm.p,
-                             (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
-                             (const int32_t*)drowwi.p, (const WorkItem*)ch.work.p, ch.scale,
-                             gsx, gsy, op->kp,
+        WF_HIP(launch_expand(ch.ck_xcls[k], (const uint32_t*)ch.meta.p,
+                             (const uint32_t*)ch.voff.p, (const int32_t*)drowwi.p,
+                             (const WorkItem*)ch.work.p, op->kp,
                              (const char*)ch.khat.p + (size_t)ch.ck_kbase[k] * b_v,
-                             (const uint32_t*)ch.kof.p, gtmp.p, ch.ck_vbase[k], opt.store,
-                             (int*)dmis.p + 1, s));
+                             (const uint32_t*)ch.kof.p, (const float*)ch.ktap.p, gtmp.p,
+                             ch.ck_vbase[k], opt.store, (int*)dmis.p + 1, s));
     } else {
       for (size_t k = 0; k < nck; ++k)
         WF_HIP(launch_gbuild((const double*)duvw.p, ch.ck_s0[k], ch.ck_cls[k],
@@ -948,12 +950,18 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
                              gtmp.p, ch.ck_vbase[k], opt.store, (int*)dmis.p, Surrogate{},
                              (const float*)dwts.p, s));
     }
-    std::swap(ch.uvw, duvw);
-    std::swap(ch.mids, dmids);
-    std::swap(ch.cents, dcents);
-    std::swap(ch.wts, dwts);
     std::swap(ch.row_wi, drowwi);
-    std::swap(ch.crow, dls);   // the chunks' class slices point into this list
+    if (fact) {
+      // the applies read kernels, taps and row words only: the coordinates, weights,
+      // centroids and class lists of the build are released with it
+      ch.ck_cls.clear();
+    } else {
+      std::swap(ch.uvw, duvw);
+      std::swap(ch.mids, dmids);
+      std::swap(ch.cents, dcents);
+      std::swap(ch.wts, dwts);
+      std::swap(ch.crow, dls);   // the chunks' class slices point into this list
+    }
     ch.otf = true;
     ch.fact = fact;
   }
@@ -986,7 +994,7 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
     return fail(WF_EINVAL, "weighted values exceed the FP16 range: scale the weights down "
                            "or store FP32 / BF16");
   if (sel.keep && !holo) {
-    if (otf) {
+    if (otf && !fact) {
       // the value pass reads coordinates through the built-row permutation
       if ((st = dalloc(ch.uperm, sizeof(int32_t) * M)) != WF_OK) return st;
       WF_HIP(hipMemcpyAsync(ch.uperm.p, ch.perm.p, sizeof(int32_t) * M,
@@ -1014,12 +1022,12 @@ wf_status build_channel(wf_op* op, int c, const double* uvw, int64_t M, double f
   in.k_estimate = pr.k_est;
   in.mem_g_bytes = otf ? (double)(ch.uvw.bytes + ch.wts.bytes + ch.uperm.bytes +
                                    ch.row_wi.bytes + ch.crow.bytes + ch.khat.bytes +
-                                   ch.kof.bytes + ch.xrow.bytes) + 12.0 * M +
+                                   ch.kof.bytes + ch.ktap.bytes + ch.xrow.bytes) + 12.0 * M +
                              sizeof(WorkItem) * wis.size()
                       : (double)b_v * taps_total + 12.0 * M + sizeof(WorkItem) * wis.size();
   in.mem_transient_bytes = otf ? (double)b_v * ch.ck_max : 0.0;
   in.value_pass_flops = vp_flops;
-  in.mem_khat_bytes = (double)(ch.khat.bytes + ch.kof.bytes);
+  in.mem_khat_bytes = (double)(ch.khat.bytes + ch.kof.bytes + ch.ktap.bytes);
   in.otf_form = otf ? (fact ? 2 : 1) : 0;
   in.mem_model_bytes = pr.mem_model;
   in.cost_model = pr.cost_model;
@@ -1199,12 +1207,11 @@ wf_status otf_bin_apply(wf_op* op, int kind, const Lane& L, const ChanOp& ch, in
       };
       if (ch.fact) {
         // factorised: the stored kernels convolved with the rows' taps
-        WF_HIP(launch_expand((const double*)ch.uvw.p, ch.ck_xcls[k], uperm,
-                             (const uint32_t*)ch.meta.p, (const uint32_t*)ch.voff.p,
-                             (const int32_t*)ch.row_wi.p, wk, ch.scale, gsx, gsy, op->kp,
+        WF_HIP(launch_expand(ch.ck_xcls[k], (const uint32_t*)ch.meta.p,
+                             (const uint32_t*)ch.voff.p, (const int32_t*)ch.row_wi.p, wk, op->kp,
                              (const char*)ch.khat.p + (size_t)ch.ck_kbase[k] * b_v,
-                             (const uint32_t*)ch.kof.p, L.gbuf, ch.ck_vbase[k], store,
-                             (int*)op->otf_mis.p + 1, L.s));
+                             (const uint32_t*)ch.kof.p, (const float*)ch.ktap.p, L.gbuf,
+                             ch.ck_vbase[k], store, (int*)op->otf_mis.p + 1, L.s));
       } else if (!op->net_otf) {
         if ((st = gbuild(ch.ck_cls[k], Surrogate{})) != WF_OK) return st;
       } else {

@@ -226,7 +226,8 @@ struct ChanOp {
   // factorised form: each row's kept residual kernel (times its weight) is stored, and an
   // apply only convolves it with the Kaiser-Bessel taps
   bool fact = false;
-  DevBuf khat, kof;                        // kernels (value format); offset per sorted row
+  DevBuf khat, kof, ktap;                  // kernels (value format); per sorted row its
+                                           // kernel offset and 2J taps (FP32)
   std::vector<int64_t> ck_kbase;           // per chunk: its first kernel value
   DevBuf xrow;                             // sorted rows of every chunk by n' class
   std::vector<ExpSlices> ck_xcls;          // per chunk: its slices of xrow
@@ -509,22 +510,21 @@ hipError_t launch_gbuild(const double* uvw, int64_t s0, const ClassSlices& cs,
                          const KernelParams& kp, void* vals, int64_t vbase, wf_store store,
                          int* mismatch, const Surrogate& sg, const float* wts, hipStream_t s);
 // Factorised strategy (c).  Build: the kept residual kernel of each listed sorted row,
-// times its data weight, in the value format at khat[kabs[s] ..] (n' x n', [s_v][s_u]);
-// mismatch[0] counts rows whose class or patch side differs from the symbolic pass.
+// times its data weight, in the value format at khat[kabs[s] ..] (n' x n', [s_v][s_u]),
+// and its 2J Kaiser-Bessel taps in FP32 at taps[s 2J ..] (u then v); mismatch[0] counts
+// rows whose class or patch side differs from the symbolic pass.
 hipError_t launch_khat(const double* uvw, int64_t s0, const ClassSlices& cs, const int32_t* perm,
                        const uint32_t* meta, const int64_t* kabs, double scale, double gsx,
                        double gsy, const double* mids, int P, const double* cents,
-                       const KernelParams& kp, void* khat, wf_store store, int* mismatch,
-                       const Surrogate& sg, const float* wts, hipStream_t s);
+                       const KernelParams& kp, void* khat, float* taps, wf_store store,
+                       int* mismatch, const Surrogate& sg, const float* wts, hipStream_t s);
 // Apply: the G rows of the listed sorted rows (by kept-kernel side class) from their
-// kernels at khat[kof[s] ..]
-// (khat points at the chunk's first kernel), written as launch_gbuild writes them;
-// over counts values beyond the FP16 range (FP16 store only).
-hipError_t launch_expand(const double* uvw, const ExpSlices& cs, const int32_t* perm,
-                         const uint32_t* meta, const uint32_t* voff, const int32_t* row_wi,
-                         const WorkItem* wi, double scale, double gsx, double gsy,
-                         const KernelParams& kp, const void* khat, const uint32_t* kof,
-                         void* vals, int64_t vbase, wf_store store, int* over, hipStream_t s);
+// kernels at khat[kof[s] ..] (khat points at the chunk's first kernel) and taps, written
+// as launch_gbuild writes them; over counts values beyond the FP16 range (FP16 store only).
+hipError_t launch_expand(const ExpSlices& cs, const uint32_t* meta, const uint32_t* voff,
+                         const int32_t* row_wi, const WorkItem* wi, const KernelParams& kp,
+                         const void* khat, const uint32_t* kof, const float* taps, void* vals,
+                         int64_t vbase, wf_store store, int* over, hipStream_t s);
 // Network inputs of the rows at positions [r0, r0 + nr) of list (identity when null),
 // positions in caller order, or in sorted order through perm.
 hipError_t launch_row_inputs(const double* uvw, const int32_t* list, const int32_t* perm,
