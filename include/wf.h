@@ -65,8 +65,8 @@ typedef enum { WF_STORE_F32 = 0, WF_STORE_F16 = 1, WF_STORE_BF16 = 2 } wf_store;
  * buffer of each branch at every apply, in one of two forms (option otf_form):
  *  - factorised: the build stores each row's thresholded residual kernel (n' x n'
  *    values, times its weight, in the store format; about n'^2 / T^2 ~ 0.4 of G's
- *    values); an apply only convolves it with the row's Kaiser-Bessel taps (FP64 taps,
- *    FP32 convolution);
+ *    values) and its 2J Kaiser-Bessel taps (evaluated in FP64, kept in FP32); an apply
+ *    only convolves the kernel with the taps (FP32);
  *  - rebuilt: only coordinates, weight and patch word are kept per row (about 48 bytes);
  *    an apply repeats the FP64 value pass of the build of (a), so that its results equal
  *    those of (a) up to the order of FP32 atomic additions.
@@ -244,8 +244,8 @@ typedef struct {
                                (two DFT sweeps of each residual kernel, 16 nk^3, and its
                                Kaiser-Bessel convolution, 4 J (n' T + T^2)); factorised:
                                FP32 flops of the convolution alone; else 0            */
-  double mem_khat_bytes;    /* factorised on-the-fly: device bytes of the stored kernels
-                               and their offsets (included in mem_g_bytes); else 0     */
+  double mem_khat_bytes;    /* factorised on-the-fly: device bytes of the stored kernels,
+                               their offsets and taps (included in mem_g_bytes); else 0 */
   int32_t otf_form;         /* on-the-fly: 1 rebuilt, 2 factorised; else 0             */
 } wf_plan_info;
 
