@@ -518,10 +518,10 @@ struct ColPlan {
   // lines: lines 32 / CW elements apart beyond their padded length (which is a multiple
   // of 32) put those CW runs on disjoint banks.
   static constexpr int LS = lds_elems<N>() + 32 / CW;
-  // CW lines of LS complex values, or of LS floats for an inverse pass whose lines cross
-  // LDS in halves (xchg_split, line_split), then the tile flags
-  static constexpr size_t lds_bytes(bool inverse) {
-    return (size_t)CW * LS * (inverse && line_split<N>() ? sizeof(float) : sizeof(float2)) + N / 8;
+  // CW lines of LS complex values, or of LS floats where lines cross LDS in halves
+  // (xchg_split, line_split), then the tile flags
+  static constexpr size_t lds_bytes() {
+    return (size_t)CW * LS * (line_split<N>() ? sizeof(float) : sizeof(float2)) + N / 8;
   }
 };
 
@@ -534,9 +534,26 @@ __device__ __forceinline__ void load_tile_flags(uint8_t* flags, const Masks& mk,
     flags[t] = mk.tile ? (uint8_t)bit_set(mk.tile, t * mk.tiles_x + ct) : (uint8_t)1;
 }
 
+// Needed-tile bits of a forward column pass's outputs.  The last pass writes outputs
+// j + r NS (j < NS = R1 R2, r < R3), whose tile rows are t0 + r S with t0 = j >> tsh and
+// S = NS >> tsh (a tile never exceeds NS): entry t0 holds bit r for each r, so that a
+// butterfly reads one word instead of R3 flags.
+template <int N>
+__device__ __forceinline__ void load_out_tile_bits(uint32_t* bits, const Masks& mk, int ct,
+                                                   int nthreads) {
+  constexpr int NS = RowPlan<N>::R1 * RowPlan<N>::R2, R3 = RowPlan<N>::R3;
+  const int S = NS >> mk.tsh;
+  for (int t0 = threadIdx.x; t0 < S; t0 += nthreads) {
+    uint32_t m = 0;
+    for (int r = 0; r < R3; ++r)
+      m |= (mk.tile ? (uint32_t)bit_set(mk.tile, (t0 + r * S) * mk.tiles_x + ct) : 1u) << r;
+    bits[t0] = m;
+  }
+}
+
 // With a sweep's layer table sl, workgroup i takes (layer, column group) pairs[i].
 template <int N>
-__global__ __launch_bounds__(ColPlan<N>::NT) void k_fwd_cols_reg(const float2* __restrict__ A,
+__global__ __launch_bounds__(ColPlan<N>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_fwd_cols_reg(const float2* __restrict__ A,
                                                                  float2* __restrict__ X,
                                                                  const float2* __restrict__ tw,
                                                                  int ny, Masks mk,
@@ -547,7 +564,10 @@ __global__ __launch_bounds__(ColPlan<N>::NT) void k_fwd_cols_reg(const float2* _
   constexpr int CW = ColPlan<N>::CW, NTC = ColPlan<N>::NTC, NT = ColPlan<N>::NT;
   constexpr int LS = ColPlan<N>::LS;
   extern __shared__ float2 buf[];
-  uint8_t* tflag = reinterpret_cast<uint8_t*>(buf + CW * LS);
+  // CW lines of LS floats (split exchange) or complex values, then the output tile bits
+  constexpr bool SPLIT = line_split<N>();
+  uint32_t* omask = SPLIT ? reinterpret_cast<uint32_t*>(reinterpret_cast<float*>(buf) + CW * LS)
+                          : reinterpret_cast<uint32_t*>(buf + CW * LS);
   const int gi = xcd_remap(blockIdx.x, gridDim.x);
   int g;
   if (sl) {
@@ -563,49 +583,53 @@ __global__ __launch_bounds__(ColPlan<N>::NT) void k_fwd_cols_reg(const float2* _
   const int q0 = g * CW;
   const int strip = q0 >> 4, c0 = q0 & (SW - 1);
   const int c = threadIdx.x % CW, tj = threadIdx.x / CW;
-  float2* line = buf + c * LS;
-  load_tile_flags(tflag, mk, N, q0 >> mk.tsh, NT);
-  const float2* __restrict__ src = A + ((int64_t)strip * ny) * SW + c0 + c;
+  void* line = SPLIT ? (void*)(reinterpret_cast<float*>(buf) + c * LS) : (void*)(buf + c * LS);
+  // the bits are read after the exchanges' barriers only
+  load_out_tile_bits<N>(omask, mk, q0 >> mk.tsh, NT);
+  // wave-uniform bases and 32-bit element offsets (a strip holds at most 16 N elements)
+  const float2* __restrict__ src = A + ((int64_t)strip * ny) * SW + c0;
+  float2 v1[N / NTC];
   {
     constexpr int B = (N / R1) / NTC;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = tj + b * NTC;
-      float2 v[R1];
+      float2* v = v1 + b * R1;
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
         const int q = j + r * (N / R1);
         if (r < R1 / 4 || r >= 3 * R1 / 4) {
           const int jrow = r < R1 / 4 ? q + N / 4 : q - 3 * (N / 4);
-          v[r] = src[(int64_t)jrow * SW];
+          v[r] = src[jrow * SW + c];
         } else {
           v[r] = make_float2(0.f, 0.f);
         }
       }
       dft_reg<R1, false>(v);
-#pragma unroll
-      for (int r = 0; r < R1; ++r) line[lds_slot(j * R1 + r)] = v[r];
     }
   }
-  __syncthreads();
-  reg_pass_lds<N, R2, R1, NTC, false>(line, tw, tj);
-  float2* __restrict__ dst = X + ((int64_t)strip * N) * SW + c0 + c;
+  float2 v3[N / NTC];
+  row_middle<N, false>(line, v1, v3, tw, tj);
+  float2* __restrict__ dst = X + ((int64_t)strip * N) * SW + c0;
   {
+    // the lane's column and butterfly index are taken afresh from the thread index (the
+    // empty asm hides that it is unchanged) rather than held through the exchanges
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int cl = tid % CW, tl = tid / CW;
     constexpr int NS = R1 * R2;
     constexpr int B = (N / R3) / NTC;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      const int j = tj + b * NTC;
-      float2 v[R3];
-#pragma unroll
-      for (int r = 0; r < R3; ++r) v[r] = line[lds_slot(j + r * NS)];
+      const int j = tl + b * NTC;
+      float2* v = v3 + b * R3;
 #pragma unroll
       for (int r = 1; r < R3; ++r) v[r] = cmul(v[r], tw[r * j]);
       dft_reg<R3, false>(v);
+      const uint32_t need = omask[j >> mk.tsh];
 #pragma unroll
       for (int r = 0; r < R3; ++r) {
-        const int qv = j + r * NS;
-        if (tflag[qv >> mk.tsh]) dst[(int64_t)qv * SW] = v[r];
+        if ((need >> r) & 1u) dst[(j + r * NS) * SW + cl] = v[r];
       }
     }
   }
@@ -894,7 +918,7 @@ static hipError_t launch_cols_reg(float2* in, float2* out, const float2* tw, int
                                   const ColPrune* pr, hipStream_t s) {
   constexpr int CW = ColPlan<N>::CW;
   if (Kx % CW != 0) return hipErrorInvalidValue;
-  const size_t lds = ColPlan<N>::lds_bytes(INV);
+  const size_t lds = ColPlan<N>::lds_bytes();
   Masks mk{nullptr, nullptr, nullptr, 1, 0};
   int ng = Kx / CW;
   if (pr) {
@@ -1039,7 +1063,7 @@ hipError_t launch_sweep_cols(bool inverse, const SweepLayer* sl, const int2* pai
   switch (Ky) {
 #define C(NN)                                                                                 \
   case NN: {                                                                                  \
-    const size_t lds = ColPlan<NN>::lds_bytes(inverse);                                       \
+    const size_t lds = ColPlan<NN>::lds_bytes();                                       \
     hipError_t e;                                                                             \
     if (inverse) {                                                                            \
       e = set_lds(k_inv_cols_reg<NN>, lds);                                                   \
