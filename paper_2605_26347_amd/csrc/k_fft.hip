@@ -224,7 +224,7 @@ __global__ __launch_bounds__(NT) void k_inv_rows(const float2* __restrict__ A,
 // With a sweep's layer table sl, workgroup (row, layer) takes the layer's grid, mask and
 // centroid from sl[blockIdx.y] and its channel's image from img (all channels' images).
 template <int N>
-__global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
+__global__ __launch_bounds__(RowPlan<N>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_fwd_rows_reg(
     const float* __restrict__ img, float2* __restrict__ A, const float2* __restrict__ tw,
     const float* __restrict__ sx, const float* __restrict__ sy, int nx, int ny, double cell,
     double wp, const uint32_t* __restrict__ smask, const SweepLayer* __restrict__ sl,
@@ -292,11 +292,17 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
   float2 v3[N / NT];
   row_middle<N, false>(buf, v1, v3, tw, threadIdx.x);
   {
+    // the thread index taken afresh (the empty asm hides that it is unchanged) rather
+    // than held through the exchanges; a wave-uniform row base and 32-bit strip offsets
+    // (a grid holds at most 2^27 elements)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    float2* __restrict__ arow = A + (int64_t)jr * SW;
     constexpr int NS = R1 * R2;
     constexpr int B = (N / R3) / NT;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      const int j = threadIdx.x + b * NT;
+      const int j = tid + b * NT;
       float2* v = v3 + b * R3;
 #pragma unroll
       for (int r = 1; r < R3; ++r) v[r] = cmul(v[r], tw[r * j]);
@@ -304,7 +310,7 @@ __global__ __launch_bounds__(RowPlan<N>::NT) void k_fwd_rows_reg(
 #pragma unroll
       for (int r = 0; r < R3; ++r) {
         const int q = j + r * NS;
-        if (!smask || strip_on<NS>(smask, j, r)) A[strip_index(jr, q, ny)] = v[r];
+        if (!smask || strip_on<NS>(smask, j, r)) arow[(q >> 4) * ny * SW + (q & (SW - 1))] = v[r];
       }
     }
   }
