@@ -542,17 +542,22 @@ __device__ __forceinline__ void load_tile_flags(uint8_t* flags, const Masks& mk,
 
 // Needed-tile bits of a forward column pass's outputs.  The last pass writes outputs
 // j + r NS (j < NS = R1 R2, r < R3), whose tile rows are t0 + r S with t0 = j >> tsh and
-// S = NS >> tsh (a tile never exceeds NS): entry t0 holds bit r for each r, so that a
-// butterfly reads one word instead of R3 flags.
+// S = NS >> tsh (a mask's tile, at most 128, never exceeds NS): entry t0 holds bit r for
+// each r, so that a butterfly reads one word instead of R3 flags.  Without a mask every
+// entry a butterfly can read (one when tsh exceeds the line) has every bit set.
 template <int N>
 __device__ __forceinline__ void load_out_tile_bits(uint32_t* bits, const Masks& mk, int ct,
                                                    int nthreads) {
   constexpr int NS = RowPlan<N>::R1 * RowPlan<N>::R2, R3 = RowPlan<N>::R3;
-  const int S = NS >> mk.tsh;
+  static_assert(R3 <= 32, "one word per entry");
+  const int S = (NS >> mk.tsh) > 0 ? (NS >> mk.tsh) : 1;
   for (int t0 = threadIdx.x; t0 < S; t0 += nthreads) {
-    uint32_t m = 0;
-    for (int r = 0; r < R3; ++r)
-      m |= (mk.tile ? (uint32_t)bit_set(mk.tile, (t0 + r * S) * mk.tiles_x + ct) : 1u) << r;
+    uint32_t m = 0xffffffffu;
+    if (mk.tile) {
+      m = 0;
+      for (int r = 0; r < R3; ++r)
+        m |= (uint32_t)bit_set(mk.tile, (t0 + r * S) * mk.tiles_x + ct) << r;
+    }
     bits[t0] = m;
   }
 }
